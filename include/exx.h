@@ -1,0 +1,153 @@
+/*
+ * exx.h -- C ABI of the MI355X (gfx950) exact-exchange pair kernel.
+ *
+ * The library evaluates the exact-exchange (EXX) energy E_xx, the orbital
+ * forces D_xx^i and the cell derivatives sigma_xx of a set of real localized
+ * orbitals, by the subdomain method of Ko, Santra and DiStasio (arXiv:2011.07209):
+ * for every unique pair of orbitals whose centres lie within R_pair it forms
+ * the pair density on a sphere of radius R_PE about the pair's grid centre,
+ * sets far-field values on the shell R_PE < r <= R_ME from a multipole
+ * expansion, solves the finite-difference Poisson equation on the sphere by
+ * conjugate gradient, and accumulates E_xx, D_xx and sigma_xx.
+ *
+ * Units: bohr and Hartree.  Cell tensor h is column-major, h[a + 3*al] is the
+ * Cartesian component a of lattice vector L_al (Sec. II B 1).  Grid arrays are
+ * [N3][N2][N1] with the L_1 index fastest; grid point g sits at h (g / N).
+ *
+ * Ownership: the caller owns every buffer passed in or out; the plan owns its
+ * tables and its device workspace.  Device pointers are HIP device (or managed)
+ * memory on the device current when the plan was made.  Calls on one plan are
+ * not thread-safe.  Errors are returned as status codes, never thrown; the
+ * message of the last failure on a plan is available from exx_last_error().
+ */
+#ifndef EXX_H_
+#define EXX_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct exx_plan_s* exx_plan_t;
+
+typedef enum {
+  EXX_OK = 0,
+  EXX_EINVAL = 1,      /* an argument is out of range or inconsistent            */
+  EXX_ENOMEM = 2,      /* a device or host allocation failed                     */
+  EXX_ENOCONV = 3,     /* at least one pair's CG hit cg_max_iter (outputs kept)  */
+  EXX_EDEVICE = 4,     /* a HIP runtime call failed                              */
+  EXX_ECAPACITY = 5    /* more pairs than the plan's fixed capacity              */
+} exx_status;
+
+typedef enum { EXX_F64 = 0, EXX_F32 = 1 } exx_dtype;
+
+typedef enum {
+  EXX_PREC_FP64 = 0,   /* every step in double precision                          */
+  EXX_PREC_MIXED = 1   /* FP32 stencil/vector work with FP64 dots and an FP64
+                          residual-correction pass per solve                      */
+} exx_precision;
+
+typedef struct {
+  int stencil_n;              /* half-width n of the axis stencils, 1..3 (Sec. III C,
+                                 eq. d2_1; the paper's default is 3)               */
+  int precision;              /* exx_precision                                      */
+  double cg_tol;              /* stop when ||r||_2 <= cg_tol ||b||_2 (FP64 residual)  */
+  int cg_max_iter;            /* per solve; hitting it is reported as EXX_ENOCONV   */
+  /* variable sphere radii: with per-orbital radii passed to exx_eval, the pair
+     radius is the rung R_PE_min + k R_PE_step (k < R_PE_nclass) nearest to
+     (R_i + R_j)/2; R_PE_nclass <= 0 keeps the single plan radius R_PE          */
+  double R_PE_min, R_PE_step;
+  int R_PE_nclass;
+  /* deterministic pair subset: pair (i,j) is kept when the top 53 bits of one
+     SplitMix64 output on the state seed ^ (i << 32) ^ j, read as a fraction,
+     fall below pair_sample_frac; >= 1 keeps every pair                        */
+  unsigned long long pair_sample_seed;
+  double pair_sample_frac;
+  long long max_pairs;        /* 0: workspace grows on demand; > 0: fixed capacity,
+                                 more pairs give EXX_ECAPACITY                     */
+  double workspace_gb;        /* cap on per-batch pair workspace (0: 24 GB)        */
+  int solve_groups;           /* persistent solve workgroups (0: one per CU)       */
+} exx_options;
+
+/* Fills *opt with the defaults: n = 3, FP64, tol 1e-10, 5000 iterations,
+   fixed radius, all pairs, on-demand workspace. */
+void exx_default_options(exx_options* opt);
+
+/* Builds a plan for an orthorhombic cell (Sec. III B 1: proto-subdomains about
+   the grid origin, translated per pair by eq. l2g).  h: host [9]; grid: host
+   [3].  R_ME must be >= the largest R_PE + n max(spacing) so that every
+   stencil neighbour of the PE sphere has a far-field value (Sec. IV A); l_max
+   <= 8.  A non-orthogonal h gives EXX_EINVAL.  opt may be NULL (defaults).
+   On success *out owns the plan's device tables (on the current device). */
+exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double R_PE, double R_ME, int l_max,
+                    const exx_options* opt, exx_plan_t* out);
+
+/* Binds the HIP stream (a hipStream_t, or NULL for the null stream) that
+   exx_eval enqueues on. */
+exx_status exx_set_stream(exx_plan_t plan, void* hip_stream);
+
+/* Evaluates E_xx (Sec. I, eq. exxGen_mlwf), D_xx (Sec. II B 2, eq. Dxx) and
+   sigma_xx (Sec. II B 3, eq. sxx_working) for n_orb orbitals.
+     orbitals  device, [n_orb][N3][N2][N1] of dtype dt, read only
+     centres   device, [n_orb][3] Cartesian orbital centres (bohr), read only
+     R_PE_orb  device, [n_orb] per-orbital radii, or NULL for the plan radius
+     E_xx      device, 1 double, overwritten
+     D_xx      device, [n_orb][N3][N2][N1] of dtype dt, overwritten; NULL skips D
+     sigma     device, 9 doubles, sigma[a + 3*al] = dE/dh_{a al}; NULL skips it
+   Unique pairs i <= j carry weight 1 (i == j) or 2 (i != j) in E and sigma;
+   D^i receives v_ij phi_j and D^j receives v_ij phi_i on the ME sphere.
+   Enqueued on the bound stream; the call returns after one host wait for the
+   pair count.  Outputs are complete when the stream is. */
+exx_status exx_eval(exx_plan_t plan, int n_orb, const void* orbitals, exx_dtype dt, const double* centres,
+                    const double* R_PE_orb, double* E_xx, void* D_xx, double* sigma);
+
+/* Per-pair results of the last exx_eval, copied to host arrays of capacity
+   cap (any may be NULL): ij [2*cap] (i, j), E [cap] (weighted contribution),
+   sigma [9*cap], iters [cap], rel_res [cap] (final recursive ||r||/||b||).
+   Pairs come in i-major, j-ascending order.  Synchronizes the bound stream.
+   Returns the number of pairs of the last evaluation in *n_pairs. */
+exx_status exx_pair_results(exx_plan_t plan, long long cap, int* ij, double* E, double* sigma, int* iters,
+                            double* rel_res, long long* n_pairs);
+
+typedef struct {
+  long long n_pairs;
+  long long cg_iter_sum;       /* sum over pairs of CG iterations (inner, mixed)   */
+  int cg_iter_max;
+  int n_unconverged;
+  int n_classes;
+  int refine_passes_max;       /* mixed precision: FP64 correction passes          */
+  double max_rel_residual;     /* max over pairs of ||b - A x|| / ||b||            */
+  double solve_ms;             /* device time of the solve kernels (last eval)     */
+  double eval_ms;              /* device time of the whole evaluation              */
+  double cg_alg_bytes;         /* algorithmic CG bytes: sum_pairs iters 8 N_PE b   */
+  double moment_flops;         /* algorithmic moment flops: 2 N_lm N_PE per pair   */
+} exx_stats;
+
+/* Statistics of the last exx_eval (synchronizes the bound stream).  Returns
+   EXX_ENOCONV when a pair did not converge. */
+exx_status exx_stats_fetch(exx_plan_t plan, exx_stats* out);
+
+/* Number of points of a sphere class of the plan (n_pe, n_halo, n_me may be
+   NULL); class 0 is the plan radius.  Host only. */
+exx_status exx_plan_geometry(exx_plan_t plan, int cls, long long* n_pe, long long* n_halo, long long* n_me);
+
+/* Host-only planning aid (no device needed): point counts of the PE sphere,
+   of its Dirichlet points (reached by the axis stencil of half-width
+   stencil_n) and of the whole ME sphere, for an orthorhombic cell, with the
+   same membership rule as exx_plan (|r|^2 <= R^2 (1 + 1e-12)). */
+exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_PE, double R_ME, int stencil_n,
+                                long long* n_pe, long long* n_halo, long long* n_me);
+
+/* Frees the plan and its device memory.  NULL is accepted. */
+exx_status exx_destroy(exx_plan_t plan);
+
+/* Message of the last failure on the plan (or of the last failed exx_plan
+   when plan is NULL).  The string stays valid until the next call on it. */
+const char* exx_last_error(exx_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXX_H_ */

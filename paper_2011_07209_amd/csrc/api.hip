@@ -1,0 +1,536 @@
+// C ABI of the gfx950 EXX library (declared in include/exx.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "exx_launch.h"
+
+using namespace exx;
+
+namespace {
+
+thread_local std::string g_plan_error;
+
+exx_status fail(exx_plan_t P, exx_status st, const std::string& msg) {
+  if (P) P->err = msg; else g_plan_error = msg;
+  return st;
+}
+
+#define EXX_HIP(P, expr)                                                                              \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return fail((P), EXX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double det3(const double* m) {
+  auto M = [&](int r, int c) { return m[r + 3 * c]; };
+  return M(0, 0) * (M(1, 1) * M(2, 2) - M(1, 2) * M(2, 1)) - M(0, 1) * (M(1, 0) * M(2, 2) - M(1, 2) * M(2, 0)) +
+         M(0, 2) * (M(1, 0) * M(2, 1) - M(1, 1) * M(2, 0));
+}
+
+void inv3(const double* m, double* inv) {
+  auto M = [&](int r, int c) { return m[r + 3 * c]; };
+  const double d = det3(m);
+  inv[0 + 3 * 0] = (M(1, 1) * M(2, 2) - M(1, 2) * M(2, 1)) / d;
+  inv[0 + 3 * 1] = (M(0, 2) * M(2, 1) - M(0, 1) * M(2, 2)) / d;
+  inv[0 + 3 * 2] = (M(0, 1) * M(1, 2) - M(0, 2) * M(1, 1)) / d;
+  inv[1 + 3 * 0] = (M(1, 2) * M(2, 0) - M(1, 0) * M(2, 2)) / d;
+  inv[1 + 3 * 1] = (M(0, 0) * M(2, 2) - M(0, 2) * M(2, 0)) / d;
+  inv[1 + 3 * 2] = (M(0, 2) * M(1, 0) - M(0, 0) * M(1, 2)) / d;
+  inv[2 + 3 * 0] = (M(1, 0) * M(2, 1) - M(1, 1) * M(2, 0)) / d;
+  inv[2 + 3 * 1] = (M(0, 1) * M(2, 0) - M(0, 0) * M(2, 1)) / d;
+  inv[2 + 3 * 2] = (M(0, 0) * M(1, 1) - M(0, 1) * M(1, 0)) / d;
+}
+
+// Central-difference weights (Fornberg 1988): second derivative (the n = 3 set
+// is the one printed with eq. d2_1) and antisymmetric first derivative (the
+// n = 3 set printed with eq. d1_1).
+void stencil_weights(int n, double* w2, double* w1) {
+  for (int q = 0; q < 4; ++q) w2[q] = w1[q] = 0.0;
+  switch (n) {
+    case 1:
+      w2[0] = -2.0; w2[1] = 1.0;
+      w1[1] = 1.0 / 2.0;
+      break;
+    case 2:
+      w2[0] = -5.0 / 2.0; w2[1] = 4.0 / 3.0; w2[2] = -1.0 / 12.0;
+      w1[1] = 2.0 / 3.0; w1[2] = -1.0 / 12.0;
+      break;
+    default:
+      w2[0] = -49.0 / 18.0; w2[1] = 3.0 / 2.0; w2[2] = -3.0 / 20.0; w2[3] = 1.0 / 90.0;
+      w1[1] = 3.0 / 4.0; w1[2] = -3.0 / 20.0; w1[3] = 1.0 / 60.0;
+      break;
+  }
+}
+
+// normalisation of the real orthonormal harmonics: N_l0, and sqrt(2) N_lm for m != 0,
+// N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
+void harmonic_norms(int L, double* out) {
+  for (int l = 0; l <= L; ++l)
+    for (int m = 0; m <= l; ++m) {
+      double ratio = 1.0;
+      for (int k = l - m + 1; k <= l + m; ++k) ratio /= (double)k;
+      const double N = std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * ratio);
+      if (m == 0) {
+        out[l * l + l] = N;
+      } else {
+        out[l * l + l + m] = std::sqrt(2.0) * N;
+        out[l * l + l - m] = std::sqrt(2.0) * N;
+      }
+    }
+}
+
+template <typename T>
+exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  if (count == 0) return EXX_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(P, EXX_ENOMEM, std::string("device allocation failed: ") + what);
+  }
+  return EXX_OK;
+}
+
+void free_plan(exx_plan_t P) {
+  if (!P) return;
+  void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
+                  P->pRes, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->slot_ws, P->queue, P->stats_dev};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& e : P->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete P;
+}
+
+}  // namespace
+
+extern "C" {
+
+void exx_default_options(exx_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->stencil_n = 3;
+  o->precision = EXX_PREC_FP64;
+  o->cg_tol = 1e-10;
+  o->cg_max_iter = 5000;
+  o->pair_sample_frac = 1.0;
+}
+
+exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double R_PE, double R_ME, int l_max,
+                    const exx_options* opt_in, exx_plan_t* out) {
+  if (!out) return fail(nullptr, EXX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!h || !grid) return fail(nullptr, EXX_EINVAL, "h or grid is NULL");
+  exx_options opt;
+  if (opt_in) opt = *opt_in; else exx_default_options(&opt);
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(h[k])) return fail(nullptr, EXX_EINVAL, "cell tensor is not finite");
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      if (r != c && h[r + 3 * c] != 0.0)
+        return fail(nullptr, EXX_EINVAL, "only orthorhombic cells are supported (off-diagonal h must be 0)");
+  for (int a = 0; a < 3; ++a) {
+    if (!(h[a + 3 * a] > 0.0)) return fail(nullptr, EXX_EINVAL, "cell edges must be positive");
+    if (grid[a] <= 0 || grid[a] > 32000) return fail(nullptr, EXX_EINVAL, "grid dimensions out of range");
+  }
+  if (!(R_pair >= 0.0) || !(R_PE > 0.0) || !(R_ME >= R_PE)) return fail(nullptr, EXX_EINVAL, "radii out of range");
+  if (l_max < 0 || l_max > kMaxL) return fail(nullptr, EXX_EINVAL, "l_max must be in [0, 8]");
+  if (opt.stencil_n < 1 || opt.stencil_n > 3) return fail(nullptr, EXX_EINVAL, "stencil_n must be 1, 2 or 3");
+  if (!(opt.cg_tol > 0.0) || opt.cg_max_iter < 1) return fail(nullptr, EXX_EINVAL, "CG tolerance/iterations invalid");
+  if (opt.precision != EXX_PREC_FP64 && opt.precision != EXX_PREC_MIXED)
+    return fail(nullptr, EXX_EINVAL, "unknown precision");
+  if (opt.R_PE_nclass < 0 || opt.R_PE_nclass > kMaxClasses) return fail(nullptr, EXX_EINVAL, "R_PE_nclass out of range");
+  if (opt.R_PE_nclass > 0 && (!(opt.R_PE_min > 0.0) || !(opt.R_PE_step > 0.0)))
+    return fail(nullptr, EXX_EINVAL, "variable radii need R_PE_min > 0 and R_PE_step > 0");
+  if (opt.max_pairs < 0 || opt.workspace_gb < 0 || opt.solve_groups < 0)
+    return fail(nullptr, EXX_EINVAL, "negative capacity option");
+
+  exx_plan_t P = new (std::nothrow) exx_plan_s();
+  if (!P) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
+  P->opt = opt;
+  std::memcpy(P->h, h, sizeof(P->h));
+  std::memcpy(P->grid, grid, sizeof(P->grid));
+  P->R_pair = R_pair;
+  P->R_PE = R_PE;
+  P->R_ME = R_ME;
+  P->l_max = l_max;
+
+  Geo& g = P->geo;
+  std::memset(&g, 0, sizeof(g));
+  std::memcpy(g.h, h, sizeof(g.h));
+  inv3(h, g.hinv);
+  const int n = opt.stencil_n;
+  double maxd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    g.L[a] = h[a + 3 * a];
+    g.N[a] = grid[a];
+    g.d[a] = g.L[a] / grid[a];
+    g.inv_d2[a] = 1.0 / (g.d[a] * g.d[a]);
+    g.inv_d[a] = 1.0 / g.d[a];
+    maxd = std::max(maxd, g.d[a]);
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int al = 0; al < 3; ++al) g.J[a + 3 * al] = g.L[al] * g.hinv[al + 3 * a];
+  g.ngrid = (long long)grid[0] * grid[1] * grid[2];
+  g.dV = std::fabs(det3(h)) / (double)g.ngrid;
+  stencil_weights(n, g.w2, g.w1);
+  g.n = n;
+  g.l_max = l_max;
+  g.n_lm = (l_max + 1) * (l_max + 1);
+  harmonic_norms(l_max, g.ylm_norm);
+
+  std::vector<double> radii;
+  if (opt.R_PE_nclass > 0) {
+    for (int k = 0; k < opt.R_PE_nclass; ++k) radii.push_back(opt.R_PE_min + k * opt.R_PE_step);
+  } else {
+    radii.push_back(R_PE);
+  }
+  const double rmax = *std::max_element(radii.begin(), radii.end());
+  if (R_ME < rmax + n * maxd) {
+    free_plan(P);
+    return fail(nullptr, EXX_EINVAL, "R_ME must be >= R_PE + n * max grid spacing");
+  }
+  P->classes.resize(radii.size());
+  int maxRg0 = 0, maxRg1 = 0;
+  for (size_t k = 0; k < radii.size(); ++k) {
+    std::string e = build_class(g.L, g.N, radii[k], R_ME, n, &P->classes[k]);
+    if (!e.empty()) {
+      free_plan(P);
+      return fail(nullptr, EXX_EINVAL, e);
+    }
+    const ClassHost& C = P->classes[k];
+    P->max_pe = std::max(P->max_pe, C.n_pe);
+    P->max_halo = std::max(P->max_halo, C.n_halo);
+    P->max_me = std::max(P->max_me, C.n_me);
+    P->max_cols = std::max<long long>(P->max_cols, C.n_cols);
+    P->max_zmax = std::max(P->max_zmax, C.Zmax);
+    maxRg0 = std::max(maxRg0, C.Rg[0]);
+    maxRg1 = std::max(maxRg1, C.Rg[1]);
+  }
+  g.lds_cx = maxRg0 + n;
+  g.lds_cy = maxRg1 + n;
+  g.lds_wx = 2 * g.lds_cx + 1;
+  g.lds_wy = 2 * g.lds_cy + 1;
+  if (P->max_cols > 8LL * kSolveThreads) {
+    free_plan(P);
+    return fail(nullptr, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");
+  }
+  if (solve_lds_bytes(g, P->max_zmax) > 160 * 1024) {
+    free_plan(P);
+    return fail(nullptr, EXX_EINVAL, "PE sphere too wide for the LDS plane buffers");
+  }
+
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    free_plan(P);
+    return fail(nullptr, EXX_EDEVICE, "no HIP device");
+  }
+  // upload the class tables into one block
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t total = 0;
+  for (const ClassHost& C : P->classes) {
+    total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
+             align(C.halo_off.size() * sizeof(short4)) + align(C.me_off.size() * sizeof(short4)) +
+             align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
+             align(C.zr_map.size() * sizeof(int));
+  }
+  if (hipMalloc(&P->class_block, total) != hipSuccess) {
+    free_plan(P);
+    return fail(nullptr, EXX_ENOMEM, "device allocation of the subdomain tables failed");
+  }
+  char* base = (char*)P->class_block;
+  size_t off = 0;
+  auto put = [&](const void* src, size_t bytes) -> const void* {
+    void* dst = base + off;
+    if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    off += align(bytes);
+    return dst;
+  };
+  for (const ClassHost& C : P->classes) {
+    ClassDev D;
+    std::memset(&D, 0, sizeof(D));
+    D.R_PE = C.R_PE;
+    D.n_cols = C.n_cols;
+    D.Zmax = C.Zmax;
+    for (int a = 0; a < 3; ++a) {
+      D.Rg[a] = C.Rg[a];
+      D.Wm[a] = C.Wm[a];
+    }
+    D.n_pe = C.n_pe;
+    D.n_halo = C.n_halo;
+    D.n_me = C.n_me;
+    D.cols = (const int4*)put(C.cols.data(), C.cols.size() * sizeof(int4));
+    D.plane_start = (const int*)put(C.plane_start.data(), C.plane_start.size() * sizeof(int));
+    D.halo_off = (const short4*)put(C.halo_off.data(), C.halo_off.size() * sizeof(short4));
+    D.me_off = (const short4*)put(C.me_off.data(), C.me_off.size() * sizeof(short4));
+    D.halo_map = (const int*)put(C.halo_map.data(), C.halo_map.size() * sizeof(int));
+    D.col_map = (const int*)put(C.col_map.data(), C.col_map.size() * sizeof(int));
+    D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
+    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || !D.col_map || !D.zr_map) {
+      free_plan(P);
+      return fail(nullptr, EXX_EDEVICE, "upload of the subdomain tables failed");
+    }
+    P->class_dev_host.push_back(D);
+  }
+  if (hipMalloc(&P->class_dev, sizeof(ClassDev) * P->class_dev_host.size()) != hipSuccess ||
+      hipMemcpy(P->class_dev, P->class_dev_host.data(), sizeof(ClassDev) * P->class_dev_host.size(),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan(P);
+    return fail(nullptr, EXX_EDEVICE, "upload of the class descriptors failed");
+  }
+  for (auto& e : P->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      free_plan(P);
+      return fail(nullptr, EXX_EDEVICE, "event creation failed");
+    }
+  if (hipMalloc(&P->queue, sizeof(int)) != hipSuccess || hipMalloc(&P->stats_dev, 8 * sizeof(double)) != hipSuccess) {
+    free_plan(P);
+    return fail(nullptr, EXX_ENOMEM, "device allocation failed");
+  }
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
+  int per_cu = solve_groups_per_cu(g, (int)P->max_cols, P->max_zmax);
+  if (per_cu < 1) {
+    free_plan(P);
+    return fail(nullptr, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
+  }
+  P->n_slots = opt.solve_groups > 0 ? opt.solve_groups : std::max(1, cus) * per_cu;
+  if (opt.max_pairs > 0) P->pair_cap_fixed = true;
+  *out = P;
+  return EXX_OK;
+}
+
+exx_status exx_set_stream(exx_plan_t P, void* s) {
+  if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
+  P->stream = (hipStream_t)s;
+  return EXX_OK;
+}
+
+exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt, const double* centres,
+                    const double* R_PE_orb, double* E_xx, void* D_xx, double* sigma) {
+  if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
+  if (n_orb < 1) return fail(P, EXX_EINVAL, "n_orb must be >= 1");
+  if (!orbitals || !centres || !E_xx) return fail(P, EXX_EINVAL, "orbitals, centres and E_xx are required");
+  if (dt != EXX_F64 && dt != EXX_F32) return fail(P, EXX_EINVAL, "unknown dtype");
+  if (P->opt.R_PE_nclass > 0 && !R_PE_orb)
+    return fail(P, EXX_EINVAL, "variable radii need per-orbital radii (R_PE_orb)");
+  const Geo& g = P->geo;
+  hipStream_t s = P->stream;
+  int dev = -1;
+  EXX_HIP(P, hipGetDevice(&dev));
+  if (dev != P->device) return fail(P, EXX_EINVAL, "current device differs from the plan's device");
+  P->timing_valid = false;
+
+  // pair list
+  if (n_orb > P->orb_cap) {
+    if (dev_alloc(P, &P->pair_count, (size_t)2 * n_orb + 1 + kMaxClasses, "pair counts")) return EXX_ENOMEM;
+    P->orb_cap = n_orb;
+  }
+  PairParams pp;
+  pp.R_pair2 = P->R_pair * P->R_pair * (1.0 + kSlack);
+  pp.R_PE = P->R_PE;
+  pp.R_min = P->opt.R_PE_min;
+  pp.R_step = P->opt.R_PE_step;
+  pp.n_class = P->opt.R_PE_nclass;
+  pp.seed = P->opt.pair_sample_seed;
+  pp.frac = P->opt.pair_sample_frac;
+  EXX_HIP(P, hipEventRecord(P->ev[0], s));
+  if (P->opt.max_pairs > 0 && P->pair_cap < P->opt.max_pairs) {
+    if (dev_alloc(P, &P->pairs, (size_t)P->opt.max_pairs, "pairs") || dev_alloc(P, &P->order, (size_t)P->opt.max_pairs, "order") ||
+        dev_alloc(P, &P->pE, (size_t)P->opt.max_pairs, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * P->opt.max_pairs, "pair sigma") ||
+        dev_alloc(P, &P->pIt, (size_t)P->opt.max_pairs, "pair iters") || dev_alloc(P, &P->pRes, (size_t)P->opt.max_pairs, "pair res"))
+      return EXX_ENOMEM;
+    P->pair_cap = P->opt.max_pairs;
+  }
+  EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
+  int total = 0;
+  EXX_HIP(P, hipMemcpyAsync(&total, P->pair_count + 2 * n_orb, sizeof(int), hipMemcpyDeviceToHost, s));
+  EXX_HIP(P, hipStreamSynchronize(s));
+  if (total < 0) return fail(P, EXX_EINVAL, "pair count overflow");
+  if (total > P->pair_cap) {
+    if (P->opt.max_pairs > 0) return fail(P, EXX_ECAPACITY, "more pairs than max_pairs");
+    const long long cap = std::max<long long>(total, 1) + total / 8;
+    if (dev_alloc(P, &P->pairs, (size_t)cap, "pairs") || dev_alloc(P, &P->order, (size_t)cap, "order") ||
+        dev_alloc(P, &P->pE, (size_t)cap, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * cap, "pair sigma") ||
+        dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res"))
+      return EXX_ENOMEM;
+    P->pair_cap = cap;
+    EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
+  }
+  P->n_pairs = total;
+  P->last_n_orb = n_orb;
+  const int ncls = (int)P->classes.size();
+  EXX_HIP(P, launch_order(P->pairs, P->pair_count, n_orb, ncls, P->order, s));
+
+  // workspace
+  const long long per_pair = 2 * P->max_pe + P->max_halo + kMaxLM;
+  const double budget = (P->opt.workspace_gb > 0 ? P->opt.workspace_gb : 24.0) * 1e9;
+  long long batch = std::max<long long>(1, (long long)(budget / (8.0 * per_pair)));
+  batch = std::min<long long>(batch, std::max<long long>(total, 1));
+  if (batch > P->batch_cap) {
+    if (dev_alloc(P, &P->rho_ws, (size_t)batch * P->max_pe, "pair densities") ||
+        dev_alloc(P, &P->bx_ws, (size_t)batch * P->max_pe, "pair potentials") ||
+        dev_alloc(P, &P->halo_ws, (size_t)batch * std::max<long long>(P->max_halo, 1), "boundary values") ||
+        dev_alloc(P, &P->Q_ws, (size_t)batch * kMaxLM, "moments"))
+      return EXX_ENOMEM;
+    P->batch_cap = batch;
+  }
+  if (!P->slot_ws) {
+    double* sw = nullptr;
+    if (dev_alloc(P, &sw, (size_t)P->n_slots * 2 * P->max_pe, "CG vectors")) return EXX_ENOMEM;
+    P->slot_ws = sw;
+  }
+
+  if (D_xx) EXX_HIP(P, launch_zero(D_xx, (size_t)n_orb * g.ngrid * (dt == EXX_F64 ? 8 : 4), s));
+  EXX_HIP(P, hipEventRecord(P->ev[1], s));
+  for (long long p0 = 0; p0 < total; p0 += batch) {
+    const long long nb = std::min(batch, total - p0);
+    EXX_HIP(P, launch_gather_moments(g, P->class_dev, P->pairs, P->order, p0, nb, orbitals, (int)dt, P->rho_ws,
+                                     P->max_pe, P->Q_ws, s));
+    EXX_HIP(P, launch_boundary(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_halo, P->Q_ws, P->halo_ws,
+                               std::max<long long>(P->max_halo, 1), s));
+    EXX_HIP(P, launch_rhs(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_pe, P->rho_ws, P->bx_ws, P->max_pe,
+                          P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+    EXX_HIP(P, launch_set_int(P->queue, 0, s));
+    SolveArgs a;
+    a.g = g;
+    a.cls = P->class_dev;
+    a.pairs = P->pairs;
+    a.order = P->order;
+    a.p0 = p0;
+    a.npair = nb;
+    a.queue = P->queue;
+    a.bx_ws = P->bx_ws;
+    a.rstride = P->max_pe;
+    a.slot_ws = (double*)P->slot_ws;
+    a.sstride = P->max_pe;
+    a.outIt = P->pIt;
+    a.outRes = P->pRes;
+    a.tol = P->opt.cg_tol;
+    a.max_iter = P->opt.cg_max_iter;
+    const int groups = (int)std::min<long long>(P->n_slots, nb);
+    EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, groups, s));
+    EXX_HIP(P, launch_finalize(g, P->class_dev, P->pairs, P->order, p0, nb, P->rho_ws, P->bx_ws, P->max_pe,
+                               P->halo_ws, std::max<long long>(P->max_halo, 1), P->pE, P->pS, s));
+    if (D_xx)
+      EXX_HIP(P, launch_dscatter(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_me, orbitals, D_xx, (int)dt,
+                                 P->bx_ws, P->max_pe, P->Q_ws, s));
+  }
+  EXX_HIP(P, hipEventRecord(P->ev[2], s));
+  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pair_count, n_orb, P->opt.cg_max_iter, E_xx, sigma,
+                           P->stats_dev, s));
+  EXX_HIP(P, hipEventRecord(P->ev[3], s));
+  P->timing_valid = true;
+  return EXX_OK;
+}
+
+exx_status exx_pair_results(exx_plan_t P, long long cap, int* ij, double* E, double* sigma, int* iters,
+                            double* rel_res, long long* n_pairs) {
+  if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
+  EXX_HIP(P, hipStreamSynchronize(P->stream));
+  const long long n = std::min<long long>(P->n_pairs, std::max<long long>(cap, 0));
+  if (n_pairs) *n_pairs = P->n_pairs;
+  if (n <= 0) return EXX_OK;
+  if (ij) {
+    std::vector<PairDev> pd((size_t)n);
+    EXX_HIP(P, hipMemcpy(pd.data(), P->pairs, sizeof(PairDev) * n, hipMemcpyDeviceToHost));
+    for (long long k = 0; k < n; ++k) {
+      ij[2 * k] = pd[k].i;
+      ij[2 * k + 1] = pd[k].j;
+    }
+  }
+  if (E) EXX_HIP(P, hipMemcpy(E, P->pE, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (sigma) EXX_HIP(P, hipMemcpy(sigma, P->pS, sizeof(double) * 9 * n, hipMemcpyDeviceToHost));
+  if (iters) EXX_HIP(P, hipMemcpy(iters, P->pIt, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (rel_res) EXX_HIP(P, hipMemcpy(rel_res, P->pRes, sizeof(double) * n, hipMemcpyDeviceToHost));
+  return EXX_OK;
+}
+
+exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
+  if (!P || !out) return fail(P, EXX_EINVAL, "plan or out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  EXX_HIP(P, hipStreamSynchronize(P->stream));
+  if (!P->timing_valid) return fail(P, EXX_EINVAL, "no evaluation to report");
+  double st[8] = {0};
+  EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
+  out->n_pairs = P->n_pairs;
+  out->cg_iter_sum = (long long)st[0];
+  out->cg_iter_max = (int)st[1];
+  out->n_unconverged = (int)st[2];
+  out->max_rel_residual = st[3];
+  out->n_classes = (int)P->classes.size();
+  float ms = 0;
+  EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[1], P->ev[2]));
+  out->solve_ms = ms;
+  EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
+  out->eval_ms = ms;
+  // algorithmic figures need per-pair classes and iteration counts
+  const long long n = P->n_pairs;
+  if (n > 0) {
+    std::vector<PairDev> pd((size_t)n);
+    std::vector<int> it((size_t)n);
+    EXX_HIP(P, hipMemcpy(pd.data(), P->pairs, sizeof(PairDev) * n, hipMemcpyDeviceToHost));
+    EXX_HIP(P, hipMemcpy(it.data(), P->pIt, sizeof(int) * n, hipMemcpyDeviceToHost));
+    double bytes = 0.0, flops = 0.0;
+    const double b = (P->opt.precision == EXX_PREC_MIXED) ? 4.0 : 8.0;
+    for (long long k = 0; k < n; ++k) {
+      const double npe = (double)P->classes[pd[k].cls].n_pe;
+      bytes += (double)it[k] * 8.0 * npe * b;
+      flops += 2.0 * P->geo.n_lm * npe;
+    }
+    out->cg_alg_bytes = bytes;
+    out->moment_flops = flops;
+  }
+  return out->n_unconverged > 0 ? fail(P, EXX_ENOCONV, "CG did not converge for some pairs") : EXX_OK;
+}
+
+exx_status exx_plan_geometry(exx_plan_t P, int cls, long long* n_pe, long long* n_halo, long long* n_me) {
+  if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
+  if (cls < 0 || cls >= (int)P->classes.size()) return fail(P, EXX_EINVAL, "class out of range");
+  const ClassHost& C = P->classes[cls];
+  if (n_pe) *n_pe = C.n_pe;
+  if (n_halo) *n_halo = C.n_halo;
+  if (n_me) *n_me = C.n_me;
+  return EXX_OK;
+}
+
+exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_PE, double R_ME, int stencil_n,
+                                long long* n_pe, long long* n_halo, long long* n_me) {
+  if (!h || !grid) return fail(nullptr, EXX_EINVAL, "h or grid is NULL");
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      if (r != c && h[r + 3 * c] != 0.0) return fail(nullptr, EXX_EINVAL, "only orthorhombic cells are supported");
+  if (stencil_n < 1 || stencil_n > 3 || !(R_PE > 0.0) || !(R_ME >= R_PE))
+    return fail(nullptr, EXX_EINVAL, "invalid radii or stencil");
+  double L[3];
+  int N[3];
+  for (int a = 0; a < 3; ++a) {
+    L[a] = h[a + 3 * a];
+    N[a] = grid[a];
+    if (!(L[a] > 0.0) || N[a] <= 0) return fail(nullptr, EXX_EINVAL, "invalid cell or grid");
+  }
+  ClassHost C;
+  std::string e = build_class(L, N, R_PE, R_ME, stencil_n, &C);
+  if (!e.empty()) return fail(nullptr, EXX_EINVAL, e);
+  if (n_pe) *n_pe = C.n_pe;
+  if (n_halo) *n_halo = C.n_halo;
+  if (n_me) *n_me = C.n_me;
+  return EXX_OK;
+}
+
+exx_status exx_destroy(exx_plan_t P) {
+  if (!P) return EXX_OK;
+  (void)hipStreamSynchronize(P->stream);
+  free_plan(P);
+  return EXX_OK;
+}
+
+const char* exx_last_error(exx_plan_t P) { return P ? P->err.c_str() : g_plan_error.c_str(); }
+
+}  // extern "C"

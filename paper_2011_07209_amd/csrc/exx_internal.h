@@ -1,0 +1,130 @@
+// Internal types of the gfx950 EXX library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "exx.h"
+
+namespace exx {
+
+constexpr int kMaxL = 8;                       // l_max limit of the multipole expansion
+constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
+constexpr int kMaxClasses = 16;
+constexpr int kSolveThreads = 1024;            // one workgroup per pair in the CG
+constexpr double kSlack = 1e-12;               // relative slack of sphere membership on |r|^2
+
+// Geometry and stencil constants, passed by value to every kernel.
+struct Geo {
+  double h[9];        // cell tensor, column-major: h[a + 3*al] = (L_al)_a
+  double L[3];        // orthorhombic edge lengths
+  double hinv[9];     // h^-1, column-major: hinv[al + 3*a] = (h^-1)_{al a}
+  double J[9];        // Jacobian J[a + 3*al] = |L_al| (h^-1)_{al a}
+  double d[3];        // grid spacing |L_al| / N_al
+  double inv_d2[3];   // 1 / d^2
+  double inv_d[3];    // 1 / d
+  double dV;          // cell volume / number of grid points
+  int N[3];
+  long long ngrid;
+  double w2[4];       // second-derivative weights w_0..w_n
+  double w1[4];       // first-derivative weights (w_q, q >= 1)
+  int n;              // stencil half-width
+  int l_max;
+  int n_lm;
+  int lds_cx, lds_cy, lds_wx, lds_wy;   // LDS plane origin and width (max over classes)
+  double ylm_norm[kMaxLM];              // N_l0 for m == 0, sqrt(2) N_l|m| otherwise
+};
+
+// A sphere class (one PE radius).  All arrays live in one device block.
+struct ClassDev {
+  double R_PE;
+  int n_cols;         // columns (x,y) of the PE sphere
+  int Zmax;           // largest |z| offset in PE
+  int Rg[3];          // largest |offset| per axis in PE
+  int Wm[3];          // lookup-map dims: 2 (Rg + n) + 1
+  long long n_pe, n_halo, n_me;
+  const int4* cols;          // [n_cols] (ox, oy, zr, 0), sorted by zr descending
+  const int* plane_start;    // [2 Zmax + 2] packed index of the first point of plane z (index z + Zmax)
+  const short4* halo_off;    // [n_halo] offsets of the Dirichlet points reached by the stencil
+  const short4* me_off;      // [n_me] PE points in packed order, then the ME shell
+  const int* halo_map;       // [Wm2][Wm1][Wm0] -> halo index or -1
+  const int* col_map;        // [Wm1][Wm0] -> column index or -1
+  const int* zr_map;         // [Wm1][Wm0] -> column half-height or -1
+};
+
+struct PairDev {
+  int i, j;
+  int c[3];
+  int cls;
+};
+
+struct ClassHost {
+  double R_PE = 0;
+  int n_cols = 0, Zmax = 0;
+  int Rg[3] = {0, 0, 0};
+  int Wm[3] = {0, 0, 0};
+  std::vector<int4> cols;
+  std::vector<int> plane_start;
+  std::vector<short4> halo_off;
+  std::vector<short4> me_off;
+  std::vector<int> halo_map, col_map, zr_map;
+  long long n_pe = 0, n_halo = 0, n_me = 0;
+};
+
+// Builds the tables of one class; returns an empty string or an error message.
+std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out);
+
+}  // namespace exx
+
+struct exx_plan_s {
+  exx_options opt;
+  double h[9];
+  int grid[3];
+  double R_pair, R_PE, R_ME;
+  int l_max;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  exx::Geo geo;
+  std::vector<exx::ClassHost> classes;
+  std::vector<exx::ClassDev> class_dev_host;   // with device pointers
+  exx::ClassDev* class_dev = nullptr;          // device copy of class_dev_host
+  void* class_block = nullptr;                 // device block holding every class table
+  long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
+  int max_zmax = 0;
+
+  // pair list
+  long long pair_cap = 0;
+  exx::PairDev* pairs = nullptr;   // canonical order
+  int* order = nullptr;            // processing order (class descending)
+  int* pair_count = nullptr;       // per-orbital counts and offsets [2 * orb_cap + 1 + classes]
+  int orb_cap = 0;
+  long long n_pairs = 0;
+  long long class_count[exx::kMaxClasses] = {0};
+
+  // per-pair results
+  double* pE = nullptr;
+  double* pS = nullptr;
+  int* pIt = nullptr;
+  double* pRes = nullptr;
+
+  // batch workspace
+  long long batch_cap = 0;
+  double* rho_ws = nullptr;    // [batch][max_pe] pair densities
+  double* bx_ws = nullptr;     // [batch][max_pe] right-hand sides, then potentials
+  double* halo_ws = nullptr;   // [batch][max_halo]
+  double* Q_ws = nullptr;      // [batch][kMaxLM]
+  int n_slots = 0;
+  void* slot_ws = nullptr;     // [slots][2][max_pe] CG vectors r, p
+  int* queue = nullptr;
+  double* stats_dev = nullptr;     // (iter_sum, iter_max, n_unconverged, max_res, n_pairs)
+  bool pair_cap_fixed = false;
+  int last_n_orb = 0;
+
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  float solve_ms = 0, eval_ms = 0;
+  bool timing_valid = false;
+  std::string err;
+};

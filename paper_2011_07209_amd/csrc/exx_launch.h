@@ -1,0 +1,69 @@
+// Host-side launchers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+
+#include "exx_internal.h"
+
+namespace exx {
+
+struct PairParams {
+  double R_pair2;           // R_pair^2 (1 + slack)
+  double R_PE;              // fixed radius (class 0) when no per-orbital radii
+  double R_min, R_step;     // variable radii rungs
+  int n_class;              // <= 0: fixed radius
+  unsigned long long seed;
+  double frac;
+};
+
+// counts[0 .. n_orb) per-orbital pair counts, counts[n_orb .. 2 n_orb] offsets
+// (exclusive, with the total at index 2 n_orb), then per-class counts.
+hipError_t launch_pairlist(const Geo& g, const PairParams& pp, const double* centres, const double* R_orb, int n_orb,
+                           int* counts, PairDev* pairs, long long cap, hipStream_t s);
+hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order, hipStream_t s);
+
+hipError_t launch_gather_moments(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order,
+                                 long long p0, long long nb, const void* orb, int dt, double* rho_ws,
+                                 long long rstride, double* Q_ws, hipStream_t s);
+hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                           long long nb, long long max_halo, const double* Q_ws, double* halo_ws, long long hstride,
+                           hipStream_t s);
+
+struct SolveArgs {
+  Geo g;
+  const ClassDev* cls = nullptr;
+  const PairDev* pairs = nullptr;
+  const int* order = nullptr;
+  long long p0 = 0, npair = 0;
+  int* queue = nullptr;
+  double* bx_ws = nullptr;     // per pair: right-hand side in, solution out
+  long long rstride = 0;
+  double* slot_ws = nullptr;   // per workgroup: r, p
+  long long sstride = 0;
+  int* outIt = nullptr;
+  double* outRes = nullptr;
+  double tol = 0;
+  int max_iter = 0;
+};
+
+hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                      long long nb, long long max_pe, const double* rho_ws, double* b_ws, long long rstride,
+                      const double* halo_ws, long long hstride, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s);
+size_t solve_lds_bytes(const Geo& g, int max_zmax);
+int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax);
+hipError_t launch_finalize(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                           long long nb, const double* rho_ws, const double* v_ws, long long rstride,
+                           const double* halo_ws, long long hstride, double* outE, double* outS, hipStream_t s);
+
+hipError_t launch_dscatter(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                           long long nb, long long max_me, const void* orb, void* D, int dt, const double* v_ws,
+                           long long rstride, const double* Q_ws, hipStream_t s);
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+
+// E_xx and sigma from per-pair results in canonical order; stats[8] receives
+// (iter_sum, iter_max, n_unconv, max_res) as doubles.
+hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* counts,
+                         int n_orb, int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
+
+}  // namespace exx

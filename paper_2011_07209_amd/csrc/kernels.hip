@@ -1,0 +1,956 @@
+// gfx950 kernels of the EXX pair path.
+//
+//   k_pair_count / k_pair_scan / k_pair_fill   unique pair list (Sec. III A Step II)
+//   k_pair_order                                processing order, largest spheres first
+//   k_gather_moments                            pair density on PE (Step III) and its
+//                                               multipole moments (Sec. I, eq. mepole)
+//   k_boundary                                  far-field values at the Dirichlet points
+//                                               (Sec. I, eq. me)
+//   k_solve                                     persistent CG on the PE sphere (eq. pe,
+//                                               axis stencil of eq. d2_1), then the
+//                                               pair's E_xx and sigma_xx (eq. exxGen_mlwf,
+//                                               eq. sxx_working with eq. d1_1)
+//   k_dscatter                                  D^i += v phi_j, D^j += v phi_i on the ME
+//                                               sphere (Sec. II B 2, eq. Dxx)
+//   k_reduce                                    E_xx, sigma_xx over pairs in a fixed order
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "exx_launch.h"
+
+namespace exx {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ int wrapi(int g, int N) {
+  g %= N;
+  return g < 0 ? g + N : g;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup in a fixed order; every thread gets the result.
+// red must hold blockDim/64 doubles.  Contains two barriers.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Regular solid harmonics R_lm(r) = |r|^l S_lm(rhat) with real orthonormal S
+// (no Condon-Shortley phase), generated as polynomials in x, y, z:
+//   (x + i y)^m gives the azimuthal factor,
+//   P_mm = (2m-1)!!,  P_{m+1,m} = (2m+1) z P_mm,
+//   (l-m) P_lm = (2l-1) z P_{l-1,m} - (l+m-1) |r|^2 P_{l-2,m},
+// so that R_lm = norm_lm P_lm Re/Im (x + i y)^m.  sink(l, index, value) receives
+// each of the (L+1)^2 values once.
+template <int L, typename F>
+__device__ __forceinline__ void solid_harmonics(double x, double y, double z, const double* norm, F&& sink) {
+  const double r2 = x * x + y * y + z * z;
+  double cm = 1.0, sm = 0.0, pmm = 1.0;
+#pragma unroll
+  for (int m = 0; m <= L; ++m) {
+    double p0 = pmm, p1 = 0.0;
+    if (m == 0) {
+      sink(0, 0, norm[0] * p0);
+    } else {
+      sink(m, m * m + 2 * m, norm[m * m + 2 * m] * p0 * cm);
+      sink(m, m * m, norm[m * m] * p0 * sm);
+    }
+    if (m < L) {
+      p1 = (2.0 * m + 1.0) * z * pmm;
+      const int l = m + 1;
+      if (m == 0) {
+        sink(l, l * l + l, norm[l * l + l] * p1);
+      } else {
+        sink(l, l * l + l + m, norm[l * l + l + m] * p1 * cm);
+        sink(l, l * l + l - m, norm[l * l + l - m] * p1 * sm);
+      }
+    }
+#pragma unroll
+    for (int l = m + 2; l <= L; ++l) {
+      const double p2 = ((2.0 * l - 1.0) * z * p1 - (l + m - 1.0) * r2 * p0) * (1.0 / (double)(l - m));
+      if (m == 0) {
+        sink(l, l * l + l, norm[l * l + l] * p2);
+      } else {
+        sink(l, l * l + l + m, norm[l * l + l + m] * p2 * cm);
+        sink(l, l * l + l - m, norm[l * l + l - m] * p2 * sm);
+      }
+      p0 = p1;
+      p1 = p2;
+    }
+    const double cn = x * cm - y * sm;
+    sm = x * sm + y * cm;
+    cm = cn;
+    pmm *= (2.0 * m + 1.0);
+  }
+}
+
+// Far-field potential 4 pi sum_lm Q_lm R_lm(r) / ((2l+1) |r|^(2l+1))
+template <int L>
+__device__ __forceinline__ double far_field(double x, double y, double z, const double* norm, const double* Q) {
+  double s[L + 1];
+#pragma unroll
+  for (int l = 0; l <= L; ++l) s[l] = 0.0;
+  solid_harmonics<L>(x, y, z, norm, [&](int l, int idx, double v) { s[l] += Q[idx] * v; });
+  const double r2 = x * x + y * y + z * z;
+  const double rinv = 1.0 / sqrt(r2);
+  const double rinv2 = rinv * rinv;
+  double rp = rinv, v = 0.0;
+#pragma unroll
+  for (int l = 0; l <= L; ++l) {
+    v += s[l] * rp * (4.0 * kPi / (2.0 * l + 1.0));
+    rp *= rinv2;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// pair list
+
+__device__ __forceinline__ unsigned long long splitmix64_once(unsigned long long state) {
+  unsigned long long z = state + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// minimum-image separation d = C_j - C_i; returns whether (i, j) is a kept pair
+__device__ __forceinline__ bool pair_keep(const Geo& g, const PairParams& pp, const double* C, int i, int j,
+                                          double* dm) {
+  double d[3], s[3];
+  for (int a = 0; a < 3; ++a) d[a] = C[3 * j + a] - C[3 * i + a];
+  for (int al = 0; al < 3; ++al)
+    s[al] = g.hinv[al + 0] * d[0] + g.hinv[al + 3] * d[1] + g.hinv[al + 6] * d[2];
+  for (int al = 0; al < 3; ++al) s[al] -= round(s[al]);
+  for (int a = 0; a < 3; ++a) dm[a] = g.h[a + 0] * s[0] + g.h[a + 3] * s[1] + g.h[a + 6] * s[2];
+  if (i != j && dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2] > pp.R_pair2) return false;
+  if (pp.frac < 1.0) {
+    unsigned long long u =
+        splitmix64_once(pp.seed ^ ((unsigned long long)(unsigned)i << 32) ^ (unsigned long long)(unsigned)j);
+    double f = (double)(u >> 11) * (1.0 / 9007199254740992.0);
+    if (!(f < pp.frac)) return false;
+  }
+  return true;
+}
+
+__global__ void k_pair_count(Geo g, PairParams pp, const double* __restrict__ C, int n_orb, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_orb) return;
+  int c = 0;
+  double dm[3];
+  for (int j = i; j < n_orb; ++j) c += pair_keep(g, pp, C, i, j, dm) ? 1 : 0;
+  cnt[i] = c;
+}
+
+// exclusive scan of the counts (one workgroup): off[i] at cnt[n_orb + i], total at cnt[2 n_orb]
+__global__ void k_pair_scan(int* cnt, int n_orb) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (n_orb + nt - 1) / nt;
+  const int lo = t * per, hi = min(n_orb, lo + per);
+  long long s = 0;
+  for (int i = lo; i < hi; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    long long a = 0;
+    for (int k = 0; k < nt; ++k) {
+      long long v = part[k];
+      part[k] = a;
+      a += v;
+    }
+    cnt[2 * n_orb] = (int)min(a, (long long)0x7fffffff);
+  }
+  __syncthreads();
+  long long a = part[t];
+  for (int i = lo; i < hi; ++i) {
+    cnt[n_orb + i] = (int)a;
+    a += cnt[i];
+  }
+}
+
+__global__ void k_pair_fill(Geo g, PairParams pp, const double* __restrict__ C, const double* __restrict__ R_orb,
+                            int n_orb, const int* __restrict__ cnt, PairDev* __restrict__ pairs, long long cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_orb) return;
+  long long k = cnt[n_orb + i];
+  double dm[3];
+  for (int j = i; j < n_orb; ++j) {
+    if (!pair_keep(g, pp, C, i, j, dm)) continue;
+    if (k < cap) {
+      PairDev P;
+      P.i = i;
+      P.j = j;
+      double Cij[3], s[3];
+      for (int a = 0; a < 3; ++a) Cij[a] = C[3 * i + a] + 0.5 * dm[a];
+      for (int al = 0; al < 3; ++al)
+        s[al] = g.hinv[al + 0] * Cij[0] + g.hinv[al + 3] * Cij[1] + g.hinv[al + 6] * Cij[2];
+      for (int al = 0; al < 3; ++al) {
+        const double f = s[al] - floor(s[al]);
+        P.c[al] = wrapi((int)round(g.N[al] * f), g.N[al]);
+      }
+      int cls = 0;
+      if (pp.n_class > 0 && R_orb) {
+        double r = 0.5 * (R_orb[i] + R_orb[j]);
+        double kk = round((r - pp.R_min) / pp.R_step);
+        kk = fmax(0.0, fmin((double)(pp.n_class - 1), kk));
+        cls = (int)kk;
+      }
+      P.cls = cls;
+      pairs[k] = P;
+    }
+    ++k;
+  }
+}
+
+// Stable counting sort of the pairs by class, largest class index (radius)
+// first.  One workgroup: each thread takes a contiguous chunk of pairs.
+__global__ __launch_bounds__(1024) void k_pair_order(const PairDev* __restrict__ pairs, const int* __restrict__ cnt,
+                                                     int n_orb, int n_class, int* __restrict__ order,
+                                                     int* __restrict__ class_cnt) {
+  __shared__ int tcount[kMaxClasses][1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const long long np = cnt[2 * n_orb];
+  const long long per = (np + nt - 1) / nt;
+  const long long lo = t * per, hi = min(np, lo + per);
+  int c[kMaxClasses];
+  for (int k = 0; k < kMaxClasses; ++k) c[k] = 0;
+  for (long long p = lo; p < hi; ++p) c[pairs[p].cls]++;
+  for (int k = 0; k < kMaxClasses; ++k) tcount[k][t] = c[k];
+  __syncthreads();
+  if (t == 0) {
+    long long a = 0;
+    for (int k = n_class - 1; k >= 0; --k) {
+      long long tot = 0;
+      for (int u = 0; u < nt; ++u) {
+        int v = tcount[k][u];
+        tcount[k][u] = (int)a;
+        a += v;
+        tot += v;
+      }
+      class_cnt[k] = (int)tot;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < kMaxClasses; ++k) c[k] = tcount[k][t];
+  for (long long p = lo; p < hi; ++p) order[c[pairs[p].cls]++] = (int)p;
+}
+
+// ---------------------------------------------------------------------------
+// pair density and moments
+
+template <typename TO>
+__device__ __forceinline__ double ldv(const TO* p, long long i) { return (double)p[i]; }
+
+template <int L, typename TO>
+__global__ __launch_bounds__(256) void k_gather_moments(Geo g, const ClassDev* __restrict__ cls,
+                                                        const PairDev* __restrict__ pairs,
+                                                        const int* __restrict__ order, long long p0,
+                                                        const TO* __restrict__ orb, double* __restrict__ rho_ws,
+                                                        long long rstride, double* __restrict__ Q_ws) {
+  constexpr int NLM = (L + 1) * (L + 1);
+  __shared__ double red[4][NLM];
+  const int b = blockIdx.x;
+  const PairDev P = pairs[order[p0 + b]];
+  const ClassDev& C = cls[P.cls];
+  const TO* phi_i = orb + (long long)P.i * g.ngrid;
+  const TO* phi_j = orb + (long long)P.j * g.ngrid;
+  double* rho = rho_ws + (long long)b * rstride;
+  double acc[NLM];
+#pragma unroll
+  for (int k = 0; k < NLM; ++k) acc[k] = 0.0;
+  const long long npe = C.n_pe;
+  for (long long k = threadIdx.x; k < npe; k += blockDim.x) {
+    const short4 o = C.me_off[k];
+    const int gx = wrapi(P.c[0] + o.x, g.N[0]);
+    const int gy = wrapi(P.c[1] + o.y, g.N[1]);
+    const int gz = wrapi(P.c[2] + o.z, g.N[2]);
+    const long long gi = gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
+    const double r = ldv(phi_i, gi) * ldv(phi_j, gi);
+    rho[k] = r;
+    solid_harmonics<L>(o.x * g.d[0], o.y * g.d[1], o.z * g.d[2], g.ylm_norm,
+                       [&](int, int idx, double v) { acc[idx] += v * r; });
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NLM; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NLM) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
+    Q_ws[(long long)b * kMaxLM + threadIdx.x] = g.dV * s;
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_boundary(Geo g, const ClassDev* __restrict__ cls,
+                                                  const PairDev* __restrict__ pairs, const int* __restrict__ order,
+                                                  long long p0, const double* __restrict__ Q_ws,
+                                                  double* __restrict__ halo_ws, long long hstride) {
+  constexpr int NLM = (L + 1) * (L + 1);
+  __shared__ double Q[NLM];
+  const int b = blockIdx.y;
+  const PairDev P = pairs[order[p0 + b]];
+  const ClassDev& C = cls[P.cls];
+  if (threadIdx.x < NLM) Q[threadIdx.x] = Q_ws[(long long)b * kMaxLM + threadIdx.x];
+  __syncthreads();
+  const long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= C.n_halo) return;
+  const short4 o = C.halo_off[h];
+  halo_ws[(long long)b * hstride + h] = far_field<L>(o.x * g.d[0], o.y * g.d[1], o.z * g.d[2], g.ylm_norm, Q);
+}
+
+// ---------------------------------------------------------------------------
+// the right-hand side, the persistent CG solve, and the per-pair E / sigma
+
+struct Stencil {
+  double w[4];      // second-derivative weights w_0..w_3
+  double c[3];      // 1 / d_al^2
+  double diag;      // w_0 (c_x + c_y + c_z)
+};
+
+// value of the pair potential at offset o: the CG vector inside PE (or 0 when
+// pe_zero), the far field at a Dirichlet point
+__device__ __forceinline__ double point_value(const ClassDev& C, int n, const double* xv, const double* halo, int ox,
+                                              int oy, int oz, bool pe_zero) {
+  const int mx = ox + C.Rg[0] + n, my = oy + C.Rg[1] + n, mz = oz + C.Rg[2] + n;
+  const int m2 = mx + C.Wm[0] * my;
+  const int zr = C.zr_map[m2];
+  if (abs(oz) <= zr) return pe_zero ? 0.0 : xv[C.plane_start[oz + C.Zmax] + C.col_map[m2]];
+  const int h = C.halo_map[m2 + C.Wm[0] * C.Wm[1] * mz];
+  return h >= 0 ? halo[h] : 0.0;
+}
+
+// b = 4 pi rho + the stencil reach into the Dirichlet points, where v takes its
+// far-field values (eq. pe discretised with eq. d2_1)
+__global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__ cls, const PairDev* __restrict__ pairs,
+                                             const int* __restrict__ order, long long p0,
+                                             const double* __restrict__ rho_ws, double* __restrict__ b_ws,
+                                             long long rstride, const double* __restrict__ halo_ws,
+                                             long long hstride) {
+  const int bq = blockIdx.y;
+  const PairDev P = pairs[order[p0 + bq]];
+  const ClassDev& C = cls[P.cls];
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C.n_pe) return;
+  const double* halo = halo_ws + (long long)bq * hstride;
+  const short4 o = C.me_off[k];
+  double acc = 4.0 * kPi * rho_ws[(long long)bq * rstride + k];
+  for (int q = 1; q <= g.n; ++q) {
+    acc += g.inv_d2[0] * g.w2[q] *
+           (point_value(C, g.n, nullptr, halo, o.x + q, o.y, o.z, true) +
+            point_value(C, g.n, nullptr, halo, o.x - q, o.y, o.z, true));
+    acc += g.inv_d2[1] * g.w2[q] *
+           (point_value(C, g.n, nullptr, halo, o.x, o.y + q, o.z, true) +
+            point_value(C, g.n, nullptr, halo, o.x, o.y - q, o.z, true));
+    acc += g.inv_d2[2] * g.w2[q] *
+           (point_value(C, g.n, nullptr, halo, o.x, o.y, o.z + q, true) +
+            point_value(C, g.n, nullptr, halo, o.x, o.y, o.z - q, true));
+  }
+  b_ws[(long long)bq * rstride + k] = acc;
+}
+
+// -(stencil Laplacian) at one point: ctr is the centre value, pl the LDS plane
+// (values of the current plane, zero off the PE sphere), wz the z window
+template <int NS>
+__device__ __forceinline__ double apply_point(const Stencil& S, double ctr, const double* pl, int pos, int wx,
+                                              const double* wz) {
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+  for (int q = 1; q <= NS; ++q) {
+    sx += S.w[q] * (pl[pos + q] + pl[pos - q]);
+    sy += S.w[q] * (pl[pos + q * wx] + pl[pos - q * wx]);
+    sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
+  }
+  return -(S.diag * ctr + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
+}
+
+template <int CPT>
+struct Cols {
+  int zr[CPT];    // half-height, -1 for no column
+  int pos[CPT];   // LDS plane position
+  int col[CPT];   // column index (valid only when zr >= 0)
+};
+
+// Pass A of a CG iteration: p = r + beta p (p = r on the first iteration) is
+// stored, q = A p is formed on the fly; returns this thread's sums of p.q and
+// (first iteration) r.r.
+template <int NS, int CPT>
+__device__ void cg_pass_a(const Stencil& S, const Cols<CPT>& cl, const int* pst, int Zmax,
+                          const double* __restrict__ r, double* __restrict__ p, double beta, bool first, double* pl0,
+                          double* pl1, int wx, double& pq, double& rr) {
+  double win[CPT][2 * NS + 1];
+  pq = 0.0;
+  rr = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      double v = 0.0;
+      if (abs(zz) <= cl.zr[c]) {
+        const int idx = pst[zz + Zmax] + cl.col[c];
+        const double rv = r[idx];
+        v = first ? rv : rv + beta * p[idx];
+        p[idx] = v;
+        rr += rv * rv;
+      }
+      win[c][k] = v;
+    }
+  }
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zn = z + NS + 1;
+    double nr[CPT], np[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nr[c] = 0.0;
+      np[c] = 0.0;
+      if (abs(zn) <= cl.zr[c]) {
+        const int idx = pst[zn + Zmax] + cl.col[c];
+        nr[c] = r[idx];
+        if (!first) np[c] = p[idx];
+      }
+    }
+    double* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (abs(z) <= cl.zr[c]) pq += win[c][NS] * apply_point<NS>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      double v = 0.0;
+      if (abs(zn) <= cl.zr[c]) {
+        v = first ? nr[c] : nr[c] + beta * np[c];
+        p[pst[zn + Zmax] + cl.col[c]] = v;
+        rr += nr[c] * nr[c];
+      }
+      win[c][2 * NS] = v;
+    }
+  }
+}
+
+// Pass B: q = A p again (same arithmetic as pass A), x += alpha p,
+// r -= alpha q; returns this thread's sum of r^2 after the update.  On the
+// first iteration r comes from r_in (the right-hand side, which x then
+// overwrites in place) and x starts from zero.
+template <int NS, int CPT>
+__device__ double cg_pass_b(const Stencil& S, const Cols<CPT>& cl, const int* pst, int Zmax, double* x,
+                            const double* r_in, double* r, const double* __restrict__ p, double alpha,
+                            bool first, double* pl0, double* pl1, int wx) {
+  double win[CPT][2 * NS + 1];
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) win[c][k] = (abs(zz) <= cl.zr[c]) ? p[pst[zz + Zmax] + cl.col[c]] : 0.0;
+  }
+  double acc = 0.0;
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zn = z + NS + 1;
+    double np[CPT], xc[CPT], rc[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      np[c] = (abs(zn) <= cl.zr[c]) ? p[pst[zn + Zmax] + cl.col[c]] : 0.0;
+      xc[c] = 0.0;
+      rc[c] = 0.0;
+      if (abs(z) <= cl.zr[c]) {
+        const int idx = pst[z + Zmax] + cl.col[c];
+        rc[c] = r_in[idx];
+        if (!first) xc[c] = x[idx];
+      }
+    }
+    double* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (abs(z) <= cl.zr[c]) {
+        const int idx = pst[z + Zmax] + cl.col[c];
+        const double q = apply_point<NS>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+        const double rn = rc[c] - alpha * q;
+        x[idx] = xc[c] + alpha * win[c][NS];
+        r[idx] = rn;
+        acc += rn * rn;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      win[c][2 * NS] = np[c];
+    }
+  }
+  return acc;
+}
+
+struct SolveKArgs {
+  const ClassDev* cls;
+  const PairDev* pairs;
+  const int* order;
+  long long p0, npair;
+  int* queue;
+  double* bx_ws;          // per pair: right-hand side in, solution out
+  long long rstride;
+  double* slot_ws;        // per workgroup: r, p
+  long long sstride;
+  int* outIt;
+  double* outRes;
+  double tol;
+  int max_iter;
+  Stencil S;
+  int lds_cx, lds_cy, lds_wx, lds_wy;
+};
+
+// One workgroup solves one pair at a time, taking pairs from a device queue
+// until the batch is exhausted (every workgroup exits when the counter passes
+// the batch size).  Unpreconditioned CG from x = 0, stop at ||r|| <= tol ||b||.
+template <int NS, int CPT>
+__global__ __launch_bounds__(kSolveThreads) void k_solve(SolveKArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[kSolveThreads / 64];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int plane = a.lds_wx * a.lds_wy;
+  double* pl0 = lds;
+  double* pl1 = lds + plane;
+  int* pst = reinterpret_cast<int*>(lds + 2 * plane);
+  double* r = a.slot_ws + (long long)blockIdx.x * 2 * a.sstride;
+  double* p = r + a.sstride;
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const long long item = s_item;
+    __syncthreads();
+    if (item >= a.npair) break;
+    const int pid = a.order[a.p0 + item];
+    const ClassDev& C = a.cls[a.pairs[pid].cls];
+    const int Zmax = C.Zmax;
+    double* x = a.bx_ws + item * a.rstride;
+
+    for (int k = tid; k < 2 * plane; k += blockDim.x) lds[k] = 0.0;
+    for (int k = tid; k < 2 * Zmax + 2; k += blockDim.x) pst[k] = C.plane_start[k];
+    Cols<CPT> cl;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int col = tid + c * kSolveThreads;
+      cl.zr[c] = -1;
+      cl.col[c] = 0;
+      cl.pos[c] = 0;
+      if (col < C.n_cols) {
+        const int4 cc = C.cols[col];
+        cl.zr[c] = cc.z;
+        cl.col[c] = col;
+        cl.pos[c] = (cc.x + a.lds_cx) + a.lds_wx * (cc.y + a.lds_cy);
+      }
+    }
+    __syncthreads();
+
+    int it = 0;
+    double rr = 0.0, bnorm = 0.0, beta = 0.0;
+    bool first = true;
+    while (it < a.max_iter) {
+      double pq_t, rr_t;
+      cg_pass_a<NS, CPT>(a.S, cl, pst, Zmax, first ? x : r, p, beta, first, pl0, pl1, a.lds_wx, pq_t, rr_t);
+      const double pq = block_sum(pq_t, red);
+      if (first) {
+        rr = block_sum(rr_t, red);
+        bnorm = sqrt(rr);
+        if (!(bnorm > 0.0)) break;   // b == 0: x = b = 0 already
+      }
+      if (!(pq > 0.0) || !(pq < INFINITY)) {   // breakdown: A is SPD, so only NaN/inf input gets here
+        it = a.max_iter;
+        rr = NAN;
+        break;
+      }
+      const double alpha = rr / pq;
+      const double rn =
+          block_sum(cg_pass_b<NS, CPT>(a.S, cl, pst, Zmax, x, first ? x : r, r, p, alpha, first, pl0, pl1, a.lds_wx),
+                    red);
+      ++it;
+      first = false;
+      if (sqrt(rn) <= a.tol * bnorm) {
+        rr = rn;
+        break;
+      }
+      if (!(rn == rn)) {
+        it = a.max_iter;
+        rr = NAN;
+        break;
+      }
+      beta = rn / rr;
+      rr = rn;
+    }
+    if (tid == 0) {
+      a.outIt[pid] = it;
+      a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// E_xx and sigma_xx of one pair from its density and potential (one workgroup
+// per pair): E = -w dV sum rho v (eq. exxGen_mlwf); sigma^{a al} = -2 w dV
+// sum_b (h^-1)_{al b} sum rbar_b rho dv/dr_a (eq. sxx_working), with dv/dr_a =
+// sum_al J_{a al} dv/dxi_al from the first-derivative stencil (eq. d1_1).
+__global__ __launch_bounds__(256) void k_finalize(Geo g, const ClassDev* __restrict__ cls,
+                                                  const PairDev* __restrict__ pairs, const int* __restrict__ order,
+                                                  long long p0, const double* __restrict__ rho_ws,
+                                                  const double* __restrict__ v_ws, long long rstride,
+                                                  const double* __restrict__ halo_ws, long long hstride,
+                                                  double* __restrict__ outE, double* __restrict__ outS) {
+  __shared__ double red[4];
+  const int bq = blockIdx.x;
+  const int pid = order[p0 + bq];
+  const PairDev P = pairs[pid];
+  const ClassDev& C = cls[P.cls];
+  const double* rho = rho_ws + (long long)bq * rstride;
+  const double* x = v_ws + (long long)bq * rstride;
+  const double* halo = halo_ws + (long long)bq * hstride;
+  double e = 0.0;
+  double T[9];
+  for (int t = 0; t < 9; ++t) T[t] = 0.0;
+  for (long long k = threadIdx.x; k < C.n_pe; k += blockDim.x) {
+    const short4 o = C.me_off[k];
+    const double rh = rho[k];
+    e += rh * x[k];
+    double dxi[3] = {0.0, 0.0, 0.0};
+    for (int q = 1; q <= g.n; ++q) {
+      dxi[0] += g.w1[q] * (point_value(C, g.n, x, halo, o.x + q, o.y, o.z, false) -
+                           point_value(C, g.n, x, halo, o.x - q, o.y, o.z, false));
+      dxi[1] += g.w1[q] * (point_value(C, g.n, x, halo, o.x, o.y + q, o.z, false) -
+                           point_value(C, g.n, x, halo, o.x, o.y - q, o.z, false));
+      dxi[2] += g.w1[q] * (point_value(C, g.n, x, halo, o.x, o.y, o.z + q, false) -
+                           point_value(C, g.n, x, halo, o.x, o.y, o.z - q, false));
+    }
+    for (int al = 0; al < 3; ++al) dxi[al] *= g.inv_d[al];
+    const double rb[3] = {o.x * g.d[0], o.y * g.d[1], o.z * g.d[2]};
+    for (int aa = 0; aa < 3; ++aa) {
+      const double ga = g.J[aa] * dxi[0] + g.J[aa + 3] * dxi[1] + g.J[aa + 6] * dxi[2];
+      for (int b = 0; b < 3; ++b) T[aa + 3 * b] += rb[b] * rh * ga;
+    }
+  }
+  e = block_sum(e, red);
+  for (int t = 0; t < 9; ++t) T[t] = block_sum(T[t], red);
+  if (threadIdx.x == 0) {
+    const double w = (P.i == P.j) ? 1.0 : 2.0;
+    outE[pid] = -w * g.dV * e;
+    for (int aa = 0; aa < 3; ++aa)
+      for (int al = 0; al < 3; ++al) {
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b) s += g.hinv[al + 3 * b] * T[aa + 3 * b];
+        outS[9 * (long long)pid + aa + 3 * al] = -2.0 * w * g.dV * s;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wavefunction forces
+
+template <int L, typename TO>
+__global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restrict__ cls,
+                                                  const PairDev* __restrict__ pairs, const int* __restrict__ order,
+                                                  long long p0, const TO* __restrict__ orb, TO* __restrict__ D,
+                                                  const double* __restrict__ v_ws, long long rstride,
+                                                  const double* __restrict__ Q_ws) {
+  constexpr int NLM = (L + 1) * (L + 1);
+  __shared__ double Q[NLM];
+  const int b = blockIdx.y;
+  const PairDev P = pairs[order[p0 + b]];
+  const ClassDev& C = cls[P.cls];
+  if (threadIdx.x < NLM) Q[threadIdx.x] = Q_ws[(long long)b * kMaxLM + threadIdx.x];
+  __syncthreads();
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C.n_me) return;
+  const short4 o = C.me_off[k];
+  const double v = (k < C.n_pe) ? v_ws[(long long)b * rstride + k]
+                                : far_field<L>(o.x * g.d[0], o.y * g.d[1], o.z * g.d[2], g.ylm_norm, Q);
+  const int gx = wrapi(P.c[0] + o.x, g.N[0]);
+  const int gy = wrapi(P.c[1] + o.y, g.N[1]);
+  const int gz = wrapi(P.c[2] + o.z, g.N[2]);
+  const long long gi = gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
+  const long long oi = (long long)P.i * g.ngrid + gi;
+  const long long oj = (long long)P.j * g.ngrid + gi;
+  const double fi = (double)orb[oi], fj = (double)orb[oj];
+  unsafeAtomicAdd(&D[oi], (TO)(v * fj));
+  if (P.i != P.j) unsafeAtomicAdd(&D[oj], (TO)(v * fi));
+}
+
+template <typename T>
+__global__ void k_zero(T* p, long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    p[k] = (T)0;
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, const double* __restrict__ pS,
+                                                const int* __restrict__ pIt, const double* __restrict__ pRes,
+                                                const int* __restrict__ cnt, int n_orb, int max_iter,
+                                                double* __restrict__ E, double* __restrict__ sigma,
+                                                double* __restrict__ stats) {
+  __shared__ double red[4];
+  const long long np = cnt[2 * n_orb];
+  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0;
+  for (int t = 0; t < 9; ++t) s[t] = 0.0;
+  for (long long k = threadIdx.x; k < np; k += blockDim.x) {
+    e += pE[k];
+    for (int t = 0; t < 9; ++t) s[t] += pS[9 * k + t];
+    isum += pIt[k];
+    imax = fmax(imax, (double)pIt[k]);
+    nunc += (pIt[k] >= max_iter) ? 1.0 : 0.0;
+    rmax = fmax(rmax, pRes[k]);
+  }
+  e = block_sum(e, red);
+  for (int t = 0; t < 9; ++t) s[t] = block_sum(s[t], red);
+  isum = block_sum(isum, red);
+  nunc = block_sum(nunc, red);
+  // max via shuffles
+  for (int o = 32; o > 0; o >>= 1) {
+    imax = fmax(imax, __shfl_xor(imax, o, 64));
+    rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+  }
+  __shared__ double mx[2][4];
+  if ((threadIdx.x & 63) == 0) {
+    mx[0][threadIdx.x >> 6] = imax;
+    mx[1][threadIdx.x >> 6] = rmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      imax = fmax(imax, mx[0][w]);
+      rmax = fmax(rmax, mx[1][w]);
+    }
+    if (E) *E = e;
+    if (sigma)
+      for (int t = 0; t < 9; ++t) sigma[t] = s[t];
+    stats[0] = isum;
+    stats[1] = imax;
+    stats[2] = nunc;
+    stats[3] = rmax;
+    stats[4] = (double)np;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+
+hipError_t launch_pairlist(const Geo& g, const PairParams& pp, const double* centres, const double* R_orb, int n_orb,
+                           int* counts, PairDev* pairs, long long cap, hipStream_t s) {
+  const int nb = (n_orb + 127) / 128;
+  k_pair_count<<<nb, 128, 0, s>>>(g, pp, centres, n_orb, counts);
+  k_pair_scan<<<1, 1024, 0, s>>>(counts, n_orb);
+  k_pair_fill<<<nb, 128, 0, s>>>(g, pp, centres, R_orb, n_orb, counts, pairs, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order,
+                        hipStream_t s) {
+  int* class_cnt = const_cast<int*>(counts) + 2 * n_orb + 1;
+  k_pair_order<<<1, 1024, 0, s>>>(pairs, counts, n_orb, n_class, order, class_cnt);
+  return hipGetLastError();
+}
+
+#define EXX_L_DISPATCH(L, ...)                       \
+  switch (L) {                                       \
+    case 0: { constexpr int LL = 0; __VA_ARGS__; } break; \
+    case 1: { constexpr int LL = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int LL = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int LL = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int LL = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int LL = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int LL = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int LL = 7; __VA_ARGS__; } break; \
+    case 8: { constexpr int LL = 8; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_gather_moments(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order,
+                                 long long p0, long long nb, const void* orb, int dt, double* rho_ws,
+                                 long long rstride, double* Q_ws, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (dt == EXX_F64) {
+    EXX_L_DISPATCH(g.l_max, (k_gather_moments<LL, double><<<(unsigned)nb, 256, 0, s>>>(
+                                g, cls, pairs, order, p0, (const double*)orb, rho_ws, rstride, Q_ws)));
+  } else {
+    EXX_L_DISPATCH(g.l_max, (k_gather_moments<LL, float><<<(unsigned)nb, 256, 0, s>>>(
+                                g, cls, pairs, order, p0, (const float*)orb, rho_ws, rstride, Q_ws)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                           long long nb, long long max_halo, const double* Q_ws, double* halo_ws, long long hstride,
+                           hipStream_t s) {
+  if (nb <= 0 || max_halo <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_halo + 255) / 256), (unsigned)nb);
+  EXX_L_DISPATCH(g.l_max, (k_boundary<LL><<<grid, 256, 0, s>>>(g, cls, pairs, order, p0, Q_ws, halo_ws, hstride)));
+  return hipGetLastError();
+}
+
+size_t solve_lds_bytes(const Geo& g, int max_zmax) {
+  return (size_t)2 * g.lds_wx * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2) * sizeof(int);
+}
+
+hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                      long long nb, long long max_pe, const double* rho_ws, double* b_ws, long long rstride,
+                      const double* halo_ws, long long hstride, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_pe + 255) / 256), (unsigned)nb);
+  k_rhs<<<grid, 256, 0, s>>>(g, cls, pairs, order, p0, rho_ws, b_ws, rstride, halo_ws, hstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                           long long nb, const double* rho_ws, const double* v_ws, long long rstride,
+                           const double* halo_ws, long long hstride, double* outE, double* outS, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  k_finalize<<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, rho_ws, v_ws, rstride, halo_ws, hstride, outE,
+                                          outS);
+  return hipGetLastError();
+}
+
+template <int NS, int K>
+static hipError_t solve_prepare(size_t lds) {
+  if (lds > 64 * 1024)
+    return hipFuncSetAttribute((const void*)k_solve<NS, K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+template <int NS>
+static hipError_t solve_ns(const SolveKArgs& a, int cpt, int groups, size_t lds, hipStream_t s, int* occ) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (cpt) {
+#define EXX_CPT(K)                                                                                   \
+  case K:                                                                                            \
+    e = solve_prepare<NS, K>(lds);                                                                   \
+    if (e != hipSuccess) return e;                                                                   \
+    if (occ) {                                                                                       \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, K>, kSolveThreads, lds);     \
+    } else {                                                                                         \
+      k_solve<NS, K><<<groups, kSolveThreads, lds, s>>>(a);                                          \
+      e = hipGetLastError();                                                                         \
+    }                                                                                                \
+    break;
+    EXX_CPT(1) EXX_CPT(2) EXX_CPT(3) EXX_CPT(4) EXX_CPT(5) EXX_CPT(6) EXX_CPT(7) EXX_CPT(8)
+#undef EXX_CPT
+    default:
+      break;
+  }
+  return e;
+}
+
+static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax, int groups, hipStream_t s,
+                                 int* occ) {
+  SolveKArgs a;
+  a.cls = in.cls;
+  a.pairs = in.pairs;
+  a.order = in.order;
+  a.p0 = in.p0;
+  a.npair = in.npair;
+  a.queue = in.queue;
+  a.bx_ws = in.bx_ws;
+  a.rstride = in.rstride;
+  a.slot_ws = in.slot_ws;
+  a.sstride = in.sstride;
+  a.outIt = in.outIt;
+  a.outRes = in.outRes;
+  a.tol = in.tol;
+  a.max_iter = in.max_iter;
+  for (int q = 0; q < 4; ++q) a.S.w[q] = in.g.w2[q];
+  for (int al = 0; al < 3; ++al) a.S.c[al] = in.g.inv_d2[al];
+  a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
+  a.lds_cx = in.g.lds_cx;
+  a.lds_cy = in.g.lds_cy;
+  a.lds_wx = in.g.lds_wx;
+  a.lds_wy = in.g.lds_wy;
+  const int cpt = (max_cols + kSolveThreads - 1) / kSolveThreads;
+  const size_t lds = solve_lds_bytes(in.g, max_zmax);
+  switch (in.g.n) {
+    case 1: return solve_ns<1>(a, cpt, groups, lds, s, occ);
+    case 2: return solve_ns<2>(a, cpt, groups, lds, s, occ);
+    case 3: return solve_ns<3>(a, cpt, groups, lds, s, occ);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax) {
+  SolveArgs a;
+  a.g = g;
+  int occ = 0;
+  if (solve_dispatch(a, max_cols, max_zmax, 1, nullptr, &occ) != hipSuccess) return 0;
+  return occ;
+}
+
+hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s) {
+  if (a.npair <= 0) return hipSuccess;
+  return solve_dispatch(a, max_cols, max_zmax, groups, s, nullptr);
+}
+
+hipError_t launch_dscatter(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                           long long nb, long long max_me, const void* orb, void* D, int dt, const double* v_ws,
+                           long long rstride, const double* Q_ws, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_me + 255) / 256), (unsigned)nb);
+  if (dt == EXX_F64) {
+    EXX_L_DISPATCH(g.l_max, (k_dscatter<LL, double><<<grid, 256, 0, s>>>(
+                                g, cls, pairs, order, p0, (const double*)orb, (double*)D, v_ws, rstride, Q_ws)));
+  } else {
+    EXX_L_DISPATCH(g.l_max, (k_dscatter<LL, float><<<grid, 256, 0, s>>>(
+                                g, cls, pairs, order, p0, (const float*)orb, (float*)D, v_ws, rstride, Q_ws)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 8 == 0) {
+    long long n = (long long)(bytes / 8);
+    unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+    k_zero<double><<<nb, 256, 0, s>>>((double*)p, n);
+  } else {
+    long long n = (long long)(bytes / 4);
+    unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+    k_zero<float><<<nb, 256, 0, s>>>((float*)p, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  k_set_int<<<1, 1, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* counts,
+                         int n_orb, int max_iter, double* E, double* sigma, double* stats, hipStream_t s) {
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, counts, n_orb, max_iter, E, sigma, stats);
+  return hipGetLastError();
+}
+
+}  // namespace exx

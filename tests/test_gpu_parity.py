@@ -1,0 +1,113 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the
+same seeded inputs.  Bar for the plain FP64 path: relative 1-norm error
+(eq. error_exx / error_sxx form) <= 1e-9 on E_xx and <= 1e-8 on D_xx and
+sigma_xx; both sides solve to ||r|| <= 1e-12 ||b|| so that the CG stopping
+point does not dominate the comparison."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2011_07209_amd import synth
+
+from gpu_util import gpu_eval, oracle_eval, rel1, subset_config
+
+pytestmark = pytest.mark.gpu
+
+TOL_E, TOL_D, TOL_S = 1e-9, 1e-8, 1e-8
+
+
+def _compare(cfg, orbs, phi, want_D=True, **opt):
+    g = gpu_eval(cfg, orbs, phi, want_D=want_D, **opt)
+    o = oracle_eval(cfg, orbs, phi, want_D=want_D, **{k: v for k, v in opt.items()
+                                                      if k in ("sample_seed", "sample_frac")})
+    print(f"[{cfg.key}] pairs gpu={len(g['pairs']['E'])} oracle={len(o['pairs'])} E gpu={g['E']:.15g} "
+          f"oracle={o['E']:.15g} iters max={g['stats']['cg_iter_max']}", flush=True)
+    assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
+    assert g["stats"]["n_unconverged"] == 0
+    assert rel1(g["E"], o["E"]) <= TOL_E, (g["E"], o["E"])
+    assert rel1(g["sigma"], o["sigma"]) <= TOL_S, (g["sigma"], o["sigma"])
+    if want_D:
+        assert rel1(g["D"], o["D"]) <= TOL_D
+    # per pair
+    Eo = np.array([p.E for p in o["pairs"]])
+    So = np.array([list(p.sigma) for p in o["pairs"]])
+    scale = np.abs(Eo).max()
+    assert np.abs(g["pairs"]["E"] - Eo).max() <= TOL_E * scale
+    assert np.abs(g["pairs"]["sigma"] - So).max() <= TOL_S * np.abs(So).max()
+    return g, o
+
+
+def test_tiny16_fp64_parity():
+    cfg = dataclasses.replace(synth.CONFIGS["tiny16"], cg_tol=1e-12)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    _compare(cfg, orbs, phi)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_small_cell_higher_order_stencils(n):
+    cfg = synth.custom(key=f"small-n{n}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=7, R_pair=7.0, R_PE=3.9,
+                       R_ME=5.3, l_max=5, stencil_n=n, cg_tol=1e-12, seed_index=40 + n)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    _compare(cfg, orbs, phi)
+
+
+def test_single_orbital_self_pair():
+    cfg = synth.custom(key="single", grid=(48, 48, 48), n_orb=1, R_PE=4.0, R_ME=5.5, stencil_n=3, cg_tol=1e-12)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g, o = _compare(cfg, orbs, phi)
+    assert len(o["pairs"]) == 1
+
+
+def test_centres_on_cell_faces_and_corners():
+    """Subdomains that wrap through the periodic boundary on every axis."""
+    cfg = synth.custom(key="wrap", grid=(48, 48, 48), n_orb=4, R_PE=4.0, R_ME=5.5, stencil_n=3, cg_tol=1e-12)
+    orbs = synth.make_orbitals(cfg)
+    orbs = dataclasses.replace(orbs, centres=np.array([[0.01, 0.02, 11.99], [11.9, 0.3, 0.2],
+                                                       [0.4, 11.7, 11.8], [6.0, 0.0, 6.0]]))
+    phi = synth.fill_orbitals(cfg, orbs)
+    _compare(cfg, orbs, phi)
+
+
+def test_pair_sample_subset_matches():
+    cfg = dataclasses.replace(synth.CONFIGS["tiny16"], cg_tol=1e-12)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g, o = _compare(cfg, orbs, phi, sample_seed=1234567, sample_frac=0.3)
+    assert 0 < len(o["pairs"]) < 100
+
+
+def test_variable_radius_classes():
+    cfg = synth.custom(key="classes", grid=(48, 48, 48), n_orb=6, R_pair=7.0, R_PE=4.0, R_ME=5.5, stencil_n=2,
+                       cg_tol=1e-12, R_PE_classes=(3.0, 0.5, 3), R_orb_range=(3.0, 4.0), seed_index=77)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g, o = _compare(cfg, orbs, phi)
+    assert len({p.R_PE for p in o["pairs"]}) >= 2
+
+
+def test_float32_orbitals_fp64_path():
+    """FP32 orbital storage, FP64 arithmetic: parity against the oracle on the
+    same (FP32-rounded) orbital values; D is accumulated in FP32."""
+    cfg = dataclasses.replace(synth.CONFIGS["tiny16"], cg_tol=1e-12)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs).astype(np.float32).astype(np.float64)
+    import torch
+    g = gpu_eval(cfg, orbs, phi, dtype=torch.float32)
+    o = oracle_eval(cfg, orbs, phi)
+    assert rel1(g["E"], o["E"]) <= TOL_E
+    assert rel1(g["sigma"], o["sigma"]) <= TOL_S
+    assert rel1(g["D"], o["D"]) <= 1e-6   # FP32 storage of D
+
+
+def test_repeat_is_bitwise_deterministic_for_E_and_sigma():
+    cfg, orbs = subset_config("tiny16", 8)
+    phi = synth.fill_orbitals(cfg, orbs)
+    a = gpu_eval(cfg, orbs, phi, want_D=False)
+    b = gpu_eval(cfg, orbs, phi, want_D=False)
+    assert a["E"] == b["E"]
+    assert np.array_equal(a["sigma"], b["sigma"])
+    assert np.array_equal(a["pairs"]["iters"], b["pairs"]["iters"])
