@@ -1,0 +1,195 @@
+"""Benchmark: EXX pair Poisson solves/s and EXX evaluation time on one MI355X.
+
+A step is one full exx_eval (pair list, pair densities, moments, boundary
+values, CG solves, E_xx, D_xx and sigma_xx) over every pair of the water-like
+64-molecule workload (cubic 23.5 bohr cell, 120^3 grid, 256 orbitals,
+R_pair 10, R_PE 6, R_ME 9 bohr, l_max 6, 19-point stencil, CG tol 1e-10), with
+the orbitals already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+
+The roofline entry is for the dominant kernel, the persistent CG solve:
+algorithmic bytes (8 N_PE b per pair per iteration) over the summed device
+time of its launches in the timed region, from HIP events that the library
+records on its stream.  The CPU baseline is the FP64 oracle on a deterministic
+pair subset of the same workload, on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "EXX pair Poisson solves/s + EXX eval time, mixed vs FP64 at 1e-6 tol"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_traffic.json")
+KERNEL_SOURCES = ["paper_2011_07209_amd/csrc/kernels.hip", "paper_2011_07209_amd/csrc/api.hip",
+                  "paper_2011_07209_amd/csrc/plan_geometry.cpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(precision: str):
+    """HBM bytes per solve launch from the committed counter runs, or None when
+    the kernels changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(precision)
+    if not e or e.get("kernel_hash") != kernel_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg, orbs, phi, n_pairs_total, sample_pairs: int):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    frac = min(1.0, sample_pairs / max(1, n_pairs_total))
+    P = oracle.make_params(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, cfg.stencil_n, cfg.cg_tol,
+                           sample_seed=2011072092, sample_frac=frac, n_threads=threads)
+    t0 = time.perf_counter()
+    r = oracle.evaluate(P, phi, orbs.centres, want_D=True)
+    dt = time.perf_counter() - t0
+    n = len(r["pairs"])
+    return {"value": n / dt, "unit": "pair solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {n_pairs_total} pairs (SplitMix64 subset, seed 2011072092), full E/D/sigma per pair, "
+                      f"{dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="water64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--cpu-sample-pairs", type=int, default=640)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="after the timed steps, copy this many GiB device-to-device (counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU pair sharding is "
+              f"a design, not part of this build)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2011_07209_amd import exx, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    cfg = synth.CONFIGS[args.workload]
+    orbs = synth.make_orbitals(cfg)
+    t0 = time.perf_counter()
+    phi = synth.fill_orbitals(cfg, orbs)
+    print(f"[bench] {cfg.key}: orbitals filled in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    orb_t = torch.from_numpy(phi).to(dev)
+    cen_t = torch.from_numpy(orbs.centres).to(dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    S = torch.zeros(9, dtype=torch.float64, device=dev)
+    D = torch.empty_like(orb_t)
+    prec = exx.EXX_PREC_MIXED if args.precision == "mixed" else exx.EXX_PREC_FP64
+    plan = exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, stencil_n=cfg.stencil_n,
+                    cg_tol=cfg.cg_tol, precision=prec, workspace_gb=64.0)
+    geo = plan.geometry()
+
+    for w in range(args.warmup):
+        plan.eval(orb_t, cen_t, E, D, S)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} E={E.item():.10f}", file=sys.stderr, flush=True)
+    zero = {"solve_launches": 0, "solve_ms_total": 0.0, "cg_alg_bytes_total": 0.0}
+    s0 = plan.stats() if args.warmup > 0 else zero
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.eval(orb_t, cen_t, E, D, S)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = plan.stats()
+    ms = (t1 - t0) * 1000.0 / args.steps
+    n_pairs = s1["n_pairs"]
+    print(f"[bench] timed {args.steps} steps: {ms:.1f} ms/step E={E.item():.10f}", file=sys.stderr, flush=True)
+
+    if args.copy_probe_gib > 0:
+        nbytes = int(args.copy_probe_gib * (1 << 30))
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    launches = s1["solve_launches"] - s0["solve_launches"]
+    solve_ms = s1["solve_ms_total"] - s0["solve_ms_total"]
+    alg = s1["cg_alg_bytes_total"] - s0["cg_alg_bytes_total"]
+    achieved = (alg / max(launches, 1)) / (solve_ms / max(launches, 1) / 1000.0) / 1e9 if solve_ms > 0 else 0.0
+    traffic = stored_traffic(args.precision)
+    plan.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, orbs, phi, n_pairs, args.cpu_sample_pairs)
+
+    out = {
+        "metric": METRIC,
+        "value": n_pairs / (ms / 1000.0),
+        "unit": "pair solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.key}: water-like 64-molecule set, cubic {cfg.cell[0]} bohr, {cfg.grid[0]}^3 grid, "
+                        f"{cfg.n_orb} orbitals, R_pair {cfg.R_pair}, R_PE {cfg.R_PE}, R_ME {cfg.R_ME}, "
+                        f"l_max {cfg.l_max}, n {cfg.stencil_n}, CG tol {cfg.cg_tol}",
+            "precision": args.precision,
+            "n_pairs": n_pairs,
+            "n_pe": geo["n_pe"],
+            "exx_eval_s": ms / 1000.0,
+            "cg_iters_mean": s1["cg_iter_sum"] / max(1, n_pairs),
+            "cg_iters_max": s1["cg_iter_max"],
+            "E_xx": E.item(),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_solve (persistent CG)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic,
+            "alg_bytes_per_launch": alg / max(launches, 1),
+            "launch_ms": solve_ms / max(launches, 1),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

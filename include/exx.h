@@ -122,6 +122,12 @@ typedef struct {
   double eval_ms;              /* device time of the whole evaluation              */
   double cg_alg_bytes;         /* algorithmic CG bytes: sum_pairs iters 8 N_PE b   */
   double moment_flops;         /* algorithmic moment flops: 2 N_lm N_PE per pair   */
+  /* running totals since the plan was made (every completed exx_eval):       */
+  long long n_evals;
+  long long solve_launches;    /* launches of the persistent CG kernel           */
+  double solve_ms_total;       /* their summed device time (HIP events)          */
+  double cg_alg_bytes_total;   /* their summed algorithmic CG bytes              */
+  double eval_ms_total;
 } exx_stats;
 
 /* Statistics of the last exx_eval (synchronizes the bound stream).  Returns

@@ -106,7 +106,46 @@ void free_plan(exx_plan_t P) {
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : P->solve_ev)
+    if (e) (void)hipEventDestroy(e);
   delete P;
+}
+
+// Adds the finished evaluation's device times and algorithmic bytes to the
+// running totals (once per evaluation).  The caller has synchronized the stream.
+exx_status harvest(exx_plan_t P) {
+  if (!P->timing_valid || P->harvested) return EXX_OK;
+  float ms = 0;
+  double solve = 0.0;
+  for (int k = 0; k + 1 < P->solve_ev_used; k += 2) {
+    EXX_HIP(P, hipEventElapsedTime(&ms, P->solve_ev[k], P->solve_ev[k + 1]));
+    solve += ms;
+  }
+  EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
+  double st[8] = {0};
+  EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
+  const double b = (P->opt.precision == EXX_PREC_MIXED) ? 4.0 : 8.0;
+  P->last_solve_ms = solve;
+  P->last_eval_ms = ms;
+  P->last_alg_bytes = st[5] * 8.0 * b;
+  for (int k = 0; k < 8; ++k) P->last_stats[k] = st[k];
+  P->n_evals += 1;
+  P->solve_launches += P->solve_ev_used / 2;
+  P->solve_ms_total += solve;
+  P->eval_ms_total += ms;
+  P->alg_bytes_total += P->last_alg_bytes;
+  P->harvested = true;
+  return EXX_OK;
+}
+
+exx_status record_solve_event(exx_plan_t P, hipStream_t s) {
+  if (P->solve_ev_used >= (int)P->solve_ev.size()) {
+    hipEvent_t e = nullptr;
+    EXX_HIP(P, hipEventCreate(&e));
+    P->solve_ev.push_back(e);
+  }
+  EXX_HIP(P, hipEventRecord(P->solve_ev[P->solve_ev_used++], s));
+  return EXX_OK;
 }
 
 }  // namespace
@@ -325,7 +364,13 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   int dev = -1;
   EXX_HIP(P, hipGetDevice(&dev));
   if (dev != P->device) return fail(P, EXX_EINVAL, "current device differs from the plan's device");
+  if (P->timing_valid && !P->harvested) {
+    EXX_HIP(P, hipEventSynchronize(P->ev[3]));
+    exx_status hs = harvest(P);
+    if (hs != EXX_OK) return hs;
+  }
   P->timing_valid = false;
+  P->solve_ev_used = 0;
 
   // pair list
   if (n_orb > P->orb_cap) {
@@ -415,7 +460,9 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.tol = P->opt.cg_tol;
     a.max_iter = P->opt.cg_max_iter;
     const int groups = (int)std::min<long long>(P->n_slots, nb);
+    { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, groups, s));
+    { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_finalize(g, P->class_dev, P->pairs, P->order, p0, nb, P->rho_ws, P->bx_ws, P->max_pe,
                                P->halo_ws, std::max<long long>(P->max_halo, 1), P->pE, P->pS, s));
     if (D_xx)
@@ -423,10 +470,11 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
                                  P->bx_ws, P->max_pe, P->Q_ws, s));
   }
   EXX_HIP(P, hipEventRecord(P->ev[2], s));
-  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pair_count, n_orb, P->opt.cg_max_iter, E_xx, sigma,
-                           P->stats_dev, s));
+  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pairs, P->class_dev, P->pair_count, n_orb,
+                           P->opt.cg_max_iter, E_xx, sigma, P->stats_dev, s));
   EXX_HIP(P, hipEventRecord(P->ev[3], s));
   P->timing_valid = true;
+  P->harvested = false;
   return EXX_OK;
 }
 
@@ -457,36 +505,25 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   std::memset(out, 0, sizeof(*out));
   EXX_HIP(P, hipStreamSynchronize(P->stream));
   if (!P->timing_valid) return fail(P, EXX_EINVAL, "no evaluation to report");
-  double st[8] = {0};
-  EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
+  exx_status hs = harvest(P);
+  if (hs != EXX_OK) return hs;
+  const double* st = P->last_stats;
   out->n_pairs = P->n_pairs;
   out->cg_iter_sum = (long long)st[0];
   out->cg_iter_max = (int)st[1];
   out->n_unconverged = (int)st[2];
   out->max_rel_residual = st[3];
   out->n_classes = (int)P->classes.size();
-  float ms = 0;
-  EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[1], P->ev[2]));
-  out->solve_ms = ms;
-  EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
-  out->eval_ms = ms;
-  // algorithmic figures need per-pair classes and iteration counts
-  const long long n = P->n_pairs;
-  if (n > 0) {
-    std::vector<PairDev> pd((size_t)n);
-    std::vector<int> it((size_t)n);
-    EXX_HIP(P, hipMemcpy(pd.data(), P->pairs, sizeof(PairDev) * n, hipMemcpyDeviceToHost));
-    EXX_HIP(P, hipMemcpy(it.data(), P->pIt, sizeof(int) * n, hipMemcpyDeviceToHost));
-    double bytes = 0.0, flops = 0.0;
-    const double b = (P->opt.precision == EXX_PREC_MIXED) ? 4.0 : 8.0;
-    for (long long k = 0; k < n; ++k) {
-      const double npe = (double)P->classes[pd[k].cls].n_pe;
-      bytes += (double)it[k] * 8.0 * npe * b;
-      flops += 2.0 * P->geo.n_lm * npe;
-    }
-    out->cg_alg_bytes = bytes;
-    out->moment_flops = flops;
-  }
+  out->refine_passes_max = (int)st[6];
+  out->solve_ms = P->last_solve_ms;
+  out->eval_ms = P->last_eval_ms;
+  out->cg_alg_bytes = P->last_alg_bytes;
+  out->moment_flops = 2.0 * P->geo.n_lm * st[7];
+  out->n_evals = P->n_evals;
+  out->solve_launches = P->solve_launches;
+  out->solve_ms_total = P->solve_ms_total;
+  out->cg_alg_bytes_total = P->alg_bytes_total;
+  out->eval_ms_total = P->eval_ms_total;
   return out->n_unconverged > 0 ? fail(P, EXX_ENOCONV, "CG did not converge for some pairs") : EXX_OK;
 }
 

@@ -124,7 +124,13 @@ struct exx_plan_s {
   int last_n_orb = 0;
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  float solve_ms = 0, eval_ms = 0;
+  std::vector<hipEvent_t> solve_ev;   // begin/end pairs around each solve launch of the last eval
+  int solve_ev_used = 0;
   bool timing_valid = false;
+  bool harvested = true;              // last eval's events already added to the totals
+  double last_solve_ms = 0, last_eval_ms = 0, last_alg_bytes = 0;
+  double last_stats[8] = {0};
+  long long n_evals = 0, solve_launches = 0;
+  double solve_ms_total = 0, eval_ms_total = 0, alg_bytes_total = 0;
   std::string err;
 };

@@ -62,8 +62,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
 // E_xx and sigma from per-pair results in canonical order; stats[8] receives
-// (iter_sum, iter_max, n_unconv, max_res) as doubles.
-hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* counts,
-                         int n_orb, int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
+// (iter_sum, iter_max, n_unconverged, max_res, n_pairs, sum iters*N_PE,
+//  refinement passes max, sum N_PE) as doubles.
+hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes,
+                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, int max_iter,
+                         double* E, double* sigma, double* stats, hipStream_t s);
 
 }  // namespace exx

@@ -710,12 +710,13 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, const double* __restrict__ pS,
                                                 const int* __restrict__ pIt, const double* __restrict__ pRes,
+                                                const PairDev* __restrict__ pairs, const ClassDev* __restrict__ cls,
                                                 const int* __restrict__ cnt, int n_orb, int max_iter,
                                                 double* __restrict__ E, double* __restrict__ sigma,
                                                 double* __restrict__ stats) {
   __shared__ double red[4];
   const long long np = cnt[2 * n_orb];
-  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0;
+  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0;
   for (int t = 0; t < 9; ++t) s[t] = 0.0;
   for (long long k = threadIdx.x; k < np; k += blockDim.x) {
     e += pE[k];
@@ -724,11 +725,16 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     imax = fmax(imax, (double)pIt[k]);
     nunc += (pIt[k] >= max_iter) ? 1.0 : 0.0;
     rmax = fmax(rmax, pRes[k]);
+    const double npe = (double)cls[pairs[k].cls].n_pe;
+    work += pIt[k] * npe;
+    pts += npe;
   }
   e = block_sum(e, red);
   for (int t = 0; t < 9; ++t) s[t] = block_sum(s[t], red);
   isum = block_sum(isum, red);
   nunc = block_sum(nunc, red);
+  work = block_sum(work, red);
+  pts = block_sum(pts, red);
   // max via shuffles
   for (int o = 32; o > 0; o >>= 1) {
     imax = fmax(imax, __shfl_xor(imax, o, 64));
@@ -753,6 +759,9 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     stats[2] = nunc;
     stats[3] = rmax;
     stats[4] = (double)np;
+    stats[5] = work;
+    stats[6] = 0.0;
+    stats[7] = pts;
   }
 }
 
@@ -947,9 +956,10 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* counts,
-                         int n_orb, int max_iter, double* E, double* sigma, double* stats, hipStream_t s) {
-  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, counts, n_orb, max_iter, E, sigma, stats);
+hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes,
+                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, int max_iter,
+                         double* E, double* sigma, double* stats, hipStream_t s) {
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pairs, cls, counts, n_orb, max_iter, E, sigma, stats);
   return hipGetLastError();
 }
 

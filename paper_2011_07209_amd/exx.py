@@ -58,6 +58,11 @@ class Stats(ctypes.Structure):
         ("eval_ms", ctypes.c_double),
         ("cg_alg_bytes", ctypes.c_double),
         ("moment_flops", ctypes.c_double),
+        ("n_evals", ctypes.c_longlong),
+        ("solve_launches", ctypes.c_longlong),
+        ("solve_ms_total", ctypes.c_double),
+        ("cg_alg_bytes_total", ctypes.c_double),
+        ("eval_ms_total", ctypes.c_double),
     ]
 
     def as_dict(self):
