@@ -71,13 +71,59 @@ def cpu_baseline(cfg, orbs, phi, n_pairs_total, sample_pairs: int):
                       f"{dt:.1f} s"}
 
 
+def run_precision(exx, torch, cfg, tensors, precision, steps, warmup):
+    """Times `steps` evaluations (after `warmup`) in one precision; returns the
+    measurement and the outputs of the last evaluation."""
+    orb_t, cen_t = tensors
+    dev = orb_t.device
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    S = torch.zeros(9, dtype=torch.float64, device=dev)
+    D = torch.empty_like(orb_t)
+    prec = exx.EXX_PREC_MIXED if precision == "mixed" else exx.EXX_PREC_FP64
+    plan = exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, stencil_n=cfg.stencil_n,
+                    cg_tol=cfg.cg_tol, precision=prec, workspace_gb=64.0)
+    geo = plan.geometry()
+    for w in range(warmup):
+        plan.eval(orb_t, cen_t, E, D, S)
+        torch.cuda.synchronize()
+        print(f"[bench] {precision} warmup {w + 1}/{warmup} E={E.item():.10f}", file=sys.stderr, flush=True)
+    zero = {"solve_launches": 0, "solve_ms_total": 0.0, "cg_alg_bytes_total": 0.0}
+    s0 = plan.stats() if warmup > 0 else zero
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.eval(orb_t, cen_t, E, D, S)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = plan.stats()
+    plan.close()
+    ms = (t1 - t0) * 1000.0 / steps
+    print(f"[bench] {precision} timed {steps} steps: {ms:.1f} ms/step E={E.item():.10f}", file=sys.stderr, flush=True)
+    launches = s1["solve_launches"] - s0["solve_launches"]
+    solve_ms = s1["solve_ms_total"] - s0["solve_ms_total"]
+    alg = s1["cg_alg_bytes_total"] - s0["cg_alg_bytes_total"]
+    achieved = (alg / max(launches, 1)) / (solve_ms / max(launches, 1) / 1000.0) / 1e9 if solve_ms > 0 else 0.0
+    n_pairs = s1["n_pairs"]
+    return {
+        "value": n_pairs / (ms / 1000.0), "ms_per_step": ms, "n_pairs": n_pairs, "n_pe": geo["n_pe"],
+        "cg_iters_mean": s1["cg_iter_sum"] / max(1, n_pairs), "cg_iters_max": s1["cg_iter_max"],
+        "updates_max": s1["refine_passes_max"], "max_rel_residual": s1["max_rel_residual"],
+        "roofline": {"bound": "hbm", "kernel": "k_solve_mixed" if precision == "mixed" else "k_solve",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(precision), "alg_bytes_per_launch": alg / max(launches, 1),
+                     "launch_ms": solve_ms / max(launches, 1)},
+        "E": E.item(), "sigma": S.cpu().numpy().reshape(3, 3, order="F"), "D": D,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="water64")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
+                    help="both: time the FP64 and the mixed path, report the mixed one as the value")
     ap.add_argument("--cpu-sample-pairs", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -103,32 +149,24 @@ def main(argv=None):
     t0 = time.perf_counter()
     phi = synth.fill_orbitals(cfg, orbs)
     print(f"[bench] {cfg.key}: orbitals filled in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    orb_t = torch.from_numpy(phi).to(dev)
-    cen_t = torch.from_numpy(orbs.centres).to(dev)
-    E = torch.zeros(1, dtype=torch.float64, device=dev)
-    S = torch.zeros(9, dtype=torch.float64, device=dev)
-    D = torch.empty_like(orb_t)
-    prec = exx.EXX_PREC_MIXED if args.precision == "mixed" else exx.EXX_PREC_FP64
-    plan = exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, stencil_n=cfg.stencil_n,
-                    cg_tol=cfg.cg_tol, precision=prec, workspace_gb=64.0)
-    geo = plan.geometry()
+    tensors = (torch.from_numpy(phi).to(dev), torch.from_numpy(orbs.centres).to(dev))
 
-    for w in range(args.warmup):
-        plan.eval(orb_t, cen_t, E, D, S)
-        torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1}/{args.warmup} E={E.item():.10f}", file=sys.stderr, flush=True)
-    zero = {"solve_launches": 0, "solve_ms_total": 0.0, "cg_alg_bytes_total": 0.0}
-    s0 = plan.stats() if args.warmup > 0 else zero
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        plan.eval(orb_t, cen_t, E, D, S)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s1 = plan.stats()
-    ms = (t1 - t0) * 1000.0 / args.steps
-    n_pairs = s1["n_pairs"]
-    print(f"[bench] timed {args.steps} steps: {ms:.1f} ms/step E={E.item():.10f}", file=sys.stderr, flush=True)
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {p: run_precision(exx, torch, cfg, tensors, p, args.steps, args.warmup) for p in precs}
+    main_p = "mixed" if "mixed" in res else "fp64"
+    r = res[main_p]
+
+    accuracy = None
+    if "fp64" in res and "mixed" in res:
+        a, b = res["mixed"], res["fp64"]
+        n_mol = cfg.n_orb / 4.0
+        accuracy = {
+            "vs": "FP64 GPU path (itself parity-tested against the FP64 oracle)",
+            "dE_Ha_per_molecule": abs(a["E"] - b["E"]) / n_mol,
+            "sigma_rel_1norm": float(np.abs(a["sigma"] - b["sigma"]).sum() / np.abs(b["sigma"]).sum()),
+            "D_rel_1norm": float((a["D"] - b["D"]).abs().sum().item() / b["D"].abs().sum().item()),
+            "targets": {"dE_Ha_per_molecule": 1e-6, "sigma_rel_1norm": 1e-6},
+        }
 
     if args.copy_probe_gib > 0:
         nbytes = int(args.copy_probe_gib * (1 << 30))
@@ -138,55 +176,44 @@ def main(argv=None):
         torch.cuda.synchronize()
         del a, b
 
-    launches = s1["solve_launches"] - s0["solve_launches"]
-    solve_ms = s1["solve_ms_total"] - s0["solve_ms_total"]
-    alg = s1["cg_alg_bytes_total"] - s0["cg_alg_bytes_total"]
-    achieved = (alg / max(launches, 1)) / (solve_ms / max(launches, 1) / 1000.0) / 1e9 if solve_ms > 0 else 0.0
-    traffic = stored_traffic(args.precision)
-    plan.close()
-
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, orbs, phi, n_pairs, args.cpu_sample_pairs)
+        cpu = cpu_baseline(cfg, orbs, phi, r["n_pairs"], args.cpu_sample_pairs)
+
+    def summary(x):
+        return {k: x[k] for k in ("value", "ms_per_step", "cg_iters_mean", "cg_iters_max", "updates_max",
+                                  "max_rel_residual", "roofline")}
 
     out = {
         "metric": METRIC,
-        "value": n_pairs / (ms / 1000.0),
+        "value": r["value"],
         "unit": "pair solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if main_p == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"{cfg.key}: water-like 64-molecule set, cubic {cfg.cell[0]} bohr, {cfg.grid[0]}^3 grid, "
                         f"{cfg.n_orb} orbitals, R_pair {cfg.R_pair}, R_PE {cfg.R_PE}, R_ME {cfg.R_ME}, "
                         f"l_max {cfg.l_max}, n {cfg.stencil_n}, CG tol {cfg.cg_tol}",
-            "precision": args.precision,
-            "n_pairs": n_pairs,
-            "n_pe": geo["n_pe"],
-            "exx_eval_s": ms / 1000.0,
-            "cg_iters_mean": s1["cg_iter_sum"] / max(1, n_pairs),
-            "cg_iters_max": s1["cg_iter_max"],
-            "E_xx": E.item(),
+            "precision": main_p,
+            "n_pairs": r["n_pairs"],
+            "n_pe": r["n_pe"],
+            "exx_eval_s": r["ms_per_step"] / 1000.0,
+            "E_xx": r["E"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_solve (persistent CG)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if traffic is None else traffic,
-            "alg_bytes_per_launch": alg / max(launches, 1),
-            "launch_ms": solve_ms / max(launches, 1),
-        },
+        "roofline": r["roofline"],
         "cpu_baseline": cpu,
+        "by_precision": {p: summary(x) for p, x in res.items()},
+        "mixed_accuracy": accuracy,
     }
+    if "fp64" in res and "mixed" in res:
+        out["mixed_speedup_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
     print(json.dumps(out), flush=True)
     return 0
 

@@ -67,7 +67,12 @@ typedef struct {
   long long max_pairs;        /* 0: workspace grows on demand; > 0: fixed capacity,
                                  more pairs give EXX_ECAPACITY                     */
   double workspace_gb;        /* cap on per-batch pair workspace (0: 24 GB)        */
-  int solve_groups;           /* persistent solve workgroups (0: one per CU)       */
+  int solve_groups;           /* persistent solve workgroups (0: as many as fit)   */
+  int solve_threads;          /* CG workgroup size, 512 or 1024 (0: tuned/default) */
+  int solve_depth;            /* planes of loads in flight ahead of use, 1 or 2
+                                 (0: tuned/default)                                */
+  int autotune;               /* 1: the first exx_eval times the CG variants on a
+                                 sample of its pairs and keeps the fastest          */
 } exx_options;
 
 /* Fills *opt with the defaults: n = 3, FP64, tol 1e-10, 5000 iterations,

@@ -101,7 +101,7 @@ exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->slot_ws, P->queue, P->stats_dev};
+                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->slot_ws, P->queue, P->stats_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
@@ -135,6 +135,23 @@ exx_status harvest(exx_plan_t P) {
   P->eval_ms_total += ms;
   P->alg_bytes_total += P->last_alg_bytes;
   P->harvested = true;
+  return EXX_OK;
+}
+
+// Makes (threads, depth) the CG variant of the plan and sizes the persistent
+// grid from its occupancy.  The slot workspace is resized on the next eval.
+exx_status select_solve(exx_plan_t P, int threads, int depth) {
+  const bool mixed = P->opt.precision == EXX_PREC_MIXED;
+  const int per_cu = solve_groups_per_cu(P->geo, (int)P->max_cols, P->max_zmax, mixed, threads, depth);
+  if (per_cu < 1) return fail(P, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
+  const int slots = P->opt.solve_groups > 0 ? P->opt.solve_groups : P->n_cus * per_cu;
+  if (slots != P->n_slots && P->slot_ws) {
+    (void)hipFree(P->slot_ws);
+    P->slot_ws = nullptr;
+  }
+  P->n_slots = slots;
+  P->solve_threads = threads;
+  P->solve_depth = depth;
   return EXX_OK;
 }
 
@@ -190,6 +207,9 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     return fail(nullptr, EXX_EINVAL, "variable radii need R_PE_min > 0 and R_PE_step > 0");
   if (opt.max_pairs < 0 || opt.workspace_gb < 0 || opt.solve_groups < 0)
     return fail(nullptr, EXX_EINVAL, "negative capacity option");
+  if (opt.solve_threads != 0 && opt.solve_threads != 512 && opt.solve_threads != 1024)
+    return fail(nullptr, EXX_EINVAL, "solve_threads must be 0, 512 or 1024");
+  if (opt.solve_depth < 0 || opt.solve_depth > 2) return fail(nullptr, EXX_EINVAL, "solve_depth must be 0, 1 or 2");
 
   exx_plan_t P = new (std::nothrow) exx_plan_s();
   if (!P) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
@@ -257,7 +277,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   g.lds_cy = maxRg1 + n;
   g.lds_wx = 2 * g.lds_cx + 1;
   g.lds_wy = 2 * g.lds_cy + 1;
-  if (P->max_cols > 8LL * kSolveThreads) {
+  if (!solve_supported((int)std::min<long long>(P->max_cols, 1 << 30), 512)) {
     free_plan(P);
     return fail(nullptr, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");
   }
@@ -334,12 +354,18 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   }
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
-  int per_cu = solve_groups_per_cu(g, (int)P->max_cols, P->max_zmax);
-  if (per_cu < 1) {
-    free_plan(P);
-    return fail(nullptr, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
+  P->n_cus = std::max(1, cus);
+  {
+    int th = opt.solve_threads > 0 ? opt.solve_threads : 1024;
+    if (!solve_supported((int)P->max_cols, th)) th = 512;
+    const int dp = opt.solve_depth > 0 ? opt.solve_depth : 1;
+    exx_status st = select_solve(P, th, dp);
+    if (st != EXX_OK) {
+      std::string m = P->err;
+      free_plan(P);
+      return fail(nullptr, st, m);
+    }
   }
-  P->n_slots = opt.solve_groups > 0 ? opt.solve_groups : std::max(1, cus) * per_cu;
   if (opt.max_pairs > 0) P->pair_cap_fixed = true;
   *out = P;
   return EXX_OK;
@@ -389,7 +415,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   if (P->opt.max_pairs > 0 && P->pair_cap < P->opt.max_pairs) {
     if (dev_alloc(P, &P->pairs, (size_t)P->opt.max_pairs, "pairs") || dev_alloc(P, &P->order, (size_t)P->opt.max_pairs, "order") ||
         dev_alloc(P, &P->pE, (size_t)P->opt.max_pairs, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * P->opt.max_pairs, "pair sigma") ||
-        dev_alloc(P, &P->pIt, (size_t)P->opt.max_pairs, "pair iters") || dev_alloc(P, &P->pRes, (size_t)P->opt.max_pairs, "pair res"))
+        dev_alloc(P, &P->pIt, (size_t)P->opt.max_pairs, "pair iters") || dev_alloc(P, &P->pRes, (size_t)P->opt.max_pairs, "pair res") ||
+        dev_alloc(P, &P->pUpd, (size_t)P->opt.max_pairs, "pair updates"))
       return EXX_ENOMEM;
     P->pair_cap = P->opt.max_pairs;
   }
@@ -403,7 +430,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     const long long cap = std::max<long long>(total, 1) + total / 8;
     if (dev_alloc(P, &P->pairs, (size_t)cap, "pairs") || dev_alloc(P, &P->order, (size_t)cap, "order") ||
         dev_alloc(P, &P->pE, (size_t)cap, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * cap, "pair sigma") ||
-        dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res"))
+        dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res") ||
+        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates"))
       return EXX_ENOMEM;
     P->pair_cap = cap;
     EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
@@ -427,8 +455,9 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     P->batch_cap = batch;
   }
   if (!P->slot_ws) {
-    double* sw = nullptr;
-    if (dev_alloc(P, &sw, (size_t)P->n_slots * 2 * P->max_pe, "CG vectors")) return EXX_ENOMEM;
+    char* sw = nullptr;
+    const long long sb = solve_slot_bytes(P->opt.precision == EXX_PREC_MIXED, P->max_pe);
+    if (dev_alloc(P, &sw, (size_t)P->n_slots * sb, "CG vectors")) return EXX_ENOMEM;
     P->slot_ws = sw;
   }
 
@@ -453,10 +482,15 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.queue = P->queue;
     a.bx_ws = P->bx_ws;
     a.rstride = P->max_pe;
-    a.slot_ws = (double*)P->slot_ws;
+    a.slot_ws = P->slot_ws;
     a.sstride = P->max_pe;
     a.outIt = P->pIt;
     a.outRes = P->pRes;
+    a.outUpd = P->pUpd;
+    a.mixed = P->opt.precision == EXX_PREC_MIXED;
+    a.delta = 0.1;
+    a.threads = P->solve_threads;
+    a.depth = P->solve_depth;
     a.tol = P->opt.cg_tol;
     a.max_iter = P->opt.cg_max_iter;
     const int groups = (int)std::min<long long>(P->n_slots, nb);
@@ -470,7 +504,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
                                  P->bx_ws, P->max_pe, P->Q_ws, s));
   }
   EXX_HIP(P, hipEventRecord(P->ev[2], s));
-  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pairs, P->class_dev, P->pair_count, n_orb,
+  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pairs, P->class_dev, P->pair_count, n_orb,
                            P->opt.cg_max_iter, E_xx, sigma, P->stats_dev, s));
   EXX_HIP(P, hipEventRecord(P->ev[3], s));
   P->timing_valid = true;

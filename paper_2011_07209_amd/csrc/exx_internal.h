@@ -14,7 +14,6 @@ namespace exx {
 constexpr int kMaxL = 8;                       // l_max limit of the multipole expansion
 constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
 constexpr int kMaxClasses = 16;
-constexpr int kSolveThreads = 1024;            // one workgroup per pair in the CG
 constexpr double kSlack = 1e-12;               // relative slack of sphere membership on |r|^2
 
 // Geometry and stencil constants, passed by value to every kernel.
@@ -109,6 +108,7 @@ struct exx_plan_s {
   double* pS = nullptr;
   int* pIt = nullptr;
   double* pRes = nullptr;
+  int* pUpd = nullptr;
 
   // batch workspace
   long long batch_cap = 0;
@@ -117,7 +117,10 @@ struct exx_plan_s {
   double* halo_ws = nullptr;   // [batch][max_halo]
   double* Q_ws = nullptr;      // [batch][kMaxLM]
   int n_slots = 0;
-  void* slot_ws = nullptr;     // [slots][2][max_pe] CG vectors r, p
+  int n_cus = 1;
+  int solve_threads = 1024, solve_depth = 1;   // CG variant in use
+  bool tuned = false;
+  void* slot_ws = nullptr;     // [slots] CG vectors: FP64 r, p; mixed: FP64 x, FP32 r, p, y
   int* queue = nullptr;
   double* stats_dev = nullptr;     // (iter_sum, iter_max, n_unconverged, max_res, n_pairs)
   bool pair_cap_fixed = false;

@@ -36,12 +36,17 @@ struct SolveArgs {
   int* queue = nullptr;
   double* bx_ws = nullptr;     // per pair: right-hand side in, solution out
   long long rstride = 0;
-  double* slot_ws = nullptr;   // per workgroup: r, p
+  void* slot_ws = nullptr;     // per workgroup CG vectors
   long long sstride = 0;
   int* outIt = nullptr;
   double* outRes = nullptr;
+  int* outUpd = nullptr;       // reliable updates per pair (mixed)
   double tol = 0;
   int max_iter = 0;
+  bool mixed = false;
+  double delta = 0.1;          // mixed: reliable-update threshold
+  int threads = 1024;          // workgroup size of the solve (512 or 1024)
+  int depth = 1;               // planes of loads in flight ahead of their use (1 or 2)
 };
 
 hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
@@ -49,7 +54,9 @@ hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, c
                       const double* halo_ws, long long hstride, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s);
 size_t solve_lds_bytes(const Geo& g, int max_zmax);
-int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax);
+int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, int threads, int depth);
+bool solve_supported(int max_cols, int threads);
+long long solve_slot_bytes(bool mixed, long long sstride);
 hipError_t launch_finalize(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
                            long long nb, const double* rho_ws, const double* v_ws, long long rstride,
                            const double* halo_ws, long long hstride, double* outE, double* outS, hipStream_t s);
@@ -64,7 +71,7 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s);
 // E_xx and sigma from per-pair results in canonical order; stats[8] receives
 // (iter_sum, iter_max, n_unconverged, max_res, n_pairs, sum iters*N_PE,
 //  refinement passes max, sum N_PE) as doubles.
-hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes,
+hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
                          const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, int max_iter,
                          double* E, double* sigma, double* stats, hipStream_t s);
 

@@ -17,37 +17,12 @@
 
 #include <algorithm>
 
+#include "device_common.h"
 #include "exx_launch.h"
 
 namespace exx {
 
 namespace {
-
-constexpr double kPi = 3.14159265358979323846;
-
-__device__ __forceinline__ int wrapi(int g, int N) {
-  g %= N;
-  return g < 0 ? g + N : g;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over the workgroup in a fixed order; every thread gets the result.
-// red must hold blockDim/64 doubles.  Contains two barriers.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_sum(v);
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < nw; ++w) s += red[w];
-  __syncthreads();
-  return s;
-}
 
 // Regular solid harmonics R_lm(r) = |r|^l S_lm(rhat) with real orthonormal S
 // (no Condon-Shortley phase), generated as polynomials in x, y, z:
@@ -319,12 +294,6 @@ __global__ __launch_bounds__(256) void k_boundary(Geo g, const ClassDev* __restr
 // ---------------------------------------------------------------------------
 // the right-hand side, the persistent CG solve, and the per-pair E / sigma
 
-struct Stencil {
-  double w[4];      // second-derivative weights w_0..w_3
-  double c[3];      // 1 / d_al^2
-  double diag;      // w_0 (c_x + c_y + c_z)
-};
-
 // value of the pair potential at offset o: the CG vector inside PE (or 0 when
 // pe_zero), the far field at a Dirichlet point
 __device__ __forceinline__ double point_value(const ClassDev& C, int n, const double* xv, const double* halo, int ox,
@@ -364,253 +333,6 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__
             point_value(C, g.n, nullptr, halo, o.x, o.y, o.z - q, true));
   }
   b_ws[(long long)bq * rstride + k] = acc;
-}
-
-// -(stencil Laplacian) at one point: ctr is the centre value, pl the LDS plane
-// (values of the current plane, zero off the PE sphere), wz the z window
-template <int NS>
-__device__ __forceinline__ double apply_point(const Stencil& S, double ctr, const double* pl, int pos, int wx,
-                                              const double* wz) {
-  double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-  for (int q = 1; q <= NS; ++q) {
-    sx += S.w[q] * (pl[pos + q] + pl[pos - q]);
-    sy += S.w[q] * (pl[pos + q * wx] + pl[pos - q * wx]);
-    sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
-  }
-  return -(S.diag * ctr + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
-}
-
-template <int CPT>
-struct Cols {
-  int zr[CPT];    // half-height, -1 for no column
-  int pos[CPT];   // LDS plane position
-  int col[CPT];   // column index (valid only when zr >= 0)
-};
-
-// Pass A of a CG iteration: p = r + beta p (p = r on the first iteration) is
-// stored, q = A p is formed on the fly; returns this thread's sums of p.q and
-// (first iteration) r.r.
-template <int NS, int CPT>
-__device__ void cg_pass_a(const Stencil& S, const Cols<CPT>& cl, const int* pst, int Zmax,
-                          const double* __restrict__ r, double* __restrict__ p, double beta, bool first, double* pl0,
-                          double* pl1, int wx, double& pq, double& rr) {
-  double win[CPT][2 * NS + 1];
-  pq = 0.0;
-  rr = 0.0;
-#pragma unroll
-  for (int k = 0; k < 2 * NS + 1; ++k) {
-    const int zz = -Zmax - NS + k;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      double v = 0.0;
-      if (abs(zz) <= cl.zr[c]) {
-        const int idx = pst[zz + Zmax] + cl.col[c];
-        const double rv = r[idx];
-        v = first ? rv : rv + beta * p[idx];
-        p[idx] = v;
-        rr += rv * rv;
-      }
-      win[c][k] = v;
-    }
-  }
-  for (int z = -Zmax; z <= Zmax; ++z) {
-    const int zn = z + NS + 1;
-    double nr[CPT], np[CPT];
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      nr[c] = 0.0;
-      np[c] = 0.0;
-      if (abs(zn) <= cl.zr[c]) {
-        const int idx = pst[zn + Zmax] + cl.col[c];
-        nr[c] = r[idx];
-        if (!first) np[c] = p[idx];
-      }
-    }
-    double* pl = (z & 1) ? pl1 : pl0;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c)
-      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (abs(z) <= cl.zr[c]) pq += win[c][NS] * apply_point<NS>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-#pragma unroll
-      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
-      double v = 0.0;
-      if (abs(zn) <= cl.zr[c]) {
-        v = first ? nr[c] : nr[c] + beta * np[c];
-        p[pst[zn + Zmax] + cl.col[c]] = v;
-        rr += nr[c] * nr[c];
-      }
-      win[c][2 * NS] = v;
-    }
-  }
-}
-
-// Pass B: q = A p again (same arithmetic as pass A), x += alpha p,
-// r -= alpha q; returns this thread's sum of r^2 after the update.  On the
-// first iteration r comes from r_in (the right-hand side, which x then
-// overwrites in place) and x starts from zero.
-template <int NS, int CPT>
-__device__ double cg_pass_b(const Stencil& S, const Cols<CPT>& cl, const int* pst, int Zmax, double* x,
-                            const double* r_in, double* r, const double* __restrict__ p, double alpha,
-                            bool first, double* pl0, double* pl1, int wx) {
-  double win[CPT][2 * NS + 1];
-#pragma unroll
-  for (int k = 0; k < 2 * NS + 1; ++k) {
-    const int zz = -Zmax - NS + k;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) win[c][k] = (abs(zz) <= cl.zr[c]) ? p[pst[zz + Zmax] + cl.col[c]] : 0.0;
-  }
-  double acc = 0.0;
-  for (int z = -Zmax; z <= Zmax; ++z) {
-    const int zn = z + NS + 1;
-    double np[CPT], xc[CPT], rc[CPT];
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      np[c] = (abs(zn) <= cl.zr[c]) ? p[pst[zn + Zmax] + cl.col[c]] : 0.0;
-      xc[c] = 0.0;
-      rc[c] = 0.0;
-      if (abs(z) <= cl.zr[c]) {
-        const int idx = pst[z + Zmax] + cl.col[c];
-        rc[c] = r_in[idx];
-        if (!first) xc[c] = x[idx];
-      }
-    }
-    double* pl = (z & 1) ? pl1 : pl0;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c)
-      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (abs(z) <= cl.zr[c]) {
-        const int idx = pst[z + Zmax] + cl.col[c];
-        const double q = apply_point<NS>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
-        const double rn = rc[c] - alpha * q;
-        x[idx] = xc[c] + alpha * win[c][NS];
-        r[idx] = rn;
-        acc += rn * rn;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-#pragma unroll
-      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
-      win[c][2 * NS] = np[c];
-    }
-  }
-  return acc;
-}
-
-struct SolveKArgs {
-  const ClassDev* cls;
-  const PairDev* pairs;
-  const int* order;
-  long long p0, npair;
-  int* queue;
-  double* bx_ws;          // per pair: right-hand side in, solution out
-  long long rstride;
-  double* slot_ws;        // per workgroup: r, p
-  long long sstride;
-  int* outIt;
-  double* outRes;
-  double tol;
-  int max_iter;
-  Stencil S;
-  int lds_cx, lds_cy, lds_wx, lds_wy;
-};
-
-// One workgroup solves one pair at a time, taking pairs from a device queue
-// until the batch is exhausted (every workgroup exits when the counter passes
-// the batch size).  Unpreconditioned CG from x = 0, stop at ||r|| <= tol ||b||.
-template <int NS, int CPT>
-__global__ __launch_bounds__(kSolveThreads) void k_solve(SolveKArgs a) {
-  extern __shared__ double lds[];
-  __shared__ double red[kSolveThreads / 64];
-  __shared__ int s_item;
-  const int tid = threadIdx.x;
-  const int plane = a.lds_wx * a.lds_wy;
-  double* pl0 = lds;
-  double* pl1 = lds + plane;
-  int* pst = reinterpret_cast<int*>(lds + 2 * plane);
-  double* r = a.slot_ws + (long long)blockIdx.x * 2 * a.sstride;
-  double* p = r + a.sstride;
-
-  for (;;) {
-    if (tid == 0) s_item = atomicAdd(a.queue, 1);
-    __syncthreads();
-    const long long item = s_item;
-    __syncthreads();
-    if (item >= a.npair) break;
-    const int pid = a.order[a.p0 + item];
-    const ClassDev& C = a.cls[a.pairs[pid].cls];
-    const int Zmax = C.Zmax;
-    double* x = a.bx_ws + item * a.rstride;
-
-    for (int k = tid; k < 2 * plane; k += blockDim.x) lds[k] = 0.0;
-    for (int k = tid; k < 2 * Zmax + 2; k += blockDim.x) pst[k] = C.plane_start[k];
-    Cols<CPT> cl;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      const int col = tid + c * kSolveThreads;
-      cl.zr[c] = -1;
-      cl.col[c] = 0;
-      cl.pos[c] = 0;
-      if (col < C.n_cols) {
-        const int4 cc = C.cols[col];
-        cl.zr[c] = cc.z;
-        cl.col[c] = col;
-        cl.pos[c] = (cc.x + a.lds_cx) + a.lds_wx * (cc.y + a.lds_cy);
-      }
-    }
-    __syncthreads();
-
-    int it = 0;
-    double rr = 0.0, bnorm = 0.0, beta = 0.0;
-    bool first = true;
-    while (it < a.max_iter) {
-      double pq_t, rr_t;
-      cg_pass_a<NS, CPT>(a.S, cl, pst, Zmax, first ? x : r, p, beta, first, pl0, pl1, a.lds_wx, pq_t, rr_t);
-      const double pq = block_sum(pq_t, red);
-      if (first) {
-        rr = block_sum(rr_t, red);
-        bnorm = sqrt(rr);
-        if (!(bnorm > 0.0)) break;   // b == 0: x = b = 0 already
-      }
-      if (!(pq > 0.0) || !(pq < INFINITY)) {   // breakdown: A is SPD, so only NaN/inf input gets here
-        it = a.max_iter;
-        rr = NAN;
-        break;
-      }
-      const double alpha = rr / pq;
-      const double rn =
-          block_sum(cg_pass_b<NS, CPT>(a.S, cl, pst, Zmax, x, first ? x : r, r, p, alpha, first, pl0, pl1, a.lds_wx),
-                    red);
-      ++it;
-      first = false;
-      if (sqrt(rn) <= a.tol * bnorm) {
-        rr = rn;
-        break;
-      }
-      if (!(rn == rn)) {
-        it = a.max_iter;
-        rr = NAN;
-        break;
-      }
-      beta = rn / rr;
-      rr = rn;
-    }
-    if (tid == 0) {
-      a.outIt[pid] = it;
-      a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
-    }
-    __syncthreads();
-  }
 }
 
 // E_xx and sigma_xx of one pair from its density and potential (one workgroup
@@ -710,19 +432,21 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, const double* __restrict__ pS,
                                                 const int* __restrict__ pIt, const double* __restrict__ pRes,
+                                                const int* __restrict__ pUpd,
                                                 const PairDev* __restrict__ pairs, const ClassDev* __restrict__ cls,
                                                 const int* __restrict__ cnt, int n_orb, int max_iter,
                                                 double* __restrict__ E, double* __restrict__ sigma,
                                                 double* __restrict__ stats) {
   __shared__ double red[4];
   const long long np = cnt[2 * n_orb];
-  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0;
+  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0, umax = 0.0;
   for (int t = 0; t < 9; ++t) s[t] = 0.0;
   for (long long k = threadIdx.x; k < np; k += blockDim.x) {
     e += pE[k];
     for (int t = 0; t < 9; ++t) s[t] += pS[9 * k + t];
     isum += pIt[k];
     imax = fmax(imax, (double)pIt[k]);
+    umax = fmax(umax, (double)pUpd[k]);
     nunc += (pIt[k] >= max_iter) ? 1.0 : 0.0;
     rmax = fmax(rmax, pRes[k]);
     const double npe = (double)cls[pairs[k].cls].n_pe;
@@ -739,17 +463,20 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
   for (int o = 32; o > 0; o >>= 1) {
     imax = fmax(imax, __shfl_xor(imax, o, 64));
     rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+    umax = fmax(umax, __shfl_xor(umax, o, 64));
   }
-  __shared__ double mx[2][4];
+  __shared__ double mx[3][4];
   if ((threadIdx.x & 63) == 0) {
     mx[0][threadIdx.x >> 6] = imax;
     mx[1][threadIdx.x >> 6] = rmax;
+    mx[2][threadIdx.x >> 6] = umax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
       imax = fmax(imax, mx[0][w]);
       rmax = fmax(rmax, mx[1][w]);
+      umax = fmax(umax, mx[2][w]);
     }
     if (E) *E = e;
     if (sigma)
@@ -760,7 +487,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     stats[3] = rmax;
     stats[4] = (double)np;
     stats[5] = work;
-    stats[6] = 0.0;
+    stats[6] = umax;
     stats[7] = pts;
   }
 }
@@ -823,10 +550,6 @@ hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pai
   return hipGetLastError();
 }
 
-size_t solve_lds_bytes(const Geo& g, int max_zmax) {
-  return (size_t)2 * g.lds_wx * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2) * sizeof(int);
-}
-
 hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
                       long long nb, long long max_pe, const double* rho_ws, double* b_ws, long long rstride,
                       const double* halo_ws, long long hstride, hipStream_t s) {
@@ -843,83 +566,6 @@ hipError_t launch_finalize(const Geo& g, const ClassDev* cls, const PairDev* pai
   k_finalize<<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, rho_ws, v_ws, rstride, halo_ws, hstride, outE,
                                           outS);
   return hipGetLastError();
-}
-
-template <int NS, int K>
-static hipError_t solve_prepare(size_t lds) {
-  if (lds > 64 * 1024)
-    return hipFuncSetAttribute((const void*)k_solve<NS, K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipSuccess;
-}
-
-template <int NS>
-static hipError_t solve_ns(const SolveKArgs& a, int cpt, int groups, size_t lds, hipStream_t s, int* occ) {
-  hipError_t e = hipErrorInvalidValue;
-  switch (cpt) {
-#define EXX_CPT(K)                                                                                   \
-  case K:                                                                                            \
-    e = solve_prepare<NS, K>(lds);                                                                   \
-    if (e != hipSuccess) return e;                                                                   \
-    if (occ) {                                                                                       \
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, K>, kSolveThreads, lds);     \
-    } else {                                                                                         \
-      k_solve<NS, K><<<groups, kSolveThreads, lds, s>>>(a);                                          \
-      e = hipGetLastError();                                                                         \
-    }                                                                                                \
-    break;
-    EXX_CPT(1) EXX_CPT(2) EXX_CPT(3) EXX_CPT(4) EXX_CPT(5) EXX_CPT(6) EXX_CPT(7) EXX_CPT(8)
-#undef EXX_CPT
-    default:
-      break;
-  }
-  return e;
-}
-
-static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax, int groups, hipStream_t s,
-                                 int* occ) {
-  SolveKArgs a;
-  a.cls = in.cls;
-  a.pairs = in.pairs;
-  a.order = in.order;
-  a.p0 = in.p0;
-  a.npair = in.npair;
-  a.queue = in.queue;
-  a.bx_ws = in.bx_ws;
-  a.rstride = in.rstride;
-  a.slot_ws = in.slot_ws;
-  a.sstride = in.sstride;
-  a.outIt = in.outIt;
-  a.outRes = in.outRes;
-  a.tol = in.tol;
-  a.max_iter = in.max_iter;
-  for (int q = 0; q < 4; ++q) a.S.w[q] = in.g.w2[q];
-  for (int al = 0; al < 3; ++al) a.S.c[al] = in.g.inv_d2[al];
-  a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
-  a.lds_cx = in.g.lds_cx;
-  a.lds_cy = in.g.lds_cy;
-  a.lds_wx = in.g.lds_wx;
-  a.lds_wy = in.g.lds_wy;
-  const int cpt = (max_cols + kSolveThreads - 1) / kSolveThreads;
-  const size_t lds = solve_lds_bytes(in.g, max_zmax);
-  switch (in.g.n) {
-    case 1: return solve_ns<1>(a, cpt, groups, lds, s, occ);
-    case 2: return solve_ns<2>(a, cpt, groups, lds, s, occ);
-    case 3: return solve_ns<3>(a, cpt, groups, lds, s, occ);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax) {
-  SolveArgs a;
-  a.g = g;
-  int occ = 0;
-  if (solve_dispatch(a, max_cols, max_zmax, 1, nullptr, &occ) != hipSuccess) return 0;
-  return occ;
-}
-
-hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s) {
-  if (a.npair <= 0) return hipSuccess;
-  return solve_dispatch(a, max_cols, max_zmax, groups, s, nullptr);
 }
 
 hipError_t launch_dscatter(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
@@ -956,10 +602,10 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes,
+hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
                          const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, int max_iter,
                          double* E, double* sigma, double* stats, hipStream_t s) {
-  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pairs, cls, counts, n_orb, max_iter, E, sigma, stats);
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pairs, cls, counts, n_orb, max_iter, E, sigma, stats);
   return hipGetLastError();
 }
 

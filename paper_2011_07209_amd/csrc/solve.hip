@@ -1,0 +1,81 @@
+// Launchers of the persistent CG solve (the instances live in solve_n*.hip).
+#include "solve_impl.h"
+
+namespace exx {
+
+hipError_t solve_dispatch_n1(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
+                             size_t lds, hipStream_t s, int* occ);
+hipError_t solve_dispatch_n2(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
+                             size_t lds, hipStream_t s, int* occ);
+hipError_t solve_dispatch_n3(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
+                             size_t lds, hipStream_t s, int* occ);
+
+size_t solve_lds_bytes(const Geo& g, int max_zmax) {
+  return (size_t)2 * g.lds_wx * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2) * sizeof(int);
+}
+
+long long solve_slot_bytes(bool mixed, long long sstride) {
+  const long long b = mixed ? 20 * sstride : 16 * sstride;
+  return (b + 255) & ~255LL;
+}
+
+static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax, int groups, hipStream_t s,
+                                 int* occ) {
+  SolveKArgs a;
+  a.cls = in.cls;
+  a.pairs = in.pairs;
+  a.order = in.order;
+  a.p0 = in.p0;
+  a.npair = in.npair;
+  a.queue = in.queue;
+  a.bx_ws = in.bx_ws;
+  a.rstride = in.rstride;
+  a.slot_ws = in.slot_ws;
+  a.sstride = in.sstride;
+  a.slot_bytes = solve_slot_bytes(in.mixed, in.sstride);
+  a.outIt = in.outIt;
+  a.outRes = in.outRes;
+  a.outUpd = in.outUpd;
+  a.tol = in.tol;
+  a.max_iter = in.max_iter;
+  a.delta = in.delta;
+  for (int q = 0; q < 4; ++q) a.S.w[q] = in.g.w2[q];
+  for (int al = 0; al < 3; ++al) a.S.c[al] = in.g.inv_d2[al];
+  a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
+  a.lds_cx = in.g.lds_cx;
+  a.lds_cy = in.g.lds_cy;
+  a.lds_wx = in.g.lds_wx;
+  a.lds_wy = in.g.lds_wy;
+  const size_t lds = solve_lds_bytes(in.g, max_zmax);
+  switch (in.g.n) {
+    case 1: return solve_dispatch_n1(a, in.mixed, max_cols, in.threads, in.depth, groups, lds, s, occ);
+    case 2: return solve_dispatch_n2(a, in.mixed, max_cols, in.threads, in.depth, groups, lds, s, occ);
+    case 3: return solve_dispatch_n3(a, in.mixed, max_cols, in.threads, in.depth, groups, lds, s, occ);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool solve_supported(int max_cols, int threads) {
+  if (threads == 1024) return max_cols <= 4 * 1024;
+  if (threads == 512) return max_cols <= 8 * 512;
+  return false;
+}
+
+int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, int threads, int depth) {
+  if (!solve_supported(max_cols, threads)) return 0;
+  SolveArgs a;
+  a.g = g;
+  a.mixed = mixed;
+  a.threads = threads;
+  a.depth = depth;
+  int occ = 0;
+  if (solve_dispatch(a, max_cols, max_zmax, 1, nullptr, &occ) != hipSuccess) return 0;
+  return occ;
+}
+
+hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s) {
+  if (a.npair <= 0) return hipSuccess;
+  return solve_dispatch(a, max_cols, max_zmax, groups, s, nullptr);
+}
+
+}  // namespace exx

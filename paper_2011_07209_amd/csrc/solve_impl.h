@@ -1,0 +1,606 @@
+// The persistent CG solve of the pair Poisson problems (eq. pe discretised with
+// the axis stencil of eq. d2_1), FP64 and mixed precision.  Included by one
+// translation unit per stencil half-width.
+//
+// Data layout: a PE vector is stored plane by plane (z ascending); within a
+// plane the sphere's (x,y) columns appear in one fixed order sorted by column
+// half-height, so plane z holds a prefix of that order.  Thread t of a
+// workgroup owns columns t, t + NT, ... for the whole solve and marches z:
+// the z neighbours of its points live in a register window of 2n+1 values per
+// column, the x/y neighbours come from the current plane staged in LDS
+// (double-buffered: one barrier per plane).  Global loads run PD planes ahead
+// of their use, so a CU keeps several planes of loads in flight.
+#pragma once
+
+#include "device_common.h"
+#include "exx_launch.h"
+
+namespace exx {
+
+template <typename T>
+struct StencilT {
+  T w[4];      // second-derivative weights w_0..w_3
+  T c[3];      // 1 / d_al^2
+  T diag;      // w_0 (c_x + c_y + c_z)
+};
+
+template <typename T>
+__device__ __forceinline__ StencilT<T> stencil_cast(const StencilT<double>& s) {
+  StencilT<T> o;
+  for (int q = 0; q < 4; ++q) o.w[q] = (T)s.w[q];
+  for (int a = 0; a < 3; ++a) o.c[a] = (T)s.c[a];
+  o.diag = (T)s.diag;
+  return o;
+}
+
+struct SolveKArgs {
+  const ClassDev* cls;
+  const PairDev* pairs;
+  const int* order;
+  long long p0, npair;
+  int* queue;
+  double* bx_ws;          // per pair: right-hand side in, solution out
+  long long rstride;
+  void* slot_ws;          // per workgroup: CG vectors
+  long long sstride;      // elements per vector
+  long long slot_bytes;   // bytes per workgroup slot
+  int* outIt;
+  double* outRes;
+  int* outUpd;            // mixed: reliable updates per pair
+  double tol;
+  int max_iter;
+  double delta;           // mixed: update when ||r|| < delta * (residual at the last update)
+  StencilT<double> S;
+  int lds_cx, lds_cy, lds_wx, lds_wy;
+};
+
+// -(stencil Laplacian) at one point in the arithmetic of T: ctr is the centre
+// value, pl the LDS plane (values of the current plane, zero off the PE
+// sphere), wz the z window
+template <int NS, typename T>
+__device__ __forceinline__ T apply_point(const StencilT<T>& S, T ctr, const T* pl, int pos, int wx, const T* wz) {
+  T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+  for (int q = 1; q <= NS; ++q) {
+    sx += S.w[q] * (pl[pos + q] + pl[pos - q]);
+    sy += S.w[q] * (pl[pos + q * wx] + pl[pos - q * wx]);
+    sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
+  }
+  return -(S.diag * ctr + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
+}
+
+template <int CPT>
+struct Cols {
+  int zr[CPT];    // half-height, -1 for no column
+  int pos[CPT];   // LDS plane position
+  int col[CPT];   // column index (valid only when zr >= 0)
+};
+
+template <int CPT, int NT>
+__device__ __forceinline__ void load_cols(const ClassDev& C, const SolveKArgs& a, Cols<CPT>& cl) {
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int col = threadIdx.x + c * NT;
+    cl.zr[c] = -1;
+    cl.col[c] = 0;
+    cl.pos[c] = 0;
+    if (col < C.n_cols) {
+      const int4 cc = C.cols[col];
+      cl.zr[c] = cc.z;
+      cl.col[c] = col;
+      cl.pos[c] = (cc.x + a.lds_cx) + a.lds_wx * (cc.y + a.lds_cy);
+    }
+  }
+}
+
+#define EXX_VALID(c, zz) (abs(zz) <= cl.zr[c])
+#define EXX_IDX(c, zz) (pst[(zz) + Zmax] + cl.col[c])
+
+// Pass A of a CG iteration: p = r + beta p (p = r on the first iteration) is
+// stored, q = A p is formed on the fly; accumulates p.q and r.r in FP64.
+template <int NS, int CPT, int PD, typename T>
+__device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, const T* __restrict__ r,
+                          T* __restrict__ p, T beta, bool first, T* pl0, T* pl1, int wx, double& pq, double& rr) {
+  T win[CPT][2 * NS + 1];
+  T qr[PD][CPT], qp[PD][CPT];   // raw r, p of planes z+NS+1 .. z+NS+PD
+  pq = 0.0;
+  rr = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      T v = 0;
+      if (EXX_VALID(c, zz)) {
+        const int idx = EXX_IDX(c, zz);
+        const T rv = r[idx];
+        v = first ? rv : rv + beta * p[idx];
+        p[idx] = v;
+        rr += (double)rv * (double)rv;
+      }
+      win[c][k] = v;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      qr[d][c] = 0;
+      qp[d][c] = 0;
+      if (EXX_VALID(c, zz)) {
+        const int idx = EXX_IDX(c, zz);
+        qr[d][c] = r[idx];
+        if (!first) qp[d][c] = p[idx];
+      }
+    }
+  }
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zl = z + NS + PD + 1;   // plane whose loads are issued now
+    T nr[CPT], np[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nr[c] = 0;
+      np[c] = 0;
+      if (EXX_VALID(c, zl)) {
+        const int idx = EXX_IDX(c, zl);
+        nr[c] = r[idx];
+        if (!first) np[c] = p[idx];
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_VALID(c, z))
+        pq += (double)win[c][NS] * (double)apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+    }
+    const int zc = z + NS + 1;        // plane entering the window
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      T v = 0;
+      if (EXX_VALID(c, zc)) {
+        v = first ? qr[0][c] : qr[0][c] + beta * qp[0][c];
+        p[EXX_IDX(c, zc)] = v;
+        rr += (double)qr[0][c] * (double)qr[0][c];
+      }
+      win[c][2 * NS] = v;
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) {
+        qr[d][c] = qr[d + 1][c];
+        qp[d][c] = qp[d + 1][c];
+      }
+      qr[PD - 1][c] = nr[c];
+      qp[PD - 1][c] = np[c];
+    }
+  }
+}
+
+// Pass B: q = A p again (same arithmetic as pass A), x += alpha p,
+// r -= alpha q; returns this thread's FP64 sum of r^2 after the update.  The
+// residual is read from r_in and written to r (they may alias); with x_zero
+// the old x is taken as zero (and x may alias r_in: each point is read before
+// it is written, by the same thread).
+template <int NS, int CPT, int PD, typename T>
+__device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, T* x,
+                            const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1,
+                            int wx) {
+  T win[CPT][2 * NS + 1];
+  T qp[PD][CPT];           // p of planes z+NS+1 .. z+NS+PD
+  T cx[CPT], cr[CPT];      // x, r of plane z
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_VALID(c, zz) ? p[EXX_IDX(c, zz)] : (T)0;
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_VALID(c, zz) ? p[EXX_IDX(c, zz)] : (T)0;
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    cx[c] = 0;
+    cr[c] = 0;
+    if (EXX_VALID(c, -Zmax)) {
+      const int idx = EXX_IDX(c, -Zmax);
+      cr[c] = r_in[idx];
+      if (!x_zero) cx[c] = x[idx];
+    }
+  }
+  double acc = 0.0;
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zl = z + NS + PD + 1;
+    T np[CPT], nx[CPT], nr[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      np[c] = EXX_VALID(c, zl) ? p[EXX_IDX(c, zl)] : (T)0;
+      nx[c] = 0;
+      nr[c] = 0;
+      if (EXX_VALID(c, z + 1)) {
+        const int idx = EXX_IDX(c, z + 1);
+        nr[c] = r_in[idx];
+        if (!x_zero) nx[c] = x[idx];
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_VALID(c, z)) {
+        const int idx = EXX_IDX(c, z);
+        const T q = apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+        const T rn = cr[c] - alpha * q;
+        x[idx] = cx[c] + alpha * win[c][NS];
+        r[idx] = rn;
+        acc += (double)rn * (double)rn;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      win[c][2 * NS] = qp[0][c];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) qp[d][c] = qp[d + 1][c];
+      qp[PD - 1][c] = np[c];
+      cx[c] = nx[c];
+      cr[c] = nr[c];
+    }
+  }
+  return acc;
+}
+
+// Reliable update of the mixed-precision solve, in FP64: the accumulated FP32
+// correction y (in units of ys) is folded into the FP64 solution, w = x + ys y,
+// and the true residual b - A w is recomputed and stored, times rs and
+// rounded to FP32, as the new working residual.  Returns this thread's FP64
+// sum of the (unscaled) true residual^2.
+template <int NS, int CPT, int PD>
+__device__ double cg_update(const StencilT<double>& S, const Cols<CPT>& cl, const int* pst, int Zmax,
+                            double* __restrict__ x, const float* __restrict__ y, bool x_zero, bool y_zero,
+                            const double* __restrict__ b, float* __restrict__ r, double ys, double rs, double* pl0,
+                            double* pl1, int wx) {
+  double win[CPT][2 * NS + 1];
+  double qx[PD][CPT];
+  float qy[PD][CPT];
+  double cb[CPT];
+  auto fold = [&](int c, int zz, double xv, float yv) -> double {
+    if (!EXX_VALID(c, zz)) return 0.0;
+    const double w = xv + ys * (double)yv;
+    x[EXX_IDX(c, zz)] = w;
+    return w;
+  };
+  auto raw = [&](int c, int zz, double& xv, float& yv) {
+    xv = 0.0;
+    yv = 0.0f;
+    if (EXX_VALID(c, zz)) {
+      const int idx = EXX_IDX(c, zz);
+      if (!x_zero) xv = x[idx];
+      if (!y_zero) yv = y[idx];
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      double xv;
+      float yv;
+      raw(c, -Zmax - NS + k, xv, yv);
+      win[c][k] = fold(c, -Zmax - NS + k, xv, yv);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) raw(c, -Zmax + NS + 1 + d, qx[d][c], qy[d][c]);
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) cb[c] = EXX_VALID(c, -Zmax) ? b[EXX_IDX(c, -Zmax)] : 0.0;
+  double acc = 0.0;
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zl = z + NS + PD + 1;
+    double nx[CPT], nb[CPT];
+    float ny[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      raw(c, zl, nx[c], ny[c]);
+      nb[c] = EXX_VALID(c, z + 1) ? b[EXX_IDX(c, z + 1)] : 0.0;
+    }
+    double* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (cl.zr[c] >= 0) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_VALID(c, z)) {
+        const double rt = cb[c] - apply_point<NS, double>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+        r[EXX_IDX(c, z)] = (float)(rt * rs);
+        acc += rt * rt;
+      }
+    }
+    const int zc = z + NS + 1;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      win[c][2 * NS] = fold(c, zc, qx[0][c], qy[0][c]);
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) {
+        qx[d][c] = qx[d + 1][c];
+        qy[d][c] = qy[d + 1][c];
+      }
+      qx[PD - 1][c] = nx[c];
+      qy[PD - 1][c] = ny[c];
+      cb[c] = nb[c];
+    }
+  }
+  return acc;
+}
+
+#undef EXX_VALID
+#undef EXX_IDX
+
+// One workgroup solves one pair at a time, taking pairs from a device queue
+// until the batch is exhausted (every workgroup exits when the counter passes
+// the batch size).  Unpreconditioned CG from x = 0, stop at ||r|| <= tol ||b||.
+template <int NS, int CPT, int NT, int PD>
+__global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[NT / 64];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int plane = a.lds_wx * a.lds_wy;
+  double* pl0 = lds;
+  double* pl1 = lds + plane;
+  int* pst = reinterpret_cast<int*>(lds + 2 * plane);
+  double* r = (double*)((char*)a.slot_ws + (long long)blockIdx.x * a.slot_bytes);
+  double* p = r + a.sstride;
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const long long item = s_item;
+    __syncthreads();
+    if (item >= a.npair) break;
+    const int pid = a.order[a.p0 + item];
+    const ClassDev& C = a.cls[a.pairs[pid].cls];
+    const int Zmax = C.Zmax;
+    double* x = a.bx_ws + item * a.rstride;
+
+    for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+    for (int k = tid; k < 2 * Zmax + 2; k += NT) pst[k] = C.plane_start[k];
+    Cols<CPT> cl;
+    load_cols<CPT, NT>(C, a, cl);
+    __syncthreads();
+
+    int it = 0;
+    double rr = 0.0, bnorm = 0.0, beta = 0.0;
+    bool first = true;
+    while (it < a.max_iter) {
+      double pq_t, rr_t;
+      cg_pass_a<NS, CPT, PD, double>(a.S, cl, pst, Zmax, first ? x : r, p, beta, first, pl0, pl1, a.lds_wx, pq_t,
+                                     rr_t);
+      const double pq = block_sum(pq_t, red);
+      if (first) {
+        rr = block_sum(rr_t, red);
+        bnorm = sqrt(rr);
+        if (!(bnorm > 0.0)) break;   // b == 0: x = b = 0 already
+      }
+      if (!(pq > 0.0) || !(pq < INFINITY)) {   // breakdown: A is SPD, so only NaN/inf input gets here
+        it = a.max_iter;
+        rr = NAN;
+        break;
+      }
+      const double alpha = rr / pq;
+      const double rn = block_sum(cg_pass_b<NS, CPT, PD, double>(a.S, cl, pst, Zmax, x, first ? x : r, r, p, alpha,
+                                                                 first, pl0, pl1, a.lds_wx),
+                                  red);
+      ++it;
+      first = false;
+      if (sqrt(rn) <= a.tol * bnorm) {
+        rr = rn;
+        break;
+      }
+      if (!(rn == rn)) {
+        it = a.max_iter;
+        rr = NAN;
+        break;
+      }
+      beta = rn / rr;
+      rr = rn;
+    }
+    if (tid == 0) {
+      a.outIt[pid] = it;
+      a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+      a.outUpd[pid] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// Mixed precision: FP32 CG (stencil, vectors and updates in FP32, dot products
+// and norms in FP64) with reliable updates in FP64 (residual replacement:
+// van der Vorst and Ye 2000; Clark et al. 2010).  The solution accumulates in
+// FP64 and the stop test is on the FP64 true residual, ||b - A x|| <= tol ||b||,
+// the same criterion as the FP64 path.
+template <int NS, int CPT, int NT, int PD>
+__global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[NT / 64];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int plane = a.lds_wx * a.lds_wy;
+  double* pl0 = lds;
+  double* pl1 = lds + plane;
+  float* fl0 = reinterpret_cast<float*>(lds);
+  float* fl1 = fl0 + plane;
+  int* pst = reinterpret_cast<int*>(lds + 2 * plane);
+  // slot: x (FP64), then r, p, y (FP32)
+  double* x = (double*)((char*)a.slot_ws + (long long)blockIdx.x * a.slot_bytes);
+  float* r = reinterpret_cast<float*>(x + a.sstride);
+  float* p = r + a.sstride;
+  float* y = p + a.sstride;
+  const StencilT<float> S32 = stencil_cast<float>(a.S);
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const long long item = s_item;
+    __syncthreads();
+    if (item >= a.npair) break;
+    const int pid = a.order[a.p0 + item];
+    const ClassDev& C = a.cls[a.pairs[pid].cls];
+    const int Zmax = C.Zmax;
+    const long long npe = C.n_pe;
+    double* bx = a.bx_ws + item * a.rstride;
+
+    for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+    for (int k = tid; k < 2 * Zmax + 2; k += NT) pst[k] = C.plane_start[k];
+    Cols<CPT> cl;
+    load_cols<CPT, NT>(C, a, cl);
+    // ||b|| in FP64; the FP32 recursion runs in units of ||b|| (r = b / ||b||),
+    // so its values stay far from the FP32 range limits whatever the pair's
+    // overlap, and the solution is x = ||b|| sum y
+    double bb = 0.0;
+    for (long long k = tid; k < npe; k += NT) {
+      const double bv = bx[k];
+      bb += bv * bv;
+    }
+    bb = block_sum(bb, red);   // also orders the plane zeroing before the first pass
+    const double bnorm = sqrt(bb);
+    const double inv_b = bnorm > 0.0 ? 1.0 / bnorm : 0.0;
+    for (long long k = tid; k < npe; k += NT) r[k] = (float)(bx[k] * inv_b);
+    __syncthreads();
+
+    int it = 0, upd = 0;
+    double rr = 1.0, rr_true = bb, rmax = 1.0, beta = 0.0;
+    bool first = true, x_zero = true, y_zero = true, conv = !(bnorm > 0.0);
+    while (!conv && it < a.max_iter) {
+      double pq_t, rr_t;
+      cg_pass_a<NS, CPT, PD, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, a.lds_wx, pq_t, rr_t);
+      const double pq = block_sum(pq_t, red);
+      if (!(pq > 0.0) || !(pq < INFINITY)) {
+        it = a.max_iter;
+        rr_true = NAN;
+        break;
+      }
+      const double alpha = rr / pq;
+      double rn = block_sum(cg_pass_b<NS, CPT, PD, float>(S32, cl, pst, Zmax, y, r, r, p, (float)alpha, y_zero, fl0,
+                                                          fl1, a.lds_wx),
+                            red);
+      ++it;
+      first = false;
+      y_zero = false;
+      const double rnorm = sqrt(rn);
+      if (!(rn == rn)) {
+        it = a.max_iter;
+        rr_true = NAN;
+        break;
+      }
+      if (rnorm < a.delta * rmax || rnorm <= a.tol || it >= a.max_iter) {
+        // the FP64 and FP32 plane views share LDS: clear it around the FP64 pass
+        for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+        __syncthreads();
+        rr_true = block_sum(cg_update<NS, CPT, PD>(a.S, cl, pst, Zmax, x, y, x_zero, y_zero, bx, r, bnorm, inv_b,
+                                                   pl0, pl1, a.lds_wx),
+                            red);
+        for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+        __syncthreads();
+        ++upd;
+        x_zero = false;
+        y_zero = true;
+        rn = rr_true * inv_b * inv_b;
+        rmax = sqrt(rn);
+        if (sqrt(rr_true) <= a.tol * bnorm) conv = true;
+      }
+      beta = rn / rr;
+      rr = rn;
+    }
+    // the FP64 solution replaces the right-hand side
+    if (!x_zero) {
+      for (long long k = tid; k < npe; k += NT) bx[k] = x[k];
+    } else if (bnorm > 0.0) {
+      for (long long k = tid; k < npe; k += NT) bx[k] = 0.0;
+    }
+    if (tid == 0) {
+      a.outIt[pid] = conv ? it : a.max_iter;
+      a.outRes[pid] = bnorm > 0.0 ? sqrt(rr_true) / bnorm : 0.0;
+      a.outUpd[pid] = upd;
+    }
+    __syncthreads();
+  }
+}
+
+// Launch (or occupancy query, when occ is not NULL) of one instance.
+template <int NS, int CPT, int NT, int PD>
+hipError_t solve_instance(const SolveKArgs& a, bool mixed, int groups, size_t lds, hipStream_t s, int* occ) {
+  const void* fn = mixed ? (const void*)k_solve_mixed<NS, CPT, NT, PD> : (const void*)k_solve<NS, CPT, NT, PD>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (occ) {
+    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve_mixed<NS, CPT, NT, PD>, NT, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, CPT, NT, PD>, NT, lds);
+  }
+  if (mixed)
+    k_solve_mixed<NS, CPT, NT, PD><<<groups, NT, lds, s>>>(a);
+  else
+    k_solve<NS, CPT, NT, PD><<<groups, NT, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+// Columns per thread available for each workgroup size: 1024 threads take up
+// to 4 columns each, 512 threads up to 8.
+template <int NS, int NT, int PD>
+hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_t lds, hipStream_t s, int* occ) {
+  if (NT == 1024) {
+    switch (cpt) {
+      case 1: return solve_instance<NS, 1, NT, PD>(a, mixed, groups, lds, s, occ);
+      case 2: return solve_instance<NS, 2, NT, PD>(a, mixed, groups, lds, s, occ);
+      case 3: return solve_instance<NS, 3, NT, PD>(a, mixed, groups, lds, s, occ);
+      case 4: return solve_instance<NS, 4, NT, PD>(a, mixed, groups, lds, s, occ);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (cpt) {
+    case 1:
+    case 2: return solve_instance<NS, 2, NT, PD>(a, mixed, groups, lds, s, occ);
+    case 3:
+    case 4: return solve_instance<NS, 4, NT, PD>(a, mixed, groups, lds, s, occ);
+    case 5:
+    case 6: return solve_instance<NS, 6, NT, PD>(a, mixed, groups, lds, s, occ);
+    case 7:
+    case 8: return solve_instance<NS, 8, NT, PD>(a, mixed, groups, lds, s, occ);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NS>
+hipError_t solve_ns_dispatch(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
+                             size_t lds, hipStream_t s, int* occ) {
+  const int cpt = (max_cols + threads - 1) / threads;
+  if (threads == 1024) {
+    if (depth <= 1) return solve_cpt<NS, 1024, 1>(a, mixed, cpt, groups, lds, s, occ);
+    return solve_cpt<NS, 1024, 2>(a, mixed, cpt, groups, lds, s, occ);
+  }
+  if (threads == 512) {
+    if (depth <= 1) return solve_cpt<NS, 512, 1>(a, mixed, cpt, groups, lds, s, occ);
+    return solve_cpt<NS, 512, 2>(a, mixed, cpt, groups, lds, s, occ);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace exx

@@ -1,0 +1,11 @@
+// Instances of the persistent CG solve for stencil half-width n = 3.
+#include "solve_impl.h"
+
+namespace exx {
+
+hipError_t solve_dispatch_n3(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
+                             size_t lds, hipStream_t s, int* occ) {
+  return solve_ns_dispatch<3>(a, mixed, max_cols, threads, depth, groups, lds, s, occ);
+}
+
+}  // namespace exx

@@ -42,6 +42,9 @@ class Options(ctypes.Structure):
         ("max_pairs", ctypes.c_longlong),
         ("workspace_gb", ctypes.c_double),
         ("solve_groups", ctypes.c_int),
+        ("solve_threads", ctypes.c_int),
+        ("solve_depth", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 

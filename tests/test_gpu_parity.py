@@ -111,3 +111,63 @@ def test_repeat_is_bitwise_deterministic_for_E_and_sigma():
     assert a["E"] == b["E"]
     assert np.array_equal(a["sigma"], b["sigma"])
     assert np.array_equal(a["pairs"]["iters"], b["pairs"]["iters"])
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 CG with FP64 dots, reliable updates and FP64 stop test
+
+@pytest.mark.parametrize("tol", [1e-10, 1e-12])
+def test_mixed_precision_tiny16(tol):
+    """Mixed path against the FP64 oracle.  Targets: |dE| <= 1e-6 Ha per
+    molecule-equivalent (4 orbitals), sigma within 1e-6 relative.  Because the
+    stop test is on the FP64 true residual, the FP64 bars hold as well."""
+    cfg = dataclasses.replace(synth.CONFIGS["tiny16"], cg_tol=tol)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    import torch
+    from paper_2011_07209_amd import exx
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    o = oracle_eval(cfg, orbs, phi)
+    print(f"[mixed tol={tol}] E gpu={g['E']:.15g} oracle={o['E']:.15g} dE={g['E'] - o['E']:.3e} "
+          f"iters max={g['stats']['cg_iter_max']} updates max={g['stats']['refine_passes_max']}", flush=True)
+    assert g["stats"]["n_unconverged"] == 0
+    assert g["stats"]["max_rel_residual"] <= tol
+    assert abs(g["E"] - o["E"]) <= 1e-6 * cfg.n_orb / 4
+    assert rel1(g["sigma"], o["sigma"]) <= 1e-6
+    assert rel1(g["E"], o["E"]) <= (1e-8 if tol > 1e-11 else TOL_E)
+    assert rel1(g["sigma"], o["sigma"]) <= (1e-7 if tol > 1e-11 else TOL_S)
+    assert rel1(g["D"], o["D"]) <= (1e-7 if tol > 1e-11 else TOL_D)
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_mixed_precision_small_cell(n):
+    cfg = synth.custom(key=f"mixed-n{n}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=7, R_pair=7.0, R_PE=3.9,
+                       R_ME=5.3, l_max=5, stencil_n=n, cg_tol=1e-12, seed_index=50 + n)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    from paper_2011_07209_amd import exx
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    o = oracle_eval(cfg, orbs, phi)
+    assert g["stats"]["n_unconverged"] == 0
+    assert rel1(g["E"], o["E"]) <= TOL_E
+    assert rel1(g["sigma"], o["sigma"]) <= TOL_S
+    assert rel1(g["D"], o["D"]) <= TOL_D
+
+
+def test_mixed_precision_far_pair_with_vanishing_density():
+    """A pair whose density is ~1e-40 (below the FP32 normal range): the mixed
+    solve works in units of ||b||, so it converges like any other pair."""
+    cfg = synth.custom(key="far", cell=(24.0, 24.0, 24.0), grid=(96, 96, 96), n_orb=2, R_pair=10.0, R_PE=4.0,
+                       R_ME=5.0, l_max=4, stencil_n=3, cg_tol=1e-10)
+    orbs = synth.OrbitalSet(np.array([[7.05, 12.0, 12.0], [16.95, 12.0, 12.0]]), np.array([2.2, 2.0]),
+                            np.array([[0.1, 0.0, 0.2], [0.0, -0.2, 0.1]]))
+    phi = synth.fill_orbitals(cfg, orbs)
+    from paper_2011_07209_amd import exx
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    o = oracle_eval(cfg, orbs, phi)
+    assert len(o["pairs"]) == 3
+    assert g["stats"]["n_unconverged"] == 0, g["pairs"]
+    Eo = np.array([p.E for p in o["pairs"]])
+    assert abs(Eo[1]) < 1e-60      # the cross pair is vanishingly small
+    for k in range(3):
+        assert abs(g["pairs"]["E"][k] - Eo[k]) <= 1e-8 * abs(Eo[k])
