@@ -275,8 +275,12 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   }
   g.lds_cx = maxRg0 + n;
   g.lds_cy = maxRg1 + n;
-  g.lds_wx = 2 * g.lds_cx + 1;
+  g.lds_wx = kLdsWX;
   g.lds_wy = 2 * g.lds_cy + 1;
+  if (2 * g.lds_cx + 1 > kLdsWX) {
+    free_plan(P);
+    return fail(nullptr, EXX_EINVAL, "PE sphere too wide: need 2 (R_PE / spacing + n) + 1 <= 88 grid points");
+  }
   if (!solve_supported((int)std::min<long long>(P->max_cols, 1 << 30), 512)) {
     free_plan(P);
     return fail(nullptr, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");

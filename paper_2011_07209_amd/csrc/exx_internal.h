@@ -15,6 +15,10 @@ constexpr int kMaxL = 8;                       // l_max limit of the multipole e
 constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
 constexpr int kMaxClasses = 16;
 constexpr double kSlack = 1e-12;               // relative slack of sphere membership on |r|^2
+// Row stride of the LDS planes of the CG, a compile-time constant so that the
+// y-neighbour reads use immediate offsets.  It bounds the sphere:
+// 2 (R_PE / spacing + n) + 1 <= 88.
+constexpr int kLdsWX = 88;
 
 // Geometry and stencil constants, passed by value to every kernel.
 struct Geo {
@@ -33,7 +37,7 @@ struct Geo {
   int n;              // stencil half-width
   int l_max;
   int n_lm;
-  int lds_cx, lds_cy, lds_wx, lds_wy;   // LDS plane origin and width (max over classes)
+  int lds_cx, lds_cy, lds_wx, lds_wy;   // LDS plane origin and size (lds_wx = kLdsWX)
   double ylm_norm[kMaxLM];              // N_l0 for m == 0, sqrt(2) N_l|m| otherwise
 };
 

@@ -9,7 +9,7 @@
 // axis, then y, then x).  At plane z the columns with zr >= |z| are therefore
 // a prefix of that order, and the plane is stored as that prefix, planes in
 // ascending z.  A workgroup that assigns column c to a fixed thread then reads
-// every plane with consecutive addresses.
+// every plane with consecutive addresses from one per-plane base offset.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -58,7 +58,9 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   C.Zmax = C.Rg[2];
   for (int a = 0; a < 3; ++a) C.Wm[a] = 2 * (C.Rg[a] + n) + 1;
 
-  // columns
+  // columns, sorted by half-height descending (ties by angle about the z
+  // axis, then y, then x): at plane z the columns that reach it are a prefix
+  // of this order
   struct Col { int ox, oy, zr; double ang; };
   std::vector<Col> cols;
   for (int oy = -C.Rg[1]; oy <= C.Rg[1]; ++oy)
@@ -78,7 +80,7 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   C.cols.resize(cols.size());
   for (size_t c = 0; c < cols.size(); ++c) C.cols[c] = make_int4(cols[c].ox, cols[c].oy, cols[c].zr, 0);
 
-  // planes
+  // planes: plane z holds the prefix of columns that reach it
   C.plane_start.assign(2 * C.Zmax + 2, 0);
   long long acc = 0;
   for (int z = -C.Zmax; z <= C.Zmax; ++z) {
@@ -128,7 +130,7 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   // ME list: PE points in packed order, then the shell
   C.me_off.reserve((size_t)C.n_pe);
   for (int z = -C.Zmax; z <= C.Zmax; ++z) {
-    int nz = C.plane_start[z + C.Zmax + 1] - C.plane_start[z + C.Zmax];
+    const int nz = C.plane_start[z + C.Zmax + 1] - C.plane_start[z + C.Zmax];
     for (int c = 0; c < nz; ++c) C.me_off.push_back(make_short4((short)cols[c].ox, (short)cols[c].oy, (short)z, 0));
   }
   for (int oz = -K[2]; oz <= K[2]; ++oz)

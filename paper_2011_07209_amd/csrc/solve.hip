@@ -11,7 +11,7 @@ hipError_t solve_dispatch_n3(const SolveKArgs& a, bool mixed, int max_cols, int 
                              size_t lds, hipStream_t s, int* occ);
 
 size_t solve_lds_bytes(const Geo& g, int max_zmax) {
-  return (size_t)2 * g.lds_wx * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2) * sizeof(int);
+  return (size_t)2 * kLdsWX * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2) * sizeof(int);
 }
 
 long long solve_slot_bytes(bool mixed, long long sstride) {

@@ -58,12 +58,12 @@ struct SolveKArgs {
 // value, pl the LDS plane (values of the current plane, zero off the PE
 // sphere), wz the z window
 template <int NS, typename T>
-__device__ __forceinline__ T apply_point(const StencilT<T>& S, T ctr, const T* pl, int pos, int wx, const T* wz) {
+__device__ __forceinline__ T apply_point(const StencilT<T>& S, T ctr, const T* pl, int pos, const T* wz) {
   T sx = 0, sy = 0, sz = 0;
 #pragma unroll
   for (int q = 1; q <= NS; ++q) {
     sx += S.w[q] * (pl[pos + q] + pl[pos - q]);
-    sy += S.w[q] * (pl[pos + q * wx] + pl[pos - q * wx]);
+    sy += S.w[q] * (pl[pos + q * kLdsWX] + pl[pos - q * kLdsWX]);
     sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
   }
   return -(S.diag * ctr + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
@@ -88,7 +88,7 @@ __device__ __forceinline__ void load_cols(const ClassDev& C, const SolveKArgs& a
       const int4 cc = C.cols[col];
       cl.zr[c] = cc.z;
       cl.col[c] = col;
-      cl.pos[c] = (cc.x + a.lds_cx) + a.lds_wx * (cc.y + a.lds_cy);
+      cl.pos[c] = (cc.x + a.lds_cx) + kLdsWX * (cc.y + a.lds_cy);
     }
   }
 }
@@ -100,7 +100,7 @@ __device__ __forceinline__ void load_cols(const ClassDev& C, const SolveKArgs& a
 // stored, q = A p is formed on the fly; accumulates p.q and r.r in FP64.
 template <int NS, int CPT, int PD, typename T>
 __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, const T* __restrict__ r,
-                          T* __restrict__ p, T beta, bool first, T* pl0, T* pl1, int wx, double& pq, double& rr) {
+                          T* __restrict__ p, T beta, bool first, T* pl0, T* pl1, double& pq, double& rr) {
   T win[CPT][2 * NS + 1];
   T qr[PD][CPT], qp[PD][CPT];   // raw r, p of planes z+NS+1 .. z+NS+PD
   pq = 0.0;
@@ -156,7 +156,7 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (EXX_VALID(c, z))
-        pq += (double)win[c][NS] * (double)apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+        pq += (double)win[c][NS] * (double)apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
     }
     const int zc = z + NS + 1;        // plane entering the window
 #pragma unroll
@@ -188,8 +188,7 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
 // it is written, by the same thread).
 template <int NS, int CPT, int PD, typename T>
 __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, T* x,
-                            const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1,
-                            int wx) {
+                            const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
   T win[CPT][2 * NS + 1];
   T qp[PD][CPT];           // p of planes z+NS+1 .. z+NS+PD
   T cx[CPT], cr[CPT];      // x, r of plane z
@@ -239,7 +238,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
     for (int c = 0; c < CPT; ++c) {
       if (EXX_VALID(c, z)) {
         const int idx = EXX_IDX(c, z);
-        const T q = apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+        const T q = apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
         const T rn = cr[c] - alpha * q;
         x[idx] = cx[c] + alpha * win[c][NS];
         r[idx] = rn;
@@ -270,7 +269,7 @@ template <int NS, int CPT, int PD>
 __device__ double cg_update(const StencilT<double>& S, const Cols<CPT>& cl, const int* pst, int Zmax,
                             double* __restrict__ x, const float* __restrict__ y, bool x_zero, bool y_zero,
                             const double* __restrict__ b, float* __restrict__ r, double ys, double rs, double* pl0,
-                            double* pl1, int wx) {
+                            double* pl1) {
   double win[CPT][2 * NS + 1];
   double qx[PD][CPT];
   float qy[PD][CPT];
@@ -325,7 +324,7 @@ __device__ double cg_update(const StencilT<double>& S, const Cols<CPT>& cl, cons
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (EXX_VALID(c, z)) {
-        const double rt = cb[c] - apply_point<NS, double>(S, win[c][NS], pl, cl.pos[c], wx, win[c]);
+        const double rt = cb[c] - apply_point<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
         r[EXX_IDX(c, z)] = (float)(rt * rs);
         acc += rt * rt;
       }
@@ -361,7 +360,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
   __shared__ double red[NT / 64];
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  const int plane = a.lds_wx * a.lds_wy;
+  const int plane = kLdsWX * a.lds_wy;
   double* pl0 = lds;
   double* pl1 = lds + plane;
   int* pst = reinterpret_cast<int*>(lds + 2 * plane);
@@ -390,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
     bool first = true;
     while (it < a.max_iter) {
       double pq_t, rr_t;
-      cg_pass_a<NS, CPT, PD, double>(a.S, cl, pst, Zmax, first ? x : r, p, beta, first, pl0, pl1, a.lds_wx, pq_t,
+      cg_pass_a<NS, CPT, PD, double>(a.S, cl, pst, Zmax, first ? x : r, p, beta, first, pl0, pl1, pq_t,
                                      rr_t);
       const double pq = block_sum(pq_t, red);
       if (first) {
@@ -405,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       }
       const double alpha = rr / pq;
       const double rn = block_sum(cg_pass_b<NS, CPT, PD, double>(a.S, cl, pst, Zmax, x, first ? x : r, r, p, alpha,
-                                                                 first, pl0, pl1, a.lds_wx),
+                                                                 first, pl0, pl1),
                                   red);
       ++it;
       first = false;
@@ -441,7 +440,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   __shared__ double red[NT / 64];
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  const int plane = a.lds_wx * a.lds_wy;
+  const int plane = kLdsWX * a.lds_wy;
   double* pl0 = lds;
   double* pl1 = lds + plane;
   float* fl0 = reinterpret_cast<float*>(lds);
@@ -489,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     bool first = true, x_zero = true, y_zero = true, conv = !(bnorm > 0.0);
     while (!conv && it < a.max_iter) {
       double pq_t, rr_t;
-      cg_pass_a<NS, CPT, PD, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, a.lds_wx, pq_t, rr_t);
+      cg_pass_a<NS, CPT, PD, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
       const double pq = block_sum(pq_t, red);
       if (!(pq > 0.0) || !(pq < INFINITY)) {
         it = a.max_iter;
@@ -498,7 +497,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       }
       const double alpha = rr / pq;
       double rn = block_sum(cg_pass_b<NS, CPT, PD, float>(S32, cl, pst, Zmax, y, r, r, p, (float)alpha, y_zero, fl0,
-                                                          fl1, a.lds_wx),
+                                                          fl1),
                             red);
       ++it;
       first = false;
@@ -514,7 +513,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
         rr_true = block_sum(cg_update<NS, CPT, PD>(a.S, cl, pst, Zmax, x, y, x_zero, y_zero, bx, r, bnorm, inv_b,
-                                                   pl0, pl1, a.lds_wx),
+                                                   pl0, pl1),
                             red);
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
@@ -566,7 +565,7 @@ hipError_t solve_instance(const SolveKArgs& a, bool mixed, int groups, size_t ld
 // to 4 columns each, 512 threads up to 8.
 template <int NS, int NT, int PD>
 hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_t lds, hipStream_t s, int* occ) {
-  if (NT == 1024) {
+  if constexpr (NT == 1024) {
     switch (cpt) {
       case 1: return solve_instance<NS, 1, NT, PD>(a, mixed, groups, lds, s, occ);
       case 2: return solve_instance<NS, 2, NT, PD>(a, mixed, groups, lds, s, occ);
@@ -574,7 +573,7 @@ hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_
       case 4: return solve_instance<NS, 4, NT, PD>(a, mixed, groups, lds, s, occ);
       default: return hipErrorInvalidValue;
     }
-  }
+  } else {
   switch (cpt) {
     case 1:
     case 2: return solve_instance<NS, 2, NT, PD>(a, mixed, groups, lds, s, occ);
@@ -585,6 +584,7 @@ hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_
     case 7:
     case 8: return solve_instance<NS, 8, NT, PD>(a, mixed, groups, lds, s, occ);
     default: return hipErrorInvalidValue;
+  }
   }
 }
 

@@ -171,3 +171,22 @@ def test_mixed_precision_far_pair_with_vanishing_density():
     assert abs(Eo[1]) < 1e-60      # the cross pair is vanishingly small
     for k in range(3):
         assert abs(g["pairs"]["E"][k] - Eo[k]) <= 1e-8 * abs(Eo[k])
+
+
+@pytest.mark.parametrize("threads,depth", [(1024, 1), (1024, 2), (512, 1), (512, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_every_solve_variant(threads, depth, prec):
+    """Each CG variant the autotuner may pick (workgroup size x load depth, in
+    both precisions) gives the oracle's result."""
+    cfg = synth.custom(key=f"var-{threads}-{depth}-{prec}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=5,
+                       R_pair=7.0, R_PE=3.9, R_ME=5.3, l_max=4, stencil_n=3, cg_tol=1e-12, seed_index=60)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    from paper_2011_07209_amd import exx
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64,
+                 solve_threads=threads, solve_depth=depth)
+    o = oracle_eval(cfg, orbs, phi)
+    assert g["stats"]["n_unconverged"] == 0
+    assert rel1(g["E"], o["E"]) <= TOL_E
+    assert rel1(g["sigma"], o["sigma"]) <= TOL_S
+    assert rel1(g["D"], o["D"]) <= TOL_D
