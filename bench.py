@@ -81,7 +81,7 @@ def run_precision(exx, torch, cfg, tensors, precision, steps, warmup):
     D = torch.empty_like(orb_t)
     prec = exx.EXX_PREC_MIXED if precision == "mixed" else exx.EXX_PREC_FP64
     plan = exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, stencil_n=cfg.stencil_n,
-                    cg_tol=cfg.cg_tol, precision=prec, workspace_gb=64.0)
+                    cg_tol=cfg.cg_tol, precision=prec, workspace_gb=64.0, autotune=1 if warmup > 0 else 0)
     geo = plan.geometry()
     for w in range(warmup):
         plan.eval(orb_t, cen_t, E, D, S)
@@ -108,6 +108,7 @@ def run_precision(exx, torch, cfg, tensors, precision, steps, warmup):
         "value": n_pairs / (ms / 1000.0), "ms_per_step": ms, "n_pairs": n_pairs, "n_pe": geo["n_pe"],
         "cg_iters_mean": s1["cg_iter_sum"] / max(1, n_pairs), "cg_iters_max": s1["cg_iter_max"],
         "updates_max": s1["refine_passes_max"], "max_rel_residual": s1["max_rel_residual"],
+        "solve_variant": {"threads": s1["solve_threads"], "depth": s1["solve_depth"], "tune_ms": s1["tune_ms"]},
         "roofline": {"bound": "hbm", "kernel": "k_solve_mixed" if precision == "mixed" else "k_solve",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(precision), "alg_bytes_per_launch": alg / max(launches, 1),
@@ -182,7 +183,7 @@ def main(argv=None):
 
     def summary(x):
         return {k: x[k] for k in ("value", "ms_per_step", "cg_iters_mean", "cg_iters_max", "updates_max",
-                                  "max_rel_residual", "roofline")}
+                                  "max_rel_residual", "solve_variant", "roofline")}
 
     out = {
         "metric": METRIC,

@@ -133,6 +133,9 @@ typedef struct {
   double solve_ms_total;       /* their summed device time (HIP events)          */
   double cg_alg_bytes_total;   /* their summed algorithmic CG bytes              */
   double eval_ms_total;
+  int solve_threads;           /* CG variant in use: workgroup size ...            */
+  int solve_depth;             /* ... and load depth (chosen by the autotuner)     */
+  double tune_ms;              /* time spent by the autotuner (first eval only)    */
 } exx_stats;
 
 /* Statistics of the last exx_eval (synchronizes the bound stream).  Returns

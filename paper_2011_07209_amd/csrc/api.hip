@@ -155,6 +155,74 @@ exx_status select_solve(exx_plan_t P, int threads, int depth) {
   return EXX_OK;
 }
 
+exx_status ensure_slots(exx_plan_t P) {
+  if (P->slot_ws) return EXX_OK;
+  char* sw = nullptr;
+  const long long sb = solve_slot_bytes(P->opt.precision == EXX_PREC_MIXED, P->max_pe);
+  if (dev_alloc(P, &sw, (size_t)P->n_slots * sb, "CG vectors")) return EXX_ENOMEM;
+  P->slot_ws = sw;
+  return EXX_OK;
+}
+
+// Autotuner: times every supported CG variant (workgroup size x load depth)
+// on the first pairs of the batch whose densities and boundary values are in
+// the workspace, and keeps the fastest.  Right-hand sides are rebuilt before
+// each trial (the solve overwrites them) and once more by the caller.
+exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hipStream_t s) {
+  static const int cand[4][2] = {{1024, 1}, {1024, 2}, {512, 1}, {512, 2}};
+  hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
+  EXX_HIP(P, hipEventCreate(&e0));
+  EXX_HIP(P, hipEventCreate(&e1));
+  EXX_HIP(P, hipEventCreate(&t0));
+  EXX_HIP(P, hipEventCreate(&t1));
+  EXX_HIP(P, hipEventRecord(t0, s));
+  float best = 1e30f;
+  int bt = P->solve_threads, bd = P->solve_depth;
+  for (const auto& c : cand) {
+    if (!solve_supported((int)P->max_cols, c[0])) continue;
+    const bool mixed = P->opt.precision == EXX_PREC_MIXED;
+    const int per_cu = solve_groups_per_cu(P->geo, (int)P->max_cols, P->max_zmax, mixed, c[0], c[1]);
+    if (per_cu < 1) continue;
+    exx_status st = select_solve(P, c[0], c[1]);
+    if (st != EXX_OK) return st;
+    st = ensure_slots(P);
+    if (st != EXX_OK) return st;
+    const long long sample = std::min<long long>(nb, 2LL * P->n_slots);
+    SolveArgs a = base;
+    a.npair = sample;
+    a.slot_ws = P->slot_ws;
+    a.threads = c[0];
+    a.depth = c[1];
+    EXX_HIP(P, launch_rhs(P->geo, P->class_dev, P->pairs, P->order, a.p0, sample, P->max_pe, P->rho_ws, P->bx_ws,
+                          P->max_pe, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+    EXX_HIP(P, launch_set_int(P->queue, 0, s));
+    EXX_HIP(P, hipEventRecord(e0, s));
+    EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, (int)std::min<long long>(P->n_slots, sample), s));
+    EXX_HIP(P, hipEventRecord(e1, s));
+    EXX_HIP(P, hipEventSynchronize(e1));
+    float ms = 0;
+    EXX_HIP(P, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bt = c[0];
+      bd = c[1];
+    }
+  }
+  EXX_HIP(P, hipEventRecord(t1, s));
+  EXX_HIP(P, hipEventSynchronize(t1));
+  float tms = 0;
+  EXX_HIP(P, hipEventElapsedTime(&tms, t0, t1));
+  P->tune_ms = tms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  exx_status st = select_solve(P, bt, bd);
+  if (st != EXX_OK) return st;
+  P->tuned = true;
+  return ensure_slots(P);
+}
+
 exx_status record_solve_event(exx_plan_t P, hipStream_t s) {
   if (P->solve_ev_used >= (int)P->solve_ev.size()) {
     hipEvent_t e = nullptr;
@@ -360,9 +428,10 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
   P->n_cus = std::max(1, cus);
   {
+    // defaults measured on MI355X: FP64 1024 x 1, mixed 1024 x 2
     int th = opt.solve_threads > 0 ? opt.solve_threads : 1024;
     if (!solve_supported((int)P->max_cols, th)) th = 512;
-    const int dp = opt.solve_depth > 0 ? opt.solve_depth : 1;
+    const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
     exx_status st = select_solve(P, th, dp);
     if (st != EXX_OK) {
       std::string m = P->err;
@@ -458,11 +527,9 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
       return EXX_ENOMEM;
     P->batch_cap = batch;
   }
-  if (!P->slot_ws) {
-    char* sw = nullptr;
-    const long long sb = solve_slot_bytes(P->opt.precision == EXX_PREC_MIXED, P->max_pe);
-    if (dev_alloc(P, &sw, (size_t)P->n_slots * sb, "CG vectors")) return EXX_ENOMEM;
-    P->slot_ws = sw;
+  {
+    exx_status st = ensure_slots(P);
+    if (st != EXX_OK) return st;
   }
 
   if (D_xx) EXX_HIP(P, launch_zero(D_xx, (size_t)n_orb * g.ngrid * (dt == EXX_F64 ? 8 : 4), s));
@@ -473,9 +540,6 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
                                      P->max_pe, P->Q_ws, s));
     EXX_HIP(P, launch_boundary(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_halo, P->Q_ws, P->halo_ws,
                                std::max<long long>(P->max_halo, 1), s));
-    EXX_HIP(P, launch_rhs(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_pe, P->rho_ws, P->bx_ws, P->max_pe,
-                          P->halo_ws, std::max<long long>(P->max_halo, 1), s));
-    EXX_HIP(P, launch_set_int(P->queue, 0, s));
     SolveArgs a;
     a.g = g;
     a.cls = P->class_dev;
@@ -497,6 +561,16 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.depth = P->solve_depth;
     a.tol = P->opt.cg_tol;
     a.max_iter = P->opt.cg_max_iter;
+    if (P->opt.autotune && !P->tuned) {
+      exx_status st = autotune_solve(P, a, nb, s);
+      if (st != EXX_OK) return st;
+      a.slot_ws = P->slot_ws;
+      a.threads = P->solve_threads;
+      a.depth = P->solve_depth;
+    }
+    EXX_HIP(P, launch_rhs(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_pe, P->rho_ws, P->bx_ws, P->max_pe,
+                          P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+    EXX_HIP(P, launch_set_int(P->queue, 0, s));
     const int groups = (int)std::min<long long>(P->n_slots, nb);
     { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, groups, s));
@@ -562,6 +636,9 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->solve_ms_total = P->solve_ms_total;
   out->cg_alg_bytes_total = P->alg_bytes_total;
   out->eval_ms_total = P->eval_ms_total;
+  out->solve_threads = P->solve_threads;
+  out->solve_depth = P->solve_depth;
+  out->tune_ms = P->tune_ms;
   return out->n_unconverged > 0 ? fail(P, EXX_ENOCONV, "CG did not converge for some pairs") : EXX_OK;
 }
 

@@ -124,6 +124,7 @@ struct exx_plan_s {
   int n_cus = 1;
   int solve_threads = 1024, solve_depth = 1;   // CG variant in use
   bool tuned = false;
+  double tune_ms = 0;
   void* slot_ws = nullptr;     // [slots] CG vectors: FP64 r, p; mixed: FP64 x, FP32 r, p, y
   int* queue = nullptr;
   double* stats_dev = nullptr;     // (iter_sum, iter_max, n_unconverged, max_res, n_pairs)

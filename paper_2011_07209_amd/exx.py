@@ -66,6 +66,9 @@ class Stats(ctypes.Structure):
         ("solve_ms_total", ctypes.c_double),
         ("cg_alg_bytes_total", ctypes.c_double),
         ("eval_ms_total", ctypes.c_double),
+        ("solve_threads", ctypes.c_int),
+        ("solve_depth", ctypes.c_int),
+        ("tune_ms", ctypes.c_double),
     ]
 
     def as_dict(self):

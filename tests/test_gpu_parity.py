@@ -190,3 +190,21 @@ def test_every_solve_variant(threads, depth, prec):
     assert rel1(g["E"], o["E"]) <= TOL_E
     assert rel1(g["sigma"], o["sigma"]) <= TOL_S
     assert rel1(g["D"], o["D"]) <= TOL_D
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotuned_solve(prec):
+    """With autotune on, the first evaluation times the CG variants on a sample
+    of its pairs, keeps the fastest, and still returns the oracle's result."""
+    cfg = dataclasses.replace(synth.CONFIGS["tiny16"], cg_tol=1e-12)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    from paper_2011_07209_amd import exx
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64,
+                 autotune=1)
+    o = oracle_eval(cfg, orbs, phi)
+    assert g["stats"]["solve_threads"] in (512, 1024) and g["stats"]["solve_depth"] in (1, 2)
+    assert g["stats"]["tune_ms"] > 0
+    assert rel1(g["E"], o["E"]) <= TOL_E
+    assert rel1(g["sigma"], o["sigma"]) <= TOL_S
+    assert rel1(g["D"], o["D"]) <= TOL_D
