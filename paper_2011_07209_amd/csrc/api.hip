@@ -85,6 +85,20 @@ void harmonic_norms(int L, double* out) {
     }
 }
 
+// bfloat16 of a finite float, rounded to nearest even
+unsigned short bf16_rne(float f) {
+  unsigned u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+double bf16_value(unsigned short h) {
+  const unsigned u = (unsigned)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
 template <typename T>
 exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
   if (*p) (void)hipFree(*p);
@@ -101,7 +115,8 @@ exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->slot_ws, P->queue, P->stats_dev};
+                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->rho_scale, P->slot_ws, P->queue,
+                  P->stats_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
@@ -364,12 +379,18 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   }
   // upload the class tables into one block
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const bool mixed = opt.precision == EXX_PREC_MIXED;
+  const int mom_rows = moment_rows(l_max);
+  auto mom_bytes = [&](const ClassHost& C) {
+    const size_t entries = (size_t)((C.n_pe + 15) / 16 * 16) * mom_rows;
+    return mixed ? 2 * align(entries * sizeof(unsigned short)) : align(entries * sizeof(double));
+  };
   size_t total = 0;
   for (const ClassHost& C : P->classes) {
     total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
              align(C.halo_off.size() * sizeof(short4)) + align(C.me_off.size() * sizeof(short4)) +
              align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
-             align(C.zr_map.size() * sizeof(int));
+             align(C.zr_map.size() * sizeof(int)) + mom_bytes(C);
   }
   if (hipMalloc(&P->class_block, total) != hipSuccess) {
     free_plan(P);
@@ -403,7 +424,24 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     D.halo_map = (const int*)put(C.halo_map.data(), C.halo_map.size() * sizeof(int));
     D.col_map = (const int*)put(C.col_map.data(), C.col_map.size() * sizeof(int));
     D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
-    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || !D.col_map || !D.zr_map) {
+    D.mom_rows = mom_rows;
+    std::vector<double> tab;
+    build_moment_table(C, g.d, l_max, mom_rows, &tab);
+    bool tab_ok;
+    if (mixed) {
+      std::vector<unsigned short> hi(tab.size()), lo(tab.size());
+      for (size_t e = 0; e < tab.size(); ++e) {
+        hi[e] = bf16_rne((float)tab[e]);
+        lo[e] = bf16_rne((float)(tab[e] - bf16_value(hi[e])));
+      }
+      D.mom_hi = (const unsigned short*)put(hi.data(), hi.size() * sizeof(unsigned short));
+      D.mom_lo = (const unsigned short*)put(lo.data(), lo.size() * sizeof(unsigned short));
+      tab_ok = D.mom_hi && D.mom_lo;
+    } else {
+      D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
+      tab_ok = D.mom_f64 != nullptr;
+    }
+    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || !D.col_map || !D.zr_map || !tab_ok) {
       free_plan(P);
       return fail(nullptr, EXX_EDEVICE, "upload of the subdomain tables failed");
     }
@@ -519,11 +557,13 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   const double budget = (P->opt.workspace_gb > 0 ? P->opt.workspace_gb : 24.0) * 1e9;
   long long batch = std::max<long long>(1, (long long)(budget / (8.0 * per_pair)));
   batch = std::min<long long>(batch, std::max<long long>(total, 1));
+  batch = std::min<long long>(batch, 65535);   // pair index on grid y of the per-point kernels
   if (batch > P->batch_cap) {
     if (dev_alloc(P, &P->rho_ws, (size_t)batch * P->max_pe, "pair densities") ||
         dev_alloc(P, &P->bx_ws, (size_t)batch * P->max_pe, "pair potentials") ||
         dev_alloc(P, &P->halo_ws, (size_t)batch * std::max<long long>(P->max_halo, 1), "boundary values") ||
-        dev_alloc(P, &P->Q_ws, (size_t)batch * kMaxLM, "moments"))
+        dev_alloc(P, &P->Q_ws, (size_t)batch * kMaxLM, "moments") ||
+        dev_alloc(P, &P->rho_scale, (size_t)batch, "density scales"))
       return EXX_ENOMEM;
     P->batch_cap = batch;
   }
@@ -536,8 +576,11 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   EXX_HIP(P, hipEventRecord(P->ev[1], s));
   for (long long p0 = 0; p0 < total; p0 += batch) {
     const long long nb = std::min(batch, total - p0);
-    EXX_HIP(P, launch_gather_moments(g, P->class_dev, P->pairs, P->order, p0, nb, orbitals, (int)dt, P->rho_ws,
-                                     P->max_pe, P->Q_ws, s));
+    EXX_HIP(P, launch_gather(g, P->class_dev, P->pairs, P->order, p0, nb, orbitals, (int)dt, P->rho_ws, P->max_pe,
+                             P->rho_scale, s));
+    EXX_HIP(P, launch_moments(g, P->class_dev, P->pair_count + 2 * n_orb + 1, ncls,
+                              P->opt.precision == EXX_PREC_MIXED, p0, nb, P->rho_ws, P->max_pe, P->rho_scale,
+                              P->Q_ws, s));
     EXX_HIP(P, launch_boundary(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_halo, P->Q_ws, P->halo_ws,
                                std::max<long long>(P->max_halo, 1), s));
     SolveArgs a;

@@ -33,4 +33,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Maximum over the workgroup; same contract as block_sum.
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s = fmax(s, red[w]);
+  __syncthreads();
+  return s;
+}
+
 }  // namespace exx

@@ -56,6 +56,13 @@ struct ClassDev {
   const int* halo_map;       // [Wm2][Wm1][Wm0] -> halo index or -1
   const int* col_map;        // [Wm1][Wm0] -> column index or -1
   const int* zr_map;         // [Wm1][Wm0] -> column half-height or -1
+  // moment table: unnormalised solid harmonics P_lm of the PE offsets, layout
+  // [k/4][row][4] over mom_rows rows and n_pe rounded up to 16 points (zeros
+  // beyond); FP64 for FP64 plans, split BF16 (hi, lo) for mixed plans
+  int mom_rows;
+  const double* mom_f64;
+  const unsigned short* mom_hi;
+  const unsigned short* mom_lo;
 };
 
 struct PairDev {
@@ -79,6 +86,10 @@ struct ClassHost {
 
 // Builds the tables of one class; returns an empty string or an error message.
 std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out);
+// Unnormalised solid harmonics P_lm(o d) of the class's PE points, laid out
+// [k/4][row][4] with rows >= (l_max + 1)^2 and n_pe rounded up to 16, zeros
+// in the padding.
+void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, std::vector<double>* out);
 
 }  // namespace exx
 
@@ -120,6 +131,7 @@ struct exx_plan_s {
   double* bx_ws = nullptr;     // [batch][max_pe] right-hand sides, then potentials
   double* halo_ws = nullptr;   // [batch][max_halo]
   double* Q_ws = nullptr;      // [batch][kMaxLM]
+  double* rho_scale = nullptr; // [batch] power-of-two scale of each pair density
   int n_slots = 0;
   int n_cus = 1;
   int solve_threads = 1024, solve_depth = 1;   // CG variant in use

@@ -20,9 +20,17 @@ hipError_t launch_pairlist(const Geo& g, const PairParams& pp, const double* cen
                            int* counts, PairDev* pairs, long long cap, hipStream_t s);
 hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order, hipStream_t s);
 
-hipError_t launch_gather_moments(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order,
-                                 long long p0, long long nb, const void* orb, int dt, double* rho_ws,
-                                 long long rstride, double* Q_ws, hipStream_t s);
+// rho_scale[b]: power of two at or above max |rho| of pair b (see k_gather)
+hipError_t launch_gather(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                         long long nb, const void* orb, int dt, double* rho_ws, long long rstride, double* rho_scale,
+                         hipStream_t s);
+// Rows of the moment tables: (l_max + 1)^2 padded to a multiple of 16.
+int moment_rows(int l_max);
+// Moments of the batch [pbeg, pbeg + nb) of the processing order; class_cnt
+// holds the per-class pair counts of the order (device).
+hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cnt, int ncls, bool mixed,
+                          long long pbeg, long long nb, const double* rho_ws, long long rstride,
+                          const double* rho_scale, double* Q_ws, hipStream_t s);
 hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
                            long long nb, long long max_halo, const double* Q_ws, double* halo_ws, long long hstride,
                            hipStream_t s);

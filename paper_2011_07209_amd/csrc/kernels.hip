@@ -1,14 +1,14 @@
-// gfx950 kernels of the EXX pair path.
+// gfx950 kernels of the EXX pair path (the CG itself is in solve_impl.h, the
+// moment contraction in moments.hip).
 //
 //   k_pair_count / k_pair_scan / k_pair_fill   unique pair list (Sec. III A Step II)
 //   k_pair_order                                processing order, largest spheres first
-//   k_gather_moments                            pair density on PE (Step III) and its
-//                                               multipole moments (Sec. I, eq. mepole)
+//   k_gather                                    pair density on PE (Step III)
 //   k_boundary                                  far-field values at the Dirichlet points
 //                                               (Sec. I, eq. me)
-//   k_solve                                     persistent CG on the PE sphere (eq. pe,
-//                                               axis stencil of eq. d2_1), then the
-//                                               pair's E_xx and sigma_xx (eq. exxGen_mlwf,
+//   k_rhs                                       CG right-hand side 4 pi rho plus the
+//                                               Dirichlet terms of eq. d2_1
+//   k_finalize                                  the pair's E_xx and sigma_xx (eq. exxGen_mlwf,
 //                                               eq. sxx_working with eq. d1_1)
 //   k_dscatter                                  D^i += v phi_j, D^j += v phi_i on the ME
 //                                               sphere (Sec. II B 2, eq. Dxx)
@@ -19,78 +19,11 @@
 
 #include "device_common.h"
 #include "exx_launch.h"
+#include "harmonics.h"
 
 namespace exx {
 
 namespace {
-
-// Regular solid harmonics R_lm(r) = |r|^l S_lm(rhat) with real orthonormal S
-// (no Condon-Shortley phase), generated as polynomials in x, y, z:
-//   (x + i y)^m gives the azimuthal factor,
-//   P_mm = (2m-1)!!,  P_{m+1,m} = (2m+1) z P_mm,
-//   (l-m) P_lm = (2l-1) z P_{l-1,m} - (l+m-1) |r|^2 P_{l-2,m},
-// so that R_lm = norm_lm P_lm Re/Im (x + i y)^m.  sink(l, index, value) receives
-// each of the (L+1)^2 values once.
-template <int L, typename F>
-__device__ __forceinline__ void solid_harmonics(double x, double y, double z, const double* norm, F&& sink) {
-  const double r2 = x * x + y * y + z * z;
-  double cm = 1.0, sm = 0.0, pmm = 1.0;
-#pragma unroll
-  for (int m = 0; m <= L; ++m) {
-    double p0 = pmm, p1 = 0.0;
-    if (m == 0) {
-      sink(0, 0, norm[0] * p0);
-    } else {
-      sink(m, m * m + 2 * m, norm[m * m + 2 * m] * p0 * cm);
-      sink(m, m * m, norm[m * m] * p0 * sm);
-    }
-    if (m < L) {
-      p1 = (2.0 * m + 1.0) * z * pmm;
-      const int l = m + 1;
-      if (m == 0) {
-        sink(l, l * l + l, norm[l * l + l] * p1);
-      } else {
-        sink(l, l * l + l + m, norm[l * l + l + m] * p1 * cm);
-        sink(l, l * l + l - m, norm[l * l + l - m] * p1 * sm);
-      }
-    }
-#pragma unroll
-    for (int l = m + 2; l <= L; ++l) {
-      const double p2 = ((2.0 * l - 1.0) * z * p1 - (l + m - 1.0) * r2 * p0) * (1.0 / (double)(l - m));
-      if (m == 0) {
-        sink(l, l * l + l, norm[l * l + l] * p2);
-      } else {
-        sink(l, l * l + l + m, norm[l * l + l + m] * p2 * cm);
-        sink(l, l * l + l - m, norm[l * l + l - m] * p2 * sm);
-      }
-      p0 = p1;
-      p1 = p2;
-    }
-    const double cn = x * cm - y * sm;
-    sm = x * sm + y * cm;
-    cm = cn;
-    pmm *= (2.0 * m + 1.0);
-  }
-}
-
-// Far-field potential 4 pi sum_lm Q_lm R_lm(r) / ((2l+1) |r|^(2l+1))
-template <int L>
-__device__ __forceinline__ double far_field(double x, double y, double z, const double* norm, const double* Q) {
-  double s[L + 1];
-#pragma unroll
-  for (int l = 0; l <= L; ++l) s[l] = 0.0;
-  solid_harmonics<L>(x, y, z, norm, [&](int l, int idx, double v) { s[l] += Q[idx] * v; });
-  const double r2 = x * x + y * y + z * z;
-  const double rinv = 1.0 / sqrt(r2);
-  const double rinv2 = rinv * rinv;
-  double rp = rinv, v = 0.0;
-#pragma unroll
-  for (int l = 0; l <= L; ++l) {
-    v += s[l] * rp * (4.0 * kPi / (2.0 * l + 1.0));
-    rp *= rinv2;
-  }
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // pair list
@@ -230,24 +163,23 @@ __global__ __launch_bounds__(1024) void k_pair_order(const PairDev* __restrict__
 template <typename TO>
 __device__ __forceinline__ double ldv(const TO* p, long long i) { return (double)p[i]; }
 
-template <int L, typename TO>
-__global__ __launch_bounds__(256) void k_gather_moments(Geo g, const ClassDev* __restrict__ cls,
-                                                        const PairDev* __restrict__ pairs,
-                                                        const int* __restrict__ order, long long p0,
-                                                        const TO* __restrict__ orb, double* __restrict__ rho_ws,
-                                                        long long rstride, double* __restrict__ Q_ws) {
-  constexpr int NLM = (L + 1) * (L + 1);
-  __shared__ double red[4][NLM];
+// One workgroup per pair: rho on the PE points in packed order, and the
+// power of two 2^e with max |rho| in [2^(e-1), 2^e) (1 for a zero density),
+// by which the mixed moment path divides rho before rounding it to BF16.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_gather(Geo g, const ClassDev* __restrict__ cls,
+                                                const PairDev* __restrict__ pairs, const int* __restrict__ order,
+                                                long long p0, const TO* __restrict__ orb, double* __restrict__ rho_ws,
+                                                long long rstride, double* __restrict__ rho_scale) {
+  __shared__ double red[4];
   const int b = blockIdx.x;
   const PairDev P = pairs[order[p0 + b]];
   const ClassDev& C = cls[P.cls];
   const TO* phi_i = orb + (long long)P.i * g.ngrid;
   const TO* phi_j = orb + (long long)P.j * g.ngrid;
   double* rho = rho_ws + (long long)b * rstride;
-  double acc[NLM];
-#pragma unroll
-  for (int k = 0; k < NLM; ++k) acc[k] = 0.0;
   const long long npe = C.n_pe;
+  double amax = 0.0;
   for (long long k = threadIdx.x; k < npe; k += blockDim.x) {
     const short4 o = C.me_off[k];
     const int gx = wrapi(P.c[0] + o.x, g.N[0]);
@@ -256,20 +188,13 @@ __global__ __launch_bounds__(256) void k_gather_moments(Geo g, const ClassDev* _
     const long long gi = gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
     const double r = ldv(phi_i, gi) * ldv(phi_j, gi);
     rho[k] = r;
-    solid_harmonics<L>(o.x * g.d[0], o.y * g.d[1], o.z * g.d[2], g.ylm_norm,
-                       [&](int, int idx, double v) { acc[idx] += v * r; });
+    amax = fmax(amax, fabs(r));
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NLM; ++k) {
-    const double v = wave_sum(acc[k]);
-    if (lane == 0) red[wave][k] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NLM) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
-    Q_ws[(long long)b * kMaxLM + threadIdx.x] = g.dV * s;
+  amax = block_max(amax, red);
+  if (threadIdx.x == 0) {
+    int e = 0;
+    if (amax > 0.0) (void)frexp(amax, &e);
+    rho_scale[b] = ldexp(1.0, e);
   }
 }
 
@@ -527,17 +452,16 @@ hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int 
     default: return hipErrorInvalidValue;            \
   }
 
-hipError_t launch_gather_moments(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order,
-                                 long long p0, long long nb, const void* orb, int dt, double* rho_ws,
-                                 long long rstride, double* Q_ws, hipStream_t s) {
+hipError_t launch_gather(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
+                         long long nb, const void* orb, int dt, double* rho_ws, long long rstride, double* rho_scale,
+                         hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  if (dt == EXX_F64) {
-    EXX_L_DISPATCH(g.l_max, (k_gather_moments<LL, double><<<(unsigned)nb, 256, 0, s>>>(
-                                g, cls, pairs, order, p0, (const double*)orb, rho_ws, rstride, Q_ws)));
-  } else {
-    EXX_L_DISPATCH(g.l_max, (k_gather_moments<LL, float><<<(unsigned)nb, 256, 0, s>>>(
-                                g, cls, pairs, order, p0, (const float*)orb, rho_ws, rstride, Q_ws)));
-  }
+  if (dt == EXX_F64)
+    k_gather<double><<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, (const double*)orb, rho_ws, rstride,
+                                                  rho_scale);
+  else
+    k_gather<float><<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, (const float*)orb, rho_ws, rstride,
+                                                 rho_scale);
   return hipGetLastError();
 }
 

@@ -2,7 +2,12 @@
 same seeded inputs.  Bar for the plain FP64 path: relative 1-norm error
 (eq. error_exx / error_sxx form) <= 1e-9 on E_xx and <= 1e-8 on D_xx and
 sigma_xx; both sides solve to ||r|| <= 1e-12 ||b|| so that the CG stopping
-point does not dominate the comparison."""
+point does not dominate the comparison.
+
+Bar for the mixed path (FP32 CG, split-BF16 moments): |dE_xx| <= 1e-6 Ha per
+molecule-equivalent (4 orbitals), sigma_xx and D_xx within 1e-6 relative.
+The FP64 bars do not apply there: the moments carry the split-BF16 product
+error (about 2^-17 relative per term)."""
 import dataclasses
 
 import numpy as np
@@ -15,6 +20,17 @@ from gpu_util import gpu_eval, oracle_eval, rel1, subset_config
 pytestmark = pytest.mark.gpu
 
 TOL_E, TOL_D, TOL_S = 1e-9, 1e-8, 1e-8
+MIXED_E_PER_MOLECULE, MIXED_D, MIXED_S = 1e-6, 1e-6, 1e-6
+
+
+def _check_mixed(g, o, n_orb):
+    dE = g["E"] - o["E"]
+    print(f"  mixed: dE={dE:.3e} Ha ({dE / (n_orb / 4):.3e} per molecule-eq) "
+          f"sigma rel={rel1(g['sigma'], o['sigma']):.3e} D rel={rel1(g['D'], o['D']):.3e}", flush=True)
+    assert g["stats"]["n_unconverged"] == 0
+    assert abs(dE) <= MIXED_E_PER_MOLECULE * n_orb / 4
+    assert rel1(g["sigma"], o["sigma"]) <= MIXED_S
+    assert rel1(g["D"], o["D"]) <= MIXED_D
 
 
 def _compare(cfg, orbs, phi, want_D=True, **opt):
@@ -118,25 +134,18 @@ def test_repeat_is_bitwise_deterministic_for_E_and_sigma():
 
 @pytest.mark.parametrize("tol", [1e-10, 1e-12])
 def test_mixed_precision_tiny16(tol):
-    """Mixed path against the FP64 oracle.  Targets: |dE| <= 1e-6 Ha per
-    molecule-equivalent (4 orbitals), sigma within 1e-6 relative.  Because the
-    stop test is on the FP64 true residual, the FP64 bars hold as well."""
+    """Mixed path against the FP64 oracle, at two CG tolerances: the reliable
+    updates and the FP64 true-residual stop reach either one."""
     cfg = dataclasses.replace(synth.CONFIGS["tiny16"], cg_tol=tol)
     orbs = synth.make_orbitals(cfg)
     phi = synth.fill_orbitals(cfg, orbs)
-    import torch
     from paper_2011_07209_amd import exx
     g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
     o = oracle_eval(cfg, orbs, phi)
-    print(f"[mixed tol={tol}] E gpu={g['E']:.15g} oracle={o['E']:.15g} dE={g['E'] - o['E']:.3e} "
+    print(f"[mixed tol={tol}] E gpu={g['E']:.15g} oracle={o['E']:.15g} "
           f"iters max={g['stats']['cg_iter_max']} updates max={g['stats']['refine_passes_max']}", flush=True)
-    assert g["stats"]["n_unconverged"] == 0
     assert g["stats"]["max_rel_residual"] <= tol
-    assert abs(g["E"] - o["E"]) <= 1e-6 * cfg.n_orb / 4
-    assert rel1(g["sigma"], o["sigma"]) <= 1e-6
-    assert rel1(g["E"], o["E"]) <= (1e-8 if tol > 1e-11 else TOL_E)
-    assert rel1(g["sigma"], o["sigma"]) <= (1e-7 if tol > 1e-11 else TOL_S)
-    assert rel1(g["D"], o["D"]) <= (1e-7 if tol > 1e-11 else TOL_D)
+    _check_mixed(g, o, cfg.n_orb)
 
 
 @pytest.mark.parametrize("n", [1, 3])
@@ -148,15 +157,13 @@ def test_mixed_precision_small_cell(n):
     from paper_2011_07209_amd import exx
     g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
     o = oracle_eval(cfg, orbs, phi)
-    assert g["stats"]["n_unconverged"] == 0
-    assert rel1(g["E"], o["E"]) <= TOL_E
-    assert rel1(g["sigma"], o["sigma"]) <= TOL_S
-    assert rel1(g["D"], o["D"]) <= TOL_D
+    _check_mixed(g, o, cfg.n_orb)
 
 
 def test_mixed_precision_far_pair_with_vanishing_density():
     """A pair whose density is ~1e-40 (below the FP32 normal range): the mixed
-    solve works in units of ||b||, so it converges like any other pair."""
+    solve works in units of ||b|| and the BF16 moments in units of the pair's
+    power-of-two density scale, so it comes out like any other pair."""
     cfg = synth.custom(key="far", cell=(24.0, 24.0, 24.0), grid=(96, 96, 96), n_orb=2, R_pair=10.0, R_PE=4.0,
                        R_ME=5.0, l_max=4, stencil_n=3, cg_tol=1e-10)
     orbs = synth.OrbitalSet(np.array([[7.05, 12.0, 12.0], [16.95, 12.0, 12.0]]), np.array([2.2, 2.0]),
@@ -170,7 +177,7 @@ def test_mixed_precision_far_pair_with_vanishing_density():
     Eo = np.array([p.E for p in o["pairs"]])
     assert abs(Eo[1]) < 1e-60      # the cross pair is vanishingly small
     for k in range(3):
-        assert abs(g["pairs"]["E"][k] - Eo[k]) <= 1e-8 * abs(Eo[k])
+        assert abs(g["pairs"]["E"][k] - Eo[k]) <= 1e-7 * abs(Eo[k]), (k, g["pairs"]["E"][k], Eo[k])
 
 
 @pytest.mark.parametrize("threads,depth", [(1024, 1), (1024, 2), (512, 1), (512, 2)])
@@ -186,6 +193,9 @@ def test_every_solve_variant(threads, depth, prec):
     g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64,
                  solve_threads=threads, solve_depth=depth)
     o = oracle_eval(cfg, orbs, phi)
+    if prec == "mixed":
+        _check_mixed(g, o, cfg.n_orb)
+        return
     assert g["stats"]["n_unconverged"] == 0
     assert rel1(g["E"], o["E"]) <= TOL_E
     assert rel1(g["sigma"], o["sigma"]) <= TOL_S
@@ -205,6 +215,9 @@ def test_autotuned_solve(prec):
     o = oracle_eval(cfg, orbs, phi)
     assert g["stats"]["solve_threads"] in (512, 1024) and g["stats"]["solve_depth"] in (1, 2)
     assert g["stats"]["tune_ms"] > 0
+    if prec == "mixed":
+        _check_mixed(g, o, cfg.n_orb)
+        return
     assert rel1(g["E"], o["E"]) <= TOL_E
     assert rel1(g["sigma"], o["sigma"]) <= TOL_S
     assert rel1(g["D"], o["D"]) <= TOL_D
