@@ -30,7 +30,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "EXX pair Poisson solves/s + EXX eval time, mixed vs FP64 at 1e-6 tol"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_traffic.json")
-KERNEL_SOURCES = ["paper_2011_07209_amd/csrc/kernels.hip", "paper_2011_07209_amd/csrc/api.hip",
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "mixed": 2500.0}   # dense FP64 and BF16 matrix peaks
+# sources of the CG kernel, its launch shape and its data layout: the stored
+# counter traffic is used only while these are unchanged
+KERNEL_SOURCES = ["paper_2011_07209_amd/csrc/solve_impl.h", "paper_2011_07209_amd/csrc/solve.hip",
+                  "paper_2011_07209_amd/csrc/solve_n1.hip", "paper_2011_07209_amd/csrc/solve_n2.hip",
+                  "paper_2011_07209_amd/csrc/solve_n3.hip", "paper_2011_07209_amd/csrc/exx_internal.h",
                   "paper_2011_07209_amd/csrc/plan_geometry.cpp"]
 
 
@@ -104,6 +109,18 @@ def run_precision(exx, torch, cfg, tensors, precision, steps, warmup):
     alg = s1["cg_alg_bytes_total"] - s0["cg_alg_bytes_total"]
     achieved = (alg / max(launches, 1)) / (solve_ms / max(launches, 1) / 1000.0) / 1e9 if solve_ms > 0 else 0.0
     n_pairs = s1["n_pairs"]
+    # moment contraction of the last timed evaluation: executed MFMA flops
+    # (padded rows and points, three products in the mixed path) and the
+    # algorithmic 2 N_lm N_PE per pair, over the device time of its launches
+    mom_s = s1["moment_ms"] / 1000.0
+    mfma = s1["moment_mfma_flops"] / mom_s / 1e12 if mom_s > 0 else 0.0
+    alg_tf = s1["moment_flops"] / mom_s / 1e12 if mom_s > 0 else 0.0
+    rho_gbs = 8.0 * s1["moment_flops"] / (2.0 * (cfg.l_max + 1) ** 2) / mom_s / 1e9 if mom_s > 0 else 0.0
+    peak = MFMA_PEAK_TFLOPS[precision]
+    moments = {"bound": "mfma", "kernel": "k_moments_bf16" if precision == "mixed" else "k_moments_f64",
+               "achieved": mfma, "peak": peak, "unit": "TFLOP/s", "frac": mfma / peak,
+               "algorithmic_tflops": alg_tf, "algorithmic_frac": alg_tf / peak,
+               "density_read_gbs": rho_gbs, "launch_ms": s1["moment_ms"]}
     return {
         "value": n_pairs / (ms / 1000.0), "ms_per_step": ms, "n_pairs": n_pairs, "n_pe": geo["n_pe"],
         "cg_iters_mean": s1["cg_iter_sum"] / max(1, n_pairs), "cg_iters_max": s1["cg_iter_max"],
@@ -113,6 +130,7 @@ def run_precision(exx, torch, cfg, tensors, precision, steps, warmup):
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(precision), "alg_bytes_per_launch": alg / max(launches, 1),
                      "launch_ms": solve_ms / max(launches, 1)},
+        "moments_roofline": moments,
         "E": E.item(), "sigma": S.cpu().numpy().reshape(3, 3, order="F"), "D": D,
     }
 
@@ -183,7 +201,7 @@ def main(argv=None):
 
     def summary(x):
         return {k: x[k] for k in ("value", "ms_per_step", "cg_iters_mean", "cg_iters_max", "updates_max",
-                                  "max_rel_residual", "solve_variant", "roofline")}
+                                  "max_rel_residual", "solve_variant", "roofline", "moments_roofline")}
 
     out = {
         "metric": METRIC,
@@ -209,6 +227,7 @@ def main(argv=None):
             "E_xx": r["E"],
         },
         "roofline": r["roofline"],
+        "moments_roofline": r["moments_roofline"],
         "cpu_baseline": cpu,
         "by_precision": {p: summary(x) for p, x in res.items()},
         "mixed_accuracy": accuracy,

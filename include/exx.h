@@ -136,6 +136,9 @@ typedef struct {
   int solve_threads;           /* CG variant in use: workgroup size ...            */
   int solve_depth;             /* ... and load depth (chosen by the autotuner)     */
   double tune_ms;              /* time spent by the autotuner (first eval only)    */
+  double moment_ms;            /* device time of the moment kernels (last eval)    */
+  double moment_mfma_flops;    /* flops the matrix cores executed for the moments
+                                  (padded rows and points; mixed: 3 products)      */
 } exx_stats;
 
 /* Statistics of the last exx_eval (synchronizes the bound stream).  Returns

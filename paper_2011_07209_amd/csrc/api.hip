@@ -115,13 +115,15 @@ exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->rho_scale, P->slot_ws, P->queue,
+                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->slot_ws, P->queue,
                   P->stats_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : P->solve_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : P->mom_ev)
     if (e) (void)hipEventDestroy(e);
   delete P;
 }
@@ -135,6 +137,18 @@ exx_status harvest(exx_plan_t P) {
   for (int k = 0; k + 1 < P->solve_ev_used; k += 2) {
     EXX_HIP(P, hipEventElapsedTime(&ms, P->solve_ev[k], P->solve_ev[k + 1]));
     solve += ms;
+  }
+  double mom = 0.0;
+  for (int k = 0; k + 1 < P->mom_ev_used; k += 2) {
+    EXX_HIP(P, hipEventElapsedTime(&ms, P->mom_ev[k], P->mom_ev[k + 1]));
+    mom += ms;
+  }
+  P->last_moment_ms = mom;
+  {
+    int cc[kMaxClasses] = {0};
+    const int ncls = (int)P->classes.size();
+    EXX_HIP(P, hipMemcpy(cc, P->pair_count + 2 * P->last_n_orb + 1, sizeof(int) * ncls, hipMemcpyDeviceToHost));
+    for (int k = 0; k < kMaxClasses; ++k) P->last_class_pairs[k] = k < ncls ? cc[k] : 0;
   }
   EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
   double st[8] = {0};
@@ -209,7 +223,7 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
     a.threads = c[0];
     a.depth = c[1];
     EXX_HIP(P, launch_rhs(P->geo, P->class_dev, P->pairs, P->order, a.p0, sample, P->max_pe, P->rho_ws, P->bx_ws,
-                          P->max_pe, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+                          P->rstride, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
     EXX_HIP(P, hipEventRecord(e0, s));
     EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, (int)std::min<long long>(P->n_slots, sample), s));
@@ -238,15 +252,18 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
   return ensure_slots(P);
 }
 
-exx_status record_solve_event(exx_plan_t P, hipStream_t s) {
-  if (P->solve_ev_used >= (int)P->solve_ev.size()) {
+// Records the next event of a begin/end list (solve or moment launches).
+exx_status record_event(exx_plan_t P, std::vector<hipEvent_t>& evs, int& used, hipStream_t s) {
+  if (used >= (int)evs.size()) {
     hipEvent_t e = nullptr;
     EXX_HIP(P, hipEventCreate(&e));
-    P->solve_ev.push_back(e);
+    evs.push_back(e);
   }
-  EXX_HIP(P, hipEventRecord(P->solve_ev[P->solve_ev_used++], s));
+  EXX_HIP(P, hipEventRecord(evs[used++], s));
   return EXX_OK;
 }
+exx_status record_solve_event(exx_plan_t P, hipStream_t s) { return record_event(P, P->solve_ev, P->solve_ev_used, s); }
+exx_status record_moment_event(exx_plan_t P, hipStream_t s) { return record_event(P, P->mom_ev, P->mom_ev_used, s); }
 
 }  // namespace
 
@@ -349,6 +366,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     }
     const ClassHost& C = P->classes[k];
     P->max_pe = std::max(P->max_pe, C.n_pe);
+    P->rstride = (P->max_pe + 31) / 32 * 32;
     P->max_halo = std::max(P->max_halo, C.n_halo);
     P->max_me = std::max(P->max_me, C.n_me);
     P->max_cols = std::max<long long>(P->max_cols, C.n_cols);
@@ -380,9 +398,10 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   // upload the class tables into one block
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const bool mixed = opt.precision == EXX_PREC_MIXED;
-  const int mom_rows = moment_rows(l_max);
+  int mom_rows = 0, mom_mfma_rows = 0;
+  moment_layout(l_max, mixed, &mom_rows, &mom_mfma_rows);
   auto mom_bytes = [&](const ClassHost& C) {
-    const size_t entries = (size_t)((C.n_pe + 15) / 16 * 16) * mom_rows;
+    const size_t entries = (size_t)((C.n_pe + 31) / 32 * 32) * mom_rows;
     return mixed ? 2 * align(entries * sizeof(unsigned short)) : align(entries * sizeof(double));
   };
   size_t total = 0;
@@ -426,7 +445,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
     D.mom_rows = mom_rows;
     std::vector<double> tab;
-    build_moment_table(C, g.d, l_max, mom_rows, &tab);
+    build_moment_table(C, g.d, l_max, mom_rows, mixed ? 8 : 4, &tab);
     bool tab_ok;
     if (mixed) {
       std::vector<unsigned short> hi(tab.size()), lo(tab.size());
@@ -508,6 +527,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   }
   P->timing_valid = false;
   P->solve_ev_used = 0;
+  P->mom_ev_used = 0;
 
   // pair list
   if (n_orb > P->orb_cap) {
@@ -553,19 +573,30 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   EXX_HIP(P, launch_order(P->pairs, P->pair_count, n_orb, ncls, P->order, s));
 
   // workspace
-  const long long per_pair = 2 * P->max_pe + P->max_halo + kMaxLM;
+  const long long per_pair = 2 * P->rstride + P->max_halo + kMaxLM;
   const double budget = (P->opt.workspace_gb > 0 ? P->opt.workspace_gb : 24.0) * 1e9;
   long long batch = std::max<long long>(1, (long long)(budget / (8.0 * per_pair)));
   batch = std::min<long long>(batch, std::max<long long>(total, 1));
   batch = std::min<long long>(batch, 65535);   // pair index on grid y of the per-point kernels
   if (batch > P->batch_cap) {
-    if (dev_alloc(P, &P->rho_ws, (size_t)batch * P->max_pe, "pair densities") ||
-        dev_alloc(P, &P->bx_ws, (size_t)batch * P->max_pe, "pair potentials") ||
+    if (dev_alloc(P, &P->rho_ws, (size_t)batch * P->rstride, "pair densities") ||
+        dev_alloc(P, &P->bx_ws, (size_t)batch * P->rstride, "pair potentials") ||
         dev_alloc(P, &P->halo_ws, (size_t)batch * std::max<long long>(P->max_halo, 1), "boundary values") ||
         dev_alloc(P, &P->Q_ws, (size_t)batch * kMaxLM, "moments") ||
         dev_alloc(P, &P->rho_scale, (size_t)batch, "density scales"))
       return EXX_ENOMEM;
     P->batch_cap = batch;
+  }
+  {
+    // partial moments of the point chunks: the full batches and the last one
+    const long long tail = total % batch;
+    const long long rows =
+        std::max<long long>(moment_splits(batch, ncls, P->max_pe) * batch,
+                            tail ? moment_splits(tail, ncls, P->max_pe) * tail : 0);
+    if (rows > P->qp_rows) {
+      if (dev_alloc(P, &P->Qp_ws, (size_t)rows * kMaxLM, "partial moments")) return EXX_ENOMEM;
+      P->qp_rows = rows;
+    }
   }
   {
     exx_status st = ensure_slots(P);
@@ -576,11 +607,13 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   EXX_HIP(P, hipEventRecord(P->ev[1], s));
   for (long long p0 = 0; p0 < total; p0 += batch) {
     const long long nb = std::min(batch, total - p0);
-    EXX_HIP(P, launch_gather(g, P->class_dev, P->pairs, P->order, p0, nb, orbitals, (int)dt, P->rho_ws, P->max_pe,
+    EXX_HIP(P, launch_gather(g, P->class_dev, P->pairs, P->order, p0, nb, orbitals, (int)dt, P->rho_ws, P->rstride,
                              P->rho_scale, s));
+    { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_moments(g, P->class_dev, P->pair_count + 2 * n_orb + 1, ncls,
-                              P->opt.precision == EXX_PREC_MIXED, p0, nb, P->rho_ws, P->max_pe, P->rho_scale,
-                              P->Q_ws, s));
+                              P->opt.precision == EXX_PREC_MIXED, p0, nb, P->rho_ws, P->rstride, P->rho_scale,
+                              P->Qp_ws, moment_splits(nb, ncls, P->max_pe), P->Q_ws, s));
+    { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_boundary(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_halo, P->Q_ws, P->halo_ws,
                                std::max<long long>(P->max_halo, 1), s));
     SolveArgs a;
@@ -592,7 +625,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.npair = nb;
     a.queue = P->queue;
     a.bx_ws = P->bx_ws;
-    a.rstride = P->max_pe;
+    a.rstride = P->rstride;
     a.slot_ws = P->slot_ws;
     a.sstride = P->max_pe;
     a.outIt = P->pIt;
@@ -611,18 +644,18 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
       a.threads = P->solve_threads;
       a.depth = P->solve_depth;
     }
-    EXX_HIP(P, launch_rhs(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_pe, P->rho_ws, P->bx_ws, P->max_pe,
+    EXX_HIP(P, launch_rhs(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_pe, P->rho_ws, P->bx_ws, P->rstride,
                           P->halo_ws, std::max<long long>(P->max_halo, 1), s));
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
     const int groups = (int)std::min<long long>(P->n_slots, nb);
     { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, groups, s));
     { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_finalize(g, P->class_dev, P->pairs, P->order, p0, nb, P->rho_ws, P->bx_ws, P->max_pe,
+    EXX_HIP(P, launch_finalize(g, P->class_dev, P->pairs, P->order, p0, nb, P->rho_ws, P->bx_ws, P->rstride,
                                P->halo_ws, std::max<long long>(P->max_halo, 1), P->pE, P->pS, s));
     if (D_xx)
       EXX_HIP(P, launch_dscatter(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_me, orbitals, D_xx, (int)dt,
-                                 P->bx_ws, P->max_pe, P->Q_ws, s));
+                                 P->bx_ws, P->rstride, P->Q_ws, s));
   }
   EXX_HIP(P, hipEventRecord(P->ev[2], s));
   EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pairs, P->class_dev, P->pair_count, n_orb,
@@ -674,6 +707,18 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->eval_ms = P->last_eval_ms;
   out->cg_alg_bytes = P->last_alg_bytes;
   out->moment_flops = 2.0 * P->geo.n_lm * st[7];
+  out->moment_ms = P->last_moment_ms;
+  {
+    // executed MFMA work: every point step of every pair, all padded rows
+    const bool mixed = P->opt.precision == EXX_PREC_MIXED;
+    double padded = 0.0;
+    for (int k = 0; k < (int)P->classes.size(); ++k)
+      padded += (double)P->last_class_pairs[k] * (double)((P->classes[k].n_pe + (mixed ? 31 : 15)) /
+                                                            (mixed ? 32 : 16) * (mixed ? 32 : 16));
+    int rows = 0, mrows = 0;
+    moment_layout(P->geo.l_max, mixed, &rows, &mrows);
+    out->moment_mfma_flops = 2.0 * mrows * padded * (mixed ? 3.0 : 1.0);
+  }
   out->n_evals = P->n_evals;
   out->solve_launches = P->solve_launches;
   out->solve_ms_total = P->solve_ms_total;

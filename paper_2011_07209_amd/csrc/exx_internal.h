@@ -56,9 +56,10 @@ struct ClassDev {
   const int* halo_map;       // [Wm2][Wm1][Wm0] -> halo index or -1
   const int* col_map;        // [Wm1][Wm0] -> column index or -1
   const int* zr_map;         // [Wm1][Wm0] -> column half-height or -1
-  // moment table: unnormalised solid harmonics P_lm of the PE offsets, layout
-  // [k/4][row][4] over mom_rows rows and n_pe rounded up to 16 points (zeros
-  // beyond); FP64 for FP64 plans, split BF16 (hi, lo) for mixed plans
+  // moment table: unnormalised solid harmonics P_lm of the PE offsets over
+  // mom_rows rows and n_pe rounded up to 32 points (zeros beyond); FP64 in
+  // layout [k/4][row][4] for FP64 plans, split BF16 (hi, lo) in layout
+  // [k/8][row][8] for mixed plans
   int mom_rows;
   const double* mom_f64;
   const unsigned short* mom_hi;
@@ -87,9 +88,10 @@ struct ClassHost {
 // Builds the tables of one class; returns an empty string or an error message.
 std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out);
 // Unnormalised solid harmonics P_lm(o d) of the class's PE points, laid out
-// [k/4][row][4] with rows >= (l_max + 1)^2 and n_pe rounded up to 16, zeros
-// in the padding.
-void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, std::vector<double>* out);
+// [k/G][row][G] (G = group, 4 or 8) with rows >= (l_max + 1)^2 and n_pe
+// rounded up to 32, zeros in the padding.
+void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, int group,
+                        std::vector<double>* out);
 
 }  // namespace exx
 
@@ -107,6 +109,7 @@ struct exx_plan_s {
   exx::ClassDev* class_dev = nullptr;          // device copy of class_dev_host
   void* class_block = nullptr;                 // device block holding every class table
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
+  long long rstride = 0;   // row stride of the per-pair workspaces: max_pe rounded up to 32
   int max_zmax = 0;
 
   // pair list
@@ -132,6 +135,8 @@ struct exx_plan_s {
   double* halo_ws = nullptr;   // [batch][max_halo]
   double* Q_ws = nullptr;      // [batch][kMaxLM]
   double* rho_scale = nullptr; // [batch] power-of-two scale of each pair density
+  double* Qp_ws = nullptr;     // [chunks][batch][kMaxLM] partial moments of the point chunks
+  long long qp_rows = 0;
   int n_slots = 0;
   int n_cus = 1;
   int solve_threads = 1024, solve_depth = 1;   // CG variant in use
@@ -146,6 +151,10 @@ struct exx_plan_s {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> solve_ev;   // begin/end pairs around each solve launch of the last eval
   int solve_ev_used = 0;
+  std::vector<hipEvent_t> mom_ev;     // begin/end pairs around each moment launch of the last eval
+  int mom_ev_used = 0;
+  double last_moment_ms = 0;
+  long long last_class_pairs[exx::kMaxClasses] = {0};
   bool timing_valid = false;
   bool harvested = true;              // last eval's events already added to the totals
   double last_solve_ms = 0, last_eval_ms = 0, last_alg_bytes = 0;

@@ -24,13 +24,18 @@ hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int 
 hipError_t launch_gather(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
                          long long nb, const void* orb, int dt, double* rho_ws, long long rstride, double* rho_scale,
                          hipStream_t s);
-// Rows of the moment tables: (l_max + 1)^2 padded to a multiple of 16.
-int moment_rows(int l_max);
-// Moments of the batch [pbeg, pbeg + nb) of the processing order; class_cnt
-// holds the per-class pair counts of the order (device).
+// Rows of the moment tables, and how many of them the matrix cores take:
+// (l_max + 1)^2 padded to a multiple of 16, except that FP64 tables keep up to
+// 4 rows past the last full 16-row tile for the vector ALU.
+void moment_layout(int l_max, bool mixed, int* rows, int* mfma_rows);
+// Number of point chunks the moment launch of a batch of nb pairs uses.
+int moment_splits(long long nb, int ncls, long long max_pe);
+// Moments of the batch [pbeg, pbeg + nb) of the processing order into Q_ws;
+// class_cnt holds the per-class pair counts of the order (device); Qp holds
+// splits * nb * kMaxLM partial sums; rho rows are zero-padded to 32 points.
 hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cnt, int ncls, bool mixed,
                           long long pbeg, long long nb, const double* rho_ws, long long rstride,
-                          const double* rho_scale, double* Q_ws, hipStream_t s);
+                          const double* rho_scale, double* Qp, int splits, double* Q_ws, hipStream_t s);
 hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
                            long long nb, long long max_halo, const double* Q_ws, double* halo_ws, long long hstride,
                            hipStream_t s);

@@ -190,6 +190,8 @@ __global__ __launch_bounds__(256) void k_gather(Geo g, const ClassDev* __restric
     rho[k] = r;
     amax = fmax(amax, fabs(r));
   }
+  const long long npad = (npe + 31) / 32 * 32;   // zeros up to the moment kernels' 32-point steps
+  for (long long k = npe + threadIdx.x; k < npad; k += blockDim.x) rho[k] = 0.0;
   amax = block_max(amax, red);
   if (threadIdx.x == 0) {
     int e = 0;

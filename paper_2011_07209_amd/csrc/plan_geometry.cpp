@@ -146,16 +146,17 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   return std::string();
 }
 
-void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, std::vector<double>* out) {
-  const long long kpad = (C.n_pe + 15) / 16 * 16;
+void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, int group,
+                        std::vector<double>* out) {
+  const long long kpad = (C.n_pe + 31) / 32 * 32;
   out->assign((size_t)(kpad * rows), 0.0);
   std::vector<double> ones(kMaxLM, 1.0), v(kMaxLM, 0.0);
   const int nlm = (l_max + 1) * (l_max + 1);
   for (long long k = 0; k < C.n_pe; ++k) {
     const short4 o = C.me_off[(size_t)k];
     solid_harmonics_host(l_max, o.x * d[0], o.y * d[1], o.z * d[2], ones.data(), v.data());
-    double* dst = out->data() + (size_t)((k >> 2) * rows * 4 + (k & 3));
-    for (int lm = 0; lm < nlm; ++lm) dst[(size_t)lm * 4] = v[lm];
+    double* dst = out->data() + (size_t)((k / group) * rows * group + (k % group));
+    for (int lm = 0; lm < nlm; ++lm) dst[(size_t)lm * group] = v[lm];
   }
 }
 

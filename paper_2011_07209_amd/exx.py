@@ -69,6 +69,8 @@ class Stats(ctypes.Structure):
         ("solve_threads", ctypes.c_int),
         ("solve_depth", ctypes.c_int),
         ("tune_ms", ctypes.c_double),
+        ("moment_ms", ctypes.c_double),
+        ("moment_mfma_flops", ctypes.c_double),
     ]
 
     def as_dict(self):
