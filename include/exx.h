@@ -64,8 +64,12 @@ typedef struct {
      fall below pair_sample_frac; >= 1 keeps every pair                        */
   unsigned long long pair_sample_seed;
   double pair_sample_frac;
-  long long max_pairs;        /* 0: workspace grows on demand; > 0: fixed capacity,
-                                 more pairs give EXX_ECAPACITY                     */
+  long long max_pairs;        /* 0: workspace grows on demand (one host wait per
+                                 exx_eval for the pair count); > 0: fixed pair
+                                 capacity, no host wait, and exx_eval may be
+                                 recorded into a HIP graph (see exx_eval); pairs
+                                 beyond it are dropped and exx_stats_fetch
+                                 returns EXX_ECAPACITY                              */
   double workspace_gb;        /* cap on per-batch pair workspace (0: 24 GB)        */
   int solve_groups;           /* persistent solve workgroups (0: as many as fit)   */
   int solve_threads;          /* CG workgroup size, 512 or 1024 (0: tuned/default) */
@@ -97,15 +101,25 @@ exx_status exx_set_stream(exx_plan_t plan, void* hip_stream);
      orbitals  device, [n_orb][N3][N2][N1] of dtype dt, read only
      centres   device, [n_orb][3] Cartesian orbital centres (bohr), read only
      R_PE_orb  device, [n_orb] per-orbital radii, or NULL for the plan radius
+     d_subset  device, [n_subset] distinct orbital indices whose D^i are wanted,
+               or NULL (n_subset 0) for every orbital; indices outside
+               [0, n_orb) are ignored
      E_xx      device, 1 double, overwritten
-     D_xx      device, [n_orb][N3][N2][N1] of dtype dt, overwritten; NULL skips D
+     D_xx      device, [n_subset or n_orb][N3][N2][N1] of dtype dt (row s holds
+               D of orbital d_subset[s]), overwritten; NULL skips D
      sigma     device, 9 doubles, sigma[a + 3*al] = dE/dh_{a al}; NULL skips it
    Unique pairs i <= j carry weight 1 (i == j) or 2 (i != j) in E and sigma;
    D^i receives v_ij phi_j and D^j receives v_ij phi_i on the ME sphere.
-   Enqueued on the bound stream; the call returns after one host wait for the
-   pair count.  Outputs are complete when the stream is. */
+   Enqueued on the bound stream; outputs are complete when the stream is.
+   Without a fixed capacity (max_pairs 0) the call waits once on the host for
+   the pair count.  With max_pairs > 0 it does not wait, and once an eager call
+   with at least n_orb orbitals has completed (which also runs the autotuner,
+   when enabled) it allocates nothing, so the stream may be recorded into a HIP
+   graph around it and the graph replayed with new orbital and centre values
+   in the same buffers.  Recording in any other state gives EXX_EINVAL. */
 exx_status exx_eval(exx_plan_t plan, int n_orb, const void* orbitals, exx_dtype dt, const double* centres,
-                    const double* R_PE_orb, double* E_xx, void* D_xx, double* sigma);
+                    const double* R_PE_orb, const int* d_subset, int n_subset, double* E_xx, void* D_xx,
+                    double* sigma);
 
 /* Per-pair results of the last exx_eval, copied to host arrays of capacity
    cap (any may be NULL): ij [2*cap] (i, j), E [cap] (weighted contribution),
@@ -139,6 +153,10 @@ typedef struct {
   double moment_ms;            /* device time of the moment kernels (last eval)    */
   double moment_mfma_flops;    /* flops the matrix cores executed for the moments
                                   (padded rows and points; mixed: 3 products)      */
+  long long pairs_kept;        /* pairs the pair list kept, also beyond max_pairs  */
+  int graph_recorded;          /* 1: the last exx_eval was recorded into a graph;
+                                  results are those of its latest replay, and the
+                                  device times are 0                               */
 } exx_stats;
 
 /* Statistics of the last exx_eval (synchronizes the bound stream).  Returns

@@ -101,6 +101,10 @@ double bf16_value(unsigned short h) {
 
 template <typename T>
 exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
+  if (P && P->capturing)
+    return fail(P, EXX_EINVAL, std::string("exx_eval needs a device allocation (") + what +
+                                   ") while its stream is recorded into a graph; run one eager exx_eval with the "
+                                   "same sizes first");
   if (*p) (void)hipFree(*p);
   *p = nullptr;
   if (count == 0) return EXX_OK;
@@ -112,10 +116,17 @@ exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
   return EXX_OK;
 }
 
+// Marks the plan as recording into a graph for the lifetime of one exx_eval.
+struct CaptureGuard {
+  exx_plan_t P;
+  CaptureGuard(exx_plan_t p, bool on) : P(p) { P->capturing = on; }
+  ~CaptureGuard() { P->capturing = false; }
+};
+
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->slot_ws, P->queue,
+                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->slot_ws, P->queue,
                   P->stats_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -126,6 +137,19 @@ void free_plan(exx_plan_t P) {
   for (auto& e : P->mom_ev)
     if (e) (void)hipEventDestroy(e);
   delete P;
+}
+
+// Copies the device statistics of the last evaluation (k_reduce's eight
+// values and the per-class pair counts).  The caller has synchronized.
+exx_status read_device_stats(exx_plan_t P) {
+  double st[8] = {0};
+  EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
+  for (int k = 0; k < 8; ++k) P->last_stats[k] = st[k];
+  int cc[kMaxClasses] = {0};
+  const int ncls = (int)P->classes.size();
+  EXX_HIP(P, hipMemcpy(cc, P->pair_count + 2 * P->last_n_orb + 1, sizeof(int) * ncls, hipMemcpyDeviceToHost));
+  for (int k = 0; k < kMaxClasses; ++k) P->last_class_pairs[k] = k < ncls ? cc[k] : 0;
+  return EXX_OK;
 }
 
 // Adds the finished evaluation's device times and algorithmic bytes to the
@@ -144,20 +168,13 @@ exx_status harvest(exx_plan_t P) {
     mom += ms;
   }
   P->last_moment_ms = mom;
-  {
-    int cc[kMaxClasses] = {0};
-    const int ncls = (int)P->classes.size();
-    EXX_HIP(P, hipMemcpy(cc, P->pair_count + 2 * P->last_n_orb + 1, sizeof(int) * ncls, hipMemcpyDeviceToHost));
-    for (int k = 0; k < kMaxClasses; ++k) P->last_class_pairs[k] = k < ncls ? cc[k] : 0;
-  }
   EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
-  double st[8] = {0};
-  EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
+  exx_status ds = read_device_stats(P);
+  if (ds != EXX_OK) return ds;
   const double b = (P->opt.precision == EXX_PREC_MIXED) ? 4.0 : 8.0;
   P->last_solve_ms = solve;
   P->last_eval_ms = ms;
-  P->last_alg_bytes = st[5] * 8.0 * b;
-  for (int k = 0; k < 8; ++k) P->last_stats[k] = st[k];
+  P->last_alg_bytes = P->last_stats[5] * 8.0 * b;
   P->n_evals += 1;
   P->solve_launches += P->solve_ev_used / 2;
   P->solve_ms_total += solve;
@@ -222,8 +239,15 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
     a.slot_ws = P->slot_ws;
     a.threads = c[0];
     a.depth = c[1];
-    EXX_HIP(P, launch_rhs(P->geo, P->class_dev, P->pairs, P->order, a.p0, sample, P->max_pe, P->rho_ws, P->bx_ws,
-                          P->rstride, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+    Batch B;
+    B.cls = P->class_dev;
+    B.pairs = P->pairs;
+    B.order = P->order;
+    B.n_eff = P->n_eff;
+    B.p0 = a.p0;
+    B.nb = sample;
+    EXX_HIP(P, launch_rhs(P->geo, B, P->max_pe, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
+                          std::max<long long>(P->max_halo, 1), s));
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
     EXX_HIP(P, hipEventRecord(e0, s));
     EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, (int)std::min<long long>(P->n_slots, sample), s));
@@ -496,7 +520,6 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
       return fail(nullptr, st, m);
     }
   }
-  if (opt.max_pairs > 0) P->pair_cap_fixed = true;
   *out = P;
   return EXX_OK;
 }
@@ -508,31 +531,51 @@ exx_status exx_set_stream(exx_plan_t P, void* s) {
 }
 
 exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt, const double* centres,
-                    const double* R_PE_orb, double* E_xx, void* D_xx, double* sigma) {
+                    const double* R_PE_orb, const int* d_subset, int n_subset, double* E_xx, void* D_xx,
+                    double* sigma) {
   if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
   if (n_orb < 1) return fail(P, EXX_EINVAL, "n_orb must be >= 1");
   if (!orbitals || !centres || !E_xx) return fail(P, EXX_EINVAL, "orbitals, centres and E_xx are required");
   if (dt != EXX_F64 && dt != EXX_F32) return fail(P, EXX_EINVAL, "unknown dtype");
   if (P->opt.R_PE_nclass > 0 && !R_PE_orb)
     return fail(P, EXX_EINVAL, "variable radii need per-orbital radii (R_PE_orb)");
+  if (n_subset < 0 || n_subset > n_orb || (n_subset > 0 && !d_subset))
+    return fail(P, EXX_EINVAL, "d_subset must hold n_subset (0 .. n_orb) orbital indices");
   const Geo& g = P->geo;
   hipStream_t s = P->stream;
   int dev = -1;
   EXX_HIP(P, hipGetDevice(&dev));
   if (dev != P->device) return fail(P, EXX_EINVAL, "current device differs from the plan's device");
-  if (P->timing_valid && !P->harvested) {
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  EXX_HIP(P, hipStreamIsCapturing(s, &cap_status));
+  const bool capturing = cap_status != hipStreamCaptureStatusNone;
+  const bool fixed = P->opt.max_pairs > 0;
+  if (capturing) {
+    if (!fixed) return fail(P, EXX_EINVAL, "recording exx_eval in a graph needs a fixed pair capacity (max_pairs > 0)");
+    if (n_orb > P->warm_orb)
+      return fail(P, EXX_EINVAL, "recording exx_eval in a graph needs one eager exx_eval with at least as many "
+                                 "orbitals first");
+  } else if (P->timing_valid && !P->harvested) {
     EXX_HIP(P, hipEventSynchronize(P->ev[3]));
     exx_status hs = harvest(P);
     if (hs != EXX_OK) return hs;
   }
   P->timing_valid = false;
+  P->last_captured = capturing;
   P->solve_ev_used = 0;
   P->mom_ev_used = 0;
+  CaptureGuard guard(P, capturing);   // dev_alloc refuses while the stream is captured
+  auto event = [&](hipEvent_t e) { return capturing ? hipSuccess : hipEventRecord(e, s); };
 
   // pair list
   if (n_orb > P->orb_cap) {
-    if (dev_alloc(P, &P->pair_count, (size_t)2 * n_orb + 1 + kMaxClasses, "pair counts")) return EXX_ENOMEM;
+    if (dev_alloc(P, &P->pair_count, (size_t)2 * n_orb + 1 + kMaxClasses, "pair counts") ||
+        dev_alloc(P, &P->d_slot, (size_t)n_orb, "D subset slots"))
+      return EXX_ENOMEM;
     P->orb_cap = n_orb;
+  }
+  if (!P->n_eff) {
+    if (dev_alloc(P, &P->n_eff, 1, "pair count")) return EXX_ENOMEM;
   }
   PairParams pp;
   pp.R_pair2 = P->R_pair * P->R_pair * (1.0 + kSlack);
@@ -542,41 +585,43 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   pp.n_class = P->opt.R_PE_nclass;
   pp.seed = P->opt.pair_sample_seed;
   pp.frac = P->opt.pair_sample_frac;
-  EXX_HIP(P, hipEventRecord(P->ev[0], s));
-  if (P->opt.max_pairs > 0 && P->pair_cap < P->opt.max_pairs) {
-    if (dev_alloc(P, &P->pairs, (size_t)P->opt.max_pairs, "pairs") || dev_alloc(P, &P->order, (size_t)P->opt.max_pairs, "order") ||
-        dev_alloc(P, &P->pE, (size_t)P->opt.max_pairs, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * P->opt.max_pairs, "pair sigma") ||
-        dev_alloc(P, &P->pIt, (size_t)P->opt.max_pairs, "pair iters") || dev_alloc(P, &P->pRes, (size_t)P->opt.max_pairs, "pair res") ||
-        dev_alloc(P, &P->pUpd, (size_t)P->opt.max_pairs, "pair updates"))
-      return EXX_ENOMEM;
-    P->pair_cap = P->opt.max_pairs;
-  }
-  EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
-  int total = 0;
-  EXX_HIP(P, hipMemcpyAsync(&total, P->pair_count + 2 * n_orb, sizeof(int), hipMemcpyDeviceToHost, s));
-  EXX_HIP(P, hipStreamSynchronize(s));
-  if (total < 0) return fail(P, EXX_EINVAL, "pair count overflow");
-  if (total > P->pair_cap) {
-    if (P->opt.max_pairs > 0) return fail(P, EXX_ECAPACITY, "more pairs than max_pairs");
-    const long long cap = std::max<long long>(total, 1) + total / 8;
+  EXX_HIP(P, event(P->ev[0]));
+  auto alloc_pairs = [&](long long cap) -> exx_status {
     if (dev_alloc(P, &P->pairs, (size_t)cap, "pairs") || dev_alloc(P, &P->order, (size_t)cap, "order") ||
         dev_alloc(P, &P->pE, (size_t)cap, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * cap, "pair sigma") ||
         dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res") ||
         dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates"))
       return EXX_ENOMEM;
     P->pair_cap = cap;
-    EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
+    return EXX_OK;
+  };
+  if (fixed && P->pair_cap < P->opt.max_pairs) {
+    if (alloc_pairs(P->opt.max_pairs) != EXX_OK) return EXX_ENOMEM;
   }
-  P->n_pairs = total;
+  EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
+  // rows of the processing order that the batch loop covers: the capacity,
+  // or (without one) the pair count, read back once to size the workspace
+  long long span = P->pair_cap;
+  if (!fixed) {
+    int total = 0;
+    EXX_HIP(P, hipMemcpyAsync(&total, P->pair_count + 2 * n_orb, sizeof(int), hipMemcpyDeviceToHost, s));
+    EXX_HIP(P, hipStreamSynchronize(s));
+    if (total < 0) return fail(P, EXX_EINVAL, "pair count overflow");
+    if (total > P->pair_cap) {
+      if (alloc_pairs(std::max<long long>(total, 1) + total / 8) != EXX_OK) return EXX_ENOMEM;
+      EXX_HIP(P, launch_pairlist(g, pp, centres, R_PE_orb, n_orb, P->pair_count, P->pairs, P->pair_cap, s));
+    }
+    span = total;
+  }
   P->last_n_orb = n_orb;
   const int ncls = (int)P->classes.size();
-  EXX_HIP(P, launch_order(P->pairs, P->pair_count, n_orb, ncls, P->order, s));
+  EXX_HIP(P, launch_order(P->pairs, P->pair_count, n_orb, ncls, P->order, P->pair_cap, P->n_eff, s));
 
   // workspace
   const long long per_pair = 2 * P->rstride + P->max_halo + kMaxLM;
   const double budget = (P->opt.workspace_gb > 0 ? P->opt.workspace_gb : 24.0) * 1e9;
   long long batch = std::max<long long>(1, (long long)(budget / (8.0 * per_pair)));
-  batch = std::min<long long>(batch, std::max<long long>(total, 1));
+  batch = std::min<long long>(batch, std::max<long long>(span, 1));
   batch = std::min<long long>(batch, 65535);   // pair index on grid y of the per-point kernels
   if (batch > P->batch_cap) {
     if (dev_alloc(P, &P->rho_ws, (size_t)batch * P->rstride, "pair densities") ||
@@ -589,10 +634,9 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   }
   {
     // partial moments of the point chunks: the full batches and the last one
-    const long long tail = total % batch;
-    const long long rows =
-        std::max<long long>(moment_splits(batch, ncls, P->max_pe) * batch,
-                            tail ? moment_splits(tail, ncls, P->max_pe) * tail : 0);
+    const long long tail = span % batch;
+    const long long rows = std::max<long long>(moment_splits(batch, ncls, P->max_pe) * batch,
+                                               tail ? moment_splits(tail, ncls, P->max_pe) * tail : 0);
     if (rows > P->qp_rows) {
       if (dev_alloc(P, &P->Qp_ws, (size_t)rows * kMaxLM, "partial moments")) return EXX_ENOMEM;
       P->qp_rows = rows;
@@ -603,26 +647,39 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     if (st != EXX_OK) return st;
   }
 
-  if (D_xx) EXX_HIP(P, launch_zero(D_xx, (size_t)n_orb * g.ngrid * (dt == EXX_F64 ? 8 : 4), s));
-  EXX_HIP(P, hipEventRecord(P->ev[1], s));
-  for (long long p0 = 0; p0 < total; p0 += batch) {
-    const long long nb = std::min(batch, total - p0);
-    EXX_HIP(P, launch_gather(g, P->class_dev, P->pairs, P->order, p0, nb, orbitals, (int)dt, P->rho_ws, P->rstride,
-                             P->rho_scale, s));
-    { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_moments(g, P->class_dev, P->pair_count + 2 * n_orb + 1, ncls,
-                              P->opt.precision == EXX_PREC_MIXED, p0, nb, P->rho_ws, P->rstride, P->rho_scale,
-                              P->Qp_ws, moment_splits(nb, ncls, P->max_pe), P->Q_ws, s));
-    { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_boundary(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_halo, P->Q_ws, P->halo_ws,
-                               std::max<long long>(P->max_halo, 1), s));
+  const int* d_slot = nullptr;
+  if (D_xx) {
+    const long long rows = d_subset ? n_subset : n_orb;
+    if (d_subset) {
+      EXX_HIP(P, launch_dslot(P->d_slot, n_orb, d_subset, n_subset, s));
+      d_slot = P->d_slot;
+    }
+    EXX_HIP(P, launch_zero(D_xx, (size_t)rows * g.ngrid * (dt == EXX_F64 ? 8 : 4), s));
+  }
+  EXX_HIP(P, event(P->ev[1]));
+  const bool mixed = P->opt.precision == EXX_PREC_MIXED;
+  for (long long p0 = 0; p0 < span; p0 += batch) {
+    Batch B;
+    B.cls = P->class_dev;
+    B.pairs = P->pairs;
+    B.order = P->order;
+    B.n_eff = P->n_eff;
+    B.p0 = p0;
+    B.nb = std::min(batch, span - p0);
+    EXX_HIP(P, launch_gather(g, B, orbitals, (int)dt, P->rho_ws, P->rstride, P->rho_scale, s));
+    if (!capturing) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
+    EXX_HIP(P, launch_moments(g, B, P->pair_count + 2 * n_orb + 1, ncls, mixed, P->rho_ws, P->rstride, P->rho_scale,
+                              P->Qp_ws, moment_splits(B.nb, ncls, P->max_pe), P->Q_ws, s));
+    if (!capturing) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
+    EXX_HIP(P, launch_boundary(g, B, P->max_halo, P->Q_ws, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
     SolveArgs a;
     a.g = g;
     a.cls = P->class_dev;
     a.pairs = P->pairs;
     a.order = P->order;
     a.p0 = p0;
-    a.npair = nb;
+    a.npair = B.nb;
+    a.n_eff = P->n_eff;
     a.queue = P->queue;
     a.bx_ws = P->bx_ws;
     a.rstride = P->rstride;
@@ -631,38 +688,41 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.outIt = P->pIt;
     a.outRes = P->pRes;
     a.outUpd = P->pUpd;
-    a.mixed = P->opt.precision == EXX_PREC_MIXED;
+    a.mixed = mixed;
     a.delta = 0.1;
     a.threads = P->solve_threads;
     a.depth = P->solve_depth;
     a.tol = P->opt.cg_tol;
     a.max_iter = P->opt.cg_max_iter;
     if (P->opt.autotune && !P->tuned) {
-      exx_status st = autotune_solve(P, a, nb, s);
+      if (capturing) return fail(P, EXX_EINVAL, "the autotuner runs in an eager exx_eval, not in a graph");
+      exx_status st = autotune_solve(P, a, B.nb, s);
       if (st != EXX_OK) return st;
       a.slot_ws = P->slot_ws;
       a.threads = P->solve_threads;
       a.depth = P->solve_depth;
     }
-    EXX_HIP(P, launch_rhs(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_pe, P->rho_ws, P->bx_ws, P->rstride,
-                          P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+    EXX_HIP(P, launch_rhs(g, B, P->max_pe, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
+                          std::max<long long>(P->max_halo, 1), s));
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
-    const int groups = (int)std::min<long long>(P->n_slots, nb);
-    { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
+    const int groups = (int)std::min<long long>(P->n_slots, B.nb);
+    if (!capturing) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, groups, s));
-    { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_finalize(g, P->class_dev, P->pairs, P->order, p0, nb, P->rho_ws, P->bx_ws, P->rstride,
-                               P->halo_ws, std::max<long long>(P->max_halo, 1), P->pE, P->pS, s));
+    if (!capturing) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
+    EXX_HIP(P, launch_finalize(g, B, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws, std::max<long long>(P->max_halo, 1),
+                               P->pE, P->pS, s));
     if (D_xx)
-      EXX_HIP(P, launch_dscatter(g, P->class_dev, P->pairs, P->order, p0, nb, P->max_me, orbitals, D_xx, (int)dt,
-                                 P->bx_ws, P->rstride, P->Q_ws, s));
+      EXX_HIP(P, launch_dscatter(g, B, P->max_me, orbitals, D_xx, d_slot, (int)dt, P->bx_ws, P->rstride, P->Q_ws, s));
   }
-  EXX_HIP(P, hipEventRecord(P->ev[2], s));
+  EXX_HIP(P, event(P->ev[2]));
   EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pairs, P->class_dev, P->pair_count, n_orb,
-                           P->opt.cg_max_iter, E_xx, sigma, P->stats_dev, s));
-  EXX_HIP(P, hipEventRecord(P->ev[3], s));
-  P->timing_valid = true;
-  P->harvested = false;
+                           P->n_eff, P->opt.cg_max_iter, E_xx, sigma, P->stats_dev, s));
+  EXX_HIP(P, event(P->ev[3]));
+  if (!capturing) {
+    P->timing_valid = true;
+    P->harvested = false;
+    if (fixed) P->warm_orb = std::max(P->warm_orb, n_orb);
+  }
   return EXX_OK;
 }
 
@@ -670,8 +730,10 @@ exx_status exx_pair_results(exx_plan_t P, long long cap, int* ij, double* E, dou
                             double* rel_res, long long* n_pairs) {
   if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
   EXX_HIP(P, hipStreamSynchronize(P->stream));
-  const long long n = std::min<long long>(P->n_pairs, std::max<long long>(cap, 0));
-  if (n_pairs) *n_pairs = P->n_pairs;
+  int stored = 0;
+  if (P->n_eff) EXX_HIP(P, hipMemcpy(&stored, P->n_eff, sizeof(int), hipMemcpyDeviceToHost));
+  const long long n = std::min<long long>(stored, std::max<long long>(cap, 0));
+  if (n_pairs) *n_pairs = stored;
   if (n <= 0) return EXX_OK;
   if (ij) {
     std::vector<PairDev> pd((size_t)n);
@@ -692,11 +754,19 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   if (!P || !out) return fail(P, EXX_EINVAL, "plan or out is NULL");
   std::memset(out, 0, sizeof(*out));
   EXX_HIP(P, hipStreamSynchronize(P->stream));
-  if (!P->timing_valid) return fail(P, EXX_EINVAL, "no evaluation to report");
-  exx_status hs = harvest(P);
-  if (hs != EXX_OK) return hs;
+  if (!P->timing_valid && !P->last_captured) return fail(P, EXX_EINVAL, "no evaluation to report");
+  if (P->timing_valid) {
+    exx_status hs = harvest(P);
+    if (hs != EXX_OK) return hs;
+  } else {
+    // the last call was recorded in a graph: device results of its latest replay, no timings
+    exx_status hs = read_device_stats(P);
+    if (hs != EXX_OK) return hs;
+    P->last_solve_ms = P->last_eval_ms = P->last_moment_ms = 0.0;
+    P->last_alg_bytes = P->last_stats[5] * 8.0 * (P->opt.precision == EXX_PREC_MIXED ? 4.0 : 8.0);
+  }
   const double* st = P->last_stats;
-  out->n_pairs = P->n_pairs;
+  out->n_pairs = std::min<long long>((long long)st[4], P->pair_cap);
   out->cg_iter_sum = (long long)st[0];
   out->cg_iter_max = (int)st[1];
   out->n_unconverged = (int)st[2];
@@ -727,6 +797,10 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->solve_threads = P->solve_threads;
   out->solve_depth = P->solve_depth;
   out->tune_ms = P->tune_ms;
+  out->pairs_kept = (long long)st[4];
+  out->graph_recorded = P->last_captured ? 1 : 0;
+  if (st[4] > (double)P->pair_cap)
+    return fail(P, EXX_ECAPACITY, "more pairs than the fixed capacity (max_pairs); results cover the first ones");
   return out->n_unconverged > 0 ? fail(P, EXX_ENOCONV, "CG did not converge for some pairs") : EXX_OK;
 }
 

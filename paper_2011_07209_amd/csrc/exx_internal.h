@@ -118,8 +118,11 @@ struct exx_plan_s {
   int* order = nullptr;            // processing order (class descending)
   int* pair_count = nullptr;       // per-orbital counts and offsets [2 * orb_cap + 1 + classes]
   int orb_cap = 0;
-  long long n_pairs = 0;
-  long long class_count[exx::kMaxClasses] = {0};
+  int* n_eff = nullptr;            // device: pairs stored in the processing order
+  int* d_slot = nullptr;           // device [orb_cap]: D row of each orbital (subset evaluations)
+  int warm_orb = 0;                // largest n_orb of a completed eager eval with a fixed capacity
+  bool capturing = false;          // inside an exx_eval recorded into a graph
+  bool last_captured = false;      // the last exx_eval was recorded into a graph
 
   // per-pair results
   double* pE = nullptr;
@@ -144,8 +147,7 @@ struct exx_plan_s {
   double tune_ms = 0;
   void* slot_ws = nullptr;     // [slots] CG vectors: FP64 r, p; mixed: FP64 x, FP32 r, p, y
   int* queue = nullptr;
-  double* stats_dev = nullptr;     // (iter_sum, iter_max, n_unconverged, max_res, n_pairs)
-  bool pair_cap_fixed = false;
+  double* stats_dev = nullptr;     // the eight values of k_reduce (see launch_reduce)
   int last_n_orb = 0;
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

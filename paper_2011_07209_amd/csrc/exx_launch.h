@@ -1,4 +1,10 @@
-// Host-side launchers of the gfx950 kernels (defined in kernels.hip).
+// Host-side launchers of the gfx950 kernels (kernels.hip, moments.hip,
+// solve.hip).
+//
+// Every per-batch launcher takes a Batch: rows [p0, p0 + nb) of the processing
+// order, where nb is the launch's capacity and the kernels themselves skip rows
+// at or beyond the device-side pair count *n_eff.  No launcher needs the pair
+// count on the host, so an evaluation can be recorded into a HIP graph.
 #pragma once
 
 #include "exx_internal.h"
@@ -14,38 +20,49 @@ struct PairParams {
   double frac;
 };
 
+struct Batch {
+  const ClassDev* cls;
+  const PairDev* pairs;
+  const int* order;     // processing order (class descending)
+  const int* n_eff;     // device: pairs in the order (the stored ones, at most the capacity)
+  long long p0, nb;     // first row and capacity of the batch
+};
+
 // counts[0 .. n_orb) per-orbital pair counts, counts[n_orb .. 2 n_orb] offsets
 // (exclusive, with the total at index 2 n_orb), then per-class counts.
 hipError_t launch_pairlist(const Geo& g, const PairParams& pp, const double* centres, const double* R_orb, int n_orb,
                            int* counts, PairDev* pairs, long long cap, hipStream_t s);
-hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order, hipStream_t s);
+// Processing order of the stored pairs (at most cap) and its length *n_eff.
+hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order, long long cap,
+                        int* n_eff, hipStream_t s);
+// slot[i] = position of orbital i in subset[0 .. n_subset), else -1.
+hipError_t launch_dslot(int* slot, int n_orb, const int* subset, int n_subset, hipStream_t s);
 
 // rho_scale[b]: power of two at or above max |rho| of pair b (see k_gather)
-hipError_t launch_gather(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                         long long nb, const void* orb, int dt, double* rho_ws, long long rstride, double* rho_scale,
-                         hipStream_t s);
+hipError_t launch_gather(const Geo& g, const Batch& B, const void* orb, int dt, double* rho_ws, long long rstride,
+                         double* rho_scale, hipStream_t s);
 // Rows of the moment tables, and how many of them the matrix cores take:
 // (l_max + 1)^2 padded to a multiple of 16, except that FP64 tables keep up to
 // 4 rows past the last full 16-row tile for the vector ALU.
 void moment_layout(int l_max, bool mixed, int* rows, int* mfma_rows);
 // Number of point chunks the moment launch of a batch of nb pairs uses.
 int moment_splits(long long nb, int ncls, long long max_pe);
-// Moments of the batch [pbeg, pbeg + nb) of the processing order into Q_ws;
-// class_cnt holds the per-class pair counts of the order (device); Qp holds
-// splits * nb * kMaxLM partial sums; rho rows are zero-padded to 32 points.
-hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cnt, int ncls, bool mixed,
-                          long long pbeg, long long nb, const double* rho_ws, long long rstride,
-                          const double* rho_scale, double* Qp, int splits, double* Q_ws, hipStream_t s);
-hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                           long long nb, long long max_halo, const double* Q_ws, double* halo_ws, long long hstride,
-                           hipStream_t s);
+// Moments of the batch into Q_ws; class_cnt holds the per-class pair counts of
+// the order (device); Qp holds splits * nb * kMaxLM partial sums; rho rows are
+// zero-padded to 32 points.
+hipError_t launch_moments(const Geo& g, const Batch& B, const int* class_cnt, int ncls, bool mixed,
+                          const double* rho_ws, long long rstride, const double* rho_scale, double* Qp, int splits,
+                          double* Q_ws, hipStream_t s);
+hipError_t launch_boundary(const Geo& g, const Batch& B, long long max_halo, const double* Q_ws, double* halo_ws,
+                           long long hstride, hipStream_t s);
 
 struct SolveArgs {
   Geo g;
   const ClassDev* cls = nullptr;
   const PairDev* pairs = nullptr;
   const int* order = nullptr;
-  long long p0 = 0, npair = 0;
+  long long p0 = 0, npair = 0;   // batch start and capacity
+  const int* n_eff = nullptr;    // device pair count of the processing order
   int* queue = nullptr;
   double* bx_ws = nullptr;     // per pair: right-hand side in, solution out
   long long rstride = 0;
@@ -62,30 +79,29 @@ struct SolveArgs {
   int depth = 1;               // planes of loads in flight ahead of their use (1 or 2)
 };
 
-hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                      long long nb, long long max_pe, const double* rho_ws, double* b_ws, long long rstride,
-                      const double* halo_ws, long long hstride, hipStream_t s);
+hipError_t launch_rhs(const Geo& g, const Batch& B, long long max_pe, const double* rho_ws, double* b_ws,
+                      long long rstride, const double* halo_ws, long long hstride, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s);
 size_t solve_lds_bytes(const Geo& g, int max_zmax);
 int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, int threads, int depth);
 bool solve_supported(int max_cols, int threads);
 long long solve_slot_bytes(bool mixed, long long sstride);
-hipError_t launch_finalize(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                           long long nb, const double* rho_ws, const double* v_ws, long long rstride,
+hipError_t launch_finalize(const Geo& g, const Batch& B, const double* rho_ws, const double* v_ws, long long rstride,
                            const double* halo_ws, long long hstride, double* outE, double* outS, hipStream_t s);
-
-hipError_t launch_dscatter(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                           long long nb, long long max_me, const void* orb, void* D, int dt, const double* v_ws,
-                           long long rstride, const double* Q_ws, hipStream_t s);
+// D^i += v phi_j (and D^j += v phi_i) into row d_slot[i] of D, or row i when
+// d_slot is null; rows with d_slot = -1 are not written.
+hipError_t launch_dscatter(const Geo& g, const Batch& B, long long max_me, const void* orb, void* D,
+                           const int* d_slot, int dt, const double* v_ws, long long rstride, const double* Q_ws,
+                           hipStream_t s);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
 // E_xx and sigma from per-pair results in canonical order; stats[8] receives
-// (iter_sum, iter_max, n_unconverged, max_res, n_pairs, sum iters*N_PE,
-//  refinement passes max, sum N_PE) as doubles.
+// (iter_sum, iter_max, n_unconverged, max_res, n_pairs kept (also beyond the
+// capacity), sum iters*N_PE, refinement passes max, sum N_PE) as doubles.
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
-                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, int max_iter,
-                         double* E, double* sigma, double* stats, hipStream_t s);
+                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
+                         int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
 
 }  // namespace exx

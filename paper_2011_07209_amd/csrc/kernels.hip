@@ -128,10 +128,12 @@ __global__ void k_pair_fill(Geo g, PairParams pp, const double* __restrict__ C, 
 // first.  One workgroup: each thread takes a contiguous chunk of pairs.
 __global__ __launch_bounds__(1024) void k_pair_order(const PairDev* __restrict__ pairs, const int* __restrict__ cnt,
                                                      int n_orb, int n_class, int* __restrict__ order,
-                                                     int* __restrict__ class_cnt) {
+                                                     int* __restrict__ class_cnt, long long cap,
+                                                     int* __restrict__ n_eff) {
   __shared__ int tcount[kMaxClasses][1024];
   const int t = threadIdx.x, nt = blockDim.x;
-  const long long np = cnt[2 * n_orb];
+  const long long np = min((long long)cnt[2 * n_orb], cap);   // pairs beyond the capacity were not stored
+  if (t == 0) *n_eff = (int)np;
   const long long per = (np + nt - 1) / nt;
   const long long lo = t * per, hi = min(np, lo + per);
   int c[kMaxClasses];
@@ -169,10 +171,12 @@ __device__ __forceinline__ double ldv(const TO* p, long long i) { return (double
 template <typename TO>
 __global__ __launch_bounds__(256) void k_gather(Geo g, const ClassDev* __restrict__ cls,
                                                 const PairDev* __restrict__ pairs, const int* __restrict__ order,
-                                                long long p0, const TO* __restrict__ orb, double* __restrict__ rho_ws,
+                                                long long p0, const int* __restrict__ n_eff,
+                                                const TO* __restrict__ orb, double* __restrict__ rho_ws,
                                                 long long rstride, double* __restrict__ rho_scale) {
   __shared__ double red[4];
   const int b = blockIdx.x;
+  if (p0 + b >= *n_eff) return;
   const PairDev P = pairs[order[p0 + b]];
   const ClassDev& C = cls[P.cls];
   const TO* phi_i = orb + (long long)P.i * g.ngrid;
@@ -203,11 +207,13 @@ __global__ __launch_bounds__(256) void k_gather(Geo g, const ClassDev* __restric
 template <int L>
 __global__ __launch_bounds__(256) void k_boundary(Geo g, const ClassDev* __restrict__ cls,
                                                   const PairDev* __restrict__ pairs, const int* __restrict__ order,
-                                                  long long p0, const double* __restrict__ Q_ws,
-                                                  double* __restrict__ halo_ws, long long hstride) {
+                                                  long long p0, const int* __restrict__ n_eff,
+                                                  const double* __restrict__ Q_ws, double* __restrict__ halo_ws,
+                                                  long long hstride) {
   constexpr int NLM = (L + 1) * (L + 1);
   __shared__ double Q[NLM];
   const int b = blockIdx.y;
+  if (p0 + b >= *n_eff) return;
   const PairDev P = pairs[order[p0 + b]];
   const ClassDev& C = cls[P.cls];
   if (threadIdx.x < NLM) Q[threadIdx.x] = Q_ws[(long long)b * kMaxLM + threadIdx.x];
@@ -237,10 +243,11 @@ __device__ __forceinline__ double point_value(const ClassDev& C, int n, const do
 // far-field values (eq. pe discretised with eq. d2_1)
 __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__ cls, const PairDev* __restrict__ pairs,
                                              const int* __restrict__ order, long long p0,
-                                             const double* __restrict__ rho_ws, double* __restrict__ b_ws,
-                                             long long rstride, const double* __restrict__ halo_ws,
-                                             long long hstride) {
+                                             const int* __restrict__ n_eff, const double* __restrict__ rho_ws,
+                                             double* __restrict__ b_ws, long long rstride,
+                                             const double* __restrict__ halo_ws, long long hstride) {
   const int bq = blockIdx.y;
+  if (p0 + bq >= *n_eff) return;
   const PairDev P = pairs[order[p0 + bq]];
   const ClassDev& C = cls[P.cls];
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,12 +275,14 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__
 // sum_al J_{a al} dv/dxi_al from the first-derivative stencil (eq. d1_1).
 __global__ __launch_bounds__(256) void k_finalize(Geo g, const ClassDev* __restrict__ cls,
                                                   const PairDev* __restrict__ pairs, const int* __restrict__ order,
-                                                  long long p0, const double* __restrict__ rho_ws,
+                                                  long long p0, const int* __restrict__ n_eff,
+                                                  const double* __restrict__ rho_ws,
                                                   const double* __restrict__ v_ws, long long rstride,
                                                   const double* __restrict__ halo_ws, long long hstride,
                                                   double* __restrict__ outE, double* __restrict__ outS) {
   __shared__ double red[4];
   const int bq = blockIdx.x;
+  if (p0 + bq >= *n_eff) return;
   const int pid = order[p0 + bq];
   const PairDev P = pairs[pid];
   const ClassDev& C = cls[P.cls];
@@ -323,12 +332,15 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const ClassDev* __restr
 template <int L, typename TO>
 __global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restrict__ cls,
                                                   const PairDev* __restrict__ pairs, const int* __restrict__ order,
-                                                  long long p0, const TO* __restrict__ orb, TO* __restrict__ D,
+                                                  long long p0, const int* __restrict__ n_eff,
+                                                  const TO* __restrict__ orb, TO* __restrict__ D,
+                                                  const int* __restrict__ d_slot,
                                                   const double* __restrict__ v_ws, long long rstride,
                                                   const double* __restrict__ Q_ws) {
   constexpr int NLM = (L + 1) * (L + 1);
   __shared__ double Q[NLM];
   const int b = blockIdx.y;
+  if (p0 + b >= *n_eff) return;
   const PairDev P = pairs[order[p0 + b]];
   const ClassDev& C = cls[P.cls];
   if (threadIdx.x < NLM) Q[threadIdx.x] = Q_ws[(long long)b * kMaxLM + threadIdx.x];
@@ -342,11 +354,13 @@ __global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restr
   const int gy = wrapi(P.c[1] + o.y, g.N[1]);
   const int gz = wrapi(P.c[2] + o.z, g.N[2]);
   const long long gi = gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
-  const long long oi = (long long)P.i * g.ngrid + gi;
-  const long long oj = (long long)P.j * g.ngrid + gi;
-  const double fi = (double)orb[oi], fj = (double)orb[oj];
-  unsafeAtomicAdd(&D[oi], (TO)(v * fj));
-  if (P.i != P.j) unsafeAtomicAdd(&D[oj], (TO)(v * fi));
+  const double fi = (double)orb[(long long)P.i * g.ngrid + gi];
+  const double fj = (double)orb[(long long)P.j * g.ngrid + gi];
+  // output rows: the orbital itself, or its slot in the requested subset (-1: not written)
+  const int si = d_slot ? d_slot[P.i] : P.i;
+  const int sj = d_slot ? d_slot[P.j] : P.j;
+  if (si >= 0) unsafeAtomicAdd(&D[(long long)si * g.ngrid + gi], (TO)(v * fj));
+  if (P.i != P.j && sj >= 0) unsafeAtomicAdd(&D[(long long)sj * g.ngrid + gi], (TO)(v * fi));
 }
 
 template <typename T>
@@ -357,15 +371,26 @@ __global__ void k_zero(T* p, long long n) {
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+// slot[i] = position of orbital i in the D subset, or -1 (entries outside
+// [0, n_orb) are skipped; the caller guarantees distinct entries)
+__global__ void k_dslot_clear(int* slot, int n_orb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_orb) slot[i] = -1;
+}
+__global__ void k_dslot_fill(int* slot, int n_orb, const int* __restrict__ subset, int n_subset) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_subset && subset[s] >= 0 && subset[s] < n_orb) slot[subset[s]] = s;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, const double* __restrict__ pS,
                                                 const int* __restrict__ pIt, const double* __restrict__ pRes,
                                                 const int* __restrict__ pUpd,
                                                 const PairDev* __restrict__ pairs, const ClassDev* __restrict__ cls,
-                                                const int* __restrict__ cnt, int n_orb, int max_iter,
-                                                double* __restrict__ E, double* __restrict__ sigma,
+                                                const int* __restrict__ cnt, int n_orb, const int* __restrict__ n_eff,
+                                                int max_iter, double* __restrict__ E, double* __restrict__ sigma,
                                                 double* __restrict__ stats) {
   __shared__ double red[4];
-  const long long np = cnt[2 * n_orb];
+  const long long np = *n_eff;
   double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0, umax = 0.0;
   for (int t = 0; t < 9; ++t) s[t] = 0.0;
   for (long long k = threadIdx.x; k < np; k += blockDim.x) {
@@ -412,7 +437,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     stats[1] = imax;
     stats[2] = nunc;
     stats[3] = rmax;
-    stats[4] = (double)np;
+    stats[4] = (double)cnt[2 * n_orb];   // every kept pair, also those beyond the capacity
     stats[5] = work;
     stats[6] = umax;
     stats[7] = pts;
@@ -433,10 +458,16 @@ hipError_t launch_pairlist(const Geo& g, const PairParams& pp, const double* cen
   return hipGetLastError();
 }
 
-hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order,
-                        hipStream_t s) {
+hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int n_class, int* order, long long cap,
+                        int* n_eff, hipStream_t s) {
   int* class_cnt = const_cast<int*>(counts) + 2 * n_orb + 1;
-  k_pair_order<<<1, 1024, 0, s>>>(pairs, counts, n_orb, n_class, order, class_cnt);
+  k_pair_order<<<1, 1024, 0, s>>>(pairs, counts, n_orb, n_class, order, class_cnt, cap, n_eff);
+  return hipGetLastError();
+}
+
+hipError_t launch_dslot(int* slot, int n_orb, const int* subset, int n_subset, hipStream_t s) {
+  k_dslot_clear<<<(n_orb + 255) / 256, 256, 0, s>>>(slot, n_orb);
+  if (n_subset > 0) k_dslot_fill<<<(n_subset + 255) / 256, 256, 0, s>>>(slot, n_orb, subset, n_subset);
   return hipGetLastError();
 }
 
@@ -454,57 +485,56 @@ hipError_t launch_order(const PairDev* pairs, const int* counts, int n_orb, int 
     default: return hipErrorInvalidValue;            \
   }
 
-hipError_t launch_gather(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                         long long nb, const void* orb, int dt, double* rho_ws, long long rstride, double* rho_scale,
-                         hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
+hipError_t launch_gather(const Geo& g, const Batch& B, const void* orb, int dt, double* rho_ws, long long rstride,
+                         double* rho_scale, hipStream_t s) {
+  if (B.nb <= 0) return hipSuccess;
   if (dt == EXX_F64)
-    k_gather<double><<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, (const double*)orb, rho_ws, rstride,
-                                                  rho_scale);
+    k_gather<double><<<(unsigned)B.nb, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, (const double*)orb,
+                                                    rho_ws, rstride, rho_scale);
   else
-    k_gather<float><<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, (const float*)orb, rho_ws, rstride,
-                                                 rho_scale);
+    k_gather<float><<<(unsigned)B.nb, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, (const float*)orb,
+                                                   rho_ws, rstride, rho_scale);
   return hipGetLastError();
 }
 
-hipError_t launch_boundary(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                           long long nb, long long max_halo, const double* Q_ws, double* halo_ws, long long hstride,
-                           hipStream_t s) {
-  if (nb <= 0 || max_halo <= 0) return hipSuccess;
-  dim3 grid((unsigned)((max_halo + 255) / 256), (unsigned)nb);
-  EXX_L_DISPATCH(g.l_max, (k_boundary<LL><<<grid, 256, 0, s>>>(g, cls, pairs, order, p0, Q_ws, halo_ws, hstride)));
+hipError_t launch_boundary(const Geo& g, const Batch& B, long long max_halo, const double* Q_ws, double* halo_ws,
+                           long long hstride, hipStream_t s) {
+  if (B.nb <= 0 || max_halo <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_halo + 255) / 256), (unsigned)B.nb);
+  EXX_L_DISPATCH(g.l_max, (k_boundary<LL><<<grid, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, Q_ws,
+                                                               halo_ws, hstride)));
   return hipGetLastError();
 }
 
-hipError_t launch_rhs(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                      long long nb, long long max_pe, const double* rho_ws, double* b_ws, long long rstride,
-                      const double* halo_ws, long long hstride, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
-  dim3 grid((unsigned)((max_pe + 255) / 256), (unsigned)nb);
-  k_rhs<<<grid, 256, 0, s>>>(g, cls, pairs, order, p0, rho_ws, b_ws, rstride, halo_ws, hstride);
+hipError_t launch_rhs(const Geo& g, const Batch& B, long long max_pe, const double* rho_ws, double* b_ws,
+                      long long rstride, const double* halo_ws, long long hstride, hipStream_t s) {
+  if (B.nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_pe + 255) / 256), (unsigned)B.nb);
+  k_rhs<<<grid, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, rho_ws, b_ws, rstride, halo_ws, hstride);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                           long long nb, const double* rho_ws, const double* v_ws, long long rstride,
+hipError_t launch_finalize(const Geo& g, const Batch& B, const double* rho_ws, const double* v_ws, long long rstride,
                            const double* halo_ws, long long hstride, double* outE, double* outS, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
-  k_finalize<<<(unsigned)nb, 256, 0, s>>>(g, cls, pairs, order, p0, rho_ws, v_ws, rstride, halo_ws, hstride, outE,
-                                          outS);
+  if (B.nb <= 0) return hipSuccess;
+  k_finalize<<<(unsigned)B.nb, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, rho_ws, v_ws, rstride,
+                                            halo_ws, hstride, outE, outS);
   return hipGetLastError();
 }
 
-hipError_t launch_dscatter(const Geo& g, const ClassDev* cls, const PairDev* pairs, const int* order, long long p0,
-                           long long nb, long long max_me, const void* orb, void* D, int dt, const double* v_ws,
-                           long long rstride, const double* Q_ws, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
-  dim3 grid((unsigned)((max_me + 255) / 256), (unsigned)nb);
+hipError_t launch_dscatter(const Geo& g, const Batch& B, long long max_me, const void* orb, void* D,
+                           const int* d_slot, int dt, const double* v_ws, long long rstride, const double* Q_ws,
+                           hipStream_t s) {
+  if (B.nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_me + 255) / 256), (unsigned)B.nb);
   if (dt == EXX_F64) {
-    EXX_L_DISPATCH(g.l_max, (k_dscatter<LL, double><<<grid, 256, 0, s>>>(
-                                g, cls, pairs, order, p0, (const double*)orb, (double*)D, v_ws, rstride, Q_ws)));
+    EXX_L_DISPATCH(g.l_max, (k_dscatter<LL, double><<<grid, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff,
+                                                                         (const double*)orb, (double*)D, d_slot,
+                                                                         v_ws, rstride, Q_ws)));
   } else {
-    EXX_L_DISPATCH(g.l_max, (k_dscatter<LL, float><<<grid, 256, 0, s>>>(
-                                g, cls, pairs, order, p0, (const float*)orb, (float*)D, v_ws, rstride, Q_ws)));
+    EXX_L_DISPATCH(g.l_max, (k_dscatter<LL, float><<<grid, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff,
+                                                                        (const float*)orb, (float*)D, d_slot,
+                                                                        v_ws, rstride, Q_ws)));
   }
   return hipGetLastError();
 }
@@ -529,9 +559,9 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
-                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, int max_iter,
-                         double* E, double* sigma, double* stats, hipStream_t s) {
-  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pairs, cls, counts, n_orb, max_iter, E, sigma, stats);
+                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
+                         int max_iter, double* E, double* sigma, double* stats, hipStream_t s) {
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pairs, cls, counts, n_orb, n_eff, max_iter, E, sigma, stats);
   return hipGetLastError();
 }
 

@@ -52,7 +52,9 @@ constexpr int kFoldSteps = 16;                            // 32-point steps betw
 // (descending class index) with class_cnt[k] pairs each; the tiles of one
 // class never straddle a class boundary.  Returns false for surplus groups.
 __device__ __forceinline__ bool locate_tile(const int* __restrict__ class_cnt, int ncls, long long pbeg,
-                                            long long pend, int* cls, long long* tb, long long* te) {
+                                            long long pend, const int* __restrict__ n_eff, int* cls, long long* tb,
+                                            long long* te) {
+  if (pend > *n_eff) pend = *n_eff;
   long long t = blockIdx.x, start = 0;
   for (int k = ncls - 1; k >= 0; --k) {
     const long long cnt = class_cnt[k];
@@ -85,11 +87,12 @@ template <int RT, int REM, int kColTiles = kColTilesF64>
 __global__ __launch_bounds__(kTilePairs / kColTiles * 4) void k_moments_f64(const ClassDev* __restrict__ cls_tab,
                                                              const int* __restrict__ class_cnt, int ncls,
                                                              long long pbeg, long long pend,
+                                                             const int* __restrict__ n_eff,
                                                              const double* __restrict__ rho_ws, long long rstride,
                                                              double* __restrict__ Qp, long long nb) {
   int cls;
   long long tb, te;
-  if (!locate_tile(class_cnt, ncls, pbeg, pend, &cls, &tb, &te)) return;
+  if (!locate_tile(class_cnt, ncls, pbeg, pend, n_eff, &cls, &tb, &te)) return;
   const ClassDev& C = cls_tab[cls];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
@@ -171,12 +174,13 @@ template <int RT, int kColTiles = kColTilesBF16>
 __global__ __launch_bounds__(kTilePairs / kColTiles * 4) void k_moments_bf16(const ClassDev* __restrict__ cls_tab,
                                                               const int* __restrict__ class_cnt, int ncls,
                                                               long long pbeg, long long pend,
+                                                              const int* __restrict__ n_eff,
                                                               const double* __restrict__ rho_ws, long long rstride,
                                                               const double* __restrict__ rho_scale,
                                                               double* __restrict__ Qp, long long nb) {
   int cls;
   long long tb, te;
-  if (!locate_tile(class_cnt, ncls, pbeg, pend, &cls, &tb, &te)) return;
+  if (!locate_tile(class_cnt, ncls, pbeg, pend, n_eff, &cls, &tb, &te)) return;
   const ClassDev& C = cls_tab[cls];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
@@ -267,10 +271,12 @@ __global__ __launch_bounds__(kTilePairs / kColTiles * 4) void k_moments_bf16(con
 
 // Q[b][lm] = dV N_lm scale_b sum_s Qp[s][b][lm], chunks added in order.
 __global__ __launch_bounds__(256) void k_moment_sum(Geo g, const double* __restrict__ Qp, int splits, long long nb,
+                                                    long long p0, const int* __restrict__ n_eff,
                                                     const double* __restrict__ rho_scale, double* __restrict__ Q_ws) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nb * g.n_lm) return;
   const long long b = t / g.n_lm;
+  if (p0 + b >= *n_eff) return;
   const int lm = (int)(t - b * g.n_lm);
   double s = 0.0;
   for (int c = 0; c < splits; ++c) s += Qp[((long long)c * nb + b) * kMaxLM + lm];
@@ -302,9 +308,12 @@ int moment_splits(long long nb, int ncls, long long max_pe) {
   return (int)std::max<long long>(s, 1);
 }
 
-hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cnt, int ncls, bool mixed,
-                          long long pbeg, long long nb, const double* rho_ws, long long rstride,
-                          const double* rho_scale, double* Qp, int splits, double* Q_ws, hipStream_t s) {
+hipError_t launch_moments(const Geo& g, const Batch& B, const int* class_cnt, int ncls, bool mixed,
+                          const double* rho_ws, long long rstride, const double* rho_scale, double* Qp, int splits,
+                          double* Q_ws, hipStream_t s) {
+  const long long nb = B.nb, pbeg = B.p0;
+  const ClassDev* cls = B.cls;
+  const int* n_eff = B.n_eff;
   if (nb <= 0) return hipSuccess;
   const long long tiles = (nb + kTilePairs - 1) / kTilePairs + ncls - 1;
   const dim3 grid((unsigned)tiles, (unsigned)splits);
@@ -316,7 +325,8 @@ hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cn
     switch (rows / 16) {
 #define EXX_MOM16(RT)                                                                                        \
   case RT:                                                                                                   \
-    k_moments_bf16<RT><<<grid, tb16, 0, s>>>(cls, class_cnt, ncls, pbeg, pend, rho_ws, rstride, rho_scale, Qp, nb); \
+    k_moments_bf16<RT><<<grid, tb16, 0, s>>>(cls, class_cnt, ncls, pbeg, pend, n_eff, rho_ws, rstride, rho_scale, Qp, \
+                                             nb);                                                                  \
     break;
       EXX_MOM16(1) EXX_MOM16(2) EXX_MOM16(3) EXX_MOM16(4) EXX_MOM16(5) EXX_MOM16(6)
 #undef EXX_MOM16
@@ -326,7 +336,8 @@ hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cn
     switch (8 * (mrows / 16) + (rows - mrows)) {
 #define EXX_MOM64(RT, REM)                                                                              \
   case 8 * RT + REM:                                                                                    \
-    k_moments_f64<RT, REM><<<grid, tb64, 0, s>>>(cls, class_cnt, ncls, pbeg, pend, rho_ws, rstride, Qp, nb); \
+    k_moments_f64<RT, REM><<<grid, tb64, 0, s>>>(cls, class_cnt, ncls, pbeg, pend, n_eff, rho_ws, rstride, Qp, \
+                                                 nb);                                                            \
     break;
       EXX_MOM64(1, 0) EXX_MOM64(2, 0) EXX_MOM64(2, 4) EXX_MOM64(3, 0) EXX_MOM64(3, 1) EXX_MOM64(4, 0)
       EXX_MOM64(5, 0) EXX_MOM64(5, 1) EXX_MOM64(6, 0)
@@ -337,7 +348,8 @@ hipError_t launch_moments(const Geo& g, const ClassDev* cls, const int* class_cn
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long n = nb * g.n_lm;
-  k_moment_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, Qp, splits, nb, mixed ? rho_scale : nullptr, Q_ws);
+  k_moment_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, Qp, splits, nb, pbeg, n_eff,
+                                                            mixed ? rho_scale : nullptr, Q_ws);
   return hipGetLastError();
 }
 

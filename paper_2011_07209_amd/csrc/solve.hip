@@ -27,6 +27,7 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.order = in.order;
   a.p0 = in.p0;
   a.npair = in.npair;
+  a.n_eff = in.n_eff;
   a.queue = in.queue;
   a.bx_ws = in.bx_ws;
   a.rstride = in.rstride;

@@ -37,7 +37,8 @@ struct SolveKArgs {
   const ClassDev* cls;
   const PairDev* pairs;
   const int* order;
-  long long p0, npair;
+  long long p0, npair;    // batch start and capacity; the batch holds min(npair, *n_eff - p0) pairs
+  const int* n_eff;       // device pair count of the processing order
   int* queue;
   double* bx_ws;          // per pair: right-hand side in, solution out
   long long rstride;
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
     __syncthreads();
     const long long item = s_item;
     __syncthreads();
-    if (item >= a.npair) break;
+    if (item >= a.npair || a.p0 + item >= (long long)*a.n_eff) break;
     const int pid = a.order[a.p0 + item];
     const ClassDev& C = a.cls[a.pairs[pid].cls];
     const int Zmax = C.Zmax;
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     __syncthreads();
     const long long item = s_item;
     __syncthreads();
-    if (item >= a.npair) break;
+    if (item >= a.npair || a.p0 + item >= (long long)*a.n_eff) break;
     const int pid = a.order[a.p0 + item];
     const ClassDev& C = a.cls[a.pairs[pid].cls];
     const int Zmax = C.Zmax;

@@ -71,6 +71,8 @@ class Stats(ctypes.Structure):
         ("tune_ms", ctypes.c_double),
         ("moment_ms", ctypes.c_double),
         ("moment_mfma_flops", ctypes.c_double),
+        ("pairs_kept", ctypes.c_longlong),
+        ("graph_recorded", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -101,7 +103,7 @@ def load():
     lib.exx_set_stream.restype = ctypes.c_int
     lib.exx_set_stream.argtypes = [vp, vp]
     lib.exx_eval.restype = ctypes.c_int
-    lib.exx_eval.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.exx_eval.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.exx_pair_results.restype = ctypes.c_int
     lib.exx_pair_results.argtypes = [vp, ctypes.c_longlong, ip, dp, dp, ip, dp, llp]
     lib.exx_stats_fetch.restype = ctypes.c_int
@@ -163,7 +165,7 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def exx_eval(plan, orbitals: torch.Tensor, centres: torch.Tensor, E_xx: torch.Tensor,
              D_xx: Optional[torch.Tensor] = None, sigma: Optional[torch.Tensor] = None,
-             R_PE_orb: Optional[torch.Tensor] = None):
+             R_PE_orb: Optional[torch.Tensor] = None, d_subset: Optional[torch.Tensor] = None):
     """Enqueues one evaluation; tensors are device tensors laid out as in exx.h."""
     if orbitals.dtype == torch.float64:
         dt = EXX_F64
@@ -172,18 +174,24 @@ def exx_eval(plan, orbitals: torch.Tensor, centres: torch.Tensor, E_xx: torch.Te
     else:
         raise ExxError(EXX_EINVAL, "orbitals must be float64 or float32")
     for name, t in (("orbitals", orbitals), ("centres", centres), ("E_xx", E_xx), ("D_xx", D_xx),
-                    ("sigma", sigma), ("R_PE_orb", R_PE_orb)):
+                    ("sigma", sigma), ("R_PE_orb", R_PE_orb), ("d_subset", d_subset)):
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
             raise ExxError(EXX_EINVAL, f"{name} must be a contiguous device tensor")
     if centres.dtype != torch.float64 or E_xx.dtype != torch.float64:
         raise ExxError(EXX_EINVAL, "centres and E_xx must be float64")
-    if D_xx is not None and (D_xx.dtype != orbitals.dtype or D_xx.numel() != orbitals.numel()):
-        raise ExxError(EXX_EINVAL, "D_xx must match the orbitals' dtype and size")
     n_orb = orbitals.shape[0]
+    n_subset = 0
+    if d_subset is not None:
+        if d_subset.dtype != torch.int32:
+            raise ExxError(EXX_EINVAL, "d_subset must be int32")
+        n_subset = d_subset.numel()
+    rows = n_subset if d_subset is not None else n_orb
+    if D_xx is not None and (D_xx.dtype != orbitals.dtype or D_xx.numel() != rows * (orbitals.numel() // n_orb)):
+        raise ExxError(EXX_EINVAL, "D_xx must match the orbitals' dtype and hold one grid per requested orbital")
     if centres.numel() != 3 * n_orb:
         raise ExxError(EXX_EINVAL, "centres must be [n_orb, 3]")
-    st = load().exx_eval(plan, int(n_orb), _ptr(orbitals), dt, _ptr(centres), _ptr(R_PE_orb), _ptr(E_xx),
-                         _ptr(D_xx), _ptr(sigma))
+    st = load().exx_eval(plan, int(n_orb), _ptr(orbitals), dt, _ptr(centres), _ptr(R_PE_orb), _ptr(d_subset),
+                         int(n_subset), _ptr(E_xx), _ptr(D_xx), _ptr(sigma))
     _check(st, plan)
 
 
@@ -207,10 +215,10 @@ def exx_pair_results(plan):
             "rel_res": res[:m]}
 
 
-def exx_stats_fetch(plan, allow_noconv: bool = False) -> dict:
+def exx_stats_fetch(plan, allow_noconv: bool = False, allow_capacity: bool = False) -> dict:
     s = Stats()
     st = load().exx_stats_fetch(plan, ctypes.byref(s))
-    if not (allow_noconv and st == EXX_ENOCONV):
+    if not ((allow_noconv and st == EXX_ENOCONV) or (allow_capacity and st == EXX_ECAPACITY)):
         _check(st, plan)
     d = s.as_dict()
     d["status"] = st
@@ -248,18 +256,22 @@ class Plan:
         self.handle = exx_plan(h, grid, R_pair, R_PE, R_ME, l_max, self.opt)
         exx_set_stream(self.handle)
 
-    def eval(self, orbitals, centres, E_xx=None, D_xx=None, sigma=None, R_PE_orb=None):
+    def eval(self, orbitals, centres, E_xx=None, D_xx=None, sigma=None, R_PE_orb=None, d_subset=None):
         dev = orbitals.device
         if E_xx is None:
             E_xx = torch.zeros(1, dtype=torch.float64, device=dev)
-        exx_eval(self.handle, orbitals, centres, E_xx, D_xx, sigma, R_PE_orb)
+        exx_eval(self.handle, orbitals, centres, E_xx, D_xx, sigma, R_PE_orb, d_subset)
         return E_xx
+
+    def set_stream(self, stream=None):
+        """Binds the stream later calls enqueue on (default: torch's current stream)."""
+        exx_set_stream(self.handle, stream)
 
     def pair_results(self):
         return exx_pair_results(self.handle)
 
-    def stats(self, allow_noconv=False):
-        return exx_stats_fetch(self.handle, allow_noconv)
+    def stats(self, allow_noconv=False, allow_capacity=False):
+        return exx_stats_fetch(self.handle, allow_noconv, allow_capacity)
 
     def geometry(self, cls=0):
         return exx_plan_geometry(self.handle, cls)

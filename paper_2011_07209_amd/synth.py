@@ -189,6 +189,38 @@ def fill_orbitals(cfg: Config, orbs: OrbitalSet, dtype=np.float64, subset: Optio
     return arr
 
 
+def fill_orbitals_device(cfg: Config, orbs: OrbitalSet, device, dtype=None, out=None, subset=None):
+    """fill_orbitals on a GPU with torch, for sets too large to build on the host
+    and ship (58 GB of FP64 orbitals for the 256-molecule set).  Same formula,
+    same order of the elementwise operations, FP64 arithmetic; the norm is a
+    device reduction, so values agree with the host generator to rounding.
+    Returns a [n, N3, N2, N1] tensor (or fills `out`)."""
+    import torch
+    if dtype is None:
+        dtype = torch.float32 if cfg.orb_dtype == "f32" else torch.float64
+    idx = range(cfg.n_orb) if subset is None else list(subset)
+    N1, N2, N3 = cfg.grid
+    if out is None:
+        out = torch.empty((len(idx), N3, N2, N1), dtype=dtype, device=device)
+    dV = float(np.prod(cfg.cell)) / float(N1 * N2 * N3)
+
+    def axis(N, L, c):
+        d = torch.arange(N, dtype=torch.float64, device=device) * (L / N) - c
+        return d - L * torch.floor(d / L + 0.5)
+
+    for k, i in enumerate(idx):
+        c, a, pc = orbs.centres[i], float(orbs.expo[i]), orbs.poly[i]
+        dx, dy, dz = axis(N1, cfg.cell[0], float(c[0])), axis(N2, cfg.cell[1], float(c[1])), axis(N3, cfg.cell[2],
+                                                                                                  float(c[2]))
+        ex, ey, ez = torch.exp(-a * dx * dx), torch.exp(-a * dy * dy), torch.exp(-a * dz * dz)
+        g = (ez[:, None, None] * ey[None, :, None]) * ex[None, None, :]
+        lin = 1.0 + float(pc[2]) * dz[:, None, None] + float(pc[1]) * dy[None, :, None] + float(pc[0]) * dx[None, None, :]
+        phi = g * lin
+        phi *= 1.0 / math.sqrt(dV * float(torch.dot(phi.reshape(-1), phi.reshape(-1)).item()))
+        out[k].copy_(phi)
+    return out
+
+
 def custom(key="custom", cell=(12.0, 12.0, 12.0), grid=(48, 48, 48), n_orb=4, R_pair=8.0, R_PE=4.0, R_ME=5.5,
            l_max=6, stencil_n=3, cg_tol=1e-12, expo=(0.9, 1.6), seed_index=17, **kw) -> Config:
     """A small configuration for tests (uniform random centres)."""
