@@ -10,8 +10,11 @@ hipError_t solve_dispatch_n2(const SolveKArgs& a, bool mixed, int max_cols, int 
 hipError_t solve_dispatch_n3(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
                              size_t lds, hipStream_t s, int* occ);
 
+// Two plane buffers, then the plane offsets of the class, with room for the
+// sweeps' look-ahead reads a few planes past the last one (their values are
+// discarded).
 size_t solve_lds_bytes(const Geo& g, int max_zmax) {
-  return (size_t)2 * kLdsWX * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2) * sizeof(int);
+  return (size_t)2 * kLdsWX * g.lds_wy * sizeof(double) + (size_t)(2 * max_zmax + 2 + 8) * sizeof(int);
 }
 
 long long solve_slot_bytes(bool mixed, long long sstride) {

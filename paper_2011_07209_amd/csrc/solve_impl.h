@@ -261,61 +261,31 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
   return acc;
 }
 
-// Reliable update of the mixed-precision solve, in FP64: the accumulated FP32
-// correction y (in units of ys) is folded into the FP64 solution, w = x + ys y,
-// and the true residual b - A w is recomputed and stored, times rs and
-// rounded to FP32, as the new working residual.  Returns this thread's FP64
-// sum of the (unscaled) true residual^2.
-template <int NS, int CPT, int PD>
-__device__ double cg_update(const StencilT<double>& S, const Cols<CPT>& cl, const int* pst, int Zmax,
-                            double* __restrict__ x, const float* __restrict__ y, bool x_zero, bool y_zero,
-                            const double* __restrict__ b, float* __restrict__ r, double ys, double rs, double* pl0,
-                            double* pl1) {
+// Reliable update of the mixed-precision solve, in FP64, second half: with the
+// accumulated FP32 correction already folded into the FP64 solution x (see
+// k_solve_mixed), the true residual b - A x is recomputed and stored, times rs
+// and rounded to FP32, as the new working residual.  Returns this thread's
+// FP64 sum of the (unscaled) true residual^2.  One plane of loads ahead: the
+// pass runs a few times per solve, and its registers bound the whole kernel's.
+template <int NS, int CPT>
+__device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& cl, const int* pst, int Zmax,
+                                   const double* __restrict__ x, const double* __restrict__ b,
+                                   float* __restrict__ r, double rs, double* pl0, double* pl1) {
   double win[CPT][2 * NS + 1];
-  double qx[PD][CPT];
-  float qy[PD][CPT];
-  double cb[CPT];
-  auto fold = [&](int c, int zz, double xv, float yv) -> double {
-    if (!EXX_VALID(c, zz)) return 0.0;
-    const double w = xv + ys * (double)yv;
-    x[EXX_IDX(c, zz)] = w;
-    return w;
-  };
-  auto raw = [&](int c, int zz, double& xv, float& yv) {
-    xv = 0.0;
-    yv = 0.0f;
-    if (EXX_VALID(c, zz)) {
-      const int idx = EXX_IDX(c, zz);
-      if (!x_zero) xv = x[idx];
-      if (!y_zero) yv = y[idx];
-    }
-  };
 #pragma unroll
   for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      double xv;
-      float yv;
-      raw(c, -Zmax - NS + k, xv, yv);
-      win[c][k] = fold(c, -Zmax - NS + k, xv, yv);
-    }
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_VALID(c, zz) ? x[EXX_IDX(c, zz)] : 0.0;
   }
-#pragma unroll
-  for (int d = 0; d < PD; ++d) {
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) raw(c, -Zmax + NS + 1 + d, qx[d][c], qy[d][c]);
-  }
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) cb[c] = EXX_VALID(c, -Zmax) ? b[EXX_IDX(c, -Zmax)] : 0.0;
   double acc = 0.0;
   for (int z = -Zmax; z <= Zmax; ++z) {
-    const int zl = z + NS + PD + 1;
-    double nx[CPT], nb[CPT];
-    float ny[CPT];
+    const int zc = z + NS + 1;        // plane entering the window
+    double nx[CPT], cb[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      raw(c, zl, nx[c], ny[c]);
-      nb[c] = EXX_VALID(c, z + 1) ? b[EXX_IDX(c, z + 1)] : 0.0;
+      nx[c] = EXX_VALID(c, zc) ? x[EXX_IDX(c, zc)] : 0.0;
+      cb[c] = EXX_VALID(c, z) ? b[EXX_IDX(c, z)] : 0.0;
     }
     double* pl = (z & 1) ? pl1 : pl0;
 #pragma unroll
@@ -330,20 +300,11 @@ __device__ double cg_update(const StencilT<double>& S, const Cols<CPT>& cl, cons
         acc += rt * rt;
       }
     }
-    const int zc = z + NS + 1;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
 #pragma unroll
       for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
-      win[c][2 * NS] = fold(c, zc, qx[0][c], qy[0][c]);
-#pragma unroll
-      for (int d = 0; d + 1 < PD; ++d) {
-        qx[d][c] = qx[d + 1][c];
-        qy[d][c] = qy[d + 1][c];
-      }
-      qx[PD - 1][c] = nx[c];
-      qy[PD - 1][c] = ny[c];
-      cb[c] = nb[c];
+      win[c][2 * NS] = nx[c];
     }
   }
   return acc;
@@ -510,12 +471,14 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         break;
       }
       if (rnorm < a.delta * rmax || rnorm <= a.tol || it >= a.max_iter) {
-        // the FP64 and FP32 plane views share LDS: clear it around the FP64 pass
+        // fold the FP32 correction into the FP64 solution, x = x + ||b|| y
+        // (a flat pass over the points), then the FP64 true residual; the
+        // FP64 and FP32 plane views share LDS, so it is cleared around the
+        // FP64 pass (the barrier also orders the fold before the sweep)
+        for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
-        rr_true = block_sum(cg_update<NS, CPT, PD>(a.S, cl, pst, Zmax, x, y, x_zero, y_zero, bx, r, bnorm, inv_b,
-                                                   pl0, pl1),
-                            red);
+        rr_true = block_sum(cg_true_residual<NS, CPT>(a.S, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
         ++upd;
