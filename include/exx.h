@@ -121,6 +121,14 @@ exx_status exx_eval(exx_plan_t plan, int n_orb, const void* orbitals, exx_dtype 
                     const double* R_PE_orb, const int* d_subset, int n_subset, double* E_xx, void* D_xx,
                     double* sigma);
 
+/* Number of pairs exx_eval would form for these centres (and radii), for
+   sizing max_pairs.  centres and R_PE_orb as in exx_eval (device).  Enqueues
+   the pair-list kernels on the bound stream and waits for them; not for use
+   while the stream is recorded into a graph.  Does not disturb the results
+   of the last exx_eval beyond its per-orbital pair counts. */
+exx_status exx_count_pairs(exx_plan_t plan, int n_orb, const double* centres, const double* R_PE_orb,
+                           long long* n_pairs);
+
 /* Per-pair results of the last exx_eval, copied to host arrays of capacity
    cap (any may be NULL): ij [2*cap] (i, j), E [cap] (weighted contribution),
    sigma [9*cap], iters [cap], rel_res [cap] (final recursive ||r||/||b||).

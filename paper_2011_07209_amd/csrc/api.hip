@@ -726,6 +726,46 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   return EXX_OK;
 }
 
+exx_status exx_count_pairs(exx_plan_t P, int n_orb, const double* centres, const double* R_PE_orb,
+                           long long* n_pairs) {
+  if (!P || !n_pairs) return fail(P, EXX_EINVAL, "plan or n_pairs is NULL");
+  if (n_orb < 1 || !centres) return fail(P, EXX_EINVAL, "n_orb >= 1 and centres are required");
+  if (P->opt.R_PE_nclass > 0 && !R_PE_orb)
+    return fail(P, EXX_EINVAL, "variable radii need per-orbital radii (R_PE_orb)");
+  int dev = -1;
+  EXX_HIP(P, hipGetDevice(&dev));
+  if (dev != P->device) return fail(P, EXX_EINVAL, "current device differs from the plan's device");
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  EXX_HIP(P, hipStreamIsCapturing(P->stream, &cap_status));
+  if (cap_status != hipStreamCaptureStatusNone) return fail(P, EXX_EINVAL, "exx_count_pairs waits on the host");
+  if (P->timing_valid && !P->harvested) {   // keep the last evaluation's statistics
+    EXX_HIP(P, hipEventSynchronize(P->ev[3]));
+    exx_status hs = harvest(P);
+    if (hs != EXX_OK) return hs;
+  }
+  if (n_orb > P->orb_cap) {
+    if (dev_alloc(P, &P->pair_count, (size_t)2 * n_orb + 1 + kMaxClasses, "pair counts") ||
+        dev_alloc(P, &P->d_slot, (size_t)n_orb, "D subset slots"))
+      return EXX_ENOMEM;
+    P->orb_cap = n_orb;
+  }
+  PairParams pp;
+  pp.R_pair2 = P->R_pair * P->R_pair * (1.0 + kSlack);
+  pp.R_PE = P->R_PE;
+  pp.R_min = P->opt.R_PE_min;
+  pp.R_step = P->opt.R_PE_step;
+  pp.n_class = P->opt.R_PE_nclass;
+  pp.seed = P->opt.pair_sample_seed;
+  pp.frac = P->opt.pair_sample_frac;
+  // capacity 0: count and scan only, nothing is stored
+  EXX_HIP(P, launch_pairlist(P->geo, pp, centres, R_PE_orb, n_orb, P->pair_count, nullptr, 0, P->stream));
+  int total = 0;
+  EXX_HIP(P, hipMemcpyAsync(&total, P->pair_count + 2 * n_orb, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  EXX_HIP(P, hipStreamSynchronize(P->stream));
+  *n_pairs = total;
+  return EXX_OK;
+}
+
 exx_status exx_pair_results(exx_plan_t P, long long cap, int* ij, double* E, double* sigma, int* iters,
                             double* rel_res, long long* n_pairs) {
   if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");

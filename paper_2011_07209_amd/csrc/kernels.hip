@@ -454,7 +454,7 @@ hipError_t launch_pairlist(const Geo& g, const PairParams& pp, const double* cen
   const int nb = (n_orb + 127) / 128;
   k_pair_count<<<nb, 128, 0, s>>>(g, pp, centres, n_orb, counts);
   k_pair_scan<<<1, 1024, 0, s>>>(counts, n_orb);
-  k_pair_fill<<<nb, 128, 0, s>>>(g, pp, centres, R_orb, n_orb, counts, pairs, cap);
+  if (cap > 0) k_pair_fill<<<nb, 128, 0, s>>>(g, pp, centres, R_orb, n_orb, counts, pairs, cap);
   return hipGetLastError();
 }
 

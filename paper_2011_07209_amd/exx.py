@@ -79,8 +79,8 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_pair_results", "exx_stats_fetch",
-           "exx_plan_geometry", "exx_subdomain_counts", "exx_destroy", "exx_last_error"]
+SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_count_pairs", "exx_pair_results",
+           "exx_stats_fetch", "exx_plan_geometry", "exx_subdomain_counts", "exx_destroy", "exx_last_error"]
 
 _lib = None
 
@@ -104,6 +104,8 @@ def load():
     lib.exx_set_stream.argtypes = [vp, vp]
     lib.exx_eval.restype = ctypes.c_int
     lib.exx_eval.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    lib.exx_count_pairs.restype = ctypes.c_int
+    lib.exx_count_pairs.argtypes = [vp, ctypes.c_int, vp, vp, llp]
     lib.exx_pair_results.restype = ctypes.c_int
     lib.exx_pair_results.argtypes = [vp, ctypes.c_longlong, ip, dp, dp, ip, dp, llp]
     lib.exx_stats_fetch.restype = ctypes.c_int
@@ -195,6 +197,14 @@ def exx_eval(plan, orbitals: torch.Tensor, centres: torch.Tensor, E_xx: torch.Te
     _check(st, plan)
 
 
+def exx_count_pairs(plan, centres: torch.Tensor, R_PE_orb: Optional[torch.Tensor] = None) -> int:
+    """Pairs exx_eval would form for these centres (waits on the host)."""
+    n = ctypes.c_longlong(0)
+    _check(load().exx_count_pairs(plan, int(centres.shape[0]), _ptr(centres), _ptr(R_PE_orb), ctypes.byref(n)),
+           plan)
+    return n.value
+
+
 def exx_pair_results(plan):
     """Per-pair results of the last evaluation as numpy arrays."""
     import numpy as np
@@ -266,6 +276,9 @@ class Plan:
     def set_stream(self, stream=None):
         """Binds the stream later calls enqueue on (default: torch's current stream)."""
         exx_set_stream(self.handle, stream)
+
+    def count_pairs(self, centres, R_PE_orb=None):
+        return exx_count_pairs(self.handle, centres, R_PE_orb)
 
     def pair_results(self):
         return exx_pair_results(self.handle)
