@@ -184,21 +184,41 @@ exx_status harvest(exx_plan_t P) {
   return EXX_OK;
 }
 
-// Makes (threads, depth) the CG variant of the plan and sizes the persistent
-// grid from its occupancy.  The slot workspace is resized on the next eval.
-exx_status select_solve(exx_plan_t P, int threads, int depth) {
+// Sizes each class's persistent solve grid from the occupancy of its CG
+// variant (class_threads, class_depth; its columns per thread select the
+// kernel instance).  The slot workspace, sized for the largest grid, is
+// resized on the next eval.
+exx_status apply_solve_variants(exx_plan_t P) {
   const bool mixed = P->opt.precision == EXX_PREC_MIXED;
-  const int per_cu = solve_groups_per_cu(P->geo, (int)P->max_cols, P->max_zmax, mixed, threads, depth);
-  if (per_cu < 1) return fail(P, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
-  const int slots = P->opt.solve_groups > 0 ? P->opt.solve_groups : P->n_cus * per_cu;
+  const size_t ncls = P->classes.size();
+  P->class_groups.assign(ncls, 0);
+  int slots = 0;
+  for (size_t k = 0; k < ncls; ++k) {
+    const ClassHost& C = P->classes[k];
+    const int per_cu = solve_groups_per_cu(P->geo, C.n_cols, C.Zmax, mixed, P->class_threads[k], P->class_depth[k]);
+    if (per_cu < 1) return fail(P, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
+    P->class_groups[k] = P->opt.solve_groups > 0 ? P->opt.solve_groups : P->n_cus * per_cu;
+    slots = std::max(slots, P->class_groups[k]);
+  }
   if (slots != P->n_slots && P->slot_ws) {
     (void)hipFree(P->slot_ws);
     P->slot_ws = nullptr;
   }
   P->n_slots = slots;
-  P->solve_threads = threads;
-  P->solve_depth = depth;
+  // the variant reported by exx_stats: that of the class with the most columns
+  const int big = (int)(std::max_element(P->classes.begin(), P->classes.end(),
+                                         [](const ClassHost& a, const ClassHost& b) { return a.n_cols < b.n_cols; }) -
+                        P->classes.begin());
+  P->solve_threads = P->class_threads[big];
+  P->solve_depth = P->class_depth[big];
   return EXX_OK;
+}
+
+// Sets the CG variant of class cls and resizes the grids.
+exx_status select_solve(exx_plan_t P, int threads, int depth, int cls) {
+  P->class_threads[cls] = threads;
+  P->class_depth[cls] = depth;
+  return apply_solve_variants(P);
 }
 
 exx_status ensure_slots(exx_plan_t P) {
@@ -210,10 +230,31 @@ exx_status ensure_slots(exx_plan_t P) {
   return EXX_OK;
 }
 
-// Autotuner: times every supported CG variant (workgroup size x load depth)
-// on the first pairs of the batch whose densities and boundary values are in
-// the workspace, and keeps the fastest.  Right-hand sides are rebuilt before
-// each trial (the solve overwrites them) and once more by the caller.
+// The CG solve of a batch: one persistent launch per sphere class, in
+// processing order, each with the kernel instance of its class's column count
+// and finding its rows of the batch on the device.
+exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
+  const int ncls = (int)P->classes.size();
+  a.ncls = ncls;
+  a.class_cnt = P->pair_count + 2 * P->last_n_orb + 1;
+  for (int k = ncls - 1; k >= 0; --k) {
+    const ClassHost& C = P->classes[k];
+    a.cls_id = ncls > 1 ? k : -1;
+    a.threads = P->class_threads[k];
+    a.depth = P->class_depth[k];
+    EXX_HIP(P, launch_set_int(P->queue, 0, s));
+    const int groups = (int)std::min<long long>(P->class_groups[k], a.npair);
+    EXX_HIP(P, launch_solve(a, C.n_cols, C.Zmax, groups, s));
+  }
+  return EXX_OK;
+}
+
+// Autotuner: for each sphere class with pairs in this batch, times every CG
+// variant (workgroup size x load depth) that can run it on a sample of the
+// class's pairs (one per workgroup of the grid), and keeps the fastest for
+// that class.  Densities and boundary values are in the workspace; right-hand
+// sides are rebuilt before each trial (the solve overwrites them) and once
+// more by the caller.
 exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hipStream_t s) {
   static const int cand[4][2] = {{1024, 1}, {1024, 2}, {512, 1}, {512, 2}};
   hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
@@ -222,44 +263,59 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
   EXX_HIP(P, hipEventCreate(&t0));
   EXX_HIP(P, hipEventCreate(&t1));
   EXX_HIP(P, hipEventRecord(t0, s));
-  float best = 1e30f;
-  int bt = P->solve_threads, bd = P->solve_depth;
-  for (const auto& c : cand) {
-    if (!solve_supported((int)P->max_cols, c[0])) continue;
-    const bool mixed = P->opt.precision == EXX_PREC_MIXED;
-    const int per_cu = solve_groups_per_cu(P->geo, (int)P->max_cols, P->max_zmax, mixed, c[0], c[1]);
-    if (per_cu < 1) continue;
-    exx_status st = select_solve(P, c[0], c[1]);
-    if (st != EXX_OK) return st;
-    st = ensure_slots(P);
-    if (st != EXX_OK) return st;
-    const long long sample = std::min<long long>(nb, 2LL * P->n_slots);
-    SolveArgs a = base;
-    a.npair = sample;
-    a.slot_ws = P->slot_ws;
-    a.threads = c[0];
-    a.depth = c[1];
-    Batch B;
-    B.cls = P->class_dev;
-    B.pairs = P->pairs;
-    B.order = P->order;
-    B.n_eff = P->n_eff;
-    B.p0 = a.p0;
-    B.nb = sample;
-    EXX_HIP(P, launch_rhs(P->geo, B, P->max_pe, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
-                          std::max<long long>(P->max_halo, 1), s));
-    EXX_HIP(P, launch_set_int(P->queue, 0, s));
-    EXX_HIP(P, hipEventRecord(e0, s));
-    EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, (int)std::min<long long>(P->n_slots, sample), s));
-    EXX_HIP(P, hipEventRecord(e1, s));
-    EXX_HIP(P, hipEventSynchronize(e1));
-    float ms = 0;
-    EXX_HIP(P, hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      bt = c[0];
-      bd = c[1];
+  const int ncls = (int)P->classes.size();
+  int cc[kMaxClasses] = {0};
+  EXX_HIP(P, hipMemcpyAsync(cc, P->pair_count + 2 * P->last_n_orb + 1, sizeof(int) * ncls, hipMemcpyDeviceToHost, s));
+  EXX_HIP(P, hipStreamSynchronize(s));
+  long long start = 0;
+  for (int k = ncls - 1; k >= 0; --k) {
+    const long long lo = std::max(start, base.p0), hi = std::min(start + cc[k], base.p0 + nb);
+    start += cc[k];
+    if (hi <= lo) continue;
+    float best = 1e30f;
+    int bt = P->class_threads[k], bd = P->class_depth[k];
+    for (const auto& c : cand) {
+      if (solve_groups_per_cu(P->geo, P->classes[k].n_cols, P->classes[k].Zmax, base.mixed, c[0], c[1]) < 1)
+        continue;
+      exx_status st = select_solve(P, c[0], c[1], k);
+      if (st != EXX_OK) return st;
+      st = ensure_slots(P);
+      if (st != EXX_OK) return st;
+      const long long sample = std::min<long long>(hi - lo, P->class_groups[k]);
+      SolveArgs a = base;
+      a.npair = lo + sample - base.p0;   // batch rows up to the end of the sample
+      a.slot_ws = P->slot_ws;
+      a.ncls = ncls;
+      a.class_cnt = P->pair_count + 2 * P->last_n_orb + 1;
+      a.cls_id = ncls > 1 ? k : -1;
+      a.threads = c[0];
+      a.depth = c[1];
+      Batch B;
+      B.cls = P->class_dev;
+      B.pairs = P->pairs;
+      B.order = P->order;
+      B.n_eff = P->n_eff;
+      B.p0 = base.p0;
+      B.nb = a.npair;
+      EXX_HIP(P, launch_rhs(P->geo, B, P->max_pe, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
+                            std::max<long long>(P->max_halo, 1), s));
+      EXX_HIP(P, launch_set_int(P->queue, 0, s));
+      EXX_HIP(P, hipEventRecord(e0, s));
+      EXX_HIP(P, launch_solve(a, P->classes[k].n_cols, P->classes[k].Zmax,
+                              (int)std::min<long long>(P->class_groups[k], sample), s));
+      EXX_HIP(P, hipEventRecord(e1, s));
+      EXX_HIP(P, hipEventSynchronize(e1));
+      float ms = 0;
+      EXX_HIP(P, hipEventElapsedTime(&ms, e0, e1));
+      const float per_pair = ms / (float)sample;
+      if (per_pair < best) {
+        best = per_pair;
+        bt = c[0];
+        bd = c[1];
+      }
     }
+    exx_status st = select_solve(P, bt, bd, k);
+    if (st != EXX_OK) return st;
   }
   EXX_HIP(P, hipEventRecord(t1, s));
   EXX_HIP(P, hipEventSynchronize(t1));
@@ -270,8 +326,6 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  exx_status st = select_solve(P, bt, bd);
-  if (st != EXX_OK) return st;
   P->tuned = true;
   return ensure_slots(P);
 }
@@ -510,10 +564,13 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   P->n_cus = std::max(1, cus);
   {
     // defaults measured on MI355X: FP64 1024 x 1, mixed 1024 x 2
-    int th = opt.solve_threads > 0 ? opt.solve_threads : 1024;
-    if (!solve_supported((int)P->max_cols, th)) th = 512;
+    // per class: 1024 threads up to 3 columns each, else 512 (1024 x 4 spills)
     const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
-    exx_status st = select_solve(P, th, dp);
+    P->class_threads.assign(P->classes.size(), 1024);
+    P->class_depth.assign(P->classes.size(), dp);
+    for (size_t k = 0; k < P->classes.size(); ++k)
+      P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= 3 * 1024 ? 1024 : 512);
+    exx_status st = apply_solve_variants(P);
     if (st != EXX_OK) {
       std::string m = P->err;
       free_plan(P);
@@ -704,10 +761,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     }
     EXX_HIP(P, launch_rhs(g, B, P->max_pe, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
                           std::max<long long>(P->max_halo, 1), s));
-    EXX_HIP(P, launch_set_int(P->queue, 0, s));
-    const int groups = (int)std::min<long long>(P->n_slots, B.nb);
     if (!capturing) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_solve(a, (int)P->max_cols, P->max_zmax, groups, s));
+    { exx_status es = launch_solves(P, a, s); if (es != EXX_OK) return es; }
     if (!capturing) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_finalize(g, B, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws, std::max<long long>(P->max_halo, 1),
                                P->pE, P->pS, s));

@@ -141,6 +141,9 @@ struct exx_plan_s {
   double* Qp_ws = nullptr;     // [chunks][batch][kMaxLM] partial moments of the point chunks
   long long qp_rows = 0;
   int n_slots = 0;
+  std::vector<int> class_groups;   // persistent solve workgroups of each class's launch
+  std::vector<int> class_threads;  // CG variant of each class: workgroup size ...
+  std::vector<int> class_depth;    // ... and load depth
   int n_cus = 1;
   int solve_threads = 1024, solve_depth = 1;   // CG variant in use
   bool tuned = false;

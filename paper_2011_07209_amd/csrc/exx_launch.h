@@ -63,6 +63,9 @@ struct SolveArgs {
   const int* order = nullptr;
   long long p0 = 0, npair = 0;   // batch start and capacity
   const int* n_eff = nullptr;    // device pair count of the processing order
+  int cls_id = -1;               // >= 0: solve only this class's rows of the batch
+  const int* class_cnt = nullptr;   // device per-class pair counts of the order
+  int ncls = 1;
   int* queue = nullptr;
   double* bx_ws = nullptr;     // per pair: right-hand side in, solution out
   long long rstride = 0;

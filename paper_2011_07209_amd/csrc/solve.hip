@@ -31,6 +31,9 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.p0 = in.p0;
   a.npair = in.npair;
   a.n_eff = in.n_eff;
+  a.cls_id = in.cls_id;
+  a.class_cnt = in.class_cnt;
+  a.ncls = in.ncls;
   a.queue = in.queue;
   a.bx_ws = in.bx_ws;
   a.rstride = in.rstride;

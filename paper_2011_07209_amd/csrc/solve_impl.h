@@ -39,6 +39,9 @@ struct SolveKArgs {
   const int* order;
   long long p0, npair;    // batch start and capacity; the batch holds min(npair, *n_eff - p0) pairs
   const int* n_eff;       // device pair count of the processing order
+  int cls_id;             // >= 0: only the rows of this sphere class (class_cnt, ncls give the ranges)
+  const int* class_cnt;
+  int ncls;
   int* queue;
   double* bx_ws;          // per pair: right-hand side in, solution out
   long long rstride;
@@ -92,6 +95,24 @@ __device__ __forceinline__ void load_cols(const ClassDev& C, const SolveKArgs& a
       cl.pos[c] = (cc.x + a.lds_cx) + kLdsWX * (cc.y + a.lds_cy);
     }
   }
+}
+
+// Rows [lo, hi) of the processing order this launch solves: the batch, cut
+// to the stored pairs and, for a per-class launch, to the class's rows
+// (classes are laid out in descending class index).
+__device__ __forceinline__ void solve_range(const SolveKArgs& a, long long* lo, long long* hi) {
+  long long l = a.p0, h = a.p0 + a.npair;
+  const long long ne = *a.n_eff;
+  if (h > ne) h = ne;
+  if (a.cls_id >= 0) {
+    long long start = 0;
+    for (int k = a.ncls - 1; k > a.cls_id; --k) start += a.class_cnt[k];
+    const long long end = start + a.class_cnt[a.cls_id];
+    if (l < start) l = start;
+    if (h > end) h = end;
+  }
+  *lo = l;
+  *hi = h;
 }
 
 #define EXX_VALID(c, zz) (abs(zz) <= cl.zr[c])
@@ -329,13 +350,16 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
   double* r = (double*)((char*)a.slot_ws + (long long)blockIdx.x * a.slot_bytes);
   double* p = r + a.sstride;
 
+  long long lo, hi;
+  solve_range(a, &lo, &hi);
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const long long item = s_item;
+    const long long row = lo + s_item;   // row of the processing order
     __syncthreads();
-    if (item >= a.npair || a.p0 + item >= (long long)*a.n_eff) break;
-    const int pid = a.order[a.p0 + item];
+    if (row >= hi) break;
+    const long long item = row - a.p0;   // row of the batch workspace
+    const int pid = a.order[row];
     const ClassDev& C = a.cls[a.pairs[pid].cls];
     const int Zmax = C.Zmax;
     double* x = a.bx_ws + item * a.rstride;
@@ -415,13 +439,16 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   float* y = p + a.sstride;
   const StencilT<float> S32 = stencil_cast<float>(a.S);
 
+  long long lo, hi;
+  solve_range(a, &lo, &hi);
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const long long item = s_item;
+    const long long row = lo + s_item;   // row of the processing order
     __syncthreads();
-    if (item >= a.npair || a.p0 + item >= (long long)*a.n_eff) break;
-    const int pid = a.order[a.p0 + item];
+    if (row >= hi) break;
+    const long long item = row - a.p0;   // row of the batch workspace
+    const int pid = a.order[row];
     const ClassDev& C = a.cls[a.pairs[pid].cls];
     const int Zmax = C.Zmax;
     const long long npe = C.n_pe;
