@@ -16,6 +16,8 @@ classes), a fixed pair capacity, one eager warm-up call (which runs the CG
 autotuner), the call recorded into a HIP graph, then K replays; before each
 replay every centre moves 0.02 bohr and the orbitals are regenerated on the
 device in the same buffers (not timed).  Each replay is timed with HIP events.
+By default each replay's CG starts from the pair's solution of the previous
+replay (--no-warm-start: from zero).
 
 The roofline entry is for the dominant kernel, the persistent CG solve:
 algorithmic bytes (8 N_PE b per pair per iteration) over the summed device
@@ -110,7 +112,7 @@ def _plan(exx, cfg, precision, **kw):
     return exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, **opt)
 
 
-def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, graph):
+def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, graph, warm=False):
     """Times `steps` evaluations (after `warmup`) in one precision; returns the
     measurement and the outputs of the last evaluation."""
     orb_t, cen_t, R_t, D = bufs
@@ -123,6 +125,7 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
         n0 = probe.count_pairs(cen_t, R_t)
         probe.close()
         kw["max_pairs"] = int(math.ceil(1.05 * n0)) + 64   # displacements change the pair list a little
+        kw["warm_start"] = 1 if warm else 0
     plan = _plan(exx, cfg, precision, **kw)
     geo = plan.geometry()
     n_warm = max(warmup, 1 if graph else 0)
@@ -132,7 +135,7 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
         print(f"[bench] {cfg.key} {precision} warmup {w + 1}/{n_warm} E={E.item():.10f}", file=sys.stderr, flush=True)
     zero = {"solve_launches": 0, "solve_ms_total": 0.0, "cg_alg_bytes_total": 0.0}
     s0 = plan.stats() if n_warm > 0 else zero
-    step_ms, step_pairs = [], []
+    step_ms, step_pairs, step_iters, step_warm = [], [], [], []
     s_last = None
     if graph:
         side = torch.cuda.Stream()
@@ -158,9 +161,12 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
             st = plan.stats()
             step_ms.append(ev0.elapsed_time(ev1))
             step_pairs.append(st["n_pairs"])
+            step_iters.append(st["cg_iter_sum"] / max(1, st["n_pairs"]))
+            step_warm.append(st["warm_pairs"])
             s_last = st
-            print(f"[bench] {cfg.key} {precision} replay {k + 1}/{steps}: {step_ms[-1]:.1f} ms, {st['n_pairs']} pairs, "
-                  f"E={E.item():.10f}", file=sys.stderr, flush=True)
+            print(f"[bench] {cfg.key} {precision} replay {k + 1}/{steps}: {step_ms[-1]:.1f} ms, {st['n_pairs']} pairs "
+                  f"({st['warm_pairs']} warm-started), mean iterations {step_iters[-1]:.1f}, E={E.item():.10f}",
+                  file=sys.stderr, flush=True)
         del g
         ms = sum(step_ms) / len(step_ms)
         value = sum(step_pairs) / (sum(step_ms) / 1000.0)
@@ -207,6 +213,7 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
     return {
         "value": value, "ms_per_step": ms, "n_pairs": n_pairs, "n_pe": geo["n_pe"],
         "eval_ms_median": statistics.median(step_ms), "eval_ms_steps": step_ms,
+        "cg_iters_mean_steps": step_iters, "warm_pairs_steps": step_warm,
         "cg_iters_mean": s_last["cg_iter_sum"] / max(1, n_pairs), "cg_iters_max": s_last["cg_iter_max"],
         "updates_max": s_last["refine_passes_max"], "max_rel_residual": s_last["max_rel_residual"],
         "solve_variant": {"threads": s_last["solve_threads"], "depth": s_last["solve_depth"],
@@ -227,6 +234,8 @@ def main(argv=None):
                     help="both: time the FP64 and the mixed path, report the mixed one as the value")
     ap.add_argument("--cpu-sample-pairs", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="water256: start every replay's CG from zero instead of the previous solution")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed steps, copy this many GiB device-to-device (counter calibration)")
     args = ap.parse_args(argv)
@@ -264,7 +273,8 @@ def main(argv=None):
         if graph:   # every precision replays the same trajectory from the same start
             synth.fill_orbitals_device(cfg, orbs, dev, out=orb_t)
             cen_t.copy_(torch.from_numpy(orbs.centres).to(dev))
-        res[p] = run_precision(exx, torch, synth, cfg, orbs, (orb_t, cen_t, R_t, D), p, steps, args.warmup, graph)
+        res[p] = run_precision(exx, torch, synth, cfg, orbs, (orb_t, cen_t, R_t, D), p, steps, args.warmup, graph,
+                               warm=graph and not args.no_warm_start)
     main_p = "mixed" if "mixed" in res else "fp64"
     r = res[main_p]
 
@@ -296,7 +306,8 @@ def main(argv=None):
         del phi
 
     def summary(x):
-        return {k: x[k] for k in ("value", "ms_per_step", "eval_ms_median", "eval_ms_steps", "cg_iters_mean",
+        return {k: x[k] for k in ("value", "ms_per_step", "eval_ms_median", "eval_ms_steps", "cg_iters_mean_steps",
+                                  "warm_pairs_steps", "cg_iters_mean",
                                   "cg_iters_max", "updates_max", "max_rel_residual", "solve_variant", "roofline",
                                   "moments_roofline")}
 
@@ -321,6 +332,7 @@ def main(argv=None):
             "exx_eval_s": r["ms_per_step"] / 1000.0,
             "timing": ("mean of event-timed graph replays over displaced centres (orbital regeneration not timed)"
                        if graph else "host clock around the timed exx_eval calls"),
+            "warm_start": bool(graph and not args.no_warm_start),
             "E_xx": r["E"],
         },
         "roofline": r["roofline"],

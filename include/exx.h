@@ -77,6 +77,13 @@ typedef struct {
                                  (0: tuned/default)                                */
   int autotune;               /* 1: the first exx_eval times the CG variants on a
                                  sample of its pairs and keeps the fastest          */
+  int warm_start;             /* 1: each exx_eval starts a pair's CG from that
+                                 pair's solution in the previous exx_eval of the
+                                 plan (same i, j and sphere class, shifted by the
+                                 change of its grid centre, at most one point per
+                                 axis), else from zero; the stop test is unchanged.
+                                 Needs max_pairs > 0; keeps 2 max_pairs N_PE FP32
+                                 values on the device                               */
 } exx_options;
 
 /* Fills *opt with the defaults: n = 3, FP64, tol 1e-10, 5000 iterations,
@@ -165,6 +172,7 @@ typedef struct {
   int graph_recorded;          /* 1: the last exx_eval was recorded into a graph;
                                   results are those of its latest replay, and the
                                   device times are 0                               */
+  long long warm_pairs;        /* pairs whose CG started from a previous solution  */
 } exx_stats;
 
 /* Statistics of the last exx_eval (synchronizes the bound stream).  Returns

@@ -126,7 +126,8 @@ struct CaptureGuard {
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->slot_ws, P->queue,
+                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
+                  P->warm_map, P->prev_pairs, P->prev_offs, P->warm_state, P->slot_ws, P->queue,
                   P->stats_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -142,9 +143,9 @@ void free_plan(exx_plan_t P) {
 // Copies the device statistics of the last evaluation (k_reduce's eight
 // values and the per-class pair counts).  The caller has synchronized.
 exx_status read_device_stats(exx_plan_t P) {
-  double st[8] = {0};
+  double st[9] = {0};
   EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
-  for (int k = 0; k < 8; ++k) P->last_stats[k] = st[k];
+  for (int k = 0; k < 9; ++k) P->last_stats[k] = st[k];
   int cc[kMaxClasses] = {0};
   const int ncls = (int)P->classes.size();
   EXX_HIP(P, hipMemcpy(cc, P->pair_count + 2 * P->last_n_orb + 1, sizeof(int) * ncls, hipMemcpyDeviceToHost));
@@ -388,6 +389,9 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (opt.solve_threads != 0 && opt.solve_threads != 512 && opt.solve_threads != 1024)
     return fail(nullptr, EXX_EINVAL, "solve_threads must be 0, 512 or 1024");
   if (opt.solve_depth < 0 || opt.solve_depth > 2) return fail(nullptr, EXX_EINVAL, "solve_depth must be 0, 1 or 2");
+  if (opt.warm_start != 0 && opt.warm_start != 1) return fail(nullptr, EXX_EINVAL, "warm_start must be 0 or 1");
+  if (opt.warm_start && opt.max_pairs <= 0)
+    return fail(nullptr, EXX_EINVAL, "warm_start needs a fixed pair capacity (max_pairs > 0)");
 
   exx_plan_t P = new (std::nothrow) exx_plan_s();
   if (!P) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
@@ -555,7 +559,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
       free_plan(P);
       return fail(nullptr, EXX_EDEVICE, "event creation failed");
     }
-  if (hipMalloc(&P->queue, sizeof(int)) != hipSuccess || hipMalloc(&P->stats_dev, 8 * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&P->queue, sizeof(int)) != hipSuccess || hipMalloc(&P->stats_dev, 9 * sizeof(double)) != hipSuccess) {
     free_plan(P);
     return fail(nullptr, EXX_ENOMEM, "device allocation failed");
   }
@@ -673,6 +677,26 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   P->last_n_orb = n_orb;
   const int ncls = (int)P->classes.size();
   EXX_HIP(P, launch_order(P->pairs, P->pair_count, n_orb, ncls, P->order, P->pair_cap, P->n_eff, s));
+  if (P->opt.warm_start) {
+    // the stores and the previous list keep their contents between calls;
+    // they are (re)made only when the capacity grows, which drops the history
+    if (P->warm_cap < P->pair_cap || !P->warm_state) {
+      if (dev_alloc(P, &P->warm_store, (size_t)2 * P->pair_cap * P->rstride, "warm-start solutions") ||
+          dev_alloc(P, &P->warm_map, (size_t)P->pair_cap, "warm-start map") ||
+          dev_alloc(P, &P->prev_pairs, (size_t)P->pair_cap, "previous pairs") ||
+          dev_alloc(P, &P->warm_state, 4, "warm-start state"))
+        return EXX_ENOMEM;
+      P->warm_cap = P->pair_cap;
+      EXX_HIP(P, launch_zero(P->warm_state, 4 * sizeof(int), s));
+    }
+    if (n_orb + 1 > P->warm_orb_cap) {
+      if (dev_alloc(P, &P->prev_offs, (size_t)n_orb + 1, "previous offsets")) return EXX_ENOMEM;
+      P->warm_orb_cap = n_orb + 1;
+      EXX_HIP(P, launch_zero(P->warm_state, 4 * sizeof(int), s));   // no usable previous list
+    }
+    EXX_HIP(P, launch_warm_match(g, P->pairs, P->n_eff, P->pair_cap, P->prev_pairs, P->prev_offs, P->warm_state,
+                                 P->warm_map, s));
+  }
 
   // workspace
   const long long per_pair = 2 * P->rstride + P->max_halo + kMaxLM;
@@ -751,6 +775,13 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.depth = P->solve_depth;
     a.tol = P->opt.cg_tol;
     a.max_iter = P->opt.cg_max_iter;
+    if (P->opt.warm_start) {
+      a.warm_store = P->warm_store;
+      a.warm_cap = P->warm_cap;
+      a.warm_state = P->warm_state;
+      a.warm_map = P->warm_map;
+      a.prev_pairs = P->prev_pairs;
+    }
     if (P->opt.autotune && !P->tuned) {
       if (capturing) return fail(P, EXX_EINVAL, "the autotuner runs in an eager exx_eval, not in a graph");
       exx_status st = autotune_solve(P, a, B.nb, s);
@@ -771,7 +802,11 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   }
   EXX_HIP(P, event(P->ev[2]));
   EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pairs, P->class_dev, P->pair_count, n_orb,
-                           P->n_eff, P->opt.cg_max_iter, E_xx, sigma, P->stats_dev, s));
+                           P->n_eff, P->opt.warm_start ? P->warm_map : nullptr, P->opt.cg_max_iter, E_xx, sigma,
+                           P->stats_dev, s));
+  if (P->opt.warm_start)
+    EXX_HIP(P, launch_warm_commit(P->pairs, P->pair_count, n_orb, P->n_eff, P->pair_cap, P->prev_pairs, P->prev_offs,
+                                  P->warm_state, s));
   EXX_HIP(P, event(P->ev[3]));
   if (!capturing) {
     P->timing_valid = true;
@@ -894,6 +929,7 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->tune_ms = P->tune_ms;
   out->pairs_kept = (long long)st[4];
   out->graph_recorded = P->last_captured ? 1 : 0;
+  out->warm_pairs = (long long)st[8];
   if (st[4] > (double)P->pair_cap)
     return fail(P, EXX_ECAPACITY, "more pairs than the fixed capacity (max_pairs); results cover the first ones");
   return out->n_unconverged > 0 ? fail(P, EXX_ENOCONV, "CG did not converge for some pairs") : EXX_OK;

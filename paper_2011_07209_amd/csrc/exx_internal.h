@@ -119,6 +119,17 @@ struct exx_plan_s {
   int* pair_count = nullptr;       // per-orbital counts and offsets [2 * orb_cap + 1 + classes]
   int orb_cap = 0;
   int* n_eff = nullptr;            // device: pairs stored in the processing order
+  // warm start: two FP32 solution stores [2][pair_cap][rstride] (which one holds
+  // the previous evaluation's solutions is the device parity in warm_state),
+  // the previous pair list and per-orbital offsets, and the match of each pair
+  // to its row in the previous list
+  float* warm_store = nullptr;
+  long long warm_cap = 0;          // pair rows per store
+  int* warm_map = nullptr;         // [pair_cap]
+  exx::PairDev* prev_pairs = nullptr;
+  int* prev_offs = nullptr;        // [orb_cap + 1]
+  int* warm_state = nullptr;       // device: parity, previous list valid, previous n_orb, previous stored pairs
+  int warm_orb_cap = 0;
   int* d_slot = nullptr;           // device [orb_cap]: D row of each orbital (subset evaluations)
   int warm_orb = 0;                // largest n_orb of a completed eager eval with a fixed capacity
   bool capturing = false;          // inside an exx_eval recorded into a graph
@@ -163,7 +174,7 @@ struct exx_plan_s {
   bool timing_valid = false;
   bool harvested = true;              // last eval's events already added to the totals
   double last_solve_ms = 0, last_eval_ms = 0, last_alg_bytes = 0;
-  double last_stats[8] = {0};
+  double last_stats[9] = {0};
   long long n_evals = 0, solve_launches = 0;
   double solve_ms_total = 0, eval_ms_total = 0, alg_bytes_total = 0;
   std::string err;

@@ -78,6 +78,12 @@ struct SolveArgs {
   int max_iter = 0;
   bool mixed = false;
   double delta = 0.1;          // mixed: reliable-update threshold
+  // warm start (warm_store null: every solve starts from zero)
+  const float* warm_store = nullptr;   // [2][warm_cap][rstride] FP32 solutions
+  long long warm_cap = 0;
+  const int* warm_state = nullptr;     // device parity at [0]
+  const int* warm_map = nullptr;
+  const PairDev* prev_pairs = nullptr;
   int threads = 1024;          // workgroup size of the solve (512 or 1024)
   int depth = 1;               // planes of loads in flight ahead of their use (1 or 2)
 };
@@ -97,14 +103,25 @@ hipError_t launch_dscatter(const Geo& g, const Batch& B, long long max_me, const
                            const int* d_slot, int dt, const double* v_ws, long long rstride, const double* Q_ws,
                            hipStream_t s);
 
+// Warm start: warm_map[p] = row of pair p in the previous evaluation's list,
+// or -1; state = (parity, previous list valid, previous n_orb, previous
+// stored pairs).  launch_warm_commit makes this evaluation's list the previous
+// one and flips the store parity.
+hipError_t launch_warm_match(const Geo& g, const PairDev* pairs, const int* n_eff, long long cap,
+                             const PairDev* prev_pairs, const int* prev_offs, const int* state, int* warm_map,
+                             hipStream_t s);
+hipError_t launch_warm_commit(const PairDev* pairs, const int* counts, int n_orb, const int* n_eff, long long cap,
+                              PairDev* prev_pairs, int* prev_offs, int* state, hipStream_t s);
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
-// E_xx and sigma from per-pair results in canonical order; stats[8] receives
+// E_xx and sigma from per-pair results in canonical order; stats[9] receives
 // (iter_sum, iter_max, n_unconverged, max_res, n_pairs kept (also beyond the
-// capacity), sum iters*N_PE, refinement passes max, sum N_PE) as doubles.
+// capacity), sum iters*N_PE, refinement passes max, sum N_PE, warm-started
+// pairs) as doubles.  warm_map may be null.
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
                          const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
-                         int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
+                         const int* warm_map, int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
 
 }  // namespace exx

@@ -363,6 +363,61 @@ __global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restr
   if (P.i != P.j && sj >= 0) unsafeAtomicAdd(&D[(long long)sj * g.ngrid + gi], (TO)(v * fi));
 }
 
+// ---------------------------------------------------------------------------
+// warm start: the previous evaluation's pair list and solutions
+
+// warm_map[p] = row of pair p in the previous list (same i, j and class, grid
+// centre moved by at most one point per axis), else -1.  Both lists are in
+// canonical order (i ascending, then j), so the previous pairs of orbital i
+// are a sorted range found from the previous per-orbital offsets.
+__global__ void k_warm_match(Geo g, const PairDev* __restrict__ pairs, const int* __restrict__ n_eff,
+                             const PairDev* __restrict__ prev_pairs, const int* __restrict__ prev_offs,
+                             const int* __restrict__ state, int* __restrict__ warm_map) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= *n_eff) return;
+  int q = -1;
+  const PairDev P = pairs[p];
+  const int prev_valid = state[1], prev_orb = state[2], prev_stored = state[3];
+  if (prev_valid && P.i < prev_orb) {
+    int lo = prev_offs[P.i], hi = prev_offs[P.i + 1];
+    if (hi > prev_stored) hi = prev_stored;
+    while (lo < hi) {   // first previous pair of orbital i with j >= P.j
+      const int mid = (lo + hi) >> 1;
+      if (prev_pairs[mid].j < P.j) lo = mid + 1; else hi = mid;
+    }
+    const int end = min(prev_offs[P.i + 1], prev_stored);
+    if (lo < end && prev_pairs[lo].j == P.j && prev_pairs[lo].cls == P.cls) {
+      bool near = true;
+      for (int a = 0; a < 3; ++a) {
+        int d = P.c[a] - prev_pairs[lo].c[a];
+        if (d > g.N[a] / 2) d -= g.N[a];
+        if (d < -g.N[a] / 2) d += g.N[a];
+        near = near && d >= -1 && d <= 1;
+      }
+      if (near) q = lo;
+    }
+  }
+  warm_map[p] = q;
+}
+
+// After an evaluation: its pair list becomes the previous one, and the store
+// its solutions were written to becomes the one the next evaluation reads.
+// One thread per element of the larger of the two copies.
+__global__ void k_warm_commit(const PairDev* __restrict__ pairs, const int* __restrict__ counts, int n_orb,
+                              const int* __restrict__ n_eff, long long cap, PairDev* __restrict__ prev_pairs,
+                              int* __restrict__ prev_offs, int* __restrict__ state) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stored = *n_eff;
+  if (t < stored && t < cap) prev_pairs[t] = pairs[t];
+  if (t <= n_orb) prev_offs[t] = counts[n_orb + t];
+  if (t == 0) {
+    state[0] = 1 - state[0];
+    state[1] = 1;
+    state[2] = n_orb;
+    state[3] = (int)stored;
+  }
+}
+
 template <typename T>
 __global__ void k_zero(T* p, long long n) {
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
@@ -387,11 +442,13 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
                                                 const int* __restrict__ pUpd,
                                                 const PairDev* __restrict__ pairs, const ClassDev* __restrict__ cls,
                                                 const int* __restrict__ cnt, int n_orb, const int* __restrict__ n_eff,
-                                                int max_iter, double* __restrict__ E, double* __restrict__ sigma,
+                                                const int* __restrict__ warm_map, int max_iter,
+                                                double* __restrict__ E, double* __restrict__ sigma,
                                                 double* __restrict__ stats) {
   __shared__ double red[4];
   const long long np = *n_eff;
-  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0, umax = 0.0;
+  double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0, umax = 0.0,
+         warm = 0.0;
   for (int t = 0; t < 9; ++t) s[t] = 0.0;
   for (long long k = threadIdx.x; k < np; k += blockDim.x) {
     e += pE[k];
@@ -404,6 +461,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     const double npe = (double)cls[pairs[k].cls].n_pe;
     work += pIt[k] * npe;
     pts += npe;
+    if (warm_map && warm_map[k] >= 0) warm += 1.0;
   }
   e = block_sum(e, red);
   for (int t = 0; t < 9; ++t) s[t] = block_sum(s[t], red);
@@ -411,6 +469,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
   nunc = block_sum(nunc, red);
   work = block_sum(work, red);
   pts = block_sum(pts, red);
+  warm = block_sum(warm, red);
   // max via shuffles
   for (int o = 32; o > 0; o >>= 1) {
     imax = fmax(imax, __shfl_xor(imax, o, 64));
@@ -441,6 +500,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     stats[5] = work;
     stats[6] = umax;
     stats[7] = pts;
+    stats[8] = warm;
   }
 }
 
@@ -539,6 +599,23 @@ hipError_t launch_dscatter(const Geo& g, const Batch& B, long long max_me, const
   return hipGetLastError();
 }
 
+hipError_t launch_warm_match(const Geo& g, const PairDev* pairs, const int* n_eff, long long cap,
+                             const PairDev* prev_pairs, const int* prev_offs, const int* state, int* warm_map,
+                             hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  k_warm_match<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(g, pairs, n_eff, prev_pairs, prev_offs, state,
+                                                             warm_map);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm_commit(const PairDev* pairs, const int* counts, int n_orb, const int* n_eff, long long cap,
+                              PairDev* prev_pairs, int* prev_offs, int* state, hipStream_t s) {
+  const long long n = std::max<long long>(cap, (long long)n_orb + 1);
+  k_warm_commit<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pairs, counts, n_orb, n_eff, cap, prev_pairs, prev_offs,
+                                                            state);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
   if (bytes % 8 == 0) {
@@ -560,8 +637,9 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
                          const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
-                         int max_iter, double* E, double* sigma, double* stats, hipStream_t s) {
-  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pairs, cls, counts, n_orb, n_eff, max_iter, E, sigma, stats);
+                         const int* warm_map, int max_iter, double* E, double* sigma, double* stats, hipStream_t s) {
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pairs, cls, counts, n_orb, n_eff, warm_map, max_iter, E, sigma,
+                             stats);
   return hipGetLastError();
 }
 

@@ -31,6 +31,13 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.p0 = in.p0;
   a.npair = in.npair;
   a.n_eff = in.n_eff;
+  a.warm_store = in.warm_store;
+  a.warm_cap = in.warm_cap;
+  a.warm_state = in.warm_state;
+  a.warm_map = in.warm_map;
+  a.prev_pairs = in.prev_pairs;
+  a.n = in.g.n;
+  for (int ax = 0; ax < 3; ++ax) a.N[ax] = in.g.N[ax];
   a.cls_id = in.cls_id;
   a.class_cnt = in.class_cnt;
   a.ncls = in.ncls;

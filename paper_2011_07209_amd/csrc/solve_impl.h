@@ -56,7 +56,58 @@ struct SolveKArgs {
   double delta;           // mixed: update when ||r|| < delta * (residual at the last update)
   StencilT<double> S;
   int lds_cx, lds_cy, lds_wx, lds_wy;
+  // warm start (warm_store null: every solve starts from zero)
+  const float* warm_store;   // [2][warm_cap][rstride]; the previous solutions are half warm_state[0]
+  long long warm_cap;
+  const int* warm_state;
+  const int* warm_map;       // row of each pair in the previous list, or -1
+  const PairDev* prev_pairs;
+  int n;                     // stencil half-width (origin of the class lookup maps)
+  int N[3];                  // grid, for the periodic change of a pair's grid centre
 };
+
+// Packed PE index of local offset (ox, oy, oz) in class C, or -1 off the sphere.
+__device__ __forceinline__ int pe_index(const ClassDev& C, int n, int ox, int oy, int oz) {
+  const int mx = ox + C.Rg[0] + n, my = oy + C.Rg[1] + n;
+  if (mx < 0 || my < 0 || mx >= C.Wm[0] || my >= C.Wm[1]) return -1;
+  const int m2 = mx + C.Wm[0] * my;
+  const int zr = C.zr_map[m2];
+  if (zr < 0 || abs(oz) > zr) return -1;
+  return C.plane_start[oz + C.Zmax] + C.col_map[m2];
+}
+
+// Initial guess of a warm-started solve: the previous solution of the same
+// pair, moved by the change of its grid centre (at most one point per axis;
+// points that come from outside the previous sphere start at zero), into x
+// for the pair's points.  Returns false when the pair starts from zero.
+template <typename TX>
+__device__ bool warm_gather(const SolveKArgs& a, const ClassDev& C, int pid, TX* x) {
+  if (!a.warm_store) return false;
+  const int q = a.warm_map[pid];
+  if (q < 0) return false;
+  const PairDev P = a.pairs[pid], Q = a.prev_pairs[q];
+  int d[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    d[ax] = P.c[ax] - Q.c[ax];
+    if (d[ax] > a.N[ax] / 2) d[ax] -= a.N[ax];
+    if (d[ax] < -a.N[ax] / 2) d[ax] += a.N[ax];
+  }
+  const float* prev = a.warm_store + (long long)a.warm_state[0] * a.warm_cap * a.rstride + (long long)q * a.rstride;
+  for (long long k = threadIdx.x; k < C.n_pe; k += blockDim.x) {
+    const short4 o = C.me_off[k];
+    const int idx = pe_index(C, a.n, o.x + d[0], o.y + d[1], o.z + d[2]);
+    x[k] = idx >= 0 ? (TX)prev[idx] : (TX)0;
+  }
+  return true;
+}
+
+// This pair's solution, for the next evaluation's warm start.
+__device__ __forceinline__ void warm_store_solution(const SolveKArgs& a, long long npe, int pid, const double* x) {
+  if (!a.warm_store) return;
+  float* cur = const_cast<float*>(a.warm_store) + (long long)(1 - a.warm_state[0]) * a.warm_cap * a.rstride +
+               (long long)pid * a.rstride;
+  for (long long k = threadIdx.x; k < npe; k += blockDim.x) cur[k] = (float)x[k];
+}
 
 // -(stencil Laplacian) at one point in the arithmetic of T: ctr is the centre
 // value, pl the LDS plane (values of the current plane, zero off the PE
@@ -288,10 +339,10 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
 // and rounded to FP32, as the new working residual.  Returns this thread's
 // FP64 sum of the (unscaled) true residual^2.  One plane of loads ahead: the
 // pass runs a few times per solve, and its registers bound the whole kernel's.
-template <int NS, int CPT>
+template <int NS, int CPT, typename TR>
 __device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& cl, const int* pst, int Zmax,
                                    const double* __restrict__ x, const double* __restrict__ b,
-                                   float* __restrict__ r, double rs, double* pl0, double* pl1) {
+                                   TR* __restrict__ r, double rs, double* pl0, double* pl1) {
   double win[CPT][2 * NS + 1];
 #pragma unroll
   for (int k = 0; k < 2 * NS + 1; ++k) {
@@ -317,7 +368,7 @@ __device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& c
     for (int c = 0; c < CPT; ++c) {
       if (EXX_VALID(c, z)) {
         const double rt = cb[c] - apply_point<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
-        r[EXX_IDX(c, z)] = (float)(rt * rs);
+        r[EXX_IDX(c, z)] = (TR)(rt * rs);
         acc += rt * rt;
       }
     }
@@ -362,6 +413,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
     const int pid = a.order[row];
     const ClassDev& C = a.cls[a.pairs[pid].cls];
     const int Zmax = C.Zmax;
+    const long long npe = C.n_pe;
     double* x = a.bx_ws + item * a.rstride;
 
     for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
@@ -373,25 +425,49 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
     int it = 0;
     double rr = 0.0, bnorm = 0.0, beta = 0.0;
     bool first = true;
+    // Warm start: with x0 gathered into p, a first half-iteration runs pass B
+    // alone with alpha = 1, x = 0 and r_in = b, which leaves r = b - A x0 in
+    // the slot and x = x0 in place of b.  The CG proper then starts from that
+    // residual.  (One pass-B call site serves both, to keep the kernel's
+    // register allocation that of the cold solve.)
+    bool init = false;
+    if (a.warm_store && a.warm_map[pid] >= 0) {
+      double bb = 0.0;
+      for (long long k = tid; k < npe; k += NT) bb += x[k] * x[k];
+      bnorm = sqrt(block_sum(bb, red));
+      init = warm_gather<double>(a, C, pid, p);
+      __syncthreads();
+    }
+    const bool from_b = !init;   // cold: the first pass reads b from x, and x starts at zero
     while (it < a.max_iter) {
-      double pq_t, rr_t;
-      cg_pass_a<NS, CPT, PD, double>(a.S, cl, pst, Zmax, first ? x : r, p, beta, first, pl0, pl1, pq_t,
-                                     rr_t);
-      const double pq = block_sum(pq_t, red);
-      if (first) {
-        rr = block_sum(rr_t, red);
-        bnorm = sqrt(rr);
-        if (!(bnorm > 0.0)) break;   // b == 0: x = b = 0 already
+      double alpha = 1.0;
+      if (!init) {
+        double pq_t, rr_t;
+        cg_pass_a<NS, CPT, PD, double>(a.S, cl, pst, Zmax, (first && from_b) ? x : r, p, beta, first, pl0, pl1,
+                                       pq_t, rr_t);
+        const double pq = block_sum(pq_t, red);
+        if (first && from_b) {
+          rr = block_sum(rr_t, red);
+          bnorm = sqrt(rr);
+          if (!(bnorm > 0.0)) break;   // b == 0: x = b = 0 already
+        }
+        if (!(pq > 0.0) || !(pq < INFINITY)) {   // breakdown: A is SPD, so only NaN/inf input gets here
+          it = a.max_iter;
+          rr = NAN;
+          break;
+        }
+        alpha = rr / pq;
       }
-      if (!(pq > 0.0) || !(pq < INFINITY)) {   // breakdown: A is SPD, so only NaN/inf input gets here
-        it = a.max_iter;
-        rr = NAN;
-        break;
-      }
-      const double alpha = rr / pq;
-      const double rn = block_sum(cg_pass_b<NS, CPT, PD, double>(a.S, cl, pst, Zmax, x, first ? x : r, r, p, alpha,
-                                                                 first, pl0, pl1),
+      const bool from_b_now = init || (first && from_b);
+      const double rn = block_sum(cg_pass_b<NS, CPT, PD, double>(a.S, cl, pst, Zmax, x, from_b_now ? x : r, r, p,
+                                                                 alpha, from_b_now, pl0, pl1),
                                   red);
+      if (init) {   // the warm start's residual
+        init = false;
+        rr = rn;
+        if (!(bnorm > 0.0) || sqrt(rn) <= a.tol * bnorm) break;
+        continue;
+      }
       ++it;
       first = false;
       if (sqrt(rn) <= a.tol * bnorm) {
@@ -406,6 +482,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       beta = rn / rr;
       rr = rn;
     }
+    warm_store_solution(a, npe, pid, x);
     if (tid == 0) {
       a.outIt[pid] = it;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
@@ -475,6 +552,18 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     int it = 0, upd = 0;
     double rr = 1.0, rr_true = bb, rmax = 1.0, beta = 0.0;
     bool first = true, x_zero = true, y_zero = true, conv = !(bnorm > 0.0);
+    // warm start: x = x0 (FP64) and the working residual (b - A x0) / ||b||
+    if (!conv && warm_gather<double>(a, C, pid, x)) {
+      for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+      __syncthreads();
+      rr_true = block_sum(cg_true_residual<NS, CPT, float>(a.S, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+      for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+      __syncthreads();
+      x_zero = false;
+      rr = rr_true * inv_b * inv_b;
+      rmax = sqrt(rr);
+      conv = sqrt(rr_true) <= a.tol * bnorm;
+    }
     while (!conv && it < a.max_iter) {
       double pq_t, rr_t;
       cg_pass_a<NS, CPT, PD, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
@@ -505,7 +594,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
-        rr_true = block_sum(cg_true_residual<NS, CPT>(a.S, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+        rr_true = block_sum(cg_true_residual<NS, CPT, float>(a.S, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
         ++upd;
@@ -524,6 +613,8 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     } else if (bnorm > 0.0) {
       for (long long k = tid; k < npe; k += NT) bx[k] = 0.0;
     }
+    __syncthreads();
+    warm_store_solution(a, npe, pid, bx);
     if (tid == 0) {
       a.outIt[pid] = conv ? it : a.max_iter;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr_true) / bnorm : 0.0;

@@ -45,6 +45,7 @@ class Options(ctypes.Structure):
         ("solve_threads", ctypes.c_int),
         ("solve_depth", ctypes.c_int),
         ("autotune", ctypes.c_int),
+        ("warm_start", ctypes.c_int),
     ]
 
 
@@ -73,6 +74,7 @@ class Stats(ctypes.Structure):
         ("moment_mfma_flops", ctypes.c_double),
         ("pairs_kept", ctypes.c_longlong),
         ("graph_recorded", ctypes.c_int),
+        ("warm_pairs", ctypes.c_longlong),
     ]
 
     def as_dict(self):

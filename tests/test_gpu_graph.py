@@ -153,3 +153,96 @@ def test_capacity_overflow_is_reported_and_keeps_the_first_pairs():
         assert np.allclose(pr["E"], Eo, rtol=1e-9, atol=0)
     finally:
         plan.close()
+
+
+# ---------------------------------------------------------------------------
+# warm start: each solve starts from the pair's previous solution
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_warm_start_over_displaced_steps_matches_cold_oracle(prec):
+    """Three MD-like steps (0.05 bohr per step).  From the second step on,
+    pairs start from their previous solution; every step still matches the
+    oracle, which always starts from zero, and needs fewer CG iterations
+    than the cold first step."""
+    orbs = synth.make_orbitals(CFG)
+    phi, orb_t, cen_t = _inputs(CFG, orbs)
+    dev = orb_t.device
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    S = torch.zeros(9, dtype=torch.float64, device=dev)
+    D = torch.empty_like(orb_t)
+    plan = _plan(CFG, max_pairs=64, warm_start=1,
+                 precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64)
+    try:
+        iters = []
+        for step in range(3):
+            if step:
+                orbs = synth.displace(CFG, orbs, step, amplitude=0.05)
+                phi = synth.fill_orbitals(CFG, orbs)
+                orb_t.copy_(torch.from_numpy(phi).to(dev))
+                cen_t.copy_(torch.from_numpy(np.ascontiguousarray(orbs.centres)).to(dev))
+            plan.eval(orb_t, cen_t, E, D, S)
+            torch.cuda.synchronize()
+            st = plan.stats()
+            o = oracle_eval(CFG, orbs, phi)
+            iters.append(st["cg_iter_sum"])
+            print(f"[warm {prec}] step {step}: warm pairs {st['warm_pairs']}/{st['n_pairs']} iters {st['cg_iter_sum']} "
+                  f"E={E.item():.15g} oracle={o['E']:.15g}", flush=True)
+            assert st["n_unconverged"] == 0
+            # a displacement may create pairs or move a pair centre by more than one point
+            if step == 0:
+                assert st["warm_pairs"] == 0
+            else:
+                assert 0.75 * st["n_pairs"] <= st["warm_pairs"] <= st["n_pairs"]
+            if prec == "fp64":
+                assert rel1(E.item(), o["E"]) <= TOL_E
+                assert rel1(S.cpu().numpy().reshape(3, 3, order="F"), o["sigma"]) <= TOL_S
+                assert rel1(D.cpu().numpy(), o["D"]) <= TOL_D
+            else:
+                assert abs(E.item() - o["E"]) <= 1e-6 * CFG.n_orb / 4
+                assert rel1(S.cpu().numpy().reshape(3, 3, order="F"), o["sigma"]) <= 1e-6
+                assert rel1(D.cpu().numpy(), o["D"]) <= 1e-6
+        assert iters[1] < iters[0] and iters[2] < iters[0]
+    finally:
+        plan.close()
+
+
+def test_warm_start_in_graph_replays():
+    """The warm-start history lives on the device (store parity, previous pair
+    list), so graph replays carry it from one replay to the next."""
+    orbs = synth.make_orbitals(CFG)
+    phi, orb_t, cen_t = _inputs(CFG, orbs)
+    dev = orb_t.device
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    S = torch.zeros(9, dtype=torch.float64, device=dev)
+    plan = _plan(CFG, max_pairs=64, warm_start=1)
+    try:
+        plan.eval(orb_t, cen_t, E, None, S)
+        torch.cuda.synchronize()
+        cold = plan.stats()["cg_iter_sum"]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            plan.set_stream(side)
+            with torch.cuda.graph(g, stream=side):
+                plan.eval(orb_t, cen_t, E, None, S)
+        torch.cuda.current_stream().wait_stream(side)
+        plan.set_stream(torch.cuda.current_stream())
+        for step in (1, 2):
+            orbs = synth.displace(CFG, orbs, step, amplitude=0.05)
+            phi = synth.fill_orbitals(CFG, orbs)
+            orb_t.copy_(torch.from_numpy(phi).to(dev))
+            cen_t.copy_(torch.from_numpy(np.ascontiguousarray(orbs.centres)).to(dev))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            st = plan.stats()
+            o = oracle_eval(CFG, orbs, phi, want_D=False)
+            print(f"[warm graph] replay {step}: warm pairs {st['warm_pairs']}/{st['n_pairs']} iters "
+                  f"{st['cg_iter_sum']} (cold {cold}) E={E.item():.15g} oracle={o['E']:.15g}", flush=True)
+            assert 0.75 * st["n_pairs"] <= st["warm_pairs"] <= st["n_pairs"] and st["cg_iter_sum"] < cold
+            assert rel1(E.item(), o["E"]) <= TOL_E
+            assert rel1(S.cpu().numpy().reshape(3, 3, order="F"), o["sigma"]) <= TOL_S
+        del g
+    finally:
+        plan.close()
