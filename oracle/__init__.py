@@ -48,6 +48,8 @@ class Params(ctypes.Structure):
         ("sample_seed", ctypes.c_ulonglong),
         ("sample_frac", ctypes.c_double),
         ("n_threads", ctypes.c_int),
+        ("R_PE_self", ctypes.c_double),
+        ("R_ME_self", ctypes.c_double),
     ]
 
 
@@ -106,7 +108,8 @@ def _dp(a):
 
 
 def make_params(h, grid, R_pair, R_PE, R_ME, l_max, stencil_n, cg_tol=1e-10, cg_max_iter=5000, h_geom=None,
-                R_PE_classes=None, sample_seed=0, sample_frac=1.0, n_threads=0) -> Params:
+                R_PE_classes=None, sample_seed=0, sample_frac=1.0, n_threads=0, R_PE_self=0.0,
+                R_ME_self=0.0) -> Params:
     """h: 3x3 array with h[:, al] = L_al (Cartesian columns)."""
     p = Params()
     h = np.asarray(h, dtype=np.float64)
@@ -123,6 +126,7 @@ def make_params(h, grid, R_pair, R_PE, R_ME, l_max, stencil_n, cg_tol=1e-10, cg_
     p.sample_seed = int(sample_seed) & 0xFFFFFFFFFFFFFFFF
     p.sample_frac = float(sample_frac)
     p.n_threads = int(n_threads)
+    p.R_PE_self, p.R_ME_self = float(R_PE_self), float(R_ME_self)
     return p
 
 

@@ -64,6 +64,9 @@ typedef struct {
   unsigned long long sample_seed;  /* deterministic pair subset                  */
   double sample_frac;              /* >= 1: all pairs                            */
   int n_threads;                   /* <= 0: OpenMP default                       */
+  /* separate radii of self pairs (i == j), Sec. III A (Step II): <= 0 takes
+     the non-self value; not combined with variable radii                      */
+  double R_PE_self, R_ME_self;
 } oracle_params;
 
 typedef struct {
@@ -232,8 +235,13 @@ static int ctx_init(ctx_t* X, const oracle_params* P) {
   oracle_stencil_weights(P->stencil_n, X->w2, X->w1);
   double rmax = P->R_PE;
   if (P->R_PE_nclass > 0) rmax = P->R_PE_min + (P->R_PE_nclass - 1) * P->R_PE_step;
-  /* the ME shell must hold every stencil neighbour of the PE sphere */
+  if (P->R_PE_nclass > 0 && (P->R_PE_self > 0.0 || P->R_ME_self > 0.0)) return -1;
+  /* the ME shell must hold every stencil neighbour of the PE sphere, for the
+     self radii as for the others */
   if (P->R_ME < rmax + P->stencil_n * maxd) return -3;
+  const double rpe_s = P->R_PE_self > 0.0 ? P->R_PE_self : P->R_PE;
+  const double rme_s = P->R_ME_self > 0.0 ? P->R_ME_self : P->R_ME;
+  if (rme_s < rpe_s + P->stencil_n * maxd) return -3;
   return 0;
 }
 
@@ -246,12 +254,18 @@ static void mic(const ctx_t* X, const double* d, double* out) {
 }
 
 static double pair_radius(const ctx_t* X, const double* R_orb, int i, int j) {
+  if (i == j && X->P.R_PE_self > 0.0 && X->P.R_PE_nclass <= 0) return X->P.R_PE_self;
   if (!R_orb || X->P.R_PE_nclass <= 0) return X->P.R_PE;
   double r = 0.5 * (R_orb[i] + R_orb[j]);
   double k = round((r - X->P.R_PE_min) / X->P.R_PE_step);
   if (k < 0) k = 0;
   if (k > X->P.R_PE_nclass - 1) k = X->P.R_PE_nclass - 1;
   return X->P.R_PE_min + k * X->P.R_PE_step;
+}
+
+/* ME radius of pair (i, j): the self value for i == j when one is given */
+static double pair_me_radius(const oracle_params* P, int i, int j) {
+  return (i == j && P->R_ME_self > 0.0) ? P->R_ME_self : P->R_ME;
 }
 
 /* grid centre of a point: NINT(N_al * frac((h^-1 C)_al)) mod N_al */
@@ -319,7 +333,8 @@ static void box_make(const ctx_t* X, box_t* bx) {
     /* |o_al| = N_al |(h_g^-1 r)_al| <= N_al |row al of h_g^-1| R_ME */
     double rn = sqrt(M3(X->hginv, al, 0) * M3(X->hginv, al, 0) + M3(X->hginv, al, 1) * M3(X->hginv, al, 1) +
                      M3(X->hginv, al, 2) * M3(X->hginv, al, 2));
-    bx->K[al] = (int)ceil(X->P.R_ME * X->P.grid[al] * rn) + X->P.stencil_n + 1;
+    const double rme = X->P.R_ME_self > X->P.R_ME ? X->P.R_ME_self : X->P.R_ME;   /* the larger ME sphere */
+    bx->K[al] = (int)ceil(rme * X->P.grid[al] * rn) + X->P.stencil_n + 1;
     bx->B[al] = 2 * bx->K[al] + 1;
   }
   bx->s[0] = 1;
@@ -470,7 +485,8 @@ static int eval_pair(const ctx_t* X, work_t* W, const double* orb, oracle_pair_r
   const double* phi_j = orb + (long)res->j * X->ngrid;
   double w = (res->i == res->j) ? 1.0 : 2.0;
   double rpe2 = res->R_PE * res->R_PE * (1.0 + OR_SLACK);
-  double rme2 = P->R_ME * P->R_ME * (1.0 + OR_SLACK);
+  const double rme = pair_me_radius(P, res->i, res->j);
+  double rme2 = rme * rme * (1.0 + OR_SLACK);
 
   memset(W->mask, 0, bx->n);
   memset(W->rho, 0, bx->n * sizeof(double));

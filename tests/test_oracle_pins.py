@@ -517,3 +517,36 @@ def test_wavefunction_force_is_energy_derivative():
     Em = oracle.evaluate(_params(cfg), phi - t * eta, orbs.centres, want_D=False)["E"]
     fd = (Ep - Em) / (2 * t)
     assert abs(fd / pred - 1) < 2e-3, (fd, pred)
+
+
+# --------------------------------------------------------------------------
+# separate self-pair radii (Sec. III A, Step II: the self and non-self
+# subdomain radii of the pair list)
+
+def test_self_radii_reduce_to_plain_runs():
+    """With R_PE_self / R_ME_self, each self pair equals a one-orbital run whose
+    plain radii are those values, and the cross pair equals the run without
+    self radii; E_xx is their sum."""
+    cfg = synth.custom(key="selfr", cell=(12.0, 12.0, 12.0), grid=(48, 48, 48), n_orb=2, R_pair=7.0, R_PE=4.0,
+                       R_ME=5.5, l_max=5, stencil_n=2, cg_tol=1e-12)
+    orbs, phi = _orbitals(cfg, [[5.0, 6.0, 6.2], [6.6, 6.3, 5.8]], [1.1, 1.4], [[0.1, 0.0, -0.2], [0.0, 0.3, 0.1]])
+    both = oracle.evaluate(_params(cfg, R_PE_self=3.6, R_ME_self=5.0), phi, orbs.centres, want_D=False)
+    plain = oracle.evaluate(_params(cfg), phi, orbs.centres, want_D=False)
+    selfcfg = dataclasses.replace(cfg, R_PE=3.6, R_ME=5.0)
+    ij = [(p.i, p.j) for p in both["pairs"]]
+    assert ij == [(0, 0), (0, 1), (1, 1)]
+    for k, i in ((0, 0), (2, 1)):
+        one = oracle.evaluate(_params(selfcfg), phi[[i]], orbs.centres[[i]], want_D=False)
+        assert both["pairs"][k].R_PE == 3.6
+        assert both["pairs"][k].n_pe == one["pairs"][0].n_pe and both["pairs"][k].n_me == one["pairs"][0].n_me
+        assert abs(both["pairs"][k].E - one["pairs"][0].E) <= 1e-13 * abs(one["pairs"][0].E)
+        assert both["pairs"][k].n_pe < plain["pairs"][k].n_pe
+    assert both["pairs"][1].E == plain["pairs"][1].E and both["pairs"][1].R_PE == 4.0
+    assert abs(both["E"] - sum(p.E for p in both["pairs"])) <= 1e-14 * abs(both["E"])
+
+
+def test_self_radii_rejected_with_variable_radii():
+    cfg = synth.custom(key="selfr2", n_orb=2)
+    with pytest.raises(ValueError):
+        oracle.evaluate(_params(cfg, R_PE_classes=(3.5, 0.25, 3), R_PE_self=3.6), np.zeros((2,) + tuple(cfg.grid[::-1])),
+                        np.array([[1.0, 1.0, 1.0], [2.0, 2.0, 2.0]]), R_orb=np.array([3.6, 3.7]), want_D=False)
