@@ -84,6 +84,11 @@ typedef struct {
                                  axis), else from zero; the stop test is unchanged.
                                  Needs max_pairs > 0; keeps 2 max_pairs N_PE FP32
                                  values on the device                               */
+  /* separate radii of self pairs (i == j), Sec. III A (Step II): PE and ME
+     spheres of the self pairs; <= 0 takes the non-self value (exx_plan's R_PE,
+     R_ME).  Self pairs then form a sphere class of their own.  Not combined
+     with variable radii (R_PE_nclass > 0: EXX_EINVAL)                          */
+  double R_PE_self, R_ME_self;
 } exx_options;
 
 /* Fills *opt with the defaults: n = 3, FP64, tol 1e-10, 5000 iterations,

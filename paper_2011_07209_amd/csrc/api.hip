@@ -384,6 +384,10 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (opt.R_PE_nclass < 0 || opt.R_PE_nclass > kMaxClasses) return fail(nullptr, EXX_EINVAL, "R_PE_nclass out of range");
   if (opt.R_PE_nclass > 0 && (!(opt.R_PE_min > 0.0) || !(opt.R_PE_step > 0.0)))
     return fail(nullptr, EXX_EINVAL, "variable radii need R_PE_min > 0 and R_PE_step > 0");
+  if (opt.R_PE_nclass > 0 && (opt.R_PE_self > 0.0 || opt.R_ME_self > 0.0))
+    return fail(nullptr, EXX_EINVAL, "self radii are not combined with variable radii");
+  if (opt.R_PE_nclass + (opt.R_PE_self > 0.0 || opt.R_ME_self > 0.0 ? 1 : 0) > kMaxClasses)
+    return fail(nullptr, EXX_EINVAL, "too many sphere classes");
   if (opt.max_pairs < 0 || opt.workspace_gb < 0 || opt.solve_groups < 0)
     return fail(nullptr, EXX_EINVAL, "negative capacity option");
   if (opt.solve_threads != 0 && opt.solve_threads != 512 && opt.solve_threads != 1024)
@@ -427,7 +431,9 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   g.n_lm = (l_max + 1) * (l_max + 1);
   harmonic_norms(l_max, g.ylm_norm);
 
-  std::vector<double> radii;
+  // sphere classes: the fixed radius or the variable-radius rungs, then (with
+  // self radii) one class of the self pairs with their own PE and ME spheres
+  std::vector<double> radii, me_radii;
   if (opt.R_PE_nclass > 0) {
     for (int k = 0; k < opt.R_PE_nclass; ++k) radii.push_back(opt.R_PE_min + k * opt.R_PE_step);
   } else {
@@ -438,10 +444,23 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     free_plan(P);
     return fail(nullptr, EXX_EINVAL, "R_ME must be >= R_PE + n * max grid spacing");
   }
+  me_radii.assign(radii.size(), R_ME);
+  P->self_class = -1;
+  if (opt.R_PE_self > 0.0 || opt.R_ME_self > 0.0) {
+    const double rpe = opt.R_PE_self > 0.0 ? opt.R_PE_self : R_PE;
+    const double rme = opt.R_ME_self > 0.0 ? opt.R_ME_self : R_ME;
+    if (rme < rpe + n * maxd) {
+      free_plan(P);
+      return fail(nullptr, EXX_EINVAL, "R_ME_self must be >= R_PE_self + n * max grid spacing");
+    }
+    P->self_class = (int)radii.size();
+    radii.push_back(rpe);
+    me_radii.push_back(rme);
+  }
   P->classes.resize(radii.size());
   int maxRg0 = 0, maxRg1 = 0;
   for (size_t k = 0; k < radii.size(); ++k) {
-    std::string e = build_class(g.L, g.N, radii[k], R_ME, n, &P->classes[k]);
+    std::string e = build_class(g.L, g.N, radii[k], me_radii[k], n, &P->classes[k]);
     if (!e.empty()) {
       free_plan(P);
       return fail(nullptr, EXX_EINVAL, e);
@@ -644,6 +663,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   pp.R_min = P->opt.R_PE_min;
   pp.R_step = P->opt.R_PE_step;
   pp.n_class = P->opt.R_PE_nclass;
+  pp.self_class = P->self_class;
   pp.seed = P->opt.pair_sample_seed;
   pp.frac = P->opt.pair_sample_frac;
   EXX_HIP(P, event(P->ev[0]));
@@ -845,6 +865,7 @@ exx_status exx_count_pairs(exx_plan_t P, int n_orb, const double* centres, const
   pp.R_min = P->opt.R_PE_min;
   pp.R_step = P->opt.R_PE_step;
   pp.n_class = P->opt.R_PE_nclass;
+  pp.self_class = P->self_class;
   pp.seed = P->opt.pair_sample_seed;
   pp.frac = P->opt.pair_sample_frac;
   // capacity 0: count and scan only, nothing is stored

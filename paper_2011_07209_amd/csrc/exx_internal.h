@@ -108,6 +108,7 @@ struct exx_plan_s {
   std::vector<exx::ClassDev> class_dev_host;   // with device pointers
   exx::ClassDev* class_dev = nullptr;          // device copy of class_dev_host
   void* class_block = nullptr;                 // device block holding every class table
+  int self_class = -1;   // class of the self pairs when they have their own radii
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
   long long rstride = 0;   // row stride of the per-pair workspaces: max_pe rounded up to 32
   int max_zmax = 0;

@@ -16,6 +16,7 @@ struct PairParams {
   double R_PE;              // fixed radius (class 0) when no per-orbital radii
   double R_min, R_step;     // variable radii rungs
   int n_class;              // <= 0: fixed radius
+  int self_class;           // class of the self pairs (i == j), or -1: by radius like the others
   unsigned long long seed;
   double frac;
 };

@@ -117,6 +117,7 @@ __global__ void k_pair_fill(Geo g, PairParams pp, const double* __restrict__ C, 
         kk = fmax(0.0, fmin((double)(pp.n_class - 1), kk));
         cls = (int)kk;
       }
+      if (i == j && pp.self_class >= 0) cls = pp.self_class;
       P.cls = cls;
       pairs[k] = P;
     }

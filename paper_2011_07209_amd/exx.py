@@ -46,6 +46,8 @@ class Options(ctypes.Structure):
         ("solve_depth", ctypes.c_int),
         ("autotune", ctypes.c_int),
         ("warm_start", ctypes.c_int),
+        ("R_PE_self", ctypes.c_double),
+        ("R_ME_self", ctypes.c_double),
     ]
 
 

@@ -221,3 +221,31 @@ def test_autotuned_solve(prec):
     assert rel1(g["E"], o["E"]) <= TOL_E
     assert rel1(g["sigma"], o["sigma"]) <= TOL_S
     assert rel1(g["D"], o["D"]) <= TOL_D
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_separate_self_radii(prec):
+    """Self pairs on their own PE and ME spheres (R_PE_self, R_ME_self), one
+    sphere class of their own, against the oracle with the same radii."""
+    import oracle
+    cfg = synth.custom(key=f"selfr-{prec}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=7, R_pair=7.0,
+                       R_PE=3.9, R_ME=5.3, l_max=5, stencil_n=3, cg_tol=1e-12, seed_index=81)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    from paper_2011_07209_amd import exx
+    g = gpu_eval(cfg, orbs, phi, R_PE_self=3.3, R_ME_self=4.6,
+                 precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64)
+    P = oracle.make_params(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, cfg.stencil_n, cfg.cg_tol,
+                           R_PE_self=3.3, R_ME_self=4.6)
+    o = oracle.evaluate(P, phi, orbs.centres)
+    assert g["stats"]["n_classes"] == 2
+    assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
+    if prec == "mixed":
+        _check_mixed(g, o, cfg.n_orb)
+        return
+    assert g["stats"]["n_unconverged"] == 0
+    assert rel1(g["E"], o["E"]) <= TOL_E
+    assert rel1(g["sigma"], o["sigma"]) <= TOL_S
+    assert rel1(g["D"], o["D"]) <= TOL_D
+    Eo = np.array([p.E for p in o["pairs"]])
+    assert np.abs(g["pairs"]["E"] - Eo).sum() <= TOL_E * np.abs(Eo).sum()
