@@ -94,6 +94,11 @@ def _load():
         lib.oracle_stencil_weights.argtypes = [ctypes.c_int, dp, dp]
         lib.oracle_apply_A.restype = ctypes.c_int
         lib.oracle_apply_A.argtypes = [P(ctypes.c_int), dp, ctypes.c_int, P(ctypes.c_ubyte), dp, dp]
+        lib.oracle_nk_stencil.restype = ctypes.c_int
+        lib.oracle_nk_stencil.argtypes = [dp, P(ctypes.c_int), P(ctypes.c_int), dp, dp, P(ctypes.c_int), dp]
+        lib.oracle_apply_arms.restype = ctypes.c_int
+        lib.oracle_apply_arms.argtypes = [P(ctypes.c_int), ctypes.c_int, ctypes.c_int, P(ctypes.c_int), dp,
+                                          P(ctypes.c_ubyte), dp, dp]
         lib.oracle_cg_mask.restype = ctypes.c_int
         lib.oracle_cg_mask.argtypes = [P(ctypes.c_int), dp, ctypes.c_int, P(ctypes.c_ubyte), dp, ctypes.c_double,
                                        ctypes.c_int, dp, P(ctypes.c_int), dp]
@@ -130,7 +135,8 @@ def make_params(h, grid, R_pair, R_PE, R_ME, l_max, stencil_n, cg_tol=1e-10, cg_
     return p
 
 
-_ERR = {-1: "invalid argument", -2: "cell not orthorhombic", -3: "R_ME < R_PE + n*max spacing", -4: "out of memory"}
+_ERR = {-1: "invalid argument", -2: "no three admissible NK auxiliary directions",
+        -3: "R_ME < R_PE + n*max stencil step", -4: "out of memory"}
 
 
 def _check(rc):
@@ -238,3 +244,35 @@ def cg_mask(K, spacing, n, mask, b, tol=1e-12, max_iter=10000):
                             float(tol), int(max_iter), _dp(x), ctypes.byref(it), ctypes.byref(rel))
     _check(rc)
     return x, it.value, rel.value
+
+
+def nk_stencil(h, grid):
+    """NK Laplacian arms of cell h (3x3, columns L_al) on a grid: dict with
+    u (k x 3 integer steps), beta, step (length of u), coef = beta / step^2, and
+    the three directions Algorithm 1 accepted (aux, k x 3) with their weights b."""
+    lib = _load()
+    hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64).flatten(order="F"))
+    N = (ctypes.c_int * 3)(*[int(g) for g in grid])
+    u = (ctypes.c_int * 18)()
+    aux = (ctypes.c_int * 9)()
+    beta = np.zeros(6)
+    step = np.zeros(6)
+    b = np.zeros(3)
+    n = _check(lib.oracle_nk_stencil(_dp(hh), N, u, _dp(beta), _dp(step), aux, _dp(b)))
+    U = np.array(list(u), dtype=np.int64).reshape(6, 3)[:n]
+    return {"u": U, "beta": beta[:n].copy(), "step": step[:n].copy(), "coef": beta[:n] / step[:n] ** 2,
+            "aux": np.array(list(aux), dtype=np.int64).reshape(3, 3), "b": b}
+
+
+def apply_arms(K, n, u, coef, mask, p):
+    """-(sum over arms of coef * second difference along u) on the mask==2 points of a [z, y, x] box."""
+    lib = _load()
+    Kc = (ctypes.c_int * 3)(*K)
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.int32).reshape(-1))
+    cc = np.ascontiguousarray(coef, dtype=np.float64)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    q = np.zeros_like(pp)
+    _check(lib.oracle_apply_arms(Kc, int(n), len(cc), uu.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(cc),
+                                 m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), _dp(pp), _dp(q)))
+    return q

@@ -17,8 +17,11 @@
  *   pair density           Sec. I, eq. rho_from_phi_mlwf, on the PE sphere (Step III)
  *   multipole moments      Sec. I, eq. mepole
  *   far-field potential    Sec. I, eq. me, on the ME shell (Step IV)
- *   near-field potential   Sec. I, eq. pe with the axis stencil of Sec. III C,
- *                          eq. d2_1, solved by conjugate gradient (Step IV)
+ *   near-field potential   Sec. I, eq. pe with the Natan-Kronik (NK) Laplacian
+ *                          of Sec. III C 1-2 (eq. lapG_mod_nk3d: pure second
+ *                          derivatives by eq. d2_1 along the lattice directions
+ *                          and the auxiliary directions of Algorithm 1), solved
+ *                          by conjugate gradient (Step IV)
  *   energy                 Sec. I, eq. exxGen_mlwf (Step V)
  *   wavefunction forces    Sec. II B 2, eq. Dxx, on the ME sphere (Step V)
  *   cell derivatives       Sec. II B 3, eq. sxx_working, gradient by Sec. III D,
@@ -31,10 +34,11 @@
  * rounds half away from zero; scatter-adds of periodic aliases accumulate) are
  * listed with their reasons in the design notes of the repository.
  *
- * Only orthorhombic cells are accepted for the Laplacian (the tilted-cell
- * Natan-Kronik representation is not part of this oracle); the cell used to
- * build pairs, centres and offset sets may differ from the physical cell so that
- * strain derivatives can be taken at frozen subdomains (Sec. III B 2).
+ * Any non-singular cell is accepted.  For an orthorhombic cell the NK Laplacian
+ * reduces to the axis stencil.  The cell used to build pairs, centres and
+ * offset sets may differ from the physical cell, so that strain derivatives can
+ * be taken at frozen subdomains (Sec. III B 2); the Laplacian, the Jacobian and
+ * the local coordinates always use the physical cell.
  */
 #include <math.h>
 #include <stdint.h>
@@ -113,13 +117,6 @@ static void matvec3(const double* m, const double* v, double* out) {
     out[r] = M3(m, r, 0) * v[0] + M3(m, r, 1) * v[1] + M3(m, r, 2) * v[2];
 }
 
-static int is_orthorhombic(const double* h) {
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      if (r != c && M3(h, r, c) != 0.0) return 0;
-  return 1;
-}
-
 static double col_norm(const double* h, int al) {
   return sqrt(M3(h, 0, al) * M3(h, 0, al) + M3(h, 1, al) * M3(h, 1, al) +
               M3(h, 2, al) * M3(h, 2, al));
@@ -142,6 +139,227 @@ void oracle_stencil_weights(int n, double* w2, double* w1) {
     w2[0] = -49.0 / 18.0; w2[1] = 3.0 / 2.0; w2[2] = -3.0 / 20.0; w2[3] = 1.0 / 90.0;
     w1[1] = 3.0 / 4.0; w1[2] = -3.0 / 20.0; w1[3] = 1.0 / 60.0;
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* The Natan-Kronik (NK) Laplacian on a general grid (Sec. III C 1-2).        */
+/*                                                                            */
+/* A grid direction u (integer steps along L_1, L_2, L_3) has the Cartesian    */
+/* step sum_al u_al L_al / N_al of length dl.  The Laplacian is written as     */
+/* sum over arms of beta * d^2/dl^2 with the pure second derivative along each */
+/* arm taken by eq. d2_1: beta / dl^2 * sum_q w_q f(o + q u).  The arms are    */
+/* the three lattice directions (eq. lapG_mod_nk3d, first sum) and up to three */
+/* auxiliary directions chosen by Algorithm 1 (second sum).                   */
+
+#define OR_MAX_ARMS 6
+#define OR_NQ 15          /* candidate auxiliary directions handed to Algorithm 1 */
+#define OR_MAX_SHELL 8
+#define OR_TIE 1e-10      /* relative tolerance of equal spacings and of the
+                             parallel / singular tests of Algorithm 1          */
+#define OR_ZERO_W 1e-12   /* arm weights below this times max F_al,al are zero */
+
+typedef struct {
+  int u[3];
+  double beta;   /* weight of d^2/dl^2 along the arm                          */
+  double step;   /* dl                                                         */
+  double coef;   /* beta / dl^2                                                */
+} nk_arm;
+
+typedef struct {
+  int n_arms;
+  nk_arm arm[OR_MAX_ARMS];
+  int aux_u[3][3];   /* the three directions Algorithm 1 accepted             */
+  double b[3];       /* their weights from M b = (F12, F13, F23)              */
+  double F[9];       /* F = J^T J                                             */
+} nk_stencil;
+
+typedef struct {
+  int u[3];
+  double len;
+  int seq;           /* position in the shell sweep                          */
+} nk_cand;
+
+static double step_len(const double* h, const int* N, const int* u) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int al = 0; al < 3; ++al)
+    for (int a = 0; a < 3; ++a) v[a] += u[al] * M3(h, a, al) / N[al];
+  return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+/* candidate order: shorter step first; equal steps (within OR_TIE) keep the
+   order of the shell sweep */
+static int cand_before(const nk_cand* x, const nk_cand* y) {
+  double m = x->len > y->len ? x->len : y->len;
+  if (x->len < y->len - OR_TIE * m) return 1;
+  if (y->len < x->len - OR_TIE * m) return 0;
+  return x->seq < y->seq;
+}
+
+/* Builds the NK arms of cell h on grid N.  Returns 0, or -2 when Algorithm 1
+   finds no three admissible auxiliary directions among its candidates. */
+static int nk_build(const double* h, const int* N, nk_stencil* S) {
+  memset(S, 0, sizeof(*S));
+  double hinv[9], J[9];
+  inv3(h, hinv);
+  double dxi[3];
+  for (int al = 0; al < 3; ++al) dxi[al] = col_norm(h, al) / N[al];
+  /* Jacobian J_{a al} = |L_al| (h^-1)_{al a} (eq. jacb); F = J^T J (eq. lapG_) */
+  for (int a = 0; a < 3; ++a)
+    for (int al = 0; al < 3; ++al) M3(J, a, al) = col_norm(h, al) * M3(hinv, al, a);
+  for (int al = 0; al < 3; ++al)
+    for (int be = 0; be < 3; ++be) {
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) s += M3(J, a, al) * M3(J, a, be);
+      M3(S->F, al, be) = s;
+    }
+
+  /* candidate auxiliary directions: non-axial grid points in shells
+     S = max_al |u_al| = 1, 2, ... about a reference point, one of each +-u
+     pair; the sweep stops at the first shell whose points all lie farther than
+     the largest step of the first shell (and holds at least OR_NQ candidates) */
+  static const int kMaxCand = 4 * (2 * OR_MAX_SHELL + 1) * (2 * OR_MAX_SHELL + 1) * (2 * OR_MAX_SHELL + 1);
+  nk_cand* cand = (nk_cand*)malloc(sizeof(nk_cand) * kMaxCand);
+  if (!cand) return -4;
+  int nc = 0;
+  double big1 = 0.0;
+  for (int sh = 1; sh <= OR_MAX_SHELL; ++sh) {
+    double shell_min = INFINITY;
+    int u[3];
+    for (u[2] = -sh; u[2] <= sh; ++u[2])
+      for (u[1] = -sh; u[1] <= sh; ++u[1])
+        for (u[0] = -sh; u[0] <= sh; ++u[0]) {
+          int m = abs(u[0]) > abs(u[1]) ? abs(u[0]) : abs(u[1]);
+          if (abs(u[2]) > m) m = abs(u[2]);
+          if (m != sh) continue;
+          double len = step_len(h, N, u);
+          if (len < shell_min) shell_min = len;
+          if (sh == 1 && len > big1) big1 = len;
+          int nz = (u[0] != 0) + (u[1] != 0) + (u[2] != 0);
+          if (nz < 2) continue;   /* axial */
+          int lead = u[0] != 0 ? u[0] : (u[1] != 0 ? u[1] : u[2]);
+          if (lead < 0) continue; /* -u is the same direction */
+          nk_cand* c = &cand[nc];
+          c->u[0] = u[0]; c->u[1] = u[1]; c->u[2] = u[2];
+          c->len = len;
+          c->seq = nc;
+          ++nc;
+        }
+    if (sh >= 2 && shell_min > big1 && nc >= OR_NQ) break;
+  }
+  /* ascending step (insertion sort: stable, so ties keep the sweep order) */
+  for (int i = 1; i < nc; ++i) {
+    nk_cand t = cand[i];
+    int j = i - 1;
+    while (j >= 0 && cand_before(&t, &cand[j])) {
+      cand[j + 1] = cand[j];
+      --j;
+    }
+    cand[j + 1] = t;
+  }
+  int nq = nc < OR_NQ ? nc : OR_NQ;
+
+  /* Algorithm 1: accept the shortest candidate, then the next whose column of M
+     is not parallel to the first (Cauchy-Schwarz), then the next that makes M
+     non-singular */
+  double Mm[9] = {0};   /* column p: (a_p1 a_p2, a_p1 a_p3, a_p2 a_p3) */
+  double a_sel[3][3];
+  int p = 0;
+  for (int q = 0; q < nq && p < 3; ++q) {
+    double ap[3];
+    for (int al = 0; al < 3; ++al) ap[al] = cand[q].u[al] * dxi[al] / cand[q].len;
+    double col[3] = {ap[0] * ap[1], ap[0] * ap[2], ap[1] * ap[2]};
+    int ok = 0;
+    if (p == 0) {
+      ok = 1;
+    } else if (p == 1) {
+      double d = 0.0, n1 = 0.0, n2 = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        d += M3(Mm, r, 0) * col[r];
+        n1 += M3(Mm, r, 0) * M3(Mm, r, 0);
+        n2 += col[r] * col[r];
+      }
+      ok = fabs(d) < (1.0 - OR_TIE) * sqrt(n1 * n2);
+    } else {
+      double T[9];
+      memcpy(T, Mm, sizeof(T));
+      for (int r = 0; r < 3; ++r) M3(T, r, 2) = col[r];
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        n0 += M3(T, r, 0) * M3(T, r, 0);
+        n1 += M3(T, r, 1) * M3(T, r, 1);
+        n2 += M3(T, r, 2) * M3(T, r, 2);
+      }
+      ok = fabs(det3(T)) > OR_TIE * sqrt(n0 * n1 * n2);
+    }
+    if (!ok) continue;
+    for (int r = 0; r < 3; ++r) M3(Mm, r, p) = col[r];
+    for (int al = 0; al < 3; ++al) {
+      a_sel[p][al] = ap[al];
+      S->aux_u[p][al] = cand[q].u[al];
+    }
+    ++p;
+  }
+  double aux_len[3];
+  for (int k = 0; k < p; ++k) aux_len[k] = step_len(h, N, S->aux_u[k]);
+  free(cand);
+  if (p < 3) return -2;
+
+  /* M b = (F12, F13, F23) (eq. nk3d_Mb_f), by Cramer's rule */
+  double f[3] = {M3(S->F, 0, 1), M3(S->F, 0, 2), M3(S->F, 1, 2)};
+  double dM = det3(Mm);
+  for (int k = 0; k < 3; ++k) {
+    double T[9];
+    memcpy(T, Mm, sizeof(T));
+    for (int r = 0; r < 3; ++r) M3(T, r, k) = f[r];
+    S->b[k] = det3(T) / dM;
+  }
+
+  /* eq. lapG_mod_nk3d: weight F_al,al - sum_p b_p a_p,al^2 on each lattice
+     direction, b_p on each auxiliary direction; zero weights are dropped */
+  double fmax = 0.0;
+  for (int al = 0; al < 3; ++al) if (M3(S->F, al, al) > fmax) fmax = M3(S->F, al, al);
+  S->n_arms = 0;
+  for (int al = 0; al < 3; ++al) {
+    double beta = M3(S->F, al, al);
+    for (int k = 0; k < 3; ++k) beta -= S->b[k] * a_sel[k][al] * a_sel[k][al];
+    if (fabs(beta) <= OR_ZERO_W * fmax) continue;
+    nk_arm* A = &S->arm[S->n_arms++];
+    A->u[0] = A->u[1] = A->u[2] = 0;
+    A->u[al] = 1;
+    A->beta = beta;
+    A->step = dxi[al];
+    A->coef = beta / (dxi[al] * dxi[al]);
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (fabs(S->b[k]) <= OR_ZERO_W * fmax) continue;
+    nk_arm* A = &S->arm[S->n_arms++];
+    for (int al = 0; al < 3; ++al) A->u[al] = S->aux_u[k][al];
+    A->beta = S->b[k];
+    A->step = aux_len[k];
+    A->coef = S->b[k] / (aux_len[k] * aux_len[k]);
+  }
+  return 0;
+}
+
+/* The NK arms of cell h on grid N, for the checks: u_out[3 k + al], beta_out,
+   step_out per arm; aux_out[3 p + al] and b_out[p] for the three directions
+   Algorithm 1 accepted.  Returns the number of arms or a negative error. */
+int oracle_nk_stencil(const double* h, const int* N, int* u_out, double* beta_out, double* step_out, int* aux_out,
+                      double* b_out) {
+  if (fabs(det3(h)) <= 0.0 || N[0] <= 0 || N[1] <= 0 || N[2] <= 0) return -1;
+  nk_stencil S;
+  int rc = nk_build(h, N, &S);
+  if (rc) return rc;
+  for (int k = 0; k < S.n_arms; ++k) {
+    for (int al = 0; al < 3; ++al) u_out[3 * k + al] = S.arm[k].u[al];
+    beta_out[k] = S.arm[k].beta;
+    step_out[k] = S.arm[k].step;
+  }
+  for (int p = 0; p < 3; ++p) {
+    for (int al = 0; al < 3; ++al) aux_out[3 * p + al] = S.aux_u[p][al];
+    b_out[p] = S.b[p];
+  }
+  return S.n_arms;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -213,6 +431,8 @@ typedef struct {
   double dV;           /* |det h| / N                                           */
   long ngrid;
   double w2[4], w1[4];
+  nk_stencil S;        /* Laplacian arms of the physical cell               */
+  int umax;            /* largest |u_al| over the arms                      */
 } ctx_t;
 
 static int ctx_init(ctx_t* X, const oracle_params* P) {
@@ -220,16 +440,26 @@ static int ctx_init(ctx_t* X, const oracle_params* P) {
   if (P->grid[0] <= 0 || P->grid[1] <= 0 || P->grid[2] <= 0) return -1;
   if (P->stencil_n < 1 || P->stencil_n > 3) return -1;
   if (P->l_max < 0 || P->l_max > OR_MAXL) return -1;
-  if (!is_orthorhombic(P->h) || !is_orthorhombic(P->h_geom)) return -2;
   if (fabs(det3(P->h)) <= 0.0 || fabs(det3(P->h_geom)) <= 0.0) return -1;
   inv3(P->h, X->hinv);
   inv3(P->h_geom, X->hginv);
   X->ngrid = (long)P->grid[0] * P->grid[1] * P->grid[2];
+  int nk = nk_build(P->h, P->grid, &X->S);
+  if (nk) return nk;
+  /* the longest stencil step in the geometry cell: Laplacian arms, and the
+     lattice directions of the first-derivative stencil of sigma */
   double maxd = 0.0;
+  X->umax = 1;
   for (int al = 0; al < 3; ++al) {
     X->dxi[al] = col_norm(P->h, al) / P->grid[al];
     double dg = col_norm(P->h_geom, al) / P->grid[al];
     if (dg > maxd) maxd = dg;
+  }
+  for (int k = 0; k < X->S.n_arms; ++k) {
+    double dg = step_len(P->h_geom, P->grid, X->S.arm[k].u);
+    if (dg > maxd) maxd = dg;
+    for (int al = 0; al < 3; ++al)
+      if (abs(X->S.arm[k].u[al]) > X->umax) X->umax = abs(X->S.arm[k].u[al]);
   }
   X->dV = fabs(det3(P->h)) / (double)X->ngrid;
   oracle_stencil_weights(P->stencil_n, X->w2, X->w1);
@@ -334,7 +564,7 @@ static void box_make(const ctx_t* X, box_t* bx) {
     double rn = sqrt(M3(X->hginv, al, 0) * M3(X->hginv, al, 0) + M3(X->hginv, al, 1) * M3(X->hginv, al, 1) +
                      M3(X->hginv, al, 2) * M3(X->hginv, al, 2));
     const double rme = X->P.R_ME_self > X->P.R_ME ? X->P.R_ME_self : X->P.R_ME;   /* the larger ME sphere */
-    bx->K[al] = (int)ceil(rme * X->P.grid[al] * rn) + X->P.stencil_n + 1;
+    bx->K[al] = (int)ceil(rme * X->P.grid[al] * rn) + X->P.stencil_n * X->umax + 1;
     bx->B[al] = 2 * bx->K[al] + 1;
   }
   bx->s[0] = 1;
@@ -350,20 +580,23 @@ static void rbar_of(const double* h, const int* N, const int* o, double* r) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* the discrete operator A = -(axis-stencil Laplacian) restricted to the PE    */
-/* points (Dirichlet zero elsewhere), and plain CG on it                       */
+/* the discrete operator A = -(NK Laplacian) restricted to the PE points      */
+/* (Dirichlet zero elsewhere), and plain CG on it                              */
+
+static long arm_stride(const box_t* bx, const int* u) {
+  return u[0] * bx->s[0] + u[1] * bx->s[1] + u[2] * bx->s[2];
+}
 
 static void apply_A(const ctx_t* X, const box_t* bx, const long* pe, long npe, const double* p, double* q) {
   int n = X->P.stencil_n;
-  double c[3];
-  for (int al = 0; al < 3; ++al) c[al] = 1.0 / (X->dxi[al] * X->dxi[al]);
   for (long k = 0; k < npe; ++k) {
     long o = pe[k];
     double acc = 0.0;
-    for (int al = 0; al < 3; ++al) {
+    for (int m = 0; m < X->S.n_arms; ++m) {
+      long st = arm_stride(bx, X->S.arm[m].u);
       double t = X->w2[0] * p[o];
-      for (int qq = 1; qq <= n; ++qq) t += X->w2[qq] * (p[o + qq * bx->s[al]] + p[o - qq * bx->s[al]]);
-      acc += c[al] * t;
+      for (int qq = 1; qq <= n; ++qq) t += X->w2[qq] * (p[o + qq * st] + p[o - qq * st]);
+      acc += X->S.arm[m].coef * t;
     }
     q[o] = -acc;
   }
@@ -565,14 +798,15 @@ static int eval_pair(const ctx_t* X, work_t* W, const double* orb, oracle_pair_r
   }
 
   /* right-hand side of the PE problem: 4 pi rho plus the stencil reach into
-     the shell, where v takes its far-field values (eq. pe with eq. d2_1) */
+     the shell, where v takes its far-field values (eq. pe with eq. d2_1 along
+     every arm of the NK Laplacian) */
   for (long k = 0; k < npe; ++k) {
     long bi = W->pe[k];
     double acc = 4.0 * OR_PI * W->rho[bi];
-    for (int al = 0; al < 3; ++al) {
-      double c = 1.0 / (X->dxi[al] * X->dxi[al]);
+    for (int m = 0; m < X->S.n_arms; ++m) {
+      long st = arm_stride(bx, X->S.arm[m].u);
       for (int qq = 1; qq <= n; ++qq)
-        acc += c * X->w2[qq] * (W->vb[bi + qq * bx->s[al]] + W->vb[bi - qq * bx->s[al]]);
+        acc += X->S.arm[m].coef * X->w2[qq] * (W->vb[bi + qq * st] + W->vb[bi - qq * st]);
     }
     W->b[bi] = acc;
   }
@@ -666,8 +900,10 @@ static int eval_pair(const ctx_t* X, work_t* W, const double* orb, oracle_pair_r
 void oracle_box_dims(const oracle_params* P, int* K) {
   ctx_t X;
   memset(&X, 0, sizeof(X));
-  X.P = *P;
-  inv3(P->h_geom, X.hginv);
+  if (ctx_init(&X, P)) {
+    K[0] = K[1] = K[2] = -1;
+    return;
+  }
   box_t bx;
   box_make(&X, &bx);
   for (int a = 0; a < 3; ++a) K[a] = bx.K[a];
@@ -804,15 +1040,61 @@ static int box_from_dims(const int* K, box_t* bx) {
   return 0;
 }
 
-static long mask_list(const box_t* bx, int n, const unsigned char* mask, long* pe) {
+static long mask_list(const box_t* bx, int reach, const unsigned char* mask, long* pe) {
   long npe = 0;
-  for (int z = n; z < bx->B[2] - n; ++z)
-    for (int y = n; y < bx->B[1] - n; ++y)
-      for (int x = n; x < bx->B[0] - n; ++x) {
+  for (int z = reach; z < bx->B[2] - reach; ++z)
+    for (int y = reach; y < bx->B[1] - reach; ++y)
+      for (int x = reach; x < bx->B[0] - reach; ++x) {
         long bi = x + bx->s[1] * y + bx->s[2] * z;
         if (mask[bi] == 2) pe[npe++] = bi;
       }
   return npe;
+}
+
+/* the three axis arms of an orthorhombic grid with the given spacings */
+static void axis_arms(ctx_t* X, const double* spacing) {
+  memset(&X->S, 0, sizeof(X->S));
+  X->S.n_arms = 3;
+  X->umax = 1;
+  for (int a = 0; a < 3; ++a) {
+    X->dxi[a] = spacing[a];
+    nk_arm* A = &X->S.arm[a];
+    A->u[a] = 1;
+    A->beta = 1.0;
+    A->step = spacing[a];
+    A->coef = 1.0 / (spacing[a] * spacing[a]);
+  }
+}
+
+/* -(sum over arms of coef * eq. d2_1 along u) on the mask == 2 points of a box;
+   n_arms arms with steps u[3 k + al] and coefficients coef[k] */
+int oracle_apply_arms(const int* K, int n, int n_arms, const int* u, const double* coef, const unsigned char* mask,
+                      const double* p, double* q) {
+  ctx_t X;
+  memset(&X, 0, sizeof(X));
+  box_t bx;
+  if (box_from_dims(K, &bx) || n < 1 || n > 3 || n_arms < 1 || n_arms > OR_MAX_ARMS) return -1;
+  X.P.stencil_n = n;
+  oracle_stencil_weights(n, X.w2, X.w1);
+  X.S.n_arms = n_arms;
+  X.umax = 1;
+  for (int k = 0; k < n_arms; ++k) {
+    for (int al = 0; al < 3; ++al) {
+      X.S.arm[k].u[al] = u[3 * k + al];
+      if (abs(u[3 * k + al]) > X.umax) X.umax = abs(u[3 * k + al]);
+    }
+    X.S.arm[k].coef = coef[k];
+  }
+  long* pe = (long*)malloc(bx.n * sizeof(long));
+  if (!pe) return -4;
+  long npe = mask_list(&bx, n * X.umax, mask, pe);
+  double* pm = (double*)calloc(bx.n, sizeof(double));
+  for (long k = 0; k < npe; ++k) pm[pe[k]] = p[pe[k]];
+  memset(q, 0, bx.n * sizeof(double));
+  apply_A(&X, &bx, pe, npe, pm, q);
+  free(pm);
+  free(pe);
+  return 0;
 }
 
 int oracle_apply_A(const int* K, const double* spacing, int n, const unsigned char* mask, const double* p,
@@ -822,7 +1104,7 @@ int oracle_apply_A(const int* K, const double* spacing, int n, const unsigned ch
   box_t bx;
   if (box_from_dims(K, &bx) || n < 1 || n > 3) return -1;
   X.P.stencil_n = n;
-  for (int a = 0; a < 3; ++a) X.dxi[a] = spacing[a];
+  axis_arms(&X, spacing);
   oracle_stencil_weights(n, X.w2, X.w1);
   long* pe = (long*)malloc(bx.n * sizeof(long));
   if (!pe) return -4;
@@ -845,7 +1127,7 @@ int oracle_cg_mask(const int* K, const double* spacing, int n, const unsigned ch
   X.P.stencil_n = n;
   X.P.cg_tol = tol;
   X.P.cg_max_iter = max_iter;
-  for (int a = 0; a < 3; ++a) X.dxi[a] = spacing[a];
+  axis_arms(&X, spacing);
   oracle_stencil_weights(n, X.w2, X.w1);
   long* pe = (long*)malloc(bx.n * sizeof(long));
   double* r = (double*)calloc(bx.n, sizeof(double));

@@ -50,10 +50,17 @@ class Config:
     R_orb_range: Optional[tuple] = None   # per-orbital radius range
     orb_dtype: str = "f64"
     seed_index: int = 0
+    hmat: Optional[tuple] = None        # general cell: h[a + 3 al] = (L_al)_a (column-major); None: diag(cell)
 
     @property
     def h(self) -> np.ndarray:
+        if self.hmat is not None:
+            return np.asarray(self.hmat, dtype=np.float64).reshape(3, 3, order="F")
         return np.diag(np.asarray(self.cell, dtype=np.float64))
+
+    @property
+    def general(self) -> bool:
+        return self.hmat is not None
 
     @property
     def n_points(self) -> int:
@@ -61,7 +68,14 @@ class Config:
 
     @property
     def spacing(self):
+        if self.hmat is not None:
+            h = self.h
+            return tuple(float(np.linalg.norm(h[:, a])) / self.grid[a] for a in range(3))
         return tuple(self.cell[a] / self.grid[a] for a in range(3))
+
+    @property
+    def dV(self) -> float:
+        return abs(float(np.linalg.det(self.h))) / float(np.prod(self.grid))
 
 
 # The five workloads: a tiny cubic cell for oracle-speed parity, and water-like
@@ -117,7 +131,12 @@ _BASIS = {
 def make_orbitals(cfg: Config, seed: Optional[int] = None) -> OrbitalSet:
     st = _streams(cfg, seed)
     L = np.asarray(cfg.cell, dtype=np.float64)
-    if cfg.lattice is None:
+    if cfg.general:
+        # general cell: uniform centres in crystal coordinates
+        if cfg.lattice is not None:
+            raise ValueError("lattice sets are built for orthorhombic cells")
+        centres = st[_S_CENTRES].uniform(0.0, 1.0, size=(cfg.n_orb, 3)) @ cfg.h.T
+    elif cfg.lattice is None:
         centres = st[_S_CENTRES].uniform(0.0, 1.0, size=(cfg.n_orb, 3)) * L
     else:
         basis = _BASIS[cfg.lattice]
@@ -146,6 +165,10 @@ def displace(cfg: Config, orbs: OrbitalSet, step: int, amplitude: float = 0.02) 
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED + cfg.seed_index, 99, step])))
     d = rng.normal(size=orbs.centres.shape)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
+    if cfg.general:
+        h = cfg.h
+        s = np.mod((orbs.centres + amplitude * d) @ np.linalg.inv(h).T, 1.0)
+        return dataclasses.replace(orbs, centres=s @ h.T)
     L = np.asarray(cfg.cell)
     return dataclasses.replace(orbs, centres=np.mod(orbs.centres + amplitude * d, L))
 
@@ -175,10 +198,38 @@ def fill_orbital(cfg_cell: Sequence[float], grid: Sequence[int], centre, expo: f
     return out
 
 
+def fill_orbital_cell(h, grid: Sequence[int], centre, expo: float, poly, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """fill_orbital for a general cell h (columns L_al): grid point n sits at
+    r = h (n / N); d = h (s - floor(s + 1/2)) with s = h^-1 (r - C)."""
+    h = np.asarray(h, dtype=np.float64)
+    hinv = np.linalg.inv(h)
+    N1, N2, N3 = grid
+    if out is None:
+        out = np.empty((N3, N2, N1), dtype=np.float64)
+    n1 = np.arange(N1, dtype=np.float64) / N1
+    n2 = np.arange(N2, dtype=np.float64) / N2
+    c = np.asarray(centre, dtype=np.float64)
+    for k in range(N3):
+        f = np.stack(np.meshgrid(n1, n2, indexing="xy"), -1).reshape(-1, 2)   # (x fastest within y)
+        fr = np.concatenate([f, np.full((f.shape[0], 1), k / N3)], 1)
+        s = (fr @ h.T - c) @ hinv.T
+        s -= np.floor(s + 0.5)
+        d = s @ h.T
+        val = np.exp(-expo * np.sum(d * d, 1)) * (1.0 + d @ np.asarray(poly, dtype=np.float64))
+        out[k] = val.reshape(N2, N1)
+    dV = abs(float(np.linalg.det(h))) / float(N1 * N2 * N3)
+    out *= 1.0 / math.sqrt(dV * float(np.vdot(out, out)))
+    return out
+
+
 def fill_orbitals(cfg: Config, orbs: OrbitalSet, dtype=np.float64, subset: Optional[Sequence[int]] = None) -> np.ndarray:
     idx = range(cfg.n_orb) if subset is None else list(subset)
     N1, N2, N3 = cfg.grid
     arr = np.empty((len(idx), N3, N2, N1), dtype=dtype)
+    if cfg.general:
+        for k, i in enumerate(idx):
+            arr[k] = fill_orbital_cell(cfg.h, cfg.grid, orbs.centres[i], orbs.expo[i], orbs.poly[i])
+        return arr
     tmp = np.empty((N3, N2, N1), dtype=np.float64) if dtype != np.float64 else None
     for k, i in enumerate(idx):
         if tmp is None:
@@ -202,6 +253,27 @@ def fill_orbitals_device(cfg: Config, orbs: OrbitalSet, device, dtype=None, out=
     N1, N2, N3 = cfg.grid
     if out is None:
         out = torch.empty((len(idx), N3, N2, N1), dtype=dtype, device=device)
+    if cfg.general:
+        # general cell: the fill_orbital_cell formula, one plane at a time
+        h = torch.tensor(cfg.h, dtype=torch.float64, device=device)
+        hinv = torch.linalg.inv(h)
+        dVg = cfg.dV
+        g2, g1 = torch.meshgrid(torch.arange(N2, dtype=torch.float64, device=device) / N2,
+                                torch.arange(N1, dtype=torch.float64, device=device) / N1, indexing="ij")
+        for k, i in enumerate(idx):
+            c = torch.tensor(orbs.centres[i], dtype=torch.float64, device=device)
+            pc = torch.tensor(orbs.poly[i], dtype=torch.float64, device=device)
+            a = float(orbs.expo[i])
+            phi = torch.empty((N3, N2, N1), dtype=torch.float64, device=device)
+            for z in range(N3):
+                fr = torch.stack([g1, g2, torch.full_like(g1, z / N3)], -1).reshape(-1, 3)
+                s = (fr @ h.T - c) @ hinv.T
+                s = s - torch.floor(s + 0.5)
+                d = s @ h.T
+                phi[z] = (torch.exp(-a * (d * d).sum(1)) * (1.0 + d @ pc)).reshape(N2, N1)
+            phi *= 1.0 / math.sqrt(dVg * float(torch.dot(phi.reshape(-1), phi.reshape(-1)).item()))
+            out[k].copy_(phi)
+        return out
     dV = float(np.prod(cfg.cell)) / float(N1 * N2 * N3)
 
     def axis(N, L, c):

@@ -550,3 +550,252 @@ def test_self_radii_rejected_with_variable_radii():
     with pytest.raises(ValueError):
         oracle.evaluate(_params(cfg, R_PE_classes=(3.5, 0.25, 3), R_PE_self=3.6), np.zeros((2,) + tuple(cfg.grid[::-1])),
                         np.array([[1.0, 1.0, 1.0], [2.0, 2.0, 2.0]]), R_orb=np.array([3.6, 3.7]), want_D=False)
+
+
+# --------------------------------------------------------------------------
+# general cells: the Natan-Kronik Laplacian (Sec. III C 1-2, Algorithm 1),
+# general proto-subdomains (Sec. III B 1) and sigma (eq. sxx_working)
+
+def _cell(a, b, c, al, be, ga):
+    """Cell with edge lengths a, b, c and angles (degrees) al = angle(L2, L3),
+    be = angle(L1, L3), ga = angle(L1, L2); columns are the lattice vectors."""
+    al, be, ga = np.radians([al, be, ga])
+    L1 = np.array([a, 0.0, 0.0])
+    L2 = np.array([b * np.cos(ga), b * np.sin(ga), 0.0])
+    cx = c * np.cos(be)
+    cy = c * (np.cos(al) - np.cos(be) * np.cos(ga)) / np.sin(ga)
+    L3 = np.array([cx, cy, np.sqrt(c * c - cx * cx - cy * cy)])
+    return np.column_stack([L1, L2, L3])
+
+
+_NK_CELLS = {
+    "hexagonal": (_cell(12.0, 12.0, 12.0, 90, 90, 120), (60, 60, 60)),
+    "acute60": (_cell(12.0, 12.0, 12.0, 90, 90, 60), (60, 60, 60)),
+    "monoclinic": (_cell(12.0, 12.0, 12.0, 90, 105, 90), (60, 60, 60)),
+    "triclinic": (_cell(12.0, 12.5, 11.5, 80, 95, 100), (60, 62, 58)),
+    "rhombohedral": (_cell(12.0, 12.0, 12.0, 113, 113, 113), (60, 60, 60)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(_NK_CELLS))
+def test_nk_arms_reproduce_the_laplacian(name):
+    """In grid-index coordinates x (r = A x, A = h diag(1/N)) the Laplacian is
+    sum_ij G_ij d_i d_j with G = (A^T A)^-1.  A sum of pure second derivatives
+    along grid steps u_k with coefficients c_k is that operator exactly when
+    sum_k c_k u_k u_k^T = G, which is what eq. lapG_mod_nk3d must achieve."""
+    h, N = _NK_CELLS[name]
+    S = oracle.nk_stencil(h, N)
+    A = h / np.asarray(N, float)
+    G = np.linalg.inv(A.T @ A)
+    Gs = sum(c * np.outer(u, u) for u, c in zip(S["u"], S["coef"]))
+    np.testing.assert_allclose(Gs, G, rtol=0, atol=1e-12 * np.abs(G).max())
+    # the arm lengths are the Cartesian steps of the grid directions
+    np.testing.assert_allclose(S["step"], np.linalg.norm(S["u"] @ A.T, axis=1), rtol=1e-14)
+    # N_pure = 3 + N_aux (Table: 4 for monoclinic/hexagonal/rhombohedral, 6 for triclinic)
+    assert len(S["u"]) == (6 if name == "triclinic" else 4)
+    assert np.all(S["beta"] > 0)
+
+
+def test_nk_orthorhombic_reduces_to_axis_stencil():
+    h = np.diag([11.0, 12.5, 13.0])
+    S = oracle.nk_stencil(h, (44, 50, 52))
+    np.testing.assert_array_equal(S["u"], np.eye(3, dtype=int))
+    np.testing.assert_allclose(S["beta"], 1.0, rtol=1e-15)
+    np.testing.assert_array_equal(S["b"], 0.0)
+
+
+@pytest.mark.parametrize("gamma,N2", [(120.0, 60), (60.0, 60), (75.0, 66), (104.0, 54)])
+def test_nk_two_dimensional_closed_form(gamma, N2):
+    """With only L1, L2 non-orthogonal the 3D construction must reproduce the 2D
+    NK Laplacian, eq. lapG_nk2d: weights F11 - F12/kappa, F22 - kappa F12 on the
+    lattice directions and F12 d^2 / kappa on the auxiliary direction
+    (L1^ + kappa L2^)/d, kappa = -(dxi_2/dxi_1) sgn(cos gamma) (eq. kappa_def).
+    Unequal spacings exercise the ratio in kappa."""
+    h = _cell(12.0, 12.0, 12.0, 90, 90, gamma)
+    N = (60, N2, 60)
+    S = oracle.nk_stencil(h, N)
+    # F = J^T J with J_{a al} = |L_al| (h^-1)_{al a} (eq. jacb)
+    Lnorm = np.linalg.norm(h, axis=0)
+    J = np.linalg.inv(h).T * Lnorm[None, :]
+    F = J.T @ J
+    dxi = Lnorm / np.asarray(N)
+    kappa = -(dxi[1] / dxi[0]) * np.sign(np.cos(np.radians(gamma)))
+    L1h, L2h = h[:, 0] / Lnorm[0], h[:, 1] / Lnorm[1]
+    d = np.linalg.norm(L1h + kappa * L2h)
+    want = {(1, 0, 0): F[0, 0] - F[0, 1] / kappa, (0, 1, 0): F[1, 1] - kappa * F[0, 1], (0, 0, 1): F[2, 2],
+            (1, -int(np.sign(np.cos(np.radians(gamma)))), 0): F[0, 1] * d * d / kappa}
+    got = {tuple(int(x) for x in u): b for u, b in zip(S["u"], S["beta"])}
+    assert set(got) == set(want), (got, want)
+    for k in want:
+        assert abs(got[k] - want[k]) <= 1e-12 * max(1.0, abs(want[k])), (k, got[k], want[k])
+
+
+@pytest.mark.parametrize("name", sorted(_NK_CELLS))
+def test_nk_first_auxiliary_direction_is_the_shortest_non_axial_step(name):
+    """Criteria (i) and (ii) of Algorithm 1: the first auxiliary direction is a
+    non-axial grid direction of the smallest possible spacing (brute force)."""
+    h, N = _NK_CELLS[name]
+    S = oracle.nk_stencil(h, N)
+    A = h / np.asarray(N, float)
+    best = min(np.linalg.norm(A @ np.array(u)) for u in np.ndindex(5, 5, 5)
+               for u in [np.array(u) - 2] if np.count_nonzero(u) >= 2)
+    assert abs(np.linalg.norm(A @ S["aux"][0]) - best) <= 1e-12 * best
+    # the three accepted directions leave M non-singular (eq. nk3d_Mb_f)
+    a = np.array([(u * np.linalg.norm(A, axis=0)) / np.linalg.norm(A @ u) for u in S["aux"]])
+    M = np.array([[p[0] * p[1] for p in a], [p[0] * p[2] for p in a], [p[1] * p[2] for p in a]])
+    assert abs(np.linalg.det(M)) > 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_nk_operator_exact_on_quadratics(n):
+    """The oracle's operator with the triclinic NK arms, applied on a box to a
+    quadratic polynomial of the Cartesian position, returns -(its Laplacian) =
+    -2 tr Q wherever its whole stencil lies on listed points."""
+    h, N = _NK_CELLS["triclinic"]
+    S = oracle.nk_stencil(h, N)
+    A = h / np.asarray(N, float)
+    K = (6, 6, 6)
+    z, y, x = np.meshgrid(*(np.arange(-k, k + 1) for k in K[::-1]), indexing="ij")
+    r = np.stack([x, y, z], -1) @ A.T
+    rng = np.random.default_rng(5)
+    Q = rng.normal(size=(3, 3))
+    Q = Q + Q.T
+    g = rng.normal(size=3)
+    f = np.einsum("...a,ab,...b->...", r, Q, r) + r @ g + 0.7
+    mask = np.full(f.shape, 2, dtype=np.uint8)
+    q = oracle.apply_arms(K, n, S["u"], S["coef"], mask, f)
+    # listed points keep n from the box faces and values off the list are zero
+    # (Dirichlet), so the operator is exact 2n inside
+    inner = (slice(2 * n, -2 * n),) * 3
+    np.testing.assert_allclose(q[inner], -2.0 * np.trace(Q), rtol=1e-9)
+
+
+def test_nk_me_sphere_must_hold_the_longest_arm():
+    """The Dirichlet points reached along an auxiliary arm need far-field values:
+    R_ME >= R_PE + n * (longest arm step), not only the lattice spacings."""
+    h, N = _NK_CELLS["triclinic"]
+    S = oracle.nk_stencil(h, N)
+    longest = S["step"].max()
+    axis = max(np.linalg.norm(h, axis=0) / np.asarray(N))
+    assert longest > axis * 1.05
+    cfg = synth.custom(grid=N, R_PE=4.0, R_ME=4.0 + 3 * (axis + longest) / 2, stencil_n=3, hmat=tuple(h.flatten("F")))
+    with pytest.raises(ValueError):
+        oracle.pair_list(_params(cfg), np.array([[1.0, 1.0, 1.0]]))
+    ok = dataclasses.replace(cfg, R_ME=4.0 + 3 * longest * 1.001)
+    assert len(oracle.pair_list(_params(ok), np.array([[1.0, 1.0, 1.0]]))) == 1
+
+
+def _gen_cfg(h, grid, **kw):
+    return synth.custom(cell=tuple(np.linalg.norm(h, axis=0)), grid=grid, hmat=tuple(np.asarray(h).flatten("F")),
+                        **kw)
+
+
+def test_sheared_description_of_a_cubic_lattice_gives_the_cubic_result():
+    """h' = h M with M unimodular and equal N on every axis describes the same
+    grid points and the same periodicity.  The NK construction for h' must find
+    the cubic axes again (the sheared axis gets weight zero and the auxiliary
+    direction L2' - L1' is the cubic y axis), so E and D agree with the cubic run
+    to rounding, with the pair centres mapped by M (eq. l2g in crystal
+    coordinates).  sigma transforms as sigma' = sigma M^-T."""
+    N = 48
+    h0 = np.diag([12.0, 12.0, 12.0])
+    M = np.array([[1, 1, 0], [0, 1, 0], [0, 0, 1]])
+    h1 = h0 @ M
+    S1 = oracle.nk_stencil(h1, (N, N, N))
+    assert sorted(tuple(int(x) for x in M @ u) for u in S1["u"]) == sorted([(1, 0, 0), (0, 0, 1), (0, -1, 0)]) or \
+        sorted(tuple(int(x) for x in M @ u) for u in S1["u"]) == sorted([(1, 0, 0), (0, 0, 1), (0, 1, 0)])
+    cfg0 = synth.custom(grid=(N, N, N), R_PE=4.0, R_ME=5.5, stencil_n=3, cg_tol=1e-13, R_pair=8.0, l_max=6)
+    # centres on grid points with even index separations: every pair centre is a grid point
+    idx = np.array([[20, 22, 24], [24, 22, 20], [22, 26, 24]])
+    C = idx * 0.25
+    orbs, phi0 = _orbitals(cfg0, C, [1.2, 0.95, 1.4], [[0.3, -0.2, 0.1], [0.0, 0.25, -0.3], [-0.2, 0.1, 0.2]])
+    r0 = oracle.evaluate(_params(cfg0), phi0, orbs.centres)
+    # the same values on the sheared grid: point n' sits at h0 (M n') / N
+    n1, n2 = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    src = (n1 + n2) % N
+    phi1 = phi0[:, :, n2, src]
+    cfg1 = _gen_cfg(h1, (N, N, N), R_PE=4.0, R_ME=5.5, stencil_n=3, cg_tol=1e-13, R_pair=8.0, l_max=6)
+    r1 = oracle.evaluate(_params(cfg1), phi1, orbs.centres)
+    assert [(p.i, p.j) for p in r0["pairs"]] == [(p.i, p.j) for p in r1["pairs"]]
+    for p0, p1 in zip(r0["pairs"], r1["pairs"]):
+        assert tuple(int(x) % N for x in M @ np.array(p1.c)) == tuple(p0.c)
+        assert p0.n_pe == p1.n_pe and p0.n_me == p1.n_me
+        assert abs(p1.E - p0.E) <= 1e-11 * abs(p0.E)
+    assert abs(r1["E"] - r0["E"]) <= 1e-11 * abs(r0["E"])
+    D1_in_cubic = r0["D"][:, :, n2, src]
+    np.testing.assert_allclose(r1["D"], D1_in_cubic, rtol=0, atol=1e-10 * np.abs(r0["D"]).max())
+    # sigma' = sigma M^-T: the x and z rows use the cubic first-derivative
+    # stencils (J' maps them to L1' and L3), so they agree to rounding; the y
+    # row comes from the diagonal L2' stencil (step sqrt(2) h), a discretization
+    # difference (4e-3 of max |sigma| here, 4.5e-4 at N = 72)
+    want = r0["sigma"] @ np.linalg.inv(M).T
+    smax = np.abs(want).max()
+    np.testing.assert_allclose(r1["sigma"][[0, 2]], want[[0, 2]], rtol=0, atol=1e-13 * smax)
+    np.testing.assert_allclose(r1["sigma"][1], want[1], rtol=0, atol=1e-2 * smax)
+
+
+@pytest.mark.parametrize("n,order", [(3, 64.0)])
+def test_gaussian_self_pair_closed_form_triclinic(n, order):
+    """Self pair of a normalized Gaussian on a triclinic grid (6 NK arms):
+    E = -sqrt(4a/pi), the error falling as h^(2n) when the spacing is halved."""
+    a = 1.2
+    h = _cell(12.0, 12.0, 12.0, 80, 95, 100)
+    errs = []
+    for N in (48, 96):
+        cfg = _gen_cfg(h, (N, N, N), R_PE=4.0, R_ME=5.6, stencil_n=n, cg_tol=1e-13)
+        centre = h @ np.array([0.5, 0.5, 0.5])
+        orbs, phi = _orbitals(cfg, [centre], [a], [[0.0, 0.0, 0.0]])
+        res = oracle.evaluate(_params(cfg), phi, orbs.centres)
+        errs.append(res["E"] / _gauss_self_energy(a) - 1.0)
+    assert abs(errs[0]) < 2e-4, errs
+    ratio = errs[0] / errs[1]
+    assert order * 0.75 < ratio < order * 1.3, (errs, ratio)
+
+
+def _tri_poly_set(N):
+    h = _cell(12.0, 12.5, 11.5, 80, 95, 100)
+    cfg = _gen_cfg(h, (N, N, N), R_PE=5.0, R_ME=7.0, stencil_n=3, cg_tol=1e-11, R_pair=8.0)
+    s = np.array([[0.50, 0.50, 0.48], [0.58, 0.55, 0.44], [0.42, 0.58, 0.55], [0.54, 0.41, 0.57]])
+    a = [1.3, 0.9, 1.5, 1.05]
+    poly = [[0.3, -0.2, 0.4], [-0.35, 0.1, 0.2], [0.15, 0.3, -0.25], [0.0, -0.4, 0.1]]
+    return cfg, s @ h.T, a, poly
+
+
+def test_virial_identity_triclinic_converges_at_stencil_order():
+    """sum_{a,al} sigma^{a al} h_{a al} = -E_xx in the continuum for any cell
+    (E scales as 1/length); with the NK Laplacian and the J-based gradient the
+    gap falls as h^6."""
+    gaps = []
+    for N in (60, 90):
+        cfg, C, a, poly = _tri_poly_set(N)
+        orbs, phi = _orbitals(cfg, C, a, poly)
+        res = oracle.evaluate(_params(cfg), phi, orbs.centres)
+        gaps.append((np.sum(res["sigma"] * cfg.h) + res["E"]) / res["E"])
+    assert abs(gaps[0]) < 5e-4, gaps
+    ratio = gaps[0] / gaps[1]
+    assert 11.39 * 0.7 < ratio < 11.39 * 1.4, (gaps, ratio)
+
+
+def test_sigma_matches_shear_strain_derivative_triclinic():
+    """sigma^{a al} = dE/dh_{a al} by central differences for off-diagonal and
+    diagonal components of a triclinic cell, with orbitals fixed in crystal
+    coordinates (phi -> phi sqrt(V0/V)) and frozen subdomains; the NK arms are
+    rebuilt for every strained cell."""
+    h0 = _cell(12.0, 12.5, 11.5, 80, 95, 100)
+    cfg = _gen_cfg(h0, (60, 60, 60), R_PE=4.5, R_ME=6.2, stencil_n=3, cg_tol=1e-13, R_pair=8.0)
+    C = np.array([[0.50, 0.50, 0.48], [0.57, 0.55, 0.45]]) @ h0.T
+    orbs, phi = _orbitals(cfg, C, [1.3, 1.0], [[0.3, -0.2, 0.4], [-0.35, 0.1, 0.2]])
+    res0 = oracle.evaluate(_params(cfg), phi, orbs.centres)
+    eps = 1e-4 * 12.0
+    V0 = abs(np.linalg.det(h0))
+    for (a, al) in [(0, 1), (1, 0), (2, 0), (1, 1)]:
+        Es = []
+        for sgn in (1, -1):
+            h = h0.copy()
+            h[a, al] += sgn * eps
+            scale = math.sqrt(V0 / abs(np.linalg.det(h)))
+            r = oracle.evaluate(_params(cfg, h=h, h_geom=h0), phi * scale, orbs.centres)
+            Es.append(r["E"])
+        fd = (Es[0] - Es[1]) / (2 * eps)
+        ref = res0["sigma"][a, al]
+        assert abs(fd - ref) < 3e-4 * np.abs(res0["sigma"]).max(), ((a, al), fd, ref)
