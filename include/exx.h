@@ -95,12 +95,17 @@ typedef struct {
    fixed radius, all pairs, on-demand workspace. */
 void exx_default_options(exx_options* opt);
 
-/* Builds a plan for an orthorhombic cell (Sec. III B 1: proto-subdomains about
-   the grid origin, translated per pair by eq. l2g).  h: host [9]; grid: host
-   [3].  R_ME must be >= the largest R_PE + n max(spacing) so that every
-   stencil neighbour of the PE sphere has a far-field value (Sec. IV A); l_max
-   <= 8.  A non-orthogonal h gives EXX_EINVAL.  opt may be NULL (defaults).
-   On success *out owns the plan's device tables (on the current device). */
+/* Builds a plan for cell h (Sec. III B 1: proto-subdomains about the grid
+   origin, translated per pair by eq. l2g in crystal coordinates).  h: host
+   [9], column-major, h[a + 3*al] = (L_al)_a, right-handed; grid: host [3].
+   An orthorhombic h uses the axis stencil of eq. d2_1; any other h the
+   Natan-Kronik Laplacian of Sec. III C 1-2 (see exx_nk_stencil), whose
+   auxiliary directions must be nearest grid neighbours (|u_al| <= 1) and whose
+   weights must be positive.  R_ME must be >= the largest R_PE + n (longest
+   stencil step, lattice axes included) so that every stencil neighbour of the
+   PE sphere has a far-field value (Sec. IV A); l_max <= 8.  Violations give
+   EXX_EINVAL.  opt may be NULL (defaults).  On success *out owns the plan's
+   device tables (on the current device). */
 exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double R_PE, double R_ME, int l_max,
                     const exx_options* opt, exx_plan_t* out);
 
@@ -189,11 +194,22 @@ exx_status exx_stats_fetch(exx_plan_t plan, exx_stats* out);
 exx_status exx_plan_geometry(exx_plan_t plan, int cls, long long* n_pe, long long* n_halo, long long* n_me);
 
 /* Host-only planning aid (no device needed): point counts of the PE sphere,
-   of its Dirichlet points (reached by the axis stencil of half-width
-   stencil_n) and of the whole ME sphere, for an orthorhombic cell, with the
-   same membership rule as exx_plan (|r|^2 <= R^2 (1 + 1e-12)). */
+   of its Dirichlet points (reached by the Laplacian's arms, and by the lattice
+   axes of the first-derivative stencil, within stencil_n steps) and of the
+   whole ME sphere, with the same membership rule as exx_plan
+   (|h (o / N)|^2 <= R^2 (1 + 1e-12), Sec. III B 1). */
 exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_PE, double R_ME, int stencil_n,
                                 long long* n_pe, long long* n_halo, long long* n_me);
+
+/* Host-only (no device needed): the Natan-Kronik Laplacian that exx_plan uses
+   for cell h (Sec. III C 1-2, eq. lapG_mod_nk3d, auxiliary directions by
+   Algorithm 1).  Writes *n_arms (3 to 6) arms: u[3 k + al] integer steps along
+   L_1, L_2, L_3, beta[k] the weight of the pure second derivative along the
+   arm and step[k] its Cartesian length, so that the Laplacian is
+   sum_k beta[k] / step[k]^2 * (eq. d2_1 along u_k).  Arrays hold 18, 6 and 6
+   entries (NULL: not written).  EXX_EINVAL for a singular cell, or when
+   Algorithm 1 finds no three admissible directions among its candidates. */
+exx_status exx_nk_stencil(const double h[9], const int grid[3], int* n_arms, int* u, double* beta, double* step);
 
 /* Frees the plan and its device memory.  NULL is accepted. */
 exx_status exx_destroy(exx_plan_t plan);

@@ -367,14 +367,16 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (opt_in) opt = *opt_in; else exx_default_options(&opt);
   for (int k = 0; k < 9; ++k)
     if (!std::isfinite(h[k])) return fail(nullptr, EXX_EINVAL, "cell tensor is not finite");
+  bool general = false;   // any off-diagonal element: the NK Laplacian of Sec. III C
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
-      if (r != c && h[r + 3 * c] != 0.0)
-        return fail(nullptr, EXX_EINVAL, "only orthorhombic cells are supported (off-diagonal h must be 0)");
+      if (r != c && h[r + 3 * c] != 0.0) general = true;
   for (int a = 0; a < 3; ++a) {
-    if (!(h[a + 3 * a] > 0.0)) return fail(nullptr, EXX_EINVAL, "cell edges must be positive");
+    if (!general && !(h[a + 3 * a] > 0.0)) return fail(nullptr, EXX_EINVAL, "cell edges must be positive");
     if (grid[a] <= 0 || grid[a] > 32000) return fail(nullptr, EXX_EINVAL, "grid dimensions out of range");
   }
+  if (general && !(det3(h) > 0.0))
+    return fail(nullptr, EXX_EINVAL, "the cell tensor must have a positive determinant (right-handed L_1, L_2, L_3)");
   if (!(R_pair >= 0.0) || !(R_PE > 0.0) || !(R_ME >= R_PE)) return fail(nullptr, EXX_EINVAL, "radii out of range");
   if (l_max < 0 || l_max > kMaxL) return fail(nullptr, EXX_EINVAL, "l_max must be in [0, 8]");
   if (opt.stencil_n < 1 || opt.stencil_n > 3) return fail(nullptr, EXX_EINVAL, "stencil_n must be 1, 2 or 3");
@@ -414,12 +416,41 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   const int n = opt.stencil_n;
   double maxd = 0.0;
   for (int a = 0; a < 3; ++a) {
-    g.L[a] = h[a + 3 * a];
+    g.L[a] = general ? std::sqrt(h[3 * a] * h[3 * a] + h[1 + 3 * a] * h[1 + 3 * a] + h[2 + 3 * a] * h[2 + 3 * a])
+                     : h[a + 3 * a];
     g.N[a] = grid[a];
     g.d[a] = g.L[a] / grid[a];
     g.inv_d2[a] = 1.0 / (g.d[a] * g.d[a]);
     g.inv_d[a] = 1.0 / g.d[a];
     maxd = std::max(maxd, g.d[a]);
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int al = 0; al < 3; ++al) g.A[a + 3 * al] = h[a + 3 * al] / grid[al];
+  g.gen = general ? 1 : 0;
+  for (int a = 0; a < 3; ++a) g.perm[a] = a;
+  std::vector<NkArm> arms;
+  if (general) {
+    std::string e = build_nk_arms(h, grid, &arms);
+    if (!e.empty()) {
+      free_plan(P);
+      return fail(nullptr, EXX_EINVAL, e);
+    }
+    if (arms.size() > 6) {
+      free_plan(P);
+      return fail(nullptr, EXX_EINVAL, "more than six NK arms");
+    }
+    g.n_arms = (int)arms.size();
+    for (size_t k = 0; k < arms.size(); ++k) {
+      for (int a = 0; a < 3; ++a) {
+        g.arm_u[k][a] = arms[k].u[a];
+        if (std::abs(arms[k].u[a]) > 1) {
+          free_plan(P);
+          return fail(nullptr, EXX_EINVAL, "an NK auxiliary direction beyond the first shell of grid neighbours");
+        }
+      }
+      g.arm_coef[k] = arms[k].beta / (arms[k].step * arms[k].step);
+      maxd = std::max(maxd, arms[k].step);
+    }
   }
   for (int a = 0; a < 3; ++a)
     for (int al = 0; al < 3; ++al) g.J[a + 3 * al] = g.L[al] * g.hinv[al + 3 * a];
@@ -442,7 +473,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   const double rmax = *std::max_element(radii.begin(), radii.end());
   if (R_ME < rmax + n * maxd) {
     free_plan(P);
-    return fail(nullptr, EXX_EINVAL, "R_ME must be >= R_PE + n * max grid spacing");
+    return fail(nullptr, EXX_EINVAL, "R_ME must be >= R_PE + n * (longest stencil step)");
   }
   me_radii.assign(radii.size(), R_ME);
   P->self_class = -1;
@@ -451,7 +482,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     const double rme = opt.R_ME_self > 0.0 ? opt.R_ME_self : R_ME;
     if (rme < rpe + n * maxd) {
       free_plan(P);
-      return fail(nullptr, EXX_EINVAL, "R_ME_self must be >= R_PE_self + n * max grid spacing");
+      return fail(nullptr, EXX_EINVAL, "R_ME_self must be >= R_PE_self + n * (longest stencil step)");
     }
     P->self_class = (int)radii.size();
     radii.push_back(rpe);
@@ -459,8 +490,33 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   }
   P->classes.resize(radii.size());
   int maxRg0 = 0, maxRg1 = 0;
+  if (general) {
+    // sweep axis of the CG: the one whose padded columns hold the fewest
+    // slots (zero padding when it is perpendicular to the other two), then the
+    // fewest arms that leave the sweep plane, then the last axis
+    const size_t big = (size_t)(std::max_element(radii.begin(), radii.end()) - radii.begin());
+    long long best_slots = -1;
+    int best_tilt = 0;
+    for (int sw = 2; sw >= 0; --sw) {
+      ClassHost T;
+      std::string e = build_class_general(h, g.N, sw, radii[big], me_radii[big], n, arms, &T);
+      if (!e.empty()) {
+        free_plan(P);
+        return fail(nullptr, EXX_EINVAL, e);
+      }
+      int tilt = 0;
+      for (const NkArm& A : arms)
+        if (A.u[sw] != 0 && (A.u[(sw + 1) % 3] != 0 || A.u[(sw + 2) % 3] != 0)) ++tilt;
+      if (best_slots < 0 || T.n_pe < best_slots || (T.n_pe == best_slots && tilt < best_tilt)) {
+        best_slots = T.n_pe;
+        best_tilt = tilt;
+        for (int a = 0; a < 3; ++a) g.perm[a] = T.perm[a];
+      }
+    }
+  }
   for (size_t k = 0; k < radii.size(); ++k) {
-    std::string e = build_class(g.L, g.N, radii[k], me_radii[k], n, &P->classes[k]);
+    std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, &P->classes[k])
+                            : build_class(g.L, g.N, radii[k], me_radii[k], n, &P->classes[k]);
     if (!e.empty()) {
       free_plan(P);
       return fail(nullptr, EXX_EINVAL, e);
@@ -472,8 +528,8 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     P->max_me = std::max(P->max_me, C.n_me);
     P->max_cols = std::max<long long>(P->max_cols, C.n_cols);
     P->max_zmax = std::max(P->max_zmax, C.Zmax);
-    maxRg0 = std::max(maxRg0, C.Rg[0]);
-    maxRg1 = std::max(maxRg1, C.Rg[1]);
+    maxRg0 = std::max(maxRg0, C.Rc[0]);
+    maxRg1 = std::max(maxRg1, C.Rc[1]);
   }
   g.lds_cx = maxRg0 + n;
   g.lds_cy = maxRg1 + n;
@@ -510,7 +566,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
              align(C.halo_off.size() * sizeof(short4)) + align(C.me_off.size() * sizeof(short4)) +
              align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
-             align(C.zr_map.size() * sizeof(int)) + mom_bytes(C);
+             align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) + mom_bytes(C);
   }
   if (hipMalloc(&P->class_block, total) != hipSuccess) {
     free_plan(P);
@@ -518,9 +574,12 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   }
   char* base = (char*)P->class_block;
   size_t off = 0;
+  // an empty table has no device address (null): kernels tell the general
+  // layout by a non-null pe_map
   auto put = [&](const void* src, size_t bytes) -> const void* {
+    if (!bytes) return nullptr;
     void* dst = base + off;
-    if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
     off += align(bytes);
     return dst;
   };
@@ -535,6 +594,8 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
       D.Wm[a] = C.Wm[a];
     }
     D.n_pe = C.n_pe;
+    D.n_real = C.n_real;
+    for (int a = 0; a < 3; ++a) D.Rc[a] = C.Rc[a];
     D.n_halo = C.n_halo;
     D.n_me = C.n_me;
     D.cols = (const int4*)put(C.cols.data(), C.cols.size() * sizeof(int4));
@@ -544,9 +605,10 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     D.halo_map = (const int*)put(C.halo_map.data(), C.halo_map.size() * sizeof(int));
     D.col_map = (const int*)put(C.col_map.data(), C.col_map.size() * sizeof(int));
     D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
+    D.pe_map = general ? (const int*)put(C.pe_map.data(), C.pe_map.size() * sizeof(int)) : nullptr;
     D.mom_rows = mom_rows;
     std::vector<double> tab;
-    build_moment_table(C, g.d, l_max, mom_rows, mixed ? 8 : 4, &tab);
+    build_moment_table(C, g.A, l_max, mom_rows, mixed ? 8 : 4, &tab);
     bool tab_ok;
     if (mixed) {
       std::vector<unsigned short> hi(tab.size()), lo(tab.size());
@@ -561,7 +623,8 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
       D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
       tab_ok = D.mom_f64 != nullptr;
     }
-    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || !D.col_map || !D.zr_map || !tab_ok) {
+    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || (!general && (!D.col_map || !D.zr_map)) ||
+        (general != (D.pe_map != nullptr)) || !tab_ok) {
       free_plan(P);
       return fail(nullptr, EXX_EDEVICE, "upload of the subdomain tables failed");
     }
@@ -588,7 +651,12 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   {
     // defaults measured on MI355X: FP64 1024 x 1, mixed 1024 x 2
     // per class: 1024 threads up to 3 columns each, else 512 (1024 x 4 spills)
-    const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
+    // general cells: one plane of loads ahead (their instances have no deeper variant)
+    if (general && opt.solve_depth > 1) {
+      free_plan(P);
+      return fail(nullptr, EXX_EINVAL, "general cells run the CG with solve_depth 1");
+    }
+    const int dp = general ? 1 : (opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1));
     P->class_threads.assign(P->classes.size(), 1024);
     P->class_depth.assign(P->classes.size(), dp);
     for (size_t k = 0; k < P->classes.size(); ++k)
@@ -960,18 +1028,19 @@ exx_status exx_plan_geometry(exx_plan_t P, int cls, long long* n_pe, long long* 
   if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
   if (cls < 0 || cls >= (int)P->classes.size()) return fail(P, EXX_EINVAL, "class out of range");
   const ClassHost& C = P->classes[cls];
-  if (n_pe) *n_pe = C.n_pe;
+  if (n_pe) *n_pe = C.n_real;
   if (n_halo) *n_halo = C.n_halo;
-  if (n_me) *n_me = C.n_me;
+  if (n_me) *n_me = C.n_me - (C.n_pe - C.n_real);   // without the dead slots of padded columns
   return EXX_OK;
 }
 
 exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_PE, double R_ME, int stencil_n,
                                 long long* n_pe, long long* n_halo, long long* n_me) {
   if (!h || !grid) return fail(nullptr, EXX_EINVAL, "h or grid is NULL");
+  bool general = false;
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
-      if (r != c && h[r + 3 * c] != 0.0) return fail(nullptr, EXX_EINVAL, "only orthorhombic cells are supported");
+      if (r != c && h[r + 3 * c] != 0.0) general = true;
   if (stencil_n < 1 || stencil_n > 3 || !(R_PE > 0.0) || !(R_ME >= R_PE))
     return fail(nullptr, EXX_EINVAL, "invalid radii or stencil");
   double L[3];
@@ -979,14 +1048,39 @@ exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_P
   for (int a = 0; a < 3; ++a) {
     L[a] = h[a + 3 * a];
     N[a] = grid[a];
-    if (!(L[a] > 0.0) || N[a] <= 0) return fail(nullptr, EXX_EINVAL, "invalid cell or grid");
+    if ((!general && !(L[a] > 0.0)) || N[a] <= 0) return fail(nullptr, EXX_EINVAL, "invalid cell or grid");
   }
   ClassHost C;
-  std::string e = build_class(L, N, R_PE, R_ME, stencil_n, &C);
+  std::string e;
+  if (general) {
+    if (!(det3(h) > 0.0)) return fail(nullptr, EXX_EINVAL, "the cell tensor must have a positive determinant");
+    std::vector<NkArm> arms;
+    e = build_nk_arms(h, N, &arms);
+    if (e.empty()) e = build_class_general(h, N, 2, R_PE, R_ME, stencil_n, arms, &C);
+  } else {
+    e = build_class(L, N, R_PE, R_ME, stencil_n, &C);
+  }
   if (!e.empty()) return fail(nullptr, EXX_EINVAL, e);
-  if (n_pe) *n_pe = C.n_pe;
+  if (n_pe) *n_pe = C.n_real;
   if (n_halo) *n_halo = C.n_halo;
-  if (n_me) *n_me = C.n_me;
+  if (n_me) *n_me = C.n_me - (C.n_pe - C.n_real);
+  return EXX_OK;
+}
+
+exx_status exx_nk_stencil(const double h[9], const int grid[3], int* n_arms, int* u, double* beta, double* step) {
+  if (!h || !grid || !n_arms) return fail(nullptr, EXX_EINVAL, "h, grid or n_arms is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (grid[a] <= 0) return fail(nullptr, EXX_EINVAL, "invalid grid");
+  std::vector<NkArm> arms;
+  std::string e = build_nk_arms(h, grid, &arms);
+  if (!e.empty()) return fail(nullptr, EXX_EINVAL, e);
+  *n_arms = (int)arms.size();
+  for (size_t k = 0; k < arms.size(); ++k) {
+    for (int a = 0; a < 3; ++a)
+      if (u) u[3 * k + a] = arms[k].u[a];
+    if (beta) beta[k] = arms[k].beta;
+    if (step) step[k] = arms[k].step;
+  }
   return EXX_OK;
 }
 

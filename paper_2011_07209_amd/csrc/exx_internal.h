@@ -39,6 +39,23 @@ struct Geo {
   int n_lm;
   int lds_cx, lds_cy, lds_wx, lds_wy;   // LDS plane origin and size (lds_wx = kLdsWX)
   double ylm_norm[kMaxLM];              // N_l0 for m == 0, sqrt(2) N_l|m| otherwise
+  // General (non-orthogonal) cells.  gen == 0: orthorhombic, offsets are
+  // r = (o_x d_x, o_y d_y, o_z d_z) and the Laplacian is the axis stencil.
+  int gen;
+  double A[9];          // r = A o, A[a + 3 al] = h_{a al} / N_al
+  int perm[3];          // CG frame: (x', y', z') = (o[perm[0]], o[perm[1]], o[perm[2]])
+  int n_arms;           // NK Laplacian: sum over arms of coef * eq. d2_1 along u
+  int arm_u[6][3];
+  double arm_coef[6];   // beta / step^2
+};
+
+// One arm of the NK Laplacian (Sec. III C 2, eq. lapG_mod_nk3d): the pure
+// second derivative along the grid direction u (integer steps along L_1, L_2,
+// L_3) of Cartesian length step, with weight beta.
+struct NkArm {
+  int u[3];
+  double beta;
+  double step;
 };
 
 // A sphere class (one PE radius).  All arrays live in one device block.
@@ -49,7 +66,13 @@ struct ClassDev {
   int Rg[3];          // largest |offset| per axis in PE
   int Wm[3];          // lookup-map dims: 2 (Rg + n) + 1
   long long n_pe, n_halo, n_me;
-  const int4* cols;          // [n_cols] (ox, oy, zr, 0), sorted by zr descending
+  // n_pe counts the slots of a PE vector; general cells pad their columns with
+  // dead slots (me_off.w = 1), n_real counts the PE points proper
+  long long n_real;
+  int Rc[3];                 // extents in the CG frame (= Rg for orthorhombic cells)
+  const int* pe_map;         // general cells: [Wm2][Wm1][Wm0] (true frame) -> slot, or -1
+  const int4* cols;          // [n_cols] (ox, oy, zr, 0), sorted by zr descending; general cells:
+                             // (x', y', lo, hi) in the CG frame, sorted by max(|lo|, |hi|)
   const int* plane_start;    // [2 Zmax + 2] packed index of the first point of plane z (index z + Zmax)
   const short4* halo_off;    // [n_halo] offsets of the Dirichlet points reached by the stencil
   const short4* me_off;      // [n_me] PE points in packed order, then the ME shell
@@ -77,20 +100,30 @@ struct ClassHost {
   int n_cols = 0, Zmax = 0;
   int Rg[3] = {0, 0, 0};
   int Wm[3] = {0, 0, 0};
+  int Rc[3] = {0, 0, 0};
+  bool general = false;
+  int perm[3] = {0, 1, 2};
   std::vector<int4> cols;
   std::vector<int> plane_start;
   std::vector<short4> halo_off;
   std::vector<short4> me_off;
-  std::vector<int> halo_map, col_map, zr_map;
-  long long n_pe = 0, n_halo = 0, n_me = 0;
+  std::vector<int> halo_map, col_map, zr_map, pe_map;
+  long long n_pe = 0, n_halo = 0, n_me = 0, n_real = 0;
 };
 
-// Builds the tables of one class; returns an empty string or an error message.
+// Builds the tables of one class of an orthorhombic cell; returns an empty
+// string or an error message.
 std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out);
-// Unnormalised solid harmonics P_lm(o d) of the class's PE points, laid out
+// The same for a general cell h with the NK arms of its Laplacian; the CG
+// sweeps along grid axis `sweep`.
+std::string build_class_general(const double h[9], const int N[3], int sweep, double R_PE, double R_ME, int n,
+                                const std::vector<NkArm>& arms, ClassHost* out);
+// The NK Laplacian of cell h on grid N (Algorithm 1 and eq. lapG_mod_nk3d).
+std::string build_nk_arms(const double h[9], const int N[3], std::vector<NkArm>* arms);
+// Unnormalised solid harmonics P_lm(A o) of the class's PE points, laid out
 // [k/G][row][G] (G = group, 4 or 8) with rows >= (l_max + 1)^2 and n_pe
-// rounded up to 32, zeros in the padding.
-void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, int group,
+// rounded up to 32, zeros in the padding and at dead slots.
+void build_moment_table(const ClassHost& C, const double A[9], int l_max, int rows, int group,
                         std::vector<double>* out);
 
 }  // namespace exx

@@ -35,6 +35,19 @@ __device__ __forceinline__ unsigned long long splitmix64_once(unsigned long long
   return z ^ (z >> 31);
 }
 
+// Cartesian local coordinate of offset o (Sec. III B 1: r = h (o / N))
+__device__ __forceinline__ void rbar_of(const Geo& g, const short4& o, double* x, double* y, double* z) {
+  if (g.gen) {
+    *x = g.A[0] * o.x + g.A[3] * o.y + g.A[6] * o.z;
+    *y = g.A[1] * o.x + g.A[4] * o.y + g.A[7] * o.z;
+    *z = g.A[2] * o.x + g.A[5] * o.y + g.A[8] * o.z;
+  } else {
+    *x = o.x * g.d[0];
+    *y = o.y * g.d[1];
+    *z = o.z * g.d[2];
+  }
+}
+
 // minimum-image separation d = C_j - C_i; returns whether (i, j) is a kept pair
 __device__ __forceinline__ bool pair_keep(const Geo& g, const PairParams& pp, const double* C, int i, int j,
                                           double* dm) {
@@ -187,6 +200,10 @@ __global__ __launch_bounds__(256) void k_gather(Geo g, const ClassDev* __restric
   double amax = 0.0;
   for (long long k = threadIdx.x; k < npe; k += blockDim.x) {
     const short4 o = C.me_off[k];
+    if (o.w) {   // dead slot of a general cell's padded column
+      rho[k] = 0.0;
+      continue;
+    }
     const int gx = wrapi(P.c[0] + o.x, g.N[0]);
     const int gy = wrapi(P.c[1] + o.y, g.N[1]);
     const int gz = wrapi(P.c[2] + o.z, g.N[2]);
@@ -222,7 +239,9 @@ __global__ __launch_bounds__(256) void k_boundary(Geo g, const ClassDev* __restr
   const long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= C.n_halo) return;
   const short4 o = C.halo_off[h];
-  halo_ws[(long long)b * hstride + h] = far_field<L>(o.x * g.d[0], o.y * g.d[1], o.z * g.d[2], g.ylm_norm, Q);
+  double x, y, z;
+  rbar_of(g, o, &x, &y, &z);
+  halo_ws[(long long)b * hstride + h] = far_field<L>(x, y, z, g.ylm_norm, Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,6 +252,13 @@ __global__ __launch_bounds__(256) void k_boundary(Geo g, const ClassDev* __restr
 __device__ __forceinline__ double point_value(const ClassDev& C, int n, const double* xv, const double* halo, int ox,
                                               int oy, int oz, bool pe_zero) {
   const int mx = ox + C.Rg[0] + n, my = oy + C.Rg[1] + n, mz = oz + C.Rg[2] + n;
+  if (C.pe_map) {   // general cell: 3D maps of the PE slots and the Dirichlet points
+    const long long m = mx + (long long)C.Wm[0] * (my + (long long)C.Wm[1] * mz);
+    const int s = C.pe_map[m];
+    if (s >= 0) return pe_zero ? 0.0 : xv[s];
+    const int h = C.halo_map[m];
+    return h >= 0 ? halo[h] : 0.0;
+  }
   const int m2 = mx + C.Wm[0] * my;
   const int zr = C.zr_map[m2];
   if (abs(oz) <= zr) return pe_zero ? 0.0 : xv[C.plane_start[oz + C.Zmax] + C.col_map[m2]];
@@ -256,6 +282,20 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__
   const double* halo = halo_ws + (long long)bq * hstride;
   const short4 o = C.me_off[k];
   double acc = 4.0 * kPi * rho_ws[(long long)bq * rstride + k];
+  if (g.gen) {
+    // every arm of the NK Laplacian (eq. lapG_mod_nk3d), eq. d2_1 along it
+    if (!o.w) {
+      for (int m = 0; m < g.n_arms; ++m) {
+        const int ux = g.arm_u[m][0], uy = g.arm_u[m][1], uz = g.arm_u[m][2];
+        for (int q = 1; q <= g.n; ++q)
+          acc += g.arm_coef[m] * g.w2[q] *
+                 (point_value(C, g.n, nullptr, halo, o.x + q * ux, o.y + q * uy, o.z + q * uz, true) +
+                  point_value(C, g.n, nullptr, halo, o.x - q * ux, o.y - q * uy, o.z - q * uz, true));
+      }
+    }
+    b_ws[(long long)bq * rstride + k] = o.w ? 0.0 : acc;
+    return;
+  }
   for (int q = 1; q <= g.n; ++q) {
     acc += g.inv_d2[0] * g.w2[q] *
            (point_value(C, g.n, nullptr, halo, o.x + q, o.y, o.z, true) +
@@ -295,6 +335,7 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const ClassDev* __restr
   for (int t = 0; t < 9; ++t) T[t] = 0.0;
   for (long long k = threadIdx.x; k < C.n_pe; k += blockDim.x) {
     const short4 o = C.me_off[k];
+    if (o.w) continue;   // dead slot
     const double rh = rho[k];
     e += rh * x[k];
     double dxi[3] = {0.0, 0.0, 0.0};
@@ -307,7 +348,8 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const ClassDev* __restr
                            point_value(C, g.n, x, halo, o.x, o.y, o.z - q, false));
     }
     for (int al = 0; al < 3; ++al) dxi[al] *= g.inv_d[al];
-    const double rb[3] = {o.x * g.d[0], o.y * g.d[1], o.z * g.d[2]};
+    double rb[3];
+    rbar_of(g, o, &rb[0], &rb[1], &rb[2]);
     for (int aa = 0; aa < 3; ++aa) {
       const double ga = g.J[aa] * dxi[0] + g.J[aa + 3] * dxi[1] + g.J[aa + 6] * dxi[2];
       for (int b = 0; b < 3; ++b) T[aa + 3 * b] += rb[b] * rh * ga;
@@ -349,8 +391,10 @@ __global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restr
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= C.n_me) return;
   const short4 o = C.me_off[k];
-  const double v = (k < C.n_pe) ? v_ws[(long long)b * rstride + k]
-                                : far_field<L>(o.x * g.d[0], o.y * g.d[1], o.z * g.d[2], g.ylm_norm, Q);
+  if (o.w) return;   // dead slot
+  double rx, ry, rz;
+  rbar_of(g, o, &rx, &ry, &rz);
+  const double v = (k < C.n_pe) ? v_ws[(long long)b * rstride + k] : far_field<L>(rx, ry, rz, g.ylm_norm, Q);
   const int gx = wrapi(P.c[0] + o.x, g.N[0]);
   const int gy = wrapi(P.c[1] + o.y, g.N[1]);
   const int gz = wrapi(P.c[2] + o.z, g.N[2]);
@@ -459,7 +503,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     umax = fmax(umax, (double)pUpd[k]);
     nunc += (pIt[k] >= max_iter) ? 1.0 : 0.0;
     rmax = fmax(rmax, pRes[k]);
-    const double npe = (double)cls[pairs[k].cls].n_pe;
+    const double npe = (double)cls[pairs[k].cls].n_real;
     work += pIt[k] * npe;
     pts += npe;
     if (warm_map && warm_map[k] >= 0) warm += 1.0;

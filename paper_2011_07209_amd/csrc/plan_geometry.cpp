@@ -11,7 +11,10 @@
 // ascending z.  A workgroup that assigns column c to a fixed thread then reads
 // every plane with consecutive addresses from one per-plane base offset.
 #include <algorithm>
+#include <array>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 
 #include "exx_internal.h"
@@ -143,10 +146,12 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
         C.me_off.push_back(make_short4((short)ox, (short)oy, (short)oz, 0));
       }
   C.n_me = (long long)C.me_off.size();
+  C.n_real = C.n_pe;
+  for (int a = 0; a < 3; ++a) C.Rc[a] = C.Rg[a];
   return std::string();
 }
 
-void build_moment_table(const ClassHost& C, const double d[3], int l_max, int rows, int group,
+void build_moment_table(const ClassHost& C, const double A[9], int l_max, int rows, int group,
                         std::vector<double>* out) {
   const long long kpad = (C.n_pe + 31) / 32 * 32;
   out->assign((size_t)(kpad * rows), 0.0);
@@ -154,10 +159,207 @@ void build_moment_table(const ClassHost& C, const double d[3], int l_max, int ro
   const int nlm = (l_max + 1) * (l_max + 1);
   for (long long k = 0; k < C.n_pe; ++k) {
     const short4 o = C.me_off[(size_t)k];
-    solid_harmonics_host(l_max, o.x * d[0], o.y * d[1], o.z * d[2], ones.data(), v.data());
+    if (o.w) continue;   // dead slot
+    const double x = A[0] * o.x + A[3] * o.y + A[6] * o.z;
+    const double y = A[1] * o.x + A[4] * o.y + A[7] * o.z;
+    const double z = A[2] * o.x + A[5] * o.y + A[8] * o.z;
+    solid_harmonics_host(l_max, x, y, z, ones.data(), v.data());
     double* dst = out->data() + (size_t)((k / group) * rows * group + (k % group));
     for (int lm = 0; lm < nlm; ++lm) dst[(size_t)lm * group] = v[lm];
   }
+}
+
+// ---------------------------------------------------------------------------
+// General (non-orthogonal) cells, Sec. III B 1: the PE sphere is the set of
+// grid offsets o with |r(o)| <= R_PE, r(o) = sum_al (o_al / N_al) L_al, an
+// ellipsoid in index space whose columns along one grid axis need not be
+// symmetric about 0.  The CG sweeps along a chosen grid axis ("z'", the other
+// two in ascending order are x', y').  Each (x', y') column holds the interval
+// [lo, hi] of z'; it is padded to the symmetric range [-zr, zr], zr = max(|lo|,
+// |hi|), so that plane z' is again a prefix of the columns sorted by zr.  The
+// padding slots ("dead", me_off.w = 1) hold no point: their density, right-hand
+// side and solution are zero and every kernel skips them.
+
+namespace {
+
+inline double r2_general(const double h[9], const int N[3], int o0, int o1, int o2) {
+  const double s0 = (double)o0 / N[0], s1 = (double)o1 / N[1], s2 = (double)o2 / N[2];
+  const double x = h[0] * s0 + h[3] * s1 + h[6] * s2;
+  const double y = h[1] * s0 + h[4] * s1 + h[7] * s2;
+  const double z = h[2] * s0 + h[5] * s1 + h[8] * s2;
+  return x * x + y * y + z * z;
+}
+
+// |o_al| <= N_al |row al of h^-1| R bounds the sphere of radius R
+void sphere_box(const double h[9], const int N[3], double R, int K[3]) {
+  const double d = h[0] * (h[4] * h[8] - h[7] * h[5]) - h[3] * (h[1] * h[8] - h[7] * h[2]) +
+                   h[6] * (h[1] * h[5] - h[4] * h[2]);
+  for (int al = 0; al < 3; ++al) {
+    // row al of h^-1 = (cross product of the other two columns) / det
+    const int b = (al + 1) % 3, c = (al + 2) % 3;
+    const double cx = h[1 + 3 * b] * h[2 + 3 * c] - h[2 + 3 * b] * h[1 + 3 * c];
+    const double cy = h[2 + 3 * b] * h[0 + 3 * c] - h[0 + 3 * b] * h[2 + 3 * c];
+    const double cz = h[0 + 3 * b] * h[1 + 3 * c] - h[1 + 3 * b] * h[0 + 3 * c];
+    K[al] = (int)std::ceil(R * N[al] * std::sqrt(cx * cx + cy * cy + cz * cz) / std::fabs(d)) + 1;
+  }
+}
+
+}  // namespace
+
+std::string build_class_general(const double h[9], const int N[3], int sweep, double R_PE, double R_ME, int n,
+                                const std::vector<NkArm>& arms, ClassHost* out) {
+  ClassHost& C = *out;
+  C = ClassHost();
+  C.R_PE = R_PE;
+  C.general = true;
+  const double pe2 = R_PE * R_PE * (1.0 + kSlack);
+  const double me2 = R_ME * R_ME * (1.0 + kSlack);
+  int perm[3];
+  {
+    int k = 0;
+    for (int a = 0; a < 3; ++a)
+      if (a != sweep) perm[k++] = a;
+    perm[2] = sweep;
+  }
+  for (int a = 0; a < 3; ++a) C.perm[a] = perm[a];
+
+  // PE points (true-frame offsets)
+  int KP[3];
+  sphere_box(h, N, R_PE, KP);
+  std::vector<std::array<int, 3>> pts;
+  for (int a = 0; a < 3; ++a) C.Rg[a] = 0;
+  for (int o2 = -KP[2]; o2 <= KP[2]; ++o2)
+    for (int o1 = -KP[1]; o1 <= KP[1]; ++o1)
+      for (int o0 = -KP[0]; o0 <= KP[0]; ++o0)
+        if (r2_general(h, N, o0, o1, o2) <= pe2) {
+          pts.push_back({o0, o1, o2});
+          C.Rg[0] = std::max(C.Rg[0], std::abs(o0));
+          C.Rg[1] = std::max(C.Rg[1], std::abs(o1));
+          C.Rg[2] = std::max(C.Rg[2], std::abs(o2));
+        }
+  for (int a = 0; a < 3; ++a) {
+    C.Rc[a] = C.Rg[perm[a]];
+    if (2 * (C.Rg[a] + n) + 1 > 32000) return "sphere too large for 16-bit offsets";
+  }
+  C.n_real = (long long)pts.size();
+
+  // columns of the CG frame: interval [lo, hi] of z' per (x', y')
+  const int Wc0 = 2 * C.Rc[0] + 1, Wc1 = 2 * C.Rc[1] + 1;
+  std::vector<int> lo((size_t)Wc0 * Wc1, INT32_MAX), hi((size_t)Wc0 * Wc1, INT32_MIN), cnt((size_t)Wc0 * Wc1, 0);
+  for (const auto& p : pts) {
+    const size_t m = (size_t)(p[perm[0]] + C.Rc[0]) + (size_t)Wc0 * (p[perm[1]] + C.Rc[1]);
+    lo[m] = std::min(lo[m], p[perm[2]]);
+    hi[m] = std::max(hi[m], p[perm[2]]);
+    cnt[m]++;
+  }
+  struct Col { int x, y, lo, hi, zr; double ang; };
+  std::vector<Col> cols;
+  for (int y = -C.Rc[1]; y <= C.Rc[1]; ++y)
+    for (int x = -C.Rc[0]; x <= C.Rc[0]; ++x) {
+      const size_t m = (size_t)(x + C.Rc[0]) + (size_t)Wc0 * (y + C.Rc[1]);
+      if (!cnt[m]) continue;
+      if (cnt[m] != hi[m] - lo[m] + 1) return "PE sphere column is not an interval";
+      cols.push_back({x, y, lo[m], hi[m], std::max(std::abs(lo[m]), std::abs(hi[m])),
+                      std::atan2((double)y, (double)x)});
+    }
+  std::stable_sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) {
+    if (a.zr != b.zr) return a.zr > b.zr;
+    if (a.ang != b.ang) return a.ang < b.ang;
+    if (a.y != b.y) return a.y < b.y;
+    return a.x < b.x;
+  });
+  C.n_cols = (int)cols.size();
+  C.Zmax = 0;
+  for (const Col& c : cols) C.Zmax = std::max(C.Zmax, c.zr);
+  C.cols.resize(cols.size());
+  for (size_t c = 0; c < cols.size(); ++c) C.cols[c] = make_int4(cols[c].x, cols[c].y, cols[c].lo, cols[c].hi);
+
+  // planes: prefix of the padded columns; slots outside [lo, hi] are dead
+  C.plane_start.assign(2 * C.Zmax + 2, 0);
+  long long acc = 0;
+  for (int z = -C.Zmax; z <= C.Zmax; ++z) {
+    C.plane_start[z + C.Zmax] = (int)acc;
+    int nz = 0;
+    while (nz < C.n_cols && cols[nz].zr >= std::abs(z)) ++nz;
+    acc += nz;
+  }
+  C.plane_start[2 * C.Zmax + 1] = (int)acc;
+  C.n_pe = acc;
+  if (acc > 0x7fffffffLL) return "PE sphere too large";
+
+  // true-frame lookup maps over the PE extents plus the stencil reach
+  int umax = 1;
+  for (const NkArm& A : arms)
+    for (int a = 0; a < 3; ++a) umax = std::max(umax, std::abs(A.u[a]));
+  for (int a = 0; a < 3; ++a) C.Wm[a] = 2 * (C.Rg[a] + n * umax) + 1;
+  const int W0 = C.Wm[0], W1 = C.Wm[1], W2 = C.Wm[2];
+  const int c0 = C.Rg[0] + n * umax, c1 = C.Rg[1] + n * umax, c2 = C.Rg[2] + n * umax;
+  auto midx = [&](int o0, int o1, int o2) {
+    return (size_t)(o0 + c0) + (size_t)W0 * ((size_t)(o1 + c1) + (size_t)W1 * (o2 + c2));
+  };
+  C.pe_map.assign((size_t)W0 * W1 * W2, -1);
+  C.me_off.reserve((size_t)C.n_pe);
+  for (int z = -C.Zmax; z <= C.Zmax; ++z) {
+    const int nz = C.plane_start[z + C.Zmax + 1] - C.plane_start[z + C.Zmax];
+    for (int c = 0; c < nz; ++c) {
+      const Col& cc = cols[c];
+      if (z < cc.lo || z > cc.hi) {
+        C.me_off.push_back(make_short4(0, 0, 0, 1));
+        continue;
+      }
+      int o[3];
+      o[perm[0]] = cc.x;
+      o[perm[1]] = cc.y;
+      o[perm[2]] = z;
+      C.pe_map[midx(o[0], o[1], o[2])] = (int)C.me_off.size();
+      C.me_off.push_back(make_short4((short)o[0], (short)o[1], (short)o[2], 0));
+    }
+  }
+  auto in_pe = [&](int o0, int o1, int o2) {
+    if (std::abs(o0) > C.Rg[0] || std::abs(o1) > C.Rg[1] || std::abs(o2) > C.Rg[2]) return false;
+    return C.pe_map[midx(o0, o1, o2)] >= 0;
+  };
+
+  // Dirichlet points: outside PE, reached from a PE point by q <= n steps along
+  // a Laplacian arm or along a lattice axis (the first-derivative stencil of
+  // sigma)
+  std::vector<std::array<int, 3>> dirs;
+  for (const NkArm& A : arms) dirs.push_back({A.u[0], A.u[1], A.u[2]});
+  for (int a = 0; a < 3; ++a) {
+    std::array<int, 3> e{0, 0, 0};
+    e[a] = 1;
+    if (std::find(dirs.begin(), dirs.end(), e) == dirs.end()) dirs.push_back(e);
+  }
+  C.halo_map.assign((size_t)W0 * W1 * W2, -1);
+  for (int o2 = -c2; o2 <= c2; ++o2)
+    for (int o1 = -c1; o1 <= c1; ++o1)
+      for (int o0 = -c0; o0 <= c0; ++o0) {
+        if (in_pe(o0, o1, o2)) continue;
+        bool reach = false;
+        for (size_t d = 0; d < dirs.size() && !reach; ++d)
+          for (int q = 1; q <= n && !reach; ++q)
+            reach = in_pe(o0 + q * dirs[d][0], o1 + q * dirs[d][1], o2 + q * dirs[d][2]) ||
+                    in_pe(o0 - q * dirs[d][0], o1 - q * dirs[d][1], o2 - q * dirs[d][2]);
+        if (!reach) continue;
+        if (r2_general(h, N, o0, o1, o2) > me2) return "R_ME does not cover the stencil reach of the PE sphere";
+        C.halo_map[midx(o0, o1, o2)] = (int)C.halo_off.size();
+        C.halo_off.push_back(make_short4((short)o0, (short)o1, (short)o2, 0));
+      }
+  C.n_halo = (long long)C.halo_off.size();
+
+  // ME shell after the PE slots
+  int KM[3];
+  sphere_box(h, N, R_ME, KM);
+  for (int o2 = -KM[2]; o2 <= KM[2]; ++o2)
+    for (int o1 = -KM[1]; o1 <= KM[1]; ++o1)
+      for (int o0 = -KM[0]; o0 <= KM[0]; ++o0) {
+        if (r2_general(h, N, o0, o1, o2) > me2) continue;
+        if (r2_general(h, N, o0, o1, o2) <= pe2) continue;
+        if (std::abs(o0) > 32000 || std::abs(o1) > 32000 || std::abs(o2) > 32000) return "ME sphere too large";
+        C.me_off.push_back(make_short4((short)o0, (short)o1, (short)o2, 0));
+      }
+  C.n_me = (long long)C.me_off.size();
+  return std::string();
 }
 
 }  // namespace exx

@@ -1,4 +1,6 @@
 // Launchers of the persistent CG solve (the instances live in solve_n*.hip).
+#include <cstring>
+
 #include "solve_impl.h"
 
 namespace exx {
@@ -56,6 +58,30 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   for (int q = 0; q < 4; ++q) a.S.w[q] = in.g.w2[q];
   for (int al = 0; al < 3; ++al) a.S.c[al] = in.g.inv_d2[al];
   a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
+  // general cell: the NK arms in the CG frame (x', y', z') = o[perm]
+  a.gen = in.g.gen;
+  std::memset(&a.G, 0, sizeof(a.G));
+  if (a.gen) {
+    for (int q = 0; q < 4; ++q) a.G.w[q] = in.g.w2[q];
+    double sum = 0.0;
+    for (int m = 0; m < in.g.n_arms; ++m) {
+      const int ux = in.g.arm_u[m][in.g.perm[0]], uy = in.g.arm_u[m][in.g.perm[1]], uz = in.g.arm_u[m][in.g.perm[2]];
+      const double cf = in.g.arm_coef[m];
+      sum += cf;
+      if (ux == 0 && uy == 0) {
+        a.G.cz += cf;
+      } else if (uz == 0) {
+        if (a.G.n_in == 3) return hipErrorInvalidValue;
+        a.G.in_off[a.G.n_in] = ux + kLdsWX * uy;
+        a.G.in_coef[a.G.n_in++] = cf;
+      } else {
+        if (a.G.n_tl == 3 || (uz != 1 && uz != -1)) return hipErrorInvalidValue;
+        a.G.tl_off[a.G.n_tl] = uz * (ux + kLdsWX * uy);   // oriented so that a step raises z' by one
+        a.G.tl_coef[a.G.n_tl++] = cf;
+      }
+    }
+    a.G.diag = in.g.w2[0] * sum;
+  }
   a.lds_cx = in.g.lds_cx;
   a.lds_cy = in.g.lds_cy;
   a.lds_wx = in.g.lds_wx;

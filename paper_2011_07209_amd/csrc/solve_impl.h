@@ -12,6 +12,8 @@
 // of their use, so a CU keeps several planes of loads in flight.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "exx_launch.h"
 
@@ -30,6 +32,40 @@ __device__ __forceinline__ StencilT<T> stencil_cast(const StencilT<double>& s) {
   for (int q = 0; q < 4; ++q) o.w[q] = (T)s.w[q];
   for (int a = 0; a < 3; ++a) o.c[a] = (T)s.c[a];
   o.diag = (T)s.diag;
+  return o;
+}
+
+// The NK Laplacian of a general cell in the CG frame (x', y' in the LDS plane,
+// z' the sweep axis).  Arms inside the sweep plane read the staged plane at
+// one LDS step off per grid step; arms that leave it (oriented so that one
+// step raises z' by one) are gathered plane by plane into a window of partial
+// sums; the z' axis arm uses the register window of the point's own column.
+template <typename T>
+struct GenStencilT {
+  T w[4];         // second-derivative weights w_0..w_3
+  T cz;           // coefficient of the z' axis arm (0 when it has none)
+  T diag;         // w_0 * (sum of all arm coefficients)
+  int n_in, n_tl;
+  int in_off[3];  // in-plane arms: LDS offset of one step, coefficient
+  T in_coef[3];
+  int tl_off[3];  // arms leaving the plane: LDS offset of one step (with z' + 1)
+  T tl_coef[3];
+};
+
+template <typename T>
+__device__ __forceinline__ GenStencilT<T> gen_stencil_cast(const GenStencilT<double>& s) {
+  GenStencilT<T> o;
+  for (int q = 0; q < 4; ++q) o.w[q] = (T)s.w[q];
+  o.cz = (T)s.cz;
+  o.diag = (T)s.diag;
+  o.n_in = s.n_in;
+  o.n_tl = s.n_tl;
+  for (int k = 0; k < 3; ++k) {
+    o.in_off[k] = s.in_off[k];
+    o.in_coef[k] = (T)s.in_coef[k];
+    o.tl_off[k] = s.tl_off[k];
+    o.tl_coef[k] = (T)s.tl_coef[k];
+  }
   return o;
 }
 
@@ -55,6 +91,8 @@ struct SolveKArgs {
   int max_iter;
   double delta;           // mixed: update when ||r|| < delta * (residual at the last update)
   StencilT<double> S;
+  int gen;                 // general cell: padded columns and the NK arms in G
+  GenStencilT<double> G;
   int lds_cx, lds_cy, lds_wx, lds_wy;
   // warm start (warm_store null: every solve starts from zero)
   const float* warm_store;   // [2][warm_cap][rstride]; the previous solutions are half warm_state[0]
@@ -70,6 +108,11 @@ struct SolveKArgs {
 __device__ __forceinline__ int pe_index(const ClassDev& C, int n, int ox, int oy, int oz) {
   const int mx = ox + C.Rg[0] + n, my = oy + C.Rg[1] + n;
   if (mx < 0 || my < 0 || mx >= C.Wm[0] || my >= C.Wm[1]) return -1;
+  if (C.pe_map) {   // general cell
+    const int mz = oz + C.Rg[2] + n;
+    if (mz < 0 || mz >= C.Wm[2]) return -1;
+    return C.pe_map[mx + C.Wm[0] * (my + C.Wm[1] * mz)];
+  }
   const int m2 = mx + C.Wm[0] * my;
   const int zr = C.zr_map[m2];
   if (zr < 0 || abs(oz) > zr) return -1;
@@ -95,7 +138,7 @@ __device__ bool warm_gather(const SolveKArgs& a, const ClassDev& C, int pid, TX*
   const float* prev = a.warm_store + (long long)a.warm_state[0] * a.warm_cap * a.rstride + (long long)q * a.rstride;
   for (long long k = threadIdx.x; k < C.n_pe; k += blockDim.x) {
     const short4 o = C.me_off[k];
-    const int idx = pe_index(C, a.n, o.x + d[0], o.y + d[1], o.z + d[2]);
+    const int idx = o.w ? -1 : pe_index(C, a.n, o.x + d[0], o.y + d[1], o.z + d[2]);
     x[k] = idx >= 0 ? (TX)prev[idx] : (TX)0;
   }
   return true;
@@ -385,10 +428,369 @@ __device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& c
 #undef EXX_VALID
 #undef EXX_IDX
 
+// ---------------------------------------------------------------------------
+// General cells.  Columns are padded to a symmetric z' range, so plane z' is
+// still a prefix of the column order and the index is pst[z' + Zmax] + col;
+// a slot holds a point only for lo <= z' <= hi (dead slots are never read or
+// written here, and read as zero through the LDS plane).
+
+template <int CPT>
+struct ColsG {
+  int lo[CPT], hi[CPT];   // z' interval of the column (lo > hi: no column)
+  int pos[CPT];           // LDS plane position
+  int col[CPT];
+};
+
+template <int CPT, int NT>
+__device__ __forceinline__ void load_cols_gen(const ClassDev& C, const SolveKArgs& a, ColsG<CPT>& cl) {
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int col = threadIdx.x + c * NT;
+    cl.lo[c] = 1;
+    cl.hi[c] = 0;
+    cl.col[c] = 0;
+    cl.pos[c] = 0;
+    if (col < C.n_cols) {
+      const int4 cc = C.cols[col];
+      cl.lo[c] = cc.z;
+      cl.hi[c] = cc.w;
+      cl.col[c] = col;
+      cl.pos[c] = (cc.x + a.lds_cx) + kLdsWX * (cc.y + a.lds_cy);
+    }
+  }
+}
+
+#define EXX_GVALID(c, zz) ((zz) >= cl.lo[c] && (zz) <= cl.hi[c])
+#define EXX_GHAS(c) (cl.lo[c] <= cl.hi[c])
+#define EXX_GIDX(c, zz) (pst[(zz) + Zmax] + cl.col[c])
+
+// Laplacian sum at a point from its own column (z' arm, centre) and the
+// in-plane arms (staged plane pl)
+template <int NS, typename T>
+__device__ __forceinline__ T gen_inplane(const GenStencilT<T>& S, T ctr, const T* pl, int pos, const T* wz) {
+  T sz = 0;
+#pragma unroll
+  for (int q = 1; q <= NS; ++q) sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
+  T s = S.diag * ctr + S.cz * sz;
+  for (int k = 0; k < S.n_in; ++k) {
+    const int off = S.in_off[k];
+    T t = 0;
+#pragma unroll
+    for (int q = 1; q <= NS; ++q) t += S.w[q] * (pl[pos + q * off] + pl[pos - q * off]);
+    s += S.in_coef[k] * t;
+  }
+  return s;
+}
+
+// Arms leaving the plane: plane z' is the +q neighbour of the column's point
+// at z' - q and the -q neighbour of its point at z' + q.  acc[k] holds the
+// partial sum of the point at z' - DL + k.
+template <int NS, int DL, typename T>
+__device__ __forceinline__ void gen_tilted(const GenStencilT<T>& S, const T* pl, int pos, T* acc) {
+  if constexpr (DL > 0) {
+    for (int k = 0; k < S.n_tl; ++k) {
+      const int off = S.tl_off[k];
+      const T cf = S.tl_coef[k];
+#pragma unroll
+      for (int q = 1; q <= NS; ++q) {
+        acc[DL - q] += cf * S.w[q] * pl[pos + q * off];
+        acc[DL + q] += cf * S.w[q] * pl[pos - q * off];
+      }
+    }
+  }
+}
+
+// Pass A (general cell): as cg_pass_a; q = A p of plane z' is complete DL
+// planes after z' (DL = n when some arm leaves the plane, else 0).
+template <int NS, int CPT, int PD, bool TL, typename T>
+__device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
+                              const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
+                              double& pq, double& rr) {
+  constexpr int DL = TL ? NS : 0;
+  T win[CPT][2 * NS + 1];
+  T acc[CPT][2 * DL + 1];
+  T qr[PD][CPT], qp[PD][CPT];
+  pq = 0.0;
+  rr = 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int k = 0; k < 2 * DL + 1; ++k) acc[c][k] = 0;
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      T v = 0;
+      if (EXX_GVALID(c, zz)) {
+        const int idx = EXX_GIDX(c, zz);
+        const T rv = r[idx];
+        v = first ? rv : rv + beta * p[idx];
+        p[idx] = v;
+        rr += (double)rv * (double)rv;
+      }
+      win[c][k] = v;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      qr[d][c] = 0;
+      qp[d][c] = 0;
+      if (EXX_GVALID(c, zz)) {
+        const int idx = EXX_GIDX(c, zz);
+        qr[d][c] = r[idx];
+        if (!first) qp[d][c] = p[idx];
+      }
+    }
+  }
+  for (int z = -Zmax; z <= Zmax + DL; ++z) {
+    const int zl = z + NS + PD + 1;
+    T nr[CPT], np[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nr[c] = 0;
+      np[c] = 0;
+      if (EXX_GVALID(c, zl)) {
+        const int idx = EXX_GIDX(c, zl);
+        nr[c] = r[idx];
+        if (!first) np[c] = p[idx];
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+    const int zo = z - DL;   // plane whose A p completes now
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_GVALID(c, z)) acc[c][DL] += gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
+      if (EXX_GHAS(c)) gen_tilted<NS, DL, T>(S, pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) pq -= (double)win[c][NS - DL] * (double)acc[c][0];
+#pragma unroll
+      for (int k = 0; k < 2 * DL; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * DL] = 0;
+    }
+    const int zc = z + NS + 1;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      T v = 0;
+      if (EXX_GVALID(c, zc)) {
+        v = first ? qr[0][c] : qr[0][c] + beta * qp[0][c];
+        p[EXX_GIDX(c, zc)] = v;
+        rr += (double)qr[0][c] * (double)qr[0][c];
+      }
+      win[c][2 * NS] = v;
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) {
+        qr[d][c] = qr[d + 1][c];
+        qp[d][c] = qp[d + 1][c];
+      }
+      qr[PD - 1][c] = nr[c];
+      qp[PD - 1][c] = np[c];
+    }
+  }
+}
+
+// Pass B (general cell): as cg_pass_b, with the update of plane z' made DL
+// planes later, when its A p is complete.  Each point's r_in and x are still
+// read (one step ahead of its update) before the same thread writes them.
+template <int NS, int CPT, int PD, bool TL, typename T>
+__device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax, T* x,
+                                const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+  constexpr int DL = TL ? NS : 0;
+  T win[CPT][2 * NS + 1];
+  T acc[CPT][2 * DL + 1];
+  T qp[PD][CPT];
+  T cx[CPT], cr[CPT];      // x, r of the plane updated in this step (z - DL)
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int k = 0; k < 2 * DL + 1; ++k) acc[c][k] = 0;
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? p[EXX_GIDX(c, zz)] : (T)0;
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_GVALID(c, zz) ? p[EXX_GIDX(c, zz)] : (T)0;
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    cx[c] = 0;
+    cr[c] = 0;
+    const int z0 = -Zmax - DL;
+    if (EXX_GVALID(c, z0)) {
+      const int idx = EXX_GIDX(c, z0);
+      cr[c] = r_in[idx];
+      if (!x_zero) cx[c] = x[idx];
+    }
+  }
+  double sum = 0.0;
+  for (int z = -Zmax; z <= Zmax + DL; ++z) {
+    const int zl = z + NS + PD + 1;
+    const int zn = z - DL + 1;   // plane updated in the next step
+    T np[CPT], nx[CPT], nr[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      np[c] = EXX_GVALID(c, zl) ? p[EXX_GIDX(c, zl)] : (T)0;
+      nx[c] = 0;
+      nr[c] = 0;
+      if (EXX_GVALID(c, zn)) {
+        const int idx = EXX_GIDX(c, zn);
+        nr[c] = r_in[idx];
+        if (!x_zero) nx[c] = x[idx];
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+    const int zo = z - DL;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_GVALID(c, z)) acc[c][DL] += gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
+      if (EXX_GHAS(c)) gen_tilted<NS, DL, T>(S, pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) {
+        const int idx = EXX_GIDX(c, zo);
+        const T rn = cr[c] + alpha * acc[c][0];   // r - alpha A p, A p = -acc
+        x[idx] = cx[c] + alpha * win[c][NS - DL];
+        r[idx] = rn;
+        sum += (double)rn * (double)rn;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * DL; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * DL] = 0;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      win[c][2 * NS] = qp[0][c];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) qp[d][c] = qp[d + 1][c];
+      qp[PD - 1][c] = np[c];
+      cx[c] = nx[c];
+      cr[c] = nr[c];
+    }
+  }
+  return sum;
+}
+
+// FP64 true residual b - A x of a general cell (see cg_true_residual).
+template <int NS, int CPT, bool TL, typename TR>
+__device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
+                                       const double* __restrict__ x, const double* __restrict__ b,
+                                       TR* __restrict__ r, double rs, double* pl0, double* pl1) {
+  constexpr int DL = TL ? NS : 0;
+  double win[CPT][2 * NS + 1];
+  double acc[CPT][2 * DL + 1];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int k = 0; k < 2 * DL + 1; ++k) acc[c][k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? x[EXX_GIDX(c, zz)] : 0.0;
+  }
+  double sum = 0.0;
+  for (int z = -Zmax; z <= Zmax + DL; ++z) {
+    const int zc = z + NS + 1;
+    const int zo = z - DL;
+    double nx[CPT], cb[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nx[c] = EXX_GVALID(c, zc) ? x[EXX_GIDX(c, zc)] : 0.0;
+      cb[c] = EXX_GVALID(c, zo) ? b[EXX_GIDX(c, zo)] : 0.0;
+    }
+    double* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = win[c][NS];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_GVALID(c, z)) acc[c][DL] += gen_inplane<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
+      if (EXX_GHAS(c)) gen_tilted<NS, DL, double>(S, pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) {
+        const double rt = cb[c] + acc[c][0];   // b - A x, A x = -acc
+        r[EXX_GIDX(c, zo)] = (TR)(rt * rs);
+        sum += rt * rt;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * DL; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * DL] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[c][k] = win[c][k + 1];
+      win[c][2 * NS] = nx[c];
+    }
+  }
+  return sum;
+}
+
+#undef EXX_GVALID
+#undef EXX_GHAS
+#undef EXX_GIDX
+
+
+// Orthorhombic (axis stencil) or general-cell (NK arms) form of the passes.
+template <bool GEN, int CPT>
+using ColsOf = std::conditional_t<GEN, ColsG<CPT>, Cols<CPT>>;
+
+template <bool GEN, int CPT, int NT>
+__device__ __forceinline__ void cols_load(const ClassDev& C, const SolveKArgs& a, ColsOf<GEN, CPT>& cl) {
+  if constexpr (GEN) load_cols_gen<CPT, NT>(C, a, cl); else load_cols<CPT, NT>(C, a, cl);
+}
+
+template <int NS, int CPT, int PD, bool GEN, bool TL, typename T>
+__device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T>& G, const ColsOf<GEN, CPT>& cl,
+                                       const int* pst, int Zmax, const T* r, T* p, T beta, bool first, T* pl0,
+                                       T* pl1, double& pq, double& rr) {
+  if constexpr (GEN)
+    cg_pass_a_gen<NS, CPT, PD, TL, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+  else
+    cg_pass_a<NS, CPT, PD, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+}
+
+template <int NS, int CPT, int PD, bool GEN, bool TL, typename T>
+__device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT<T>& G, const ColsOf<GEN, CPT>& cl,
+                                         const int* pst, int Zmax, T* x, const T* r_in, T* r, const T* p, T alpha,
+                                         bool x_zero, T* pl0, T* pl1) {
+  if constexpr (GEN)
+    return cg_pass_b_gen<NS, CPT, PD, TL, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+  else
+    return cg_pass_b<NS, CPT, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+}
+
+template <int NS, int CPT, bool GEN, bool TL, typename TR>
+__device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsOf<GEN, CPT>& cl, const int* pst,
+                                                int Zmax, const double* x, const double* b, TR* r, double rs,
+                                                double* pl0, double* pl1) {
+  if constexpr (GEN)
+    return cg_true_residual_gen<NS, CPT, TL, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+  else
+    return cg_true_residual<NS, CPT, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+}
+
 // One workgroup solves one pair at a time, taking pairs from a device queue
 // until the batch is exhausted (every workgroup exits when the counter passes
 // the batch size).  Unpreconditioned CG from x = 0, stop at ||r|| <= tol ||b||.
-template <int NS, int CPT, int NT, int PD>
+template <int NS, int CPT, int NT, int PD, bool GEN, bool TL>
 __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[NT / 64];
@@ -418,8 +820,8 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
 
     for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
     for (int k = tid; k < 2 * Zmax + 2; k += NT) pst[k] = C.plane_start[k];
-    Cols<CPT> cl;
-    load_cols<CPT, NT>(C, a, cl);
+    ColsOf<GEN, CPT> cl;
+    cols_load<GEN, CPT, NT>(C, a, cl);
     __syncthreads();
 
     int it = 0;
@@ -443,8 +845,8 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       double alpha = 1.0;
       if (!init) {
         double pq_t, rr_t;
-        cg_pass_a<NS, CPT, PD, double>(a.S, cl, pst, Zmax, (first && from_b) ? x : r, p, beta, first, pl0, pl1,
-                                       pq_t, rr_t);
+        pass_a<NS, CPT, PD, GEN, TL, double>(a.S, a.G, cl, pst, Zmax, (first && from_b) ? x : r, p, beta, first,
+                                             pl0, pl1, pq_t, rr_t);
         const double pq = block_sum(pq_t, red);
         if (first && from_b) {
           rr = block_sum(rr_t, red);
@@ -459,8 +861,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
         alpha = rr / pq;
       }
       const bool from_b_now = init || (first && from_b);
-      const double rn = block_sum(cg_pass_b<NS, CPT, PD, double>(a.S, cl, pst, Zmax, x, from_b_now ? x : r, r, p,
-                                                                 alpha, from_b_now, pl0, pl1),
+      const double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, double>(a.S, a.G, cl, pst, Zmax, x,
+                                                                       from_b_now ? x : r, r, p, alpha, from_b_now,
+                                                                       pl0, pl1),
                                   red);
       if (init) {   // the warm start's residual
         init = false;
@@ -497,7 +900,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
 // van der Vorst and Ye 2000; Clark et al. 2010).  The solution accumulates in
 // FP64 and the stop test is on the FP64 true residual, ||b - A x|| <= tol ||b||,
 // the same criterion as the FP64 path.
-template <int NS, int CPT, int NT, int PD>
+template <int NS, int CPT, int NT, int PD, bool GEN, bool TL>
 __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[NT / 64];
@@ -515,6 +918,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   float* p = r + a.sstride;
   float* y = p + a.sstride;
   const StencilT<float> S32 = stencil_cast<float>(a.S);
+  const GenStencilT<float> G32 = gen_stencil_cast<float>(a.G);
 
   long long lo, hi;
   solve_range(a, &lo, &hi);
@@ -533,8 +937,8 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
 
     for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
     for (int k = tid; k < 2 * Zmax + 2; k += NT) pst[k] = C.plane_start[k];
-    Cols<CPT> cl;
-    load_cols<CPT, NT>(C, a, cl);
+    ColsOf<GEN, CPT> cl;
+    cols_load<GEN, CPT, NT>(C, a, cl);
     // ||b|| in FP64; the FP32 recursion runs in units of ||b|| (r = b / ||b||),
     // so its values stay far from the FP32 range limits whatever the pair's
     // overlap, and the solution is x = ||b|| sum y
@@ -556,7 +960,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     if (!conv && warm_gather<double>(a, C, pid, x)) {
       for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
       __syncthreads();
-      rr_true = block_sum(cg_true_residual<NS, CPT, float>(a.S, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+      rr_true = block_sum(true_residual<NS, CPT, GEN, TL, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
       for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
       __syncthreads();
       x_zero = false;
@@ -566,7 +970,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     }
     while (!conv && it < a.max_iter) {
       double pq_t, rr_t;
-      cg_pass_a<NS, CPT, PD, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
+      pass_a<NS, CPT, PD, GEN, TL, float>(S32, G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
       const double pq = block_sum(pq_t, red);
       if (!(pq > 0.0) || !(pq < INFINITY)) {
         it = a.max_iter;
@@ -574,8 +978,8 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         break;
       }
       const double alpha = rr / pq;
-      double rn = block_sum(cg_pass_b<NS, CPT, PD, float>(S32, cl, pst, Zmax, y, r, r, p, (float)alpha, y_zero, fl0,
-                                                          fl1),
+      double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, float>(S32, G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
+                                                                y_zero, fl0, fl1),
                             red);
       ++it;
       first = false;
@@ -594,7 +998,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
-        rr_true = block_sum(cg_true_residual<NS, CPT, float>(a.S, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+        rr_true = block_sum(true_residual<NS, CPT, GEN, TL, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
         ++upd;
@@ -625,22 +1029,36 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
 }
 
 // Launch (or occupancy query, when occ is not NULL) of one instance.
-template <int NS, int CPT, int NT, int PD>
-hipError_t solve_instance(const SolveKArgs& a, bool mixed, int groups, size_t lds, hipStream_t s, int* occ) {
-  const void* fn = mixed ? (const void*)k_solve_mixed<NS, CPT, NT, PD> : (const void*)k_solve<NS, CPT, NT, PD>;
+template <int NS, int CPT, int NT, int PD, bool GEN, bool TL>
+hipError_t solve_instance_g(const SolveKArgs& a, bool mixed, int groups, size_t lds, hipStream_t s, int* occ) {
+  const void* fn = mixed ? (const void*)k_solve_mixed<NS, CPT, NT, PD, GEN, TL>
+                         : (const void*)k_solve<NS, CPT, NT, PD, GEN, TL>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   if (occ) {
-    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve_mixed<NS, CPT, NT, PD>, NT, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, CPT, NT, PD>, NT, lds);
+    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve_mixed<NS, CPT, NT, PD, GEN, TL>, NT, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, CPT, NT, PD, GEN, TL>, NT, lds);
   }
   if (mixed)
-    k_solve_mixed<NS, CPT, NT, PD><<<groups, NT, lds, s>>>(a);
+    k_solve_mixed<NS, CPT, NT, PD, GEN, TL><<<groups, NT, lds, s>>>(a);
   else
-    k_solve<NS, CPT, NT, PD><<<groups, NT, lds, s>>>(a);
+    k_solve<NS, CPT, NT, PD, GEN, TL><<<groups, NT, lds, s>>>(a);
   return hipGetLastError();
+}
+
+// Orthorhombic cells take every load depth; general cells run with one plane
+// of loads ahead, and with the window of partial sums only when some arm
+// leaves the sweep plane.
+template <int NS, int CPT, int NT, int PD>
+hipError_t solve_instance(const SolveKArgs& a, bool mixed, int groups, size_t lds, hipStream_t s, int* occ) {
+  if (!a.gen) return solve_instance_g<NS, CPT, NT, PD, false, false>(a, mixed, groups, lds, s, occ);
+  if constexpr (PD == 1) {
+    if (a.G.n_tl > 0) return solve_instance_g<NS, CPT, NT, 1, true, true>(a, mixed, groups, lds, s, occ);
+    return solve_instance_g<NS, CPT, NT, 1, true, false>(a, mixed, groups, lds, s, occ);
+  }
+  return hipErrorInvalidValue;
 }
 
 // Columns per thread available for each workgroup size: 1024 threads take up

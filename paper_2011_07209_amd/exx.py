@@ -84,7 +84,8 @@ class Stats(ctypes.Structure):
 
 
 SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_count_pairs", "exx_pair_results",
-           "exx_stats_fetch", "exx_plan_geometry", "exx_subdomain_counts", "exx_destroy", "exx_last_error"]
+           "exx_stats_fetch", "exx_plan_geometry", "exx_subdomain_counts", "exx_nk_stencil", "exx_destroy",
+           "exx_last_error"]
 
 _lib = None
 
@@ -118,6 +119,8 @@ def load():
     lib.exx_plan_geometry.argtypes = [vp, ctypes.c_int, llp, llp, llp]
     lib.exx_subdomain_counts.restype = ctypes.c_int
     lib.exx_subdomain_counts.argtypes = [dp, ip, ctypes.c_double, ctypes.c_double, ctypes.c_int, llp, llp, llp]
+    lib.exx_nk_stencil.restype = ctypes.c_int
+    lib.exx_nk_stencil.argtypes = [dp, ip, ip, ip, dp, dp]
     lib.exx_destroy.restype = ctypes.c_int
     lib.exx_destroy.argtypes = [vp]
     lib.exx_last_error.restype = ctypes.c_char_p
@@ -255,6 +258,23 @@ def exx_subdomain_counts(h, grid, R_PE, R_ME, stencil_n):
     _check(load().exx_subdomain_counts(hc, gc, float(R_PE), float(R_ME), int(stencil_n), ctypes.byref(a),
                                        ctypes.byref(b), ctypes.byref(c)), None)
     return {"n_pe": a.value, "n_halo": b.value, "n_me": c.value}
+
+
+def exx_nk_stencil(h, grid):
+    """The library's NK Laplacian for cell h: dict u (k x 3), beta, step."""
+    import numpy as np
+    hv = np.asarray(h, dtype=np.float64)
+    hv = hv.flatten(order="F") if hv.shape == (3, 3) else hv.reshape(9)
+    hc = (ctypes.c_double * 9)(*hv.tolist())
+    gc = (ctypes.c_int * 3)(*[int(x) for x in grid])
+    n = ctypes.c_int()
+    u = (ctypes.c_int * 18)()
+    beta = (ctypes.c_double * 6)()
+    step = (ctypes.c_double * 6)()
+    _check(load().exx_nk_stencil(hc, gc, ctypes.byref(n), u, beta, step), None)
+    k = n.value
+    return {"u": np.array(list(u), dtype=np.int64).reshape(6, 3)[:k], "beta": np.array(list(beta))[:k],
+            "step": np.array(list(step))[:k]}
 
 
 def exx_destroy(plan):

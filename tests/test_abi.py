@@ -55,13 +55,27 @@ def test_default_options(lib):
     assert o.cg_max_iter == 5000 and o.pair_sample_frac == 1.0 and o.R_PE_nclass == 0
 
 
-@pytest.mark.parametrize("case", ["shear", "rme", "lmax", "stencil", "grid", "tol"])
+@pytest.mark.parametrize("case", ["singular", "left_handed", "arm_reach", "rme", "lmax", "stencil", "grid", "tol"])
 def test_plan_rejects_invalid_arguments(lib, case):
     h = np.diag([12.0, 12.0, 12.0])
     grid, R_pair, R_PE, R_ME, L = (60, 60, 60), 8.0, 5.0, 7.0, 6
     opt = exx.exx_default_options(stencil_n=1)
-    if case == "shear":
+    if case == "singular":
+        h[:, 1] = h[:, 0]
+    elif case == "left_handed":
         h[0, 1] = 0.5
+        h[:, 2] *= -1.0
+    elif case == "arm_reach":
+        # a triclinic cell whose longest NK arm is longer than the lattice
+        # spacings: R_ME covers n axis steps but not n arm steps
+        from test_oracle_pins import _cell
+        h = _cell(12.0, 12.5, 11.5, 80, 95, 100)
+        grid = (60, 62, 58)
+        opt.stencil_n = 3
+        axis = max(np.linalg.norm(h, axis=0) / np.asarray(grid))
+        longest = max(exx.exx_nk_stencil(h, grid)["step"])
+        assert longest > 1.05 * axis
+        R_ME = R_PE + 3 * (axis + longest) / 2
     elif case == "rme":
         R_ME = 5.1
     elif case == "lmax":
