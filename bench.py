@@ -9,7 +9,7 @@ FP64 and in mixed precision; the mixed figure is the headline value.  Prints
 one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|fp64|mixed]
-                  [--workload water64|water128|water256|water512]
+                  [--workload water64|water128|water256|water512|hex64|tri64]
 
 water256 runs as the MD-like repeated-call case: per-orbital sphere radii (9
 classes), a fixed pair capacity, one eager warm-up call (which runs the CG
@@ -51,7 +51,7 @@ KERNEL_SOURCES = ["paper_2011_07209_amd/csrc/solve_impl.h", "paper_2011_07209_am
                   "paper_2011_07209_amd/csrc/solve_n1.hip", "paper_2011_07209_amd/csrc/solve_n2.hip",
                   "paper_2011_07209_amd/csrc/solve_n3.hip", "paper_2011_07209_amd/csrc/exx_internal.h",
                   "paper_2011_07209_amd/csrc/plan_geometry.cpp"]
-MOLECULES = {"water64": 64, "water128": 128, "water256": 256, "water512": 512}
+MOLECULES = {"water64": 64, "water128": 128, "water256": 256, "water512": 512, "hex64": 64, "tri64": 64}
 D_CHECK_ROWS = 16   # orbitals whose D the mixed/FP64 comparison uses
 
 
@@ -80,6 +80,12 @@ def stored_traffic(workload: str, precision: str):
 def describe(cfg) -> str:
     grid = "x".join(str(n) for n in cfg.grid)
     cell = "x".join(f"{x:g}" for x in cfg.cell)
+    if cfg.general:
+        import numpy as np
+        h = cfg.h
+        ang = [math.degrees(math.acos(np.dot(h[:, i], h[:, j]) / np.linalg.norm(h[:, i]) / np.linalg.norm(h[:, j])))
+               for i, j in ((1, 2), (0, 2), (0, 1))]
+        cell += " (angles " + "/".join(f"{x:.0f}" for x in ang) + " deg, NK Laplacian)"
     radii = (f"R_PE {cfg.R_orb_range[0]:g}-{cfg.R_orb_range[1]:g} per orbital ({cfg.R_PE_classes[2]} classes)"
              if cfg.R_PE_classes else f"R_PE {cfg.R_PE:g}")
     return (f"{cfg.key}: water-like {MOLECULES[cfg.key]}-molecule set, {cfg.lattice} lattice, cell {cell} bohr, "

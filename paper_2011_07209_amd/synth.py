@@ -78,7 +78,18 @@ class Config:
         return abs(float(np.linalg.det(self.h))) / float(np.prod(self.grid))
 
 
-# The five workloads: a tiny cubic cell for oracle-speed parity, and water-like
+def _cell_matrix(a, b, c, alpha, beta, gamma):
+    """Column-major h (h[a + 3 al] = (L_al)_a) of a cell with edge lengths a, b,
+    c and angles alpha = (L2, L3), beta = (L1, L3), gamma = (L1, L2) in degrees;
+    L1 along x, L2 in the xy plane."""
+    al, be, ga = (math.radians(x) for x in (alpha, beta, gamma))
+    cx = c * math.cos(be)
+    cy = c * (math.cos(al) - math.cos(be) * math.cos(ga)) / math.sin(ga)
+    cz = math.sqrt(c * c - cx * cx - cy * cy)
+    return [a, 0.0, 0.0, b * math.cos(ga), b * math.sin(ga), 0.0, cx, cy, cz]
+
+
+# The workloads: a tiny cubic cell for oracle-speed parity, and water-like
 # sets of 64, 128, 256 and 512 molecules (4 orbitals each).
 CONFIGS = {
     "tiny16": Config("tiny16", (12.0, 12.0, 12.0), (60, 60, 60), 16, 8.0, 5.0, 7.0, 6, 1,
@@ -92,6 +103,13 @@ CONFIGS = {
                        seed_index=4),
     "water512": Config("water512", (47.0, 47.0, 47.0), (240, 240, 240), 2048, 10.0, 6.0, 9.0, 8, 3,
                        lattice="sc", reps=8, orb_dtype="f32", seed_index=5),
+    # water-like 64-molecule sets in non-orthogonal cells of the same volume
+    # and grid spacing as water64 (Sec. III B-C): hexagonal (one auxiliary
+    # stencil direction) and triclinic (three)
+    "hex64": Config("hex64", (24.6, 24.6, 24.6), (126, 126, 126), 256, 10.0, 6.0, 9.0, 6, 3,
+                    lattice="sc", reps=4, seed_index=6, hmat=tuple(_cell_matrix(24.6, 24.6, 24.6, 90, 90, 120))),
+    "tri64": Config("tri64", (23.8, 23.8, 23.8), (122, 122, 122), 256, 10.0, 6.0, 9.0, 6, 3,
+                    lattice="sc", reps=4, seed_index=7, hmat=tuple(_cell_matrix(23.8, 23.8, 23.8, 80, 95, 100))),
 }
 
 
@@ -131,11 +149,26 @@ _BASIS = {
 def make_orbitals(cfg: Config, seed: Optional[int] = None) -> OrbitalSet:
     st = _streams(cfg, seed)
     L = np.asarray(cfg.cell, dtype=np.float64)
-    if cfg.general:
+    if cfg.general and cfg.lattice is None:
         # general cell: uniform centres in crystal coordinates
-        if cfg.lattice is not None:
-            raise ValueError("lattice sets are built for orthorhombic cells")
         centres = st[_S_CENTRES].uniform(0.0, 1.0, size=(cfg.n_orb, 3)) @ cfg.h.T
+    elif cfg.general:
+        # molecule sites on the lattice in crystal coordinates, Cartesian jitter
+        # and tetrahedral orbital offsets as for the orthorhombic sets, wrapped
+        # back into the cell in crystal coordinates
+        h = cfg.h
+        basis = _BASIS[cfg.lattice]
+        cells = np.stack(np.meshgrid(*[np.arange(cfg.reps)] * 3, indexing="ij"), -1).reshape(-1, 3)
+        frac = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) / cfg.reps
+        sites = frac @ h.T + st[_S_SITES].uniform(-cfg.jitter, cfg.jitter, size=frac.shape)
+        n_mol = sites.shape[0]
+        assert 4 * n_mol == cfg.n_orb, (n_mol, cfg.n_orb)
+        centres = np.empty((cfg.n_orb, 3))
+        for m in range(n_mol):
+            R = _rotation(st[_S_ROT])
+            dist = st[_S_OFFSET].uniform(cfg.offset[0], cfg.offset[1], size=4)
+            centres[4 * m:4 * m + 4] = sites[m] + dist[:, None] * (_TETRA @ R.T)
+        centres = np.mod(centres @ np.linalg.inv(h).T, 1.0) @ h.T
     elif cfg.lattice is None:
         centres = st[_S_CENTRES].uniform(0.0, 1.0, size=(cfg.n_orb, 3)) * L
     else:
