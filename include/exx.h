@@ -89,6 +89,18 @@ typedef struct {
      R_ME).  Self pairs then form a sphere class of their own.  Not combined
      with variable radii (R_PE_nclass > 0: EXX_EINVAL)                          */
   double R_PE_self, R_ME_self;
+  /* fluctuating cells (Sec. III B 2): 1 builds the tables so that
+     exx_set_cell may later switch to any cell whose Laplacian arms are
+     nearest grid neighbours (general layout even for an orthorhombic h, and
+     Dirichlet points along every nearest-neighbour direction); 0: the cell
+     may only change within its kind (orthorhombic stays orthorhombic, a
+     general cell keeps its arm directions)                                   */
+  int cell_fluctuation;
+  /* re-assembly criterion: when exx_set_cell finds max |h h0^-1 - I| above
+     this strain (h0: the cell the tables were built for), the
+     proto-subdomains are rebuilt from scratch at the new cell with the plan's
+     radii (0: never)                                                         */
+  double reassemble_strain;
 } exx_options;
 
 /* Fills *opt with the defaults: n = 3, FP64, tol 1e-10, 5000 iterations,
@@ -183,7 +195,34 @@ typedef struct {
                                   results are those of its latest replay, and the
                                   device times are 0                               */
   long long warm_pairs;        /* pairs whose CG started from a previous solution  */
+  double cell_strain;          /* max |h h0^-1 - I| of the current cell against the
+                                  cell the tables were built for                  */
+  int reassemblies;            /* proto-subdomain re-assemblies by exx_set_cell    */
+  int n_arms;                  /* arms of the Laplacian in use (3 to 6)           */
 } exx_stats;
+
+/* Fluctuating cell (Sec. III B 2): makes h (host [9], column-major,
+   right-handed) the plan's cell for the following exx_eval calls while the
+   proto-subdomains keep their grid offsets, so their points have fixed scaled
+   coordinates s = o / N, local coordinates r = h s, and a fixed count.  The
+   Laplacian arms are chosen again for h (Algorithm 1, Sec. III C 2), the
+   Jacobian, h^-1 and the volume element follow h, and the pair list and pair
+   centres of the next exx_eval use h (centres are Cartesian, for the new
+   cell).  With reassemble_strain > 0 and a strain above it, the tables are
+   rebuilt for h from the plan's radii (new point counts; the warm-start
+   history is dropped).  Waits for the plan's stream; not capturable: HIP
+   graphs recorded before the call keep the old cell and tables, record them
+   again.  EXX_EINVAL for a singular or left-handed h, for a non-orthogonal h
+   on a plan built without cell_fluctuation for an orthorhombic cell, or when
+   the new arms leave the Dirichlet points the tables hold (re-assemble or
+   plan again). */
+exx_status exx_set_cell(exx_plan_t plan, const double h[9]);
+
+/* Host helper: the EXX stress and internal pressure from sigma_xx (Sec. II B
+   3): Pi[a + 3 b] = -(1/V) sum_al sigma[a + 3 al] h[b + 3 al] (eq.
+   pixx_working) and *p_int = Tr Pi / 3 (eq. pxx_working), V = |det h|.  Pi or
+   p_int may be NULL. */
+exx_status exx_pressure(const double h[9], const double sigma[9], double* Pi, double* p_int);
 
 /* Statistics of the last exx_eval (synchronizes the bound stream).  Returns
    EXX_ENOCONV when a pair did not converge. */

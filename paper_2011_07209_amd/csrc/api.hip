@@ -344,6 +344,351 @@ exx_status record_event(exx_plan_t P, std::vector<hipEvent_t>& evs, int& used, h
 exx_status record_solve_event(exx_plan_t P, hipStream_t s) { return record_event(P, P->solve_ev, P->solve_ev_used, s); }
 exx_status record_moment_event(exx_plan_t P, hipStream_t s) { return record_event(P, P->mom_ev, P->mom_ev_used, s); }
 
+// ---------------------------------------------------------------------------
+// The cell (Sec. III B): geometry, Laplacian arms and sphere-class tables.
+
+bool off_diagonal(const double h[9]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      if (r != c && h[r + 3 * c] != 0.0) return true;
+  return false;
+}
+
+// Cell-dependent fields of the geometry: h, h^-1, edge lengths and spacings,
+// the Jacobian of eq. jacb, the offset map r = A o and the volume element.
+void set_cell_geometry(Geo& g, const double h[9], bool general) {
+  std::memcpy(g.h, h, sizeof(g.h));
+  inv3(h, g.hinv);
+  for (int a = 0; a < 3; ++a) {
+    g.L[a] = general ? std::sqrt(h[3 * a] * h[3 * a] + h[1 + 3 * a] * h[1 + 3 * a] + h[2 + 3 * a] * h[2 + 3 * a])
+                     : h[a + 3 * a];
+    g.d[a] = g.L[a] / g.N[a];
+    g.inv_d2[a] = 1.0 / (g.d[a] * g.d[a]);
+    g.inv_d[a] = 1.0 / g.d[a];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int al = 0; al < 3; ++al) {
+      g.J[a + 3 * al] = g.L[al] * g.hinv[al + 3 * a];
+      g.A[a + 3 * al] = h[a + 3 * al] / g.N[al];
+    }
+  g.dV = std::fabs(det3(h)) / (double)g.ngrid;
+  g.gen = general ? 1 : 0;
+}
+
+// NK arms of cell h into g (general layout); every arm must be a nearest grid
+// neighbour direction.  Returns an empty string or the reason.
+std::string set_cell_arms(Geo& g, const double h[9], std::vector<NkArm>* arms) {
+  std::string e = build_nk_arms(h, g.N, arms);
+  if (!e.empty()) return e;
+  if (arms->size() > 6) return "more than six NK arms";
+  g.n_arms = (int)arms->size();
+  for (size_t k = 0; k < arms->size(); ++k) {
+    for (int a = 0; a < 3; ++a) {
+      if (std::abs((*arms)[k].u[a]) > 1) return "an NK auxiliary direction beyond the first shell of grid neighbours";
+      g.arm_u[k][a] = (*arms)[k].u[a];
+    }
+    g.arm_coef[k] = (*arms)[k].beta / ((*arms)[k].step * (*arms)[k].step);
+  }
+  return std::string();
+}
+
+double cell_strain(const double h[9], const double h0[9]) {
+  double h0inv[9];
+  inv3(h0, h0inv);
+  double m = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += h[r + 3 * k] * h0inv[k + 3 * c];
+      m = std::max(m, std::fabs(s - (r == c ? 1.0 : 0.0)));
+    }
+  return m;
+}
+
+// Moment tables of every class for the plan's current offset map, into the
+// class block (same sizes as at assembly).
+exx_status upload_moment_tables(exx_plan_t P, const Geo& g) {
+  const bool mixed = P->opt.precision == EXX_PREC_MIXED;
+  int mom_rows = 0, mom_mfma_rows = 0;
+  moment_layout(P->l_max, mixed, &mom_rows, &mom_mfma_rows);
+  for (size_t k = 0; k < P->classes.size(); ++k) {
+    std::vector<double> tab;
+    build_moment_table(P->classes[k], g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);
+    const ClassDev& D = P->class_dev_host[k];
+    if (mixed) {
+      std::vector<unsigned short> hi(tab.size()), lo(tab.size());
+      for (size_t e = 0; e < tab.size(); ++e) {
+        hi[e] = bf16_rne((float)tab[e]);
+        lo[e] = bf16_rne((float)(tab[e] - bf16_value(hi[e])));
+      }
+      EXX_HIP(P, hipMemcpy((void*)D.mom_hi, hi.data(), hi.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
+      EXX_HIP(P, hipMemcpy((void*)D.mom_lo, lo.data(), lo.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
+    } else {
+      EXX_HIP(P, hipMemcpy((void*)D.mom_f64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
+  return EXX_OK;
+}
+
+// Builds the cell-dependent part of the plan for cell h: geometry, Laplacian
+// arms, the sphere classes and their device tables.  Everything is built
+// aside and replaces the plan's tables only on success.  Host-side checks run
+// before any device call.
+exx_status assemble_cell(exx_plan_t P, const double h[9]) {
+  const exx_options& opt = P->opt;
+  const int n = opt.stencil_n;
+  const bool general = opt.cell_fluctuation != 0 || off_diagonal(h);
+  Geo g = P->geo;
+  set_cell_geometry(g, h, general);
+  for (int a = 0; a < 3; ++a) g.perm[a] = a;
+  g.n_arms = 0;
+  double maxd = std::max(g.d[0], std::max(g.d[1], g.d[2]));
+  std::vector<NkArm> arms;
+  if (general) {
+    std::string e = set_cell_arms(g, h, &arms);
+    if (!e.empty()) return fail(P, EXX_EINVAL, e);
+    for (const NkArm& A : arms) maxd = std::max(maxd, A.step);
+  }
+  if (opt.cell_fluctuation) {
+    // Dirichlet points along every nearest-neighbour direction
+    for (int u2 = -1; u2 <= 1; ++u2)
+      for (int u1 = -1; u1 <= 1; ++u1)
+        for (int u0 = -1; u0 <= 1; ++u0) {
+          const int u[3] = {u0, u1, u2};
+          double v[3] = {0, 0, 0};
+          for (int al = 0; al < 3; ++al)
+            for (int a = 0; a < 3; ++a) v[a] += u[al] * g.A[a + 3 * al];
+          maxd = std::max(maxd, std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+        }
+  }
+
+  // sphere classes: the fixed radius or the variable-radius rungs, then (with
+  // self radii) one class of the self pairs with their own PE and ME spheres
+  std::vector<double> radii, me_radii;
+  if (opt.R_PE_nclass > 0) {
+    for (int k = 0; k < opt.R_PE_nclass; ++k) radii.push_back(opt.R_PE_min + k * opt.R_PE_step);
+  } else {
+    radii.push_back(P->R_PE);
+  }
+  const double rmax = *std::max_element(radii.begin(), radii.end());
+  if (P->R_ME < rmax + n * maxd) return fail(P, EXX_EINVAL, "R_ME must be >= R_PE + n * (longest stencil step)");
+  me_radii.assign(radii.size(), P->R_ME);
+  int self_class = -1;
+  if (opt.R_PE_self > 0.0 || opt.R_ME_self > 0.0) {
+    const double rpe = opt.R_PE_self > 0.0 ? opt.R_PE_self : P->R_PE;
+    const double rme = opt.R_ME_self > 0.0 ? opt.R_ME_self : P->R_ME;
+    if (rme < rpe + n * maxd)
+      return fail(P, EXX_EINVAL, "R_ME_self must be >= R_PE_self + n * (longest stencil step)");
+    self_class = (int)radii.size();
+    radii.push_back(rpe);
+    me_radii.push_back(rme);
+  }
+  std::vector<ClassHost> classes(radii.size());
+  const bool all_dirs = opt.cell_fluctuation != 0;
+  if (general) {
+    // sweep axis of the CG: the one whose padded columns hold the fewest
+    // slots (zero padding when it is perpendicular to the other two), then the
+    // fewest arms that leave the sweep plane, then the last axis
+    const size_t big = (size_t)(std::max_element(radii.begin(), radii.end()) - radii.begin());
+    long long best_slots = -1;
+    int best_tilt = 0;
+    for (int sw = 2; sw >= 0; --sw) {
+      ClassHost T;
+      std::string e = build_class_general(h, g.N, sw, radii[big], me_radii[big], n, arms, all_dirs, &T);
+      if (!e.empty()) return fail(P, EXX_EINVAL, e);
+      int tilt = 0;
+      for (const NkArm& A : arms)
+        if (A.u[sw] != 0 && (A.u[(sw + 1) % 3] != 0 || A.u[(sw + 2) % 3] != 0)) ++tilt;
+      if (best_slots < 0 || T.n_pe < best_slots || (T.n_pe == best_slots && tilt < best_tilt)) {
+        best_slots = T.n_pe;
+        best_tilt = tilt;
+        for (int a = 0; a < 3; ++a) g.perm[a] = T.perm[a];
+      }
+    }
+  }
+  long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
+  int max_zmax = 0, maxRc0 = 0, maxRc1 = 0;
+  for (size_t k = 0; k < radii.size(); ++k) {
+    std::string e = general
+                        ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs, &classes[k])
+                        : build_class(g.L, g.N, radii[k], me_radii[k], n, &classes[k]);
+    if (!e.empty()) return fail(P, EXX_EINVAL, e);
+    const ClassHost& C = classes[k];
+    max_pe = std::max(max_pe, C.n_pe);
+    max_halo = std::max(max_halo, C.n_halo);
+    max_me = std::max(max_me, C.n_me);
+    max_cols = std::max<long long>(max_cols, C.n_cols);
+    max_zmax = std::max(max_zmax, C.Zmax);
+    maxRc0 = std::max(maxRc0, C.Rc[0]);
+    maxRc1 = std::max(maxRc1, C.Rc[1]);
+  }
+  g.lds_cx = maxRc0 + n;
+  g.lds_cy = maxRc1 + n;
+  g.lds_wx = kLdsWX;
+  g.lds_wy = 2 * g.lds_cy + 1;
+  if (2 * g.lds_cx + 1 > kLdsWX)
+    return fail(P, EXX_EINVAL, "PE sphere too wide: need 2 (R_PE / spacing + n) + 1 <= 88 grid points");
+  if (!solve_supported((int)std::min<long long>(max_cols, 1 << 30), 512))
+    return fail(P, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");
+  if (solve_lds_bytes(g, max_zmax) > 160 * 1024) return fail(P, EXX_EINVAL, "PE sphere too wide for the LDS plane buffers");
+
+  if (!P->class_block && hipGetDevice(&P->device) != hipSuccess) return fail(P, EXX_EDEVICE, "no HIP device");
+  // upload the class tables into one block
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const bool mixed = opt.precision == EXX_PREC_MIXED;
+  int mom_rows = 0, mom_mfma_rows = 0;
+  moment_layout(P->l_max, mixed, &mom_rows, &mom_mfma_rows);
+  auto mom_bytes = [&](const ClassHost& C) {
+    const size_t entries = (size_t)((C.n_pe + 31) / 32 * 32) * mom_rows;
+    return mixed ? 2 * align(entries * sizeof(unsigned short)) : align(entries * sizeof(double));
+  };
+  size_t total = 0;
+  for (const ClassHost& C : classes) {
+    total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
+             align(C.halo_off.size() * sizeof(short4)) + align(C.me_off.size() * sizeof(short4)) +
+             align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
+             align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) + mom_bytes(C);
+  }
+  void* block = nullptr;
+  ClassDev* class_dev = nullptr;
+  if (hipMalloc(&block, total) != hipSuccess) return fail(P, EXX_ENOMEM, "device allocation of the subdomain tables failed");
+  auto give_up = [&](exx_status st, const char* msg) {
+    (void)hipFree(block);
+    if (class_dev) (void)hipFree(class_dev);
+    return fail(P, st, msg);
+  };
+  char* base = (char*)block;
+  size_t off = 0;
+  // an empty table has no device address (null): kernels tell the general
+  // layout by a non-null pe_map
+  auto put = [&](const void* src, size_t bytes) -> const void* {
+    if (!bytes) return nullptr;
+    void* dst = base + off;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    off += align(bytes);
+    return dst;
+  };
+  std::vector<ClassDev> class_dev_host;
+  for (const ClassHost& C : classes) {
+    ClassDev D;
+    std::memset(&D, 0, sizeof(D));
+    D.R_PE = C.R_PE;
+    D.n_cols = C.n_cols;
+    D.Zmax = C.Zmax;
+    for (int a = 0; a < 3; ++a) {
+      D.Rg[a] = C.Rg[a];
+      D.Wm[a] = C.Wm[a];
+      D.Rc[a] = C.Rc[a];
+    }
+    D.n_pe = C.n_pe;
+    D.n_real = C.n_real;
+    D.n_halo = C.n_halo;
+    D.n_me = C.n_me;
+    D.cols = (const int4*)put(C.cols.data(), C.cols.size() * sizeof(int4));
+    D.plane_start = (const int*)put(C.plane_start.data(), C.plane_start.size() * sizeof(int));
+    D.halo_off = (const short4*)put(C.halo_off.data(), C.halo_off.size() * sizeof(short4));
+    D.me_off = (const short4*)put(C.me_off.data(), C.me_off.size() * sizeof(short4));
+    D.halo_map = (const int*)put(C.halo_map.data(), C.halo_map.size() * sizeof(int));
+    D.col_map = (const int*)put(C.col_map.data(), C.col_map.size() * sizeof(int));
+    D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
+    D.pe_map = general ? (const int*)put(C.pe_map.data(), C.pe_map.size() * sizeof(int)) : nullptr;
+    D.mom_rows = mom_rows;
+    std::vector<double> tab;
+    build_moment_table(C, g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);
+    bool tab_ok;
+    if (mixed) {
+      std::vector<unsigned short> hi(tab.size()), lo(tab.size());
+      for (size_t e = 0; e < tab.size(); ++e) {
+        hi[e] = bf16_rne((float)tab[e]);
+        lo[e] = bf16_rne((float)(tab[e] - bf16_value(hi[e])));
+      }
+      D.mom_hi = (const unsigned short*)put(hi.data(), hi.size() * sizeof(unsigned short));
+      D.mom_lo = (const unsigned short*)put(lo.data(), lo.size() * sizeof(unsigned short));
+      tab_ok = D.mom_hi && D.mom_lo;
+    } else {
+      D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
+      tab_ok = D.mom_f64 != nullptr;
+    }
+    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || (!general && (!D.col_map || !D.zr_map)) ||
+        (general != (D.pe_map != nullptr)) || !tab_ok)
+      return give_up(EXX_EDEVICE, "upload of the subdomain tables failed");
+    class_dev_host.push_back(D);
+  }
+  if (hipMalloc(&class_dev, sizeof(ClassDev) * class_dev_host.size()) != hipSuccess ||
+      hipMemcpy(class_dev, class_dev_host.data(), sizeof(ClassDev) * class_dev_host.size(),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return give_up(EXX_EDEVICE, "upload of the class descriptors failed");
+
+  // commit
+  if (P->class_block) (void)hipFree(P->class_block);
+  if (P->class_dev) (void)hipFree(P->class_dev);
+  P->class_block = block;
+  P->class_dev = class_dev;
+  P->class_dev_host = class_dev_host;
+  P->classes.swap(classes);
+  P->geo = g;
+  P->self_class = self_class;
+  P->max_pe = max_pe;
+  P->rstride = (max_pe + 31) / 32 * 32;
+  P->max_halo = max_halo;
+  P->max_me = max_me;
+  P->max_cols = max_cols;
+  P->max_zmax = max_zmax;
+  std::memcpy(P->h, h, sizeof(P->h));
+  std::memcpy(P->h0, h, sizeof(P->h0));
+  P->cell_strain = 0.0;
+  P->all_dirs = all_dirs;
+  P->arm_dirs.clear();
+  for (const NkArm& A : arms) P->arm_dirs.push_back({A.u[0], A.u[1], A.u[2]});
+  return EXX_OK;
+}
+
+// Default CG variant of each class: 1024 threads up to three columns each,
+// else 512 (1024 x 4 spills); FP64 loads one plane ahead, mixed two, general
+// cells one.
+void default_solve_variants(exx_plan_t P) {
+  const exx_options& opt = P->opt;
+  const int dp = P->geo.gen ? 1 : (opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1));
+  P->class_threads.assign(P->classes.size(), 1024);
+  P->class_depth.assign(P->classes.size(), dp);
+  for (size_t k = 0; k < P->classes.size(); ++k)
+    P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= 3 * 1024 ? 1024 : 512);
+}
+
+// A new cell for the same proto-subdomains (fixed grid offsets, Sec. III B 2):
+// geometry, arms and moment tables.
+exx_status update_cell(exx_plan_t P, const double h[9]) {
+  Geo g = P->geo;
+  const bool general = g.gen != 0;
+  if (!general && off_diagonal(h))
+    return fail(P, EXX_EINVAL, "the plan holds orthorhombic tables (build it with cell_fluctuation for other cells)");
+  set_cell_geometry(g, h, general);
+  if (general) {
+    std::vector<NkArm> arms;
+    std::string e = set_cell_arms(g, h, &arms);
+    if (!e.empty()) return fail(P, EXX_EINVAL, e);
+    if (!P->all_dirs) {
+      // the Dirichlet points cover the arms (and axes) the tables were built for
+      for (const NkArm& A : arms) {
+        const int nz = (A.u[0] != 0) + (A.u[1] != 0) + (A.u[2] != 0);
+        bool known = nz == 1;
+        for (const auto& d : P->arm_dirs)
+          known = known || (d[0] == A.u[0] && d[1] == A.u[1] && d[2] == A.u[2]) ||
+                  (d[0] == -A.u[0] && d[1] == -A.u[1] && d[2] == -A.u[2]);
+        if (!known)
+          return fail(P, EXX_EINVAL, "the new cell's Laplacian needs Dirichlet points the tables do not hold "
+                                     "(build the plan with cell_fluctuation, or re-assemble)");
+      }
+    }
+  }
+  exx_status st = upload_moment_tables(P, g);
+  if (st != EXX_OK) return st;
+  P->geo = g;
+  std::memcpy(P->h, h, sizeof(P->h));
+  P->cell_strain = cell_strain(h, P->h0);
+  return EXX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -398,6 +743,10 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (opt.warm_start != 0 && opt.warm_start != 1) return fail(nullptr, EXX_EINVAL, "warm_start must be 0 or 1");
   if (opt.warm_start && opt.max_pairs <= 0)
     return fail(nullptr, EXX_EINVAL, "warm_start needs a fixed pair capacity (max_pairs > 0)");
+  if (opt.cell_fluctuation != 0 && opt.cell_fluctuation != 1)
+    return fail(nullptr, EXX_EINVAL, "cell_fluctuation must be 0 or 1");
+  if (!(opt.reassemble_strain >= 0.0) || !std::isfinite(opt.reassemble_strain))
+    return fail(nullptr, EXX_EINVAL, "reassemble_strain must be >= 0");
 
   exx_plan_t P = new (std::nothrow) exx_plan_s();
   if (!P) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
@@ -411,230 +760,25 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
 
   Geo& g = P->geo;
   std::memset(&g, 0, sizeof(g));
-  std::memcpy(g.h, h, sizeof(g.h));
-  inv3(h, g.hinv);
-  const int n = opt.stencil_n;
-  double maxd = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    g.L[a] = general ? std::sqrt(h[3 * a] * h[3 * a] + h[1 + 3 * a] * h[1 + 3 * a] + h[2 + 3 * a] * h[2 + 3 * a])
-                     : h[a + 3 * a];
-    g.N[a] = grid[a];
-    g.d[a] = g.L[a] / grid[a];
-    g.inv_d2[a] = 1.0 / (g.d[a] * g.d[a]);
-    g.inv_d[a] = 1.0 / g.d[a];
-    maxd = std::max(maxd, g.d[a]);
-  }
-  for (int a = 0; a < 3; ++a)
-    for (int al = 0; al < 3; ++al) g.A[a + 3 * al] = h[a + 3 * al] / grid[al];
-  g.gen = general ? 1 : 0;
-  for (int a = 0; a < 3; ++a) g.perm[a] = a;
-  std::vector<NkArm> arms;
-  if (general) {
-    std::string e = build_nk_arms(h, grid, &arms);
-    if (!e.empty()) {
-      free_plan(P);
-      return fail(nullptr, EXX_EINVAL, e);
-    }
-    if (arms.size() > 6) {
-      free_plan(P);
-      return fail(nullptr, EXX_EINVAL, "more than six NK arms");
-    }
-    g.n_arms = (int)arms.size();
-    for (size_t k = 0; k < arms.size(); ++k) {
-      for (int a = 0; a < 3; ++a) {
-        g.arm_u[k][a] = arms[k].u[a];
-        if (std::abs(arms[k].u[a]) > 1) {
-          free_plan(P);
-          return fail(nullptr, EXX_EINVAL, "an NK auxiliary direction beyond the first shell of grid neighbours");
-        }
-      }
-      g.arm_coef[k] = arms[k].beta / (arms[k].step * arms[k].step);
-      maxd = std::max(maxd, arms[k].step);
-    }
-  }
-  for (int a = 0; a < 3; ++a)
-    for (int al = 0; al < 3; ++al) g.J[a + 3 * al] = g.L[al] * g.hinv[al + 3 * a];
+  for (int a = 0; a < 3; ++a) g.N[a] = grid[a];
   g.ngrid = (long long)grid[0] * grid[1] * grid[2];
-  g.dV = std::fabs(det3(h)) / (double)g.ngrid;
-  stencil_weights(n, g.w2, g.w1);
-  g.n = n;
+  stencil_weights(opt.stencil_n, g.w2, g.w1);
+  g.n = opt.stencil_n;
   g.l_max = l_max;
   g.n_lm = (l_max + 1) * (l_max + 1);
   harmonic_norms(l_max, g.ylm_norm);
-
-  // sphere classes: the fixed radius or the variable-radius rungs, then (with
-  // self radii) one class of the self pairs with their own PE and ME spheres
-  std::vector<double> radii, me_radii;
-  if (opt.R_PE_nclass > 0) {
-    for (int k = 0; k < opt.R_PE_nclass; ++k) radii.push_back(opt.R_PE_min + k * opt.R_PE_step);
-  } else {
-    radii.push_back(R_PE);
-  }
-  const double rmax = *std::max_element(radii.begin(), radii.end());
-  if (R_ME < rmax + n * maxd) {
+  // general cells run the CG with one plane of loads ahead
+  if ((general || opt.cell_fluctuation) && opt.solve_depth > 1) {
     free_plan(P);
-    return fail(nullptr, EXX_EINVAL, "R_ME must be >= R_PE + n * (longest stencil step)");
+    return fail(nullptr, EXX_EINVAL, "general cells run the CG with solve_depth 1");
   }
-  me_radii.assign(radii.size(), R_ME);
-  P->self_class = -1;
-  if (opt.R_PE_self > 0.0 || opt.R_ME_self > 0.0) {
-    const double rpe = opt.R_PE_self > 0.0 ? opt.R_PE_self : R_PE;
-    const double rme = opt.R_ME_self > 0.0 ? opt.R_ME_self : R_ME;
-    if (rme < rpe + n * maxd) {
+  {
+    exx_status st = assemble_cell(P, h);
+    if (st != EXX_OK) {
+      std::string m = P->err;
       free_plan(P);
-      return fail(nullptr, EXX_EINVAL, "R_ME_self must be >= R_PE_self + n * (longest stencil step)");
+      return fail(nullptr, st, m);
     }
-    P->self_class = (int)radii.size();
-    radii.push_back(rpe);
-    me_radii.push_back(rme);
-  }
-  P->classes.resize(radii.size());
-  int maxRg0 = 0, maxRg1 = 0;
-  if (general) {
-    // sweep axis of the CG: the one whose padded columns hold the fewest
-    // slots (zero padding when it is perpendicular to the other two), then the
-    // fewest arms that leave the sweep plane, then the last axis
-    const size_t big = (size_t)(std::max_element(radii.begin(), radii.end()) - radii.begin());
-    long long best_slots = -1;
-    int best_tilt = 0;
-    for (int sw = 2; sw >= 0; --sw) {
-      ClassHost T;
-      std::string e = build_class_general(h, g.N, sw, radii[big], me_radii[big], n, arms, &T);
-      if (!e.empty()) {
-        free_plan(P);
-        return fail(nullptr, EXX_EINVAL, e);
-      }
-      int tilt = 0;
-      for (const NkArm& A : arms)
-        if (A.u[sw] != 0 && (A.u[(sw + 1) % 3] != 0 || A.u[(sw + 2) % 3] != 0)) ++tilt;
-      if (best_slots < 0 || T.n_pe < best_slots || (T.n_pe == best_slots && tilt < best_tilt)) {
-        best_slots = T.n_pe;
-        best_tilt = tilt;
-        for (int a = 0; a < 3; ++a) g.perm[a] = T.perm[a];
-      }
-    }
-  }
-  for (size_t k = 0; k < radii.size(); ++k) {
-    std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, &P->classes[k])
-                            : build_class(g.L, g.N, radii[k], me_radii[k], n, &P->classes[k]);
-    if (!e.empty()) {
-      free_plan(P);
-      return fail(nullptr, EXX_EINVAL, e);
-    }
-    const ClassHost& C = P->classes[k];
-    P->max_pe = std::max(P->max_pe, C.n_pe);
-    P->rstride = (P->max_pe + 31) / 32 * 32;
-    P->max_halo = std::max(P->max_halo, C.n_halo);
-    P->max_me = std::max(P->max_me, C.n_me);
-    P->max_cols = std::max<long long>(P->max_cols, C.n_cols);
-    P->max_zmax = std::max(P->max_zmax, C.Zmax);
-    maxRg0 = std::max(maxRg0, C.Rc[0]);
-    maxRg1 = std::max(maxRg1, C.Rc[1]);
-  }
-  g.lds_cx = maxRg0 + n;
-  g.lds_cy = maxRg1 + n;
-  g.lds_wx = kLdsWX;
-  g.lds_wy = 2 * g.lds_cy + 1;
-  if (2 * g.lds_cx + 1 > kLdsWX) {
-    free_plan(P);
-    return fail(nullptr, EXX_EINVAL, "PE sphere too wide: need 2 (R_PE / spacing + n) + 1 <= 88 grid points");
-  }
-  if (!solve_supported((int)std::min<long long>(P->max_cols, 1 << 30), 512)) {
-    free_plan(P);
-    return fail(nullptr, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");
-  }
-  if (solve_lds_bytes(g, P->max_zmax) > 160 * 1024) {
-    free_plan(P);
-    return fail(nullptr, EXX_EINVAL, "PE sphere too wide for the LDS plane buffers");
-  }
-
-  if (hipGetDevice(&P->device) != hipSuccess) {
-    free_plan(P);
-    return fail(nullptr, EXX_EDEVICE, "no HIP device");
-  }
-  // upload the class tables into one block
-  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const bool mixed = opt.precision == EXX_PREC_MIXED;
-  int mom_rows = 0, mom_mfma_rows = 0;
-  moment_layout(l_max, mixed, &mom_rows, &mom_mfma_rows);
-  auto mom_bytes = [&](const ClassHost& C) {
-    const size_t entries = (size_t)((C.n_pe + 31) / 32 * 32) * mom_rows;
-    return mixed ? 2 * align(entries * sizeof(unsigned short)) : align(entries * sizeof(double));
-  };
-  size_t total = 0;
-  for (const ClassHost& C : P->classes) {
-    total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
-             align(C.halo_off.size() * sizeof(short4)) + align(C.me_off.size() * sizeof(short4)) +
-             align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
-             align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) + mom_bytes(C);
-  }
-  if (hipMalloc(&P->class_block, total) != hipSuccess) {
-    free_plan(P);
-    return fail(nullptr, EXX_ENOMEM, "device allocation of the subdomain tables failed");
-  }
-  char* base = (char*)P->class_block;
-  size_t off = 0;
-  // an empty table has no device address (null): kernels tell the general
-  // layout by a non-null pe_map
-  auto put = [&](const void* src, size_t bytes) -> const void* {
-    if (!bytes) return nullptr;
-    void* dst = base + off;
-    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
-    off += align(bytes);
-    return dst;
-  };
-  for (const ClassHost& C : P->classes) {
-    ClassDev D;
-    std::memset(&D, 0, sizeof(D));
-    D.R_PE = C.R_PE;
-    D.n_cols = C.n_cols;
-    D.Zmax = C.Zmax;
-    for (int a = 0; a < 3; ++a) {
-      D.Rg[a] = C.Rg[a];
-      D.Wm[a] = C.Wm[a];
-    }
-    D.n_pe = C.n_pe;
-    D.n_real = C.n_real;
-    for (int a = 0; a < 3; ++a) D.Rc[a] = C.Rc[a];
-    D.n_halo = C.n_halo;
-    D.n_me = C.n_me;
-    D.cols = (const int4*)put(C.cols.data(), C.cols.size() * sizeof(int4));
-    D.plane_start = (const int*)put(C.plane_start.data(), C.plane_start.size() * sizeof(int));
-    D.halo_off = (const short4*)put(C.halo_off.data(), C.halo_off.size() * sizeof(short4));
-    D.me_off = (const short4*)put(C.me_off.data(), C.me_off.size() * sizeof(short4));
-    D.halo_map = (const int*)put(C.halo_map.data(), C.halo_map.size() * sizeof(int));
-    D.col_map = (const int*)put(C.col_map.data(), C.col_map.size() * sizeof(int));
-    D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
-    D.pe_map = general ? (const int*)put(C.pe_map.data(), C.pe_map.size() * sizeof(int)) : nullptr;
-    D.mom_rows = mom_rows;
-    std::vector<double> tab;
-    build_moment_table(C, g.A, l_max, mom_rows, mixed ? 8 : 4, &tab);
-    bool tab_ok;
-    if (mixed) {
-      std::vector<unsigned short> hi(tab.size()), lo(tab.size());
-      for (size_t e = 0; e < tab.size(); ++e) {
-        hi[e] = bf16_rne((float)tab[e]);
-        lo[e] = bf16_rne((float)(tab[e] - bf16_value(hi[e])));
-      }
-      D.mom_hi = (const unsigned short*)put(hi.data(), hi.size() * sizeof(unsigned short));
-      D.mom_lo = (const unsigned short*)put(lo.data(), lo.size() * sizeof(unsigned short));
-      tab_ok = D.mom_hi && D.mom_lo;
-    } else {
-      D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
-      tab_ok = D.mom_f64 != nullptr;
-    }
-    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || (!general && (!D.col_map || !D.zr_map)) ||
-        (general != (D.pe_map != nullptr)) || !tab_ok) {
-      free_plan(P);
-      return fail(nullptr, EXX_EDEVICE, "upload of the subdomain tables failed");
-    }
-    P->class_dev_host.push_back(D);
-  }
-  if (hipMalloc(&P->class_dev, sizeof(ClassDev) * P->class_dev_host.size()) != hipSuccess ||
-      hipMemcpy(P->class_dev, P->class_dev_host.data(), sizeof(ClassDev) * P->class_dev_host.size(),
-                hipMemcpyHostToDevice) != hipSuccess) {
-    free_plan(P);
-    return fail(nullptr, EXX_EDEVICE, "upload of the class descriptors failed");
   }
   for (auto& e : P->ev)
     if (hipEventCreate(&e) != hipSuccess) {
@@ -650,17 +794,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   P->n_cus = std::max(1, cus);
   {
     // defaults measured on MI355X: FP64 1024 x 1, mixed 1024 x 2
-    // per class: 1024 threads up to 3 columns each, else 512 (1024 x 4 spills)
-    // general cells: one plane of loads ahead (their instances have no deeper variant)
-    if (general && opt.solve_depth > 1) {
-      free_plan(P);
-      return fail(nullptr, EXX_EINVAL, "general cells run the CG with solve_depth 1");
-    }
-    const int dp = general ? 1 : (opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1));
-    P->class_threads.assign(P->classes.size(), 1024);
-    P->class_depth.assign(P->classes.size(), dp);
-    for (size_t k = 0; k < P->classes.size(); ++k)
-      P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= 3 * 1024 ? 1024 : 512);
+    default_solve_variants(P);
     exx_status st = apply_solve_variants(P);
     if (st != EXX_OK) {
       std::string m = P->err;
@@ -669,6 +803,60 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     }
   }
   *out = P;
+  return EXX_OK;
+}
+
+exx_status exx_set_cell(exx_plan_t P, const double h[9]) {
+  if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
+  if (!h) return fail(P, EXX_EINVAL, "h is NULL");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(h[k])) return fail(P, EXX_EINVAL, "cell tensor is not finite");
+  if (!(det3(h) > 0.0))
+    return fail(P, EXX_EINVAL, "the cell tensor must have a positive determinant (right-handed L_1, L_2, L_3)");
+  int dev = -1;
+  EXX_HIP(P, hipGetDevice(&dev));
+  if (dev != P->device) return fail(P, EXX_EINVAL, "current device differs from the plan's device");
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  EXX_HIP(P, hipStreamIsCapturing(P->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(P, EXX_EINVAL, "exx_set_cell is not capturable");
+  // the tables are rewritten: no evaluation may still read them
+  EXX_HIP(P, hipStreamSynchronize(P->stream));
+  if (P->opt.reassemble_strain > 0.0 && cell_strain(h, P->h0) > P->opt.reassemble_strain) {
+    // re-assembly (Sec. III B 2): new proto-subdomains for h from the plan's radii
+    exx_status st = assemble_cell(P, h);
+    if (st != EXX_OK) return st;
+    // workspaces, CG slots and warm-start stores are sized for the old tables
+    // and are made again by the next eval, which also drops the warm-start
+    // history; graphs need a new eager call
+    P->batch_cap = 0;
+    P->qp_rows = 0;
+    if (P->slot_ws) (void)hipFree(P->slot_ws);
+    P->slot_ws = nullptr;
+    P->warm_cap = 0;
+    P->warm_orb = 0;
+    P->tuned = false;
+    default_solve_variants(P);
+    st = apply_solve_variants(P);
+    if (st != EXX_OK) return st;
+    P->reassemblies++;
+    return EXX_OK;
+  }
+  return update_cell(P, h);
+}
+
+exx_status exx_pressure(const double h[9], const double sigma[9], double* Pi, double* p_int) {
+  if (!h || !sigma) return fail(nullptr, EXX_EINVAL, "h or sigma is NULL");
+  const double V = std::fabs(det3(h));
+  if (!(V > 0.0) || !std::isfinite(V)) return fail(nullptr, EXX_EINVAL, "singular cell");
+  double T[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0.0;
+      for (int al = 0; al < 3; ++al) s += sigma[a + 3 * al] * h[b + 3 * al];
+      T[a + 3 * b] = -s / V;   // eq. pixx_working
+    }
+  if (Pi) std::memcpy(Pi, T, sizeof(T));
+  if (p_int) *p_int = (T[0] + T[4] + T[8]) / 3.0;   // eq. pxx_working
   return EXX_OK;
 }
 
@@ -1013,6 +1201,9 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->solve_ms_total = P->solve_ms_total;
   out->cg_alg_bytes_total = P->alg_bytes_total;
   out->eval_ms_total = P->eval_ms_total;
+  out->cell_strain = P->cell_strain;
+  out->reassemblies = P->reassemblies;
+  out->n_arms = P->geo.gen ? P->geo.n_arms : 3;
   out->solve_threads = P->solve_threads;
   out->solve_depth = P->solve_depth;
   out->tune_ms = P->tune_ms;
@@ -1056,7 +1247,7 @@ exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_P
     if (!(det3(h) > 0.0)) return fail(nullptr, EXX_EINVAL, "the cell tensor must have a positive determinant");
     std::vector<NkArm> arms;
     e = build_nk_arms(h, N, &arms);
-    if (e.empty()) e = build_class_general(h, N, 2, R_PE, R_ME, stencil_n, arms, &C);
+    if (e.empty()) e = build_class_general(h, N, 2, R_PE, R_ME, stencil_n, arms, false, &C);
   } else {
     e = build_class(L, N, R_PE, R_ME, stencil_n, &C);
   }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -116,8 +117,10 @@ struct ClassHost {
 std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out);
 // The same for a general cell h with the NK arms of its Laplacian; the CG
 // sweeps along grid axis `sweep`.
+// all_dirs: Dirichlet points along every nearest-neighbour direction (for
+// cells that may change later), else along the arms and the lattice axes.
 std::string build_class_general(const double h[9], const int N[3], int sweep, double R_PE, double R_ME, int n,
-                                const std::vector<NkArm>& arms, ClassHost* out);
+                                const std::vector<NkArm>& arms, bool all_dirs, ClassHost* out);
 // The NK Laplacian of cell h on grid N (Algorithm 1 and eq. lapG_mod_nk3d).
 std::string build_nk_arms(const double h[9], const int N[3], std::vector<NkArm>* arms);
 // Unnormalised solid harmonics P_lm(A o) of the class's PE points, laid out
@@ -130,7 +133,12 @@ void build_moment_table(const ClassHost& C, const double A[9], int l_max, int ro
 
 struct exx_plan_s {
   exx_options opt;
-  double h[9];
+  double h[9];        // the current cell
+  double h0[9];       // the cell the proto-subdomain tables were built for
+  double cell_strain = 0.0;   // max |h h0^-1 - I|
+  int reassemblies = 0;
+  bool all_dirs = false;      // Dirichlet points along every nearest-neighbour direction
+  std::vector<std::array<int, 3>> arm_dirs;   // arms the tables were built for (general layout)
   int grid[3];
   double R_pair, R_PE, R_ME;
   int l_max;

@@ -207,7 +207,7 @@ void sphere_box(const double h[9], const int N[3], double R, int K[3]) {
 }  // namespace
 
 std::string build_class_general(const double h[9], const int N[3], int sweep, double R_PE, double R_ME, int n,
-                                const std::vector<NkArm>& arms, ClassHost* out) {
+                                const std::vector<NkArm>& arms, bool all_dirs, ClassHost* out) {
   ClassHost& C = *out;
   C = ClassHost();
   C.R_PE = R_PE;
@@ -324,11 +324,18 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
   // a Laplacian arm or along a lattice axis (the first-derivative stencil of
   // sigma)
   std::vector<std::array<int, 3>> dirs;
-  for (const NkArm& A : arms) dirs.push_back({A.u[0], A.u[1], A.u[2]});
-  for (int a = 0; a < 3; ++a) {
-    std::array<int, 3> e{0, 0, 0};
-    e[a] = 1;
-    if (std::find(dirs.begin(), dirs.end(), e) == dirs.end()) dirs.push_back(e);
+  if (all_dirs) {
+    for (int u2 = -1; u2 <= 1; ++u2)
+      for (int u1 = -1; u1 <= 1; ++u1)
+        for (int u0 = -1; u0 <= 1; ++u0)
+          if (u0 || u1 || u2) dirs.push_back({u0, u1, u2});
+  } else {
+    for (const NkArm& A : arms) dirs.push_back({A.u[0], A.u[1], A.u[2]});
+    for (int a = 0; a < 3; ++a) {
+      std::array<int, 3> e{0, 0, 0};
+      e[a] = 1;
+      if (std::find(dirs.begin(), dirs.end(), e) == dirs.end()) dirs.push_back(e);
+    }
   }
   C.halo_map.assign((size_t)W0 * W1 * W2, -1);
   for (int o2 = -c2; o2 <= c2; ++o2)

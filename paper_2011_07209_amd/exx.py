@@ -48,6 +48,8 @@ class Options(ctypes.Structure):
         ("warm_start", ctypes.c_int),
         ("R_PE_self", ctypes.c_double),
         ("R_ME_self", ctypes.c_double),
+        ("cell_fluctuation", ctypes.c_int),
+        ("reassemble_strain", ctypes.c_double),
     ]
 
 
@@ -77,6 +79,9 @@ class Stats(ctypes.Structure):
         ("pairs_kept", ctypes.c_longlong),
         ("graph_recorded", ctypes.c_int),
         ("warm_pairs", ctypes.c_longlong),
+        ("cell_strain", ctypes.c_double),
+        ("reassemblies", ctypes.c_int),
+        ("n_arms", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -84,8 +89,8 @@ class Stats(ctypes.Structure):
 
 
 SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_count_pairs", "exx_pair_results",
-           "exx_stats_fetch", "exx_plan_geometry", "exx_subdomain_counts", "exx_nk_stencil", "exx_destroy",
-           "exx_last_error"]
+           "exx_stats_fetch", "exx_plan_geometry", "exx_subdomain_counts", "exx_nk_stencil", "exx_set_cell",
+           "exx_pressure", "exx_destroy", "exx_last_error"]
 
 _lib = None
 
@@ -121,6 +126,10 @@ def load():
     lib.exx_subdomain_counts.argtypes = [dp, ip, ctypes.c_double, ctypes.c_double, ctypes.c_int, llp, llp, llp]
     lib.exx_nk_stencil.restype = ctypes.c_int
     lib.exx_nk_stencil.argtypes = [dp, ip, ip, ip, dp, dp]
+    lib.exx_set_cell.restype = ctypes.c_int
+    lib.exx_set_cell.argtypes = [vp, dp]
+    lib.exx_pressure.restype = ctypes.c_int
+    lib.exx_pressure.argtypes = [dp, dp, dp, dp]
     lib.exx_destroy.restype = ctypes.c_int
     lib.exx_destroy.argtypes = [vp]
     lib.exx_last_error.restype = ctypes.c_char_p
@@ -277,6 +286,26 @@ def exx_nk_stencil(h, grid):
             "step": np.array(list(step))[:k]}
 
 
+def _h9(h):
+    import numpy as np
+    hv = np.asarray(h, dtype=np.float64)
+    hv = hv.flatten(order="F") if hv.shape == (3, 3) else hv.reshape(9)
+    return (ctypes.c_double * 9)(*hv.tolist())
+
+
+def exx_set_cell(plan, h):
+    _check(load().exx_set_cell(plan, _h9(h)), plan)
+
+
+def exx_pressure(h, sigma):
+    """(Pi (3x3, [a, b]), p_int) from sigma (3x3 [a, al]) and the cell h."""
+    import numpy as np
+    Pi = (ctypes.c_double * 9)()
+    p = ctypes.c_double()
+    _check(load().exx_pressure(_h9(h), _h9(sigma), Pi, ctypes.byref(p)), None)
+    return np.array(list(Pi)).reshape(3, 3, order="F"), p.value
+
+
 def exx_destroy(plan):
     if plan:
         _check(load().exx_destroy(plan), None)
@@ -309,6 +338,9 @@ class Plan:
 
     def stats(self, allow_noconv=False, allow_capacity=False):
         return exx_stats_fetch(self.handle, allow_noconv, allow_capacity)
+
+    def set_cell(self, h):
+        exx_set_cell(self.handle, h)
 
     def geometry(self, cls=0):
         return exx_plan_geometry(self.handle, cls)

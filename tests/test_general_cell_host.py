@@ -69,3 +69,31 @@ def test_library_general_subdomains_match_the_oracle(name):
                         max(0, -dx):pe.shape[2] + min(0, -dx)] = src
                 reach |= shifted
     assert lib["n_halo"] == int((reach & ~pe).sum())
+
+
+def test_pressure_tensor_isotropic_closed_form():
+    """For pure Gaussian densities sigma = -(E/3) h^-T in any cell (the
+    closed form the oracle pins), so eq. pixx_working gives Pi = E/(3V) I and
+    eq. pxx_working p_int = E/(3V) (eq. liq_press in the cubic case)."""
+    for name in ("triclinic", "hexagonal", "orthorhombic"):
+        h, _ = CELLS[name]
+        E = -3.7
+        sigma = -(E / 3.0) * np.linalg.inv(h).T
+        Pi, p = exx.exx_pressure(h, sigma)
+        V = abs(np.linalg.det(h))
+        np.testing.assert_allclose(Pi, E / (3 * V) * np.eye(3), rtol=0, atol=1e-14 * abs(E / V))
+        assert abs(p - E / (3 * V)) <= 1e-14 * abs(E / V)
+
+
+def test_pressure_tensor_components():
+    """Pi_ab = -(1/V) sum_al sigma^{a al} h_{b al}, written out by components."""
+    rng = np.random.default_rng(3)
+    h, _ = CELLS["triclinic"]
+    sigma = rng.normal(size=(3, 3))
+    Pi, p = exx.exx_pressure(h, sigma)
+    V = abs(np.linalg.det(h))
+    for a in range(3):
+        for b in range(3):
+            want = -sum(sigma[a, al] * h[b, al] for al in range(3)) / V
+            assert abs(Pi[a, b] - want) <= 1e-14 * abs(sigma).max() * abs(h).max() / V
+    assert abs(p - np.trace(Pi) / 3) <= 1e-15 * abs(Pi).max()
