@@ -63,9 +63,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str, precision: str):
+def stored_traffic(workload: str, precision: str, threads: int, depth: int):
     """HBM bytes per solve launch from the committed counter runs, or None when
-    the kernels changed since they were taken."""
+    the kernels changed since they were taken or the run used another CG
+    variant (workgroup size, load depth) than the one measured."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -73,6 +74,9 @@ def stored_traffic(workload: str, precision: str):
         return None
     e = d.get(f"{workload}/{precision}")
     if not e or e.get("kernel_hash") != kernel_hash():
+        return None
+    args = [a.strip() for a in e.get("kernel", "").split("<", 1)[-1].rstrip(">").split(",")]
+    if len(args) < 4 or args[2] != str(threads) or args[3] != str(depth):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -196,7 +200,8 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
         achieved = (alg / max(launches, 1)) / (solve_ms / max(launches, 1) / 1000.0) / 1e9 if solve_ms > 0 else 0.0
         cg = {"bound": "hbm", "kernel": "k_solve_mixed" if precision == "mixed" else "k_solve",
               "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-              "traffic": stored_traffic(cfg.key, precision), "alg_bytes_per_launch": alg / max(launches, 1),
+              "traffic": stored_traffic(cfg.key, precision, s_last["solve_threads"], s_last["solve_depth"]),
+              "alg_bytes_per_launch": alg / max(launches, 1),
               "launch_ms": solve_ms / max(launches, 1)}
     print(f"[bench] {cfg.key} {precision} timed {steps} steps: {ms:.1f} ms/step E={E.item():.10f}", file=sys.stderr,
           flush=True)

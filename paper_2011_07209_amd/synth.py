@@ -287,23 +287,23 @@ def fill_orbitals_device(cfg: Config, orbs: OrbitalSet, device, dtype=None, out=
     if out is None:
         out = torch.empty((len(idx), N3, N2, N1), dtype=dtype, device=device)
     if cfg.general:
-        # general cell: the fill_orbital_cell formula, one plane at a time
+        # general cell: the fill_orbital_cell formula over the whole grid at once
         h = torch.tensor(cfg.h, dtype=torch.float64, device=device)
         hinv = torch.linalg.inv(h)
         dVg = cfg.dV
-        g2, g1 = torch.meshgrid(torch.arange(N2, dtype=torch.float64, device=device) / N2,
-                                torch.arange(N1, dtype=torch.float64, device=device) / N1, indexing="ij")
+        g3, g2, g1 = torch.meshgrid(torch.arange(N3, dtype=torch.float64, device=device) / N3,
+                                    torch.arange(N2, dtype=torch.float64, device=device) / N2,
+                                    torch.arange(N1, dtype=torch.float64, device=device) / N1, indexing="ij")
+        r0 = torch.stack([g1, g2, g3], -1).reshape(-1, 3) @ h.T   # grid point positions, x fastest
+        del g1, g2, g3
         for k, i in enumerate(idx):
             c = torch.tensor(orbs.centres[i], dtype=torch.float64, device=device)
             pc = torch.tensor(orbs.poly[i], dtype=torch.float64, device=device)
             a = float(orbs.expo[i])
-            phi = torch.empty((N3, N2, N1), dtype=torch.float64, device=device)
-            for z in range(N3):
-                fr = torch.stack([g1, g2, torch.full_like(g1, z / N3)], -1).reshape(-1, 3)
-                s = (fr @ h.T - c) @ hinv.T
-                s = s - torch.floor(s + 0.5)
-                d = s @ h.T
-                phi[z] = (torch.exp(-a * (d * d).sum(1)) * (1.0 + d @ pc)).reshape(N2, N1)
+            s = (r0 - c) @ hinv.T
+            s -= torch.floor(s + 0.5)
+            d = s @ h.T
+            phi = (torch.exp(-a * (d * d).sum(1)) * (1.0 + d @ pc)).reshape(N3, N2, N1)
             phi *= 1.0 / math.sqrt(dVg * float(torch.dot(phi.reshape(-1), phi.reshape(-1)).item()))
             out[k].copy_(phi)
         return out
