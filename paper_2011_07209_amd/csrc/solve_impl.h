@@ -743,6 +743,202 @@ __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG
   return sum;
 }
 
+// ---------------------------------------------------------------------------
+// General cells with arms leaving the sweep plane.  Every arm, the z' axis
+// included, is applied by scattering the staged plane z' into acc[k], the
+// Laplacian partial sums of the column's points at z' - n + k; the point at
+// z' - n is complete after plane z'.  Besides acc, a column keeps p of its last
+// n + 1 planes and loads one plane ahead, so a thread holds about 2.5 (2n + 1)
+// values per column instead of the 2n + 1 window plus the 2n + 1 sums.
+
+template <int NS, typename T>
+__device__ __forceinline__ void tl_scatter(const GenStencilT<T>& S, T v, bool point, const T* pl, int pos, T* acc) {
+  if (point) {   // the point (column, z') exists: centre and in-plane arms
+    T s = S.diag * v;
+    for (int k = 0; k < S.n_in; ++k) {
+      const int off = S.in_off[k];
+      T t = 0;
+#pragma unroll
+      for (int q = 1; q <= NS; ++q) t += S.w[q] * (pl[pos + q * off] + pl[pos - q * off]);
+      s += S.in_coef[k] * t;
+    }
+    acc[NS] += s;
+  }
+  // z' arm: v is the +q neighbour of the point q planes down, the -q
+  // neighbour of the point q planes up
+#pragma unroll
+  for (int q = 1; q <= NS; ++q) {
+    const T t = S.cz * S.w[q] * v;
+    acc[NS - q] += t;
+    acc[NS + q] += t;
+  }
+  gen_tilted<NS, NS, T>(S, pl, pos, acc);
+}
+
+template <int NS, int CPT, typename T>
+__device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
+                             const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
+                             double& pq, double& rr) {
+  T pd[CPT][NS + 1];       // p of planes z - n .. z
+  T acc[CPT][2 * NS + 1];
+  T cr[CPT], cp[CPT];      // r and the previous p of plane z
+  pq = 0.0;
+  rr = 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+    for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0;
+#pragma unroll
+    for (int k = 0; k < NS + 1; ++k) pd[c][k] = 0;
+    cr[c] = 0;
+    cp[c] = 0;
+    if (EXX_GVALID(c, -Zmax)) {
+      const int idx = EXX_GIDX(c, -Zmax);
+      cr[c] = r[idx];
+      if (!first) cp[c] = p[idx];
+    }
+  }
+  for (int z = -Zmax; z <= Zmax + NS; ++z) {
+    T nr[CPT], np[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nr[c] = 0;
+      np[c] = 0;
+      if (EXX_GVALID(c, z + 1)) {
+        const int idx = EXX_GIDX(c, z + 1);
+        nr[c] = r[idx];
+        if (!first) np[c] = p[idx];
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      T v = 0;
+      if (EXX_GVALID(c, z)) {
+        v = first ? cr[c] : cr[c] + beta * cp[c];
+        p[EXX_GIDX(c, z)] = v;
+        rr += (double)cr[c] * (double)cr[c];
+      }
+      pd[c][NS] = v;
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = v;
+    }
+    __syncthreads();
+    const int zo = z - NS;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_GHAS(c)) tl_scatter<NS, T>(S, pd[c][NS], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) pq -= (double)pd[c][0] * (double)acc[c][0];
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * NS] = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) pd[c][k] = pd[c][k + 1];
+      cr[c] = nr[c];
+      cp[c] = np[c];
+    }
+  }
+}
+
+template <int NS, int CPT, typename T>
+__device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax, T* x,
+                               const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+  T pd[CPT][NS + 1];
+  T acc[CPT][2 * NS + 1];
+  T cp[CPT];               // p of plane z
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+    for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0;
+#pragma unroll
+    for (int k = 0; k < NS + 1; ++k) pd[c][k] = 0;
+    cp[c] = EXX_GVALID(c, -Zmax) ? p[EXX_GIDX(c, -Zmax)] : (T)0;
+  }
+  double sum = 0.0;
+  for (int z = -Zmax; z <= Zmax + NS; ++z) {
+    const int zo = z - NS;
+    T np[CPT], ox[CPT], orr[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      np[c] = EXX_GVALID(c, z + 1) ? p[EXX_GIDX(c, z + 1)] : (T)0;
+      ox[c] = 0;
+      orr[c] = 0;
+      if (EXX_GVALID(c, zo)) {   // read before the same thread writes them below
+        const int idx = EXX_GIDX(c, zo);
+        orr[c] = r_in[idx];
+        if (!x_zero) ox[c] = x[idx];
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      pd[c][NS] = cp[c];
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = cp[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_GHAS(c)) tl_scatter<NS, T>(S, pd[c][NS], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) {
+        const int idx = EXX_GIDX(c, zo);
+        const T rn = orr[c] + alpha * acc[c][0];   // r - alpha A p, A p = -acc
+        x[idx] = ox[c] + alpha * pd[c][0];
+        r[idx] = rn;
+        sum += (double)rn * (double)rn;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * NS] = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) pd[c][k] = pd[c][k + 1];
+      cp[c] = np[c];
+    }
+  }
+  return sum;
+}
+
+template <int NS, int CPT, typename TR>
+__device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
+                                      const double* __restrict__ x, const double* __restrict__ b,
+                                      TR* __restrict__ r, double rs, double* pl0, double* pl1) {
+  double acc[CPT][2 * NS + 1];
+  double cx[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+    for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0.0;
+    cx[c] = EXX_GVALID(c, -Zmax) ? x[EXX_GIDX(c, -Zmax)] : 0.0;
+  }
+  double sum = 0.0;
+  for (int z = -Zmax; z <= Zmax + NS; ++z) {
+    const int zo = z - NS;
+    double nx[CPT], ob[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nx[c] = EXX_GVALID(c, z + 1) ? x[EXX_GIDX(c, z + 1)] : 0.0;
+      ob[c] = EXX_GVALID(c, zo) ? b[EXX_GIDX(c, zo)] : 0.0;
+    }
+    double* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = cx[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (EXX_GHAS(c)) tl_scatter<NS, double>(S, cx[c], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) {
+        const double rt = ob[c] + acc[c][0];   // b - A x, A x = -acc
+        r[EXX_GIDX(c, zo)] = (TR)(rt * rs);
+        sum += rt * rt;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * NS] = 0.0;
+      cx[c] = nx[c];
+    }
+  }
+  return sum;
+}
+
 #undef EXX_GVALID
 #undef EXX_GHAS
 #undef EXX_GIDX
@@ -761,8 +957,10 @@ template <int NS, int CPT, int PD, bool GEN, bool TL, typename T>
 __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T>& G, const ColsOf<GEN, CPT>& cl,
                                        const int* pst, int Zmax, const T* r, T* p, T beta, bool first, T* pl0,
                                        T* pl1, double& pq, double& rr) {
-  if constexpr (GEN)
-    cg_pass_a_gen<NS, CPT, PD, TL, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+  if constexpr (GEN && TL)
+    cg_pass_a_tl<NS, CPT, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+  else if constexpr (GEN)
+    cg_pass_a_gen<NS, CPT, PD, false, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else
     cg_pass_a<NS, CPT, PD, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
 }
@@ -771,8 +969,10 @@ template <int NS, int CPT, int PD, bool GEN, bool TL, typename T>
 __device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT<T>& G, const ColsOf<GEN, CPT>& cl,
                                          const int* pst, int Zmax, T* x, const T* r_in, T* r, const T* p, T alpha,
                                          bool x_zero, T* pl0, T* pl1) {
-  if constexpr (GEN)
-    return cg_pass_b_gen<NS, CPT, PD, TL, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+  if constexpr (GEN && TL)
+    return cg_pass_b_tl<NS, CPT, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+  else if constexpr (GEN)
+    return cg_pass_b_gen<NS, CPT, PD, false, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
   else
     return cg_pass_b<NS, CPT, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
 }
@@ -781,8 +981,10 @@ template <int NS, int CPT, bool GEN, bool TL, typename TR>
 __device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsOf<GEN, CPT>& cl, const int* pst,
                                                 int Zmax, const double* x, const double* b, TR* r, double rs,
                                                 double* pl0, double* pl1) {
-  if constexpr (GEN)
-    return cg_true_residual_gen<NS, CPT, TL, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+  if constexpr (GEN && TL)
+    return cg_true_residual_tl<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+  else if constexpr (GEN)
+    return cg_true_residual_gen<NS, CPT, false, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else
     return cg_true_residual<NS, CPT, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
 }
