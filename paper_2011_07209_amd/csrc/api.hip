@@ -644,11 +644,11 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
 }
 
 // Default CG variant of each class: 1024 threads up to three columns each,
-// else 512 (1024 x 4 spills); FP64 loads one plane ahead, mixed two, general
-// cells one.
+// else 512 (1024 x 4 spills); FP64 loads one plane ahead, mixed two (cells
+// with arms leaving the sweep plane always load one ahead).
 void default_solve_variants(exx_plan_t P) {
   const exx_options& opt = P->opt;
-  const int dp = P->geo.gen ? 1 : (opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1));
+  const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
   P->class_threads.assign(P->classes.size(), 1024);
   P->class_depth.assign(P->classes.size(), dp);
   for (size_t k = 0; k < P->classes.size(); ++k)
@@ -767,11 +767,6 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   g.l_max = l_max;
   g.n_lm = (l_max + 1) * (l_max + 1);
   harmonic_norms(l_max, g.ylm_norm);
-  // general cells run the CG with one plane of loads ahead
-  if ((general || opt.cell_fluctuation) && opt.solve_depth > 1) {
-    free_plan(P);
-    return fail(nullptr, EXX_EINVAL, "general cells run the CG with solve_depth 1");
-  }
   {
     exx_status st = assemble_cell(P, h);
     if (st != EXX_OK) {

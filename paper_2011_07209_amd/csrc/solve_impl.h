@@ -484,7 +484,7 @@ __device__ __forceinline__ T gen_inplane(const GenStencilT<T>& S, T ctr, const T
 
 // Arms leaving the plane: plane z' is the +q neighbour of the column's point
 // at z' - q and the -q neighbour of its point at z' + q.  acc[k] holds the
-// partial sum of the point at z' - DL + k.
+// partial sum of the point at z' - DL + k (DL = n).
 template <int NS, int DL, typename T>
 __device__ __forceinline__ void gen_tilted(const GenStencilT<T>& S, const T* pl, int pos, T* acc) {
   if constexpr (DL > 0) {
@@ -500,22 +500,16 @@ __device__ __forceinline__ void gen_tilted(const GenStencilT<T>& S, const T* pl,
   }
 }
 
-// Pass A (general cell): as cg_pass_a; q = A p of plane z' is complete DL
-// planes after z' (DL = n when some arm leaves the plane, else 0).
-template <int NS, int CPT, int PD, bool TL, typename T>
+// Pass A (general cell, every arm inside the sweep plane or along z'): as
+// cg_pass_a, with the in-plane arms at runtime LDS offsets.
+template <int NS, int CPT, int PD, typename T>
 __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
                               const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
                               double& pq, double& rr) {
-  constexpr int DL = TL ? NS : 0;
   T win[CPT][2 * NS + 1];
-  T acc[CPT][2 * DL + 1];
   T qr[PD][CPT], qp[PD][CPT];
   pq = 0.0;
   rr = 0.0;
-#pragma unroll
-  for (int c = 0; c < CPT; ++c)
-#pragma unroll
-    for (int k = 0; k < 2 * DL + 1; ++k) acc[c][k] = 0;
 #pragma unroll
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
@@ -546,7 +540,7 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
       }
     }
   }
-  for (int z = -Zmax; z <= Zmax + DL; ++z) {
+  for (int z = -Zmax; z <= Zmax; ++z) {
     const int zl = z + NS + PD + 1;
     T nr[CPT], np[CPT];
 #pragma unroll
@@ -564,16 +558,10 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
     for (int c = 0; c < CPT; ++c)
       if (EXX_GHAS(c)) pl[cl.pos[c]] = win[c][NS];
     __syncthreads();
-    const int zo = z - DL;   // plane whose A p completes now
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (EXX_GVALID(c, z)) acc[c][DL] += gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
-      if (EXX_GHAS(c)) gen_tilted<NS, DL, T>(S, pl, cl.pos[c], acc[c]);
-      if (EXX_GVALID(c, zo)) pq -= (double)win[c][NS - DL] * (double)acc[c][0];
-#pragma unroll
-      for (int k = 0; k < 2 * DL; ++k) acc[c][k] = acc[c][k + 1];
-      acc[c][2 * DL] = 0;
-    }
+    for (int c = 0; c < CPT; ++c)
+      if (EXX_GVALID(c, z))
+        pq -= (double)win[c][NS] * (double)gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
     const int zc = z + NS + 1;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -597,21 +585,15 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
   }
 }
 
-// Pass B (general cell): as cg_pass_b, with the update of plane z' made DL
-// planes later, when its A p is complete.  Each point's r_in and x are still
-// read (one step ahead of its update) before the same thread writes them.
-template <int NS, int CPT, int PD, bool TL, typename T>
+// Pass B (general cell, in-plane arms): as cg_pass_b; the plane's x and r
+// are loaded in the step that updates them (ahead of the barrier), which
+// keeps two fewer values per column live across steps.  Each point's r_in and
+// x are read before the same thread writes them.
+template <int NS, int CPT, int PD, typename T>
 __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax, T* x,
                                 const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
-  constexpr int DL = TL ? NS : 0;
   T win[CPT][2 * NS + 1];
-  T acc[CPT][2 * DL + 1];
   T qp[PD][CPT];
-  T cx[CPT], cr[CPT];      // x, r of the plane updated in this step (z - DL)
-#pragma unroll
-  for (int c = 0; c < CPT; ++c)
-#pragma unroll
-    for (int k = 0; k < 2 * DL + 1; ++k) acc[c][k] = 0;
 #pragma unroll
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
@@ -624,31 +606,19 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
 #pragma unroll
     for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_GVALID(c, zz) ? p[EXX_GIDX(c, zz)] : (T)0;
   }
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    cx[c] = 0;
-    cr[c] = 0;
-    const int z0 = -Zmax - DL;
-    if (EXX_GVALID(c, z0)) {
-      const int idx = EXX_GIDX(c, z0);
-      cr[c] = r_in[idx];
-      if (!x_zero) cx[c] = x[idx];
-    }
-  }
   double sum = 0.0;
-  for (int z = -Zmax; z <= Zmax + DL; ++z) {
+  for (int z = -Zmax; z <= Zmax; ++z) {
     const int zl = z + NS + PD + 1;
-    const int zn = z - DL + 1;   // plane updated in the next step
-    T np[CPT], nx[CPT], nr[CPT];
+    T np[CPT], ox[CPT], orr[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       np[c] = EXX_GVALID(c, zl) ? p[EXX_GIDX(c, zl)] : (T)0;
-      nx[c] = 0;
-      nr[c] = 0;
-      if (EXX_GVALID(c, zn)) {
-        const int idx = EXX_GIDX(c, zn);
-        nr[c] = r_in[idx];
-        if (!x_zero) nx[c] = x[idx];
+      ox[c] = 0;
+      orr[c] = 0;
+      if (EXX_GVALID(c, z)) {
+        const int idx = EXX_GIDX(c, z);
+        orr[c] = r_in[idx];
+        if (!x_zero) ox[c] = x[idx];
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -656,21 +626,16 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
     for (int c = 0; c < CPT; ++c)
       if (EXX_GHAS(c)) pl[cl.pos[c]] = win[c][NS];
     __syncthreads();
-    const int zo = z - DL;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      if (EXX_GVALID(c, z)) acc[c][DL] += gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
-      if (EXX_GHAS(c)) gen_tilted<NS, DL, T>(S, pl, cl.pos[c], acc[c]);
-      if (EXX_GVALID(c, zo)) {
-        const int idx = EXX_GIDX(c, zo);
-        const T rn = cr[c] + alpha * acc[c][0];   // r - alpha A p, A p = -acc
-        x[idx] = cx[c] + alpha * win[c][NS - DL];
+      if (EXX_GVALID(c, z)) {
+        const int idx = EXX_GIDX(c, z);
+        const T lap = gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
+        const T rn = orr[c] + alpha * lap;   // r - alpha A p, A p = -lap
+        x[idx] = ox[c] + alpha * win[c][NS];
         r[idx] = rn;
         sum += (double)rn * (double)rn;
       }
-#pragma unroll
-      for (int k = 0; k < 2 * DL; ++k) acc[c][k] = acc[c][k + 1];
-      acc[c][2 * DL] = 0;
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -680,25 +645,18 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
 #pragma unroll
       for (int d = 0; d + 1 < PD; ++d) qp[d][c] = qp[d + 1][c];
       qp[PD - 1][c] = np[c];
-      cx[c] = nx[c];
-      cr[c] = nr[c];
     }
   }
   return sum;
 }
 
-// FP64 true residual b - A x of a general cell (see cg_true_residual).
-template <int NS, int CPT, bool TL, typename TR>
+// FP64 true residual b - A x of a general cell with in-plane arms (see
+// cg_true_residual).
+template <int NS, int CPT, typename TR>
 __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
                                        const double* __restrict__ x, const double* __restrict__ b,
                                        TR* __restrict__ r, double rs, double* pl0, double* pl1) {
-  constexpr int DL = TL ? NS : 0;
   double win[CPT][2 * NS + 1];
-  double acc[CPT][2 * DL + 1];
-#pragma unroll
-  for (int c = 0; c < CPT; ++c)
-#pragma unroll
-    for (int k = 0; k < 2 * DL + 1; ++k) acc[c][k] = 0.0;
 #pragma unroll
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
@@ -706,14 +664,13 @@ __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG
     for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? x[EXX_GIDX(c, zz)] : 0.0;
   }
   double sum = 0.0;
-  for (int z = -Zmax; z <= Zmax + DL; ++z) {
+  for (int z = -Zmax; z <= Zmax; ++z) {
     const int zc = z + NS + 1;
-    const int zo = z - DL;
     double nx[CPT], cb[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       nx[c] = EXX_GVALID(c, zc) ? x[EXX_GIDX(c, zc)] : 0.0;
-      cb[c] = EXX_GVALID(c, zo) ? b[EXX_GIDX(c, zo)] : 0.0;
+      cb[c] = EXX_GVALID(c, z) ? b[EXX_GIDX(c, z)] : 0.0;
     }
     double* pl = (z & 1) ? pl1 : pl0;
 #pragma unroll
@@ -722,16 +679,11 @@ __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      if (EXX_GVALID(c, z)) acc[c][DL] += gen_inplane<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
-      if (EXX_GHAS(c)) gen_tilted<NS, DL, double>(S, pl, cl.pos[c], acc[c]);
-      if (EXX_GVALID(c, zo)) {
-        const double rt = cb[c] + acc[c][0];   // b - A x, A x = -acc
-        r[EXX_GIDX(c, zo)] = (TR)(rt * rs);
+      if (EXX_GVALID(c, z)) {
+        const double rt = cb[c] + gen_inplane<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
+        r[EXX_GIDX(c, z)] = (TR)(rt * rs);
         sum += rt * rt;
       }
-#pragma unroll
-      for (int k = 0; k < 2 * DL; ++k) acc[c][k] = acc[c][k + 1];
-      acc[c][2 * DL] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -960,7 +912,7 @@ __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T
   if constexpr (GEN && TL)
     cg_pass_a_tl<NS, CPT, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else if constexpr (GEN)
-    cg_pass_a_gen<NS, CPT, PD, false, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+    cg_pass_a_gen<NS, CPT, PD, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else
     cg_pass_a<NS, CPT, PD, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
 }
@@ -972,7 +924,7 @@ __device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT
   if constexpr (GEN && TL)
     return cg_pass_b_tl<NS, CPT, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
   else if constexpr (GEN)
-    return cg_pass_b_gen<NS, CPT, PD, false, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+    return cg_pass_b_gen<NS, CPT, PD, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
   else
     return cg_pass_b<NS, CPT, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
 }
@@ -984,7 +936,7 @@ __device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsO
   if constexpr (GEN && TL)
     return cg_true_residual_tl<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else if constexpr (GEN)
-    return cg_true_residual_gen<NS, CPT, false, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+    return cg_true_residual_gen<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else
     return cg_true_residual<NS, CPT, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
 }
@@ -1250,17 +1202,14 @@ hipError_t solve_instance_g(const SolveKArgs& a, bool mixed, int groups, size_t 
   return hipGetLastError();
 }
 
-// Orthorhombic cells take every load depth; general cells run with one plane
-// of loads ahead, and with the window of partial sums only when some arm
-// leaves the sweep plane.
+// Orthorhombic cells and general cells whose arms stay in the sweep plane
+// take every load depth; with arms leaving the plane the passes load one
+// plane ahead whatever the depth asked.
 template <int NS, int CPT, int NT, int PD>
 hipError_t solve_instance(const SolveKArgs& a, bool mixed, int groups, size_t lds, hipStream_t s, int* occ) {
   if (!a.gen) return solve_instance_g<NS, CPT, NT, PD, false, false>(a, mixed, groups, lds, s, occ);
-  if constexpr (PD == 1) {
-    if (a.G.n_tl > 0) return solve_instance_g<NS, CPT, NT, 1, true, true>(a, mixed, groups, lds, s, occ);
-    return solve_instance_g<NS, CPT, NT, 1, true, false>(a, mixed, groups, lds, s, occ);
-  }
-  return hipErrorInvalidValue;
+  if (a.G.n_tl > 0) return solve_instance_g<NS, CPT, NT, 1, true, true>(a, mixed, groups, lds, s, occ);
+  return solve_instance_g<NS, CPT, NT, PD, true, false>(a, mixed, groups, lds, s, occ);
 }
 
 // Columns per thread available for each workgroup size: 1024 threads take up
