@@ -82,6 +82,17 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
     }
     a.G.diag = in.g.w2[0] * sum;
   }
+  for (int q = 0; q < 4; ++q) a.G32.w[q] = (float)a.G.w[q];
+  a.G32.cz = (float)a.G.cz;
+  a.G32.diag = (float)a.G.diag;
+  a.G32.n_in = a.G.n_in;
+  a.G32.n_tl = a.G.n_tl;
+  for (int k = 0; k < 3; ++k) {
+    a.G32.in_off[k] = a.G.in_off[k];
+    a.G32.in_coef[k] = (float)a.G.in_coef[k];
+    a.G32.tl_off[k] = a.G.tl_off[k];
+    a.G32.tl_coef[k] = (float)a.G.tl_coef[k];
+  }
   a.lds_cx = in.g.lds_cx;
   a.lds_cy = in.g.lds_cy;
   a.lds_wx = in.g.lds_wx;

@@ -52,23 +52,6 @@ struct GenStencilT {
   T tl_coef[3];
 };
 
-template <typename T>
-__device__ __forceinline__ GenStencilT<T> gen_stencil_cast(const GenStencilT<double>& s) {
-  GenStencilT<T> o;
-  for (int q = 0; q < 4; ++q) o.w[q] = (T)s.w[q];
-  o.cz = (T)s.cz;
-  o.diag = (T)s.diag;
-  o.n_in = s.n_in;
-  o.n_tl = s.n_tl;
-  for (int k = 0; k < 3; ++k) {
-    o.in_off[k] = s.in_off[k];
-    o.in_coef[k] = (T)s.in_coef[k];
-    o.tl_off[k] = s.tl_off[k];
-    o.tl_coef[k] = (T)s.tl_coef[k];
-  }
-  return o;
-}
-
 struct SolveKArgs {
   const ClassDev* cls;
   const PairDev* pairs;
@@ -93,6 +76,10 @@ struct SolveKArgs {
   StencilT<double> S;
   int gen;                 // general cell: padded columns and the NK arms in G
   GenStencilT<double> G;
+  // G in FP32 for the mixed passes, made on the host: the passes index the
+  // arms with a runtime index, which reads kernel arguments with scalar
+  // loads, where a local copy would live in scratch memory
+  GenStencilT<float> G32;
   int lds_cx, lds_cy, lds_wx, lds_wy;
   // warm start (warm_store null: every solve starts from zero)
   const float* warm_store;   // [2][warm_cap][rstride]; the previous solutions are half warm_state[0]
@@ -1072,7 +1059,6 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   float* p = r + a.sstride;
   float* y = p + a.sstride;
   const StencilT<float> S32 = stencil_cast<float>(a.S);
-  const GenStencilT<float> G32 = gen_stencil_cast<float>(a.G);
 
   long long lo, hi;
   solve_range(a, &lo, &hi);
@@ -1124,7 +1110,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     }
     while (!conv && it < a.max_iter) {
       double pq_t, rr_t;
-      pass_a<NS, CPT, PD, GEN, TL, float>(S32, G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
+      pass_a<NS, CPT, PD, GEN, TL, float>(S32, a.G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
       const double pq = block_sum(pq_t, red);
       if (!(pq > 0.0) || !(pq < INFINITY)) {
         it = a.max_iter;
@@ -1132,7 +1118,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         break;
       }
       const double alpha = rr / pq;
-      double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, float>(S32, G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
+      double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
                                                                 y_zero, fl0, fl1),
                             red);
       ++it;
