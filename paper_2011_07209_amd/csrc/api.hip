@@ -253,7 +253,9 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
 // Autotuner: for each sphere class with pairs in this batch, times every CG
 // variant (workgroup size x load depth) that can run it on a sample of the
 // class's pairs (one per workgroup of the grid), and keeps the fastest for
-// that class.  Densities and boundary values are in the workspace; right-hand
+// that class.  The class's current (default) variant is timed first and is
+// replaced only by one at least 3% faster, so that repeated plans settle on
+// the same variant when timings are close.  Densities and boundary values are in the workspace; right-hand
 // sides are rebuilt before each trial (the solve overwrites them) and once
 // more by the caller.
 exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hipStream_t s) {
@@ -275,7 +277,16 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
     if (hi <= lo) continue;
     float best = 1e30f;
     int bt = P->class_threads[k], bd = P->class_depth[k];
-    for (const auto& c : cand) {
+    int order[5][2] = {{bt, bd}};
+    int nc = 1;
+    for (const auto& c : cand)
+      if (c[0] != bt || c[1] != bd) {
+        order[nc][0] = c[0];
+        order[nc][1] = c[1];
+        ++nc;
+      }
+    for (int ci = 0; ci < nc; ++ci) {
+      const int* c = order[ci];
       if (solve_groups_per_cu(P->geo, P->classes[k].n_cols, P->classes[k].Zmax, base.mixed, c[0], c[1]) < 1)
         continue;
       exx_status st = select_solve(P, c[0], c[1], k);
@@ -309,7 +320,7 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
       float ms = 0;
       EXX_HIP(P, hipEventElapsedTime(&ms, e0, e1));
       const float per_pair = ms / (float)sample;
-      if (per_pair < best) {
+      if (ci == 0 ? per_pair < best : per_pair < 0.97f * best) {
         best = per_pair;
         bt = c[0];
         bd = c[1];
@@ -643,16 +654,19 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
   return EXX_OK;
 }
 
-// Default CG variant of each class: 1024 threads up to three columns each,
-// else 512 (1024 x 4 spills); FP64 loads one plane ahead, mixed two (cells
-// with arms leaving the sweep plane always load one ahead).
+// Default CG variant of each class (measured on MI355X): 1024 threads up to
+// three columns each for orthorhombic cells (1024 x 4 spills), up to four for
+// general cells (whose passes keep fewer values per column), else 512; FP64
+// loads one plane ahead, mixed two (cells with arms leaving the sweep plane
+// always load one ahead).
 void default_solve_variants(exx_plan_t P) {
   const exx_options& opt = P->opt;
   const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
+  const int cpt = P->geo.gen ? 4 : 3;
   P->class_threads.assign(P->classes.size(), 1024);
   P->class_depth.assign(P->classes.size(), dp);
   for (size_t k = 0; k < P->classes.size(); ++k)
-    P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= 3 * 1024 ? 1024 : 512);
+    P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= cpt * 1024 ? 1024 : 512);
 }
 
 // A new cell for the same proto-subdomains (fixed grid offsets, Sec. III B 2):
