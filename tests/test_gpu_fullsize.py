@@ -252,3 +252,54 @@ def test_water512_fp32_orbitals_lmax8_subset():
     assert np.abs(Da - Db).sum() <= 1e-5 * np.abs(Db).sum()
     del orb_t
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# general cells (hexagonal, triclinic): every pair, autotuned as the benchmark
+# runs them, FP64 against the oracle on sampled pairs and mixed against FP64
+
+@pytest.mark.parametrize("key", ["hex64", "tri64"])
+def test_general_cell_full_size(key):
+    cfg = synth.CONFIGS[key]
+    orbs = synth.make_orbitals(cfg)
+    orb_t = synth.fill_orbitals_device(cfg, orbs, DEV)
+    cen_t = torch.from_numpy(orbs.centres).to(DEV)
+    sub = torch.tensor([0, 63, 128, 255], dtype=torch.int32, device=DEV)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        plan = _plan(cfg, autotune=1, precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64)
+        E = torch.zeros(1, dtype=torch.float64, device=DEV)
+        S = torch.zeros(9, dtype=torch.float64, device=DEV)
+        D = torch.empty((4,) + tuple(orb_t.shape[1:]), dtype=torch.float64, device=DEV)
+        plan.eval(orb_t, cen_t, E, D, S, d_subset=sub)
+        torch.cuda.synchronize()
+        st = plan.stats()
+        res[prec] = (E.item(), S.cpu().numpy().reshape(3, 3, order="F"), D.cpu().numpy(), plan.pair_results(), st)
+        plan.close()
+        print(f"[{key}] {prec}: pairs={st['n_pairs']} arms={st['n_arms']} E={E.item():.12f} "
+              f"iters mean={st['cg_iter_sum'] / st['n_pairs']:.1f} variant={st['solve_threads']}x{st['solve_depth']}",
+              flush=True)
+        assert st["n_unconverged"] == 0
+    E, S, _, pr, st = res["fp64"]
+    # the pair list (minimum image and R_pair in the general cell) is the oracle's
+    ora = oracle.pair_list(_oracle_params(cfg), orbs.centres)
+    assert [tuple(int(x) for x in ij) for ij in pr["ij"]] == [(p.i, p.j) for p in ora]
+    assert st["n_arms"] == (4 if key == "hex64" else 6)
+    # random pairs (mostly far apart), a self pair, and the two strongest
+    # non-self pairs
+    off = [k for k in range(len(pr["E"])) if pr["ij"][k, 0] != pr["ij"][k, 1]]
+    strong = sorted(off, key=lambda k: abs(pr["E"][k]), reverse=True)[:2]
+    _check_pairs(key, cfg, orbs, orb_t, pr, sorted(set(_picks(pr, 3, 64 + len(key)) + strong)))
+    assert abs(np.sum(S * cfg.h) / -E - 1) < 2e-3   # virial identity, discretization-level gap
+    # rotational invariance of E makes sigma h^T, i.e. the stress of eq.
+    # pixx_working, symmetric (sigma itself is not, in a non-orthogonal cell)
+    Pi, _ = exx.exx_pressure(cfg.h, S)
+    assert np.abs(Pi - Pi.T).max() <= 1e-3 * np.abs(Pi).max()
+    (Ea, Sa, Da, _, _), (Eb, Sb, Db, _, _) = res["mixed"], res["fp64"]
+    n_mol = cfg.n_orb / 4
+    print(f"[{key}] mixed - fp64: dE/molecule={(Ea - Eb) / n_mol:.3e} "
+          f"sigma rel={np.abs(Sa - Sb).sum() / np.abs(Sb).sum():.3e} D rel={np.abs(Da - Db).sum() / np.abs(Db).sum():.3e}",
+          flush=True)
+    assert abs(Ea - Eb) <= 1e-6 * n_mol
+    assert np.abs(Sa - Sb).sum() <= 1e-6 * np.abs(Sb).sum()
+    assert np.abs(Da - Db).sum() <= 1e-6 * np.abs(Db).sum()
