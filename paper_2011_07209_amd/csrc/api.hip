@@ -517,27 +517,46 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
       }
     }
   }
+  // CG layout of an orthorhombic cell: runs of four columns per thread (the
+  // quad layout) for mixed plans by default or when asked, if every class's
+  // runs fit one workgroup of 1024 threads and one LDS row of 88 points with
+  // the runs' 4-point neighbour vectors (R / spacing + 7 on both sides of an
+  // origin that is a multiple of 4, so that runs start at even positions);
+  // else one column per thread slot
+  bool quads = !general && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED &&
+                                                  opt.solve_threads != 512));
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
   int max_zmax = 0, maxRc0 = 0, maxRc1 = 0;
-  for (size_t k = 0; k < radii.size(); ++k) {
-    std::string e = general
-                        ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs, &classes[k])
-                        : build_class(g.L, g.N, radii[k], me_radii[k], n, &classes[k]);
-    if (!e.empty()) return fail(P, EXX_EINVAL, e);
-    const ClassHost& C = classes[k];
-    max_pe = std::max(max_pe, C.n_pe);
-    max_halo = std::max(max_halo, C.n_halo);
-    max_me = std::max(max_me, C.n_me);
-    max_cols = std::max<long long>(max_cols, C.n_cols);
-    max_zmax = std::max(max_zmax, C.Zmax);
-    maxRc0 = std::max(maxRc0, C.Rc[0]);
-    maxRc1 = std::max(maxRc1, C.Rc[1]);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    max_pe = max_halo = max_me = max_cols = 0;
+    max_zmax = maxRc0 = maxRc1 = 0;
+    for (size_t k = 0; k < radii.size(); ++k) {
+      std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs,
+                                                    &classes[k])
+                              : build_class(g.L, g.N, radii[k], me_radii[k], n, quads, &classes[k]);
+      if (!e.empty()) return fail(P, EXX_EINVAL, e);
+      const ClassHost& C = classes[k];
+      max_pe = std::max(max_pe, C.n_pe);
+      max_halo = std::max(max_halo, C.n_halo);
+      max_me = std::max(max_me, C.n_me);
+      max_cols = std::max<long long>(max_cols, C.n_cols);
+      max_zmax = std::max(max_zmax, C.Zmax);
+      maxRc0 = std::max(maxRc0, C.Rc[0]);
+      maxRc1 = std::max(maxRc1, C.Rc[1]);
+    }
+    if (!quads) break;
+    const int cx4 = (maxRc0 + 7 + 3) / 4 * 4;
+    if (max_cols <= 4 * 1024 && cx4 + maxRc0 + 7 <= kLdsWX - 1) break;
+    if (opt.cg_layout == 2)
+      return fail(P, EXX_EINVAL, "quad layout: the PE sphere needs more than 1024 runs or a wider LDS row");
+    quads = false;
   }
-  g.lds_cx = maxRc0 + n;
+  g.quads = quads ? 1 : 0;
+  g.lds_cx = quads ? (maxRc0 + 7 + 3) / 4 * 4 : maxRc0 + n;
   g.lds_cy = maxRc1 + n;
   g.lds_wx = kLdsWX;
   g.lds_wy = 2 * g.lds_cy + 1;
-  if (2 * g.lds_cx + 1 > kLdsWX)
+  if (!quads && 2 * g.lds_cx + 1 > kLdsWX)
     return fail(P, EXX_EINVAL, "PE sphere too wide: need 2 (R_PE / spacing + n) + 1 <= 88 grid points");
   if (!solve_supported((int)std::min<long long>(max_cols, 1 << 30), 512))
     return fail(P, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");
@@ -665,6 +684,7 @@ void default_solve_variants(exx_plan_t P) {
   const int cpt = P->geo.gen ? 4 : 3;
   P->class_threads.assign(P->classes.size(), 1024);
   P->class_depth.assign(P->classes.size(), dp);
+  if (P->geo.quads) return;   // one run per thread: 1024 threads
   for (size_t k = 0; k < P->classes.size(); ++k)
     P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= cpt * 1024 ? 1024 : 512);
 }
@@ -761,6 +781,11 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     return fail(nullptr, EXX_EINVAL, "cell_fluctuation must be 0 or 1");
   if (!(opt.reassemble_strain >= 0.0) || !std::isfinite(opt.reassemble_strain))
     return fail(nullptr, EXX_EINVAL, "reassemble_strain must be >= 0");
+  if (opt.cg_layout < 0 || opt.cg_layout > 2) return fail(nullptr, EXX_EINVAL, "cg_layout must be 0, 1 or 2");
+  if (opt.cg_layout == 2 && (general || opt.cell_fluctuation))
+    return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) is for orthorhombic cells without cell_fluctuation");
+  if (opt.cg_layout == 2 && opt.solve_threads == 512)
+    return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) runs 1024 threads per workgroup");
 
   exx_plan_t P = new (std::nothrow) exx_plan_s();
   if (!P) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
@@ -1213,6 +1238,7 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->cell_strain = P->cell_strain;
   out->reassemblies = P->reassemblies;
   out->n_arms = P->geo.gen ? P->geo.n_arms : 3;
+  out->cg_layout = P->geo.quads ? 2 : 1;
   out->solve_threads = P->solve_threads;
   out->solve_depth = P->solve_depth;
   out->tune_ms = P->tune_ms;
@@ -1258,7 +1284,7 @@ exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_P
     e = build_nk_arms(h, N, &arms);
     if (e.empty()) e = build_class_general(h, N, 2, R_PE, R_ME, stencil_n, arms, false, &C);
   } else {
-    e = build_class(L, N, R_PE, R_ME, stencil_n, &C);
+    e = build_class(L, N, R_PE, R_ME, stencil_n, false, &C);
   }
   if (!e.empty()) return fail(nullptr, EXX_EINVAL, e);
   if (n_pe) *n_pe = C.n_real;

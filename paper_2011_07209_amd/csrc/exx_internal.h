@@ -43,6 +43,9 @@ struct Geo {
   // General (non-orthogonal) cells.  gen == 0: orthorhombic, offsets are
   // r = (o_x d_x, o_y d_y, o_z d_z) and the Laplacian is the axis stencil.
   int gen;
+  // Orthorhombic cells only: 1 when the columns are laid out in runs of four
+  // x-adjacent columns (one run per CG thread), 0 for single columns.
+  int quads;
   double A[9];          // r = A o, A[a + 3 al] = h_{a al} / N_al
   int perm[3];          // CG frame: (x', y', z') = (o[perm[0]], o[perm[1]], o[perm[2]])
   int n_arms;           // NK Laplacian: sum over arms of coef * eq. d2_1 along u
@@ -103,6 +106,7 @@ struct ClassHost {
   int Wm[3] = {0, 0, 0};
   int Rc[3] = {0, 0, 0};
   bool general = false;
+  bool quads = false;
   int perm[3] = {0, 1, 2};
   std::vector<int4> cols;
   std::vector<int> plane_start;
@@ -114,7 +118,11 @@ struct ClassHost {
 
 // Builds the tables of one class of an orthorhombic cell; returns an empty
 // string or an error message.
-std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out);
+// quads: columns grouped into runs of four x-adjacent columns of one row
+// (starting at x = 4k on even rows, 4k + 2 on odd ones), each run padded to
+// its tallest column with dead slots, the runs sorted by that height.
+std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, bool quads,
+                        ClassHost* out);
 // The same for a general cell h with the NK arms of its Laplacian; the CG
 // sweeps along grid axis `sweep`.
 // all_dirs: Dirichlet points along every nearest-neighbour direction (for

@@ -296,6 +296,10 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__
     b_ws[(long long)bq * rstride + k] = o.w ? 0.0 : acc;
     return;
   }
+  if (o.w) {   // dead slot of a padded run
+    b_ws[(long long)bq * rstride + k] = 0.0;
+    return;
+  }
   for (int q = 1; q <= g.n; ++q) {
     acc += g.inv_d2[0] * g.w2[q] *
            (point_value(C, g.n, nullptr, halo, o.x + q, o.y, o.z, true) +

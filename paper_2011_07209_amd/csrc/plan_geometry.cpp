@@ -10,6 +10,14 @@
 // a prefix of that order, and the plane is stored as that prefix, planes in
 // ascending z.  A workgroup that assigns column c to a fixed thread then reads
 // every plane with consecutive addresses from one per-plane base offset.
+//
+// Quad layout (orthorhombic cells, one CG thread per run): the columns are
+// grouped into runs of four x-adjacent columns of a row (x = 4k + s .. 4k + s
+// + 3, s = 0 on even rows and 2 on odd rows), each run padded to its tallest
+// column; the runs are sorted by that height (descending), and plane z holds
+// the runs that reach it, four slots each.  A slot whose own column does not reach plane z, or lies
+// outside the sphere, is dead (me_off.w = 1): it holds no point, stays zero in
+// every vector, and every kernel skips it.
 #include <algorithm>
 #include <array>
 #include <climits>
@@ -34,10 +42,12 @@ inline double r2_of(const double L[3], const int N[3], int ox, int oy, int oz) {
 
 }  // namespace
 
-std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, ClassHost* out) {
+std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, bool quads,
+                        ClassHost* out) {
   ClassHost& C = *out;
   C = ClassHost();
   C.R_PE = R_PE;
+  C.quads = quads;
   const double pe2 = R_PE * R_PE * (1.0 + kSlack);
   const double me2 = R_ME * R_ME * (1.0 + kSlack);
   int K[3];   // bounding half-widths of the ME sphere
@@ -67,12 +77,15 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   // of this order
   struct Col { int ox, oy, zr; double ang; };
   std::vector<Col> cols;
+  const int Wr = 2 * C.Rg[0] + 1;
+  std::vector<int> zr_at((size_t)Wr * (2 * C.Rg[1] + 1), -1);
   for (int oy = -C.Rg[1]; oy <= C.Rg[1]; ++oy)
     for (int ox = -C.Rg[0]; ox <= C.Rg[0]; ++ox) {
       int zr = -1;
       for (int oz = 0; oz <= C.Rg[2]; ++oz)
         if (r2_of(L, N, ox, oy, oz) <= pe2) zr = oz; else break;
       if (zr >= 0) cols.push_back({ox, oy, zr, std::atan2((double)oy, (double)ox)});
+      zr_at[(size_t)(ox + C.Rg[0]) + (size_t)Wr * (oy + C.Rg[1])] = zr;
     }
   std::stable_sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) {
     if (a.zr != b.zr) return a.zr > b.zr;
@@ -80,17 +93,72 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
     if (a.oy != b.oy) return a.oy < b.oy;
     return a.ox < b.ox;
   });
-  C.n_cols = (int)cols.size();
-  C.cols.resize(cols.size());
-  for (size_t c = 0; c < cols.size(); ++c) C.cols[c] = make_int4(cols[c].ox, cols[c].oy, cols[c].zr, 0);
 
-  // planes: plane z holds the prefix of columns that reach it
+  // the layout's columns: (ox, oy, half-height zr of the column itself or -1
+  // outside the sphere, half-height zq of the unit the prefix is taken over)
+  struct Lay { int ox, oy, zr, zq; };
+  std::vector<Lay> lay;
+  if (!quads) {
+    for (const Col& c : cols) lay.push_back({c.ox, c.oy, c.zr, c.zr});
+  } else {
+    auto zr_of = [&](int ox, int oy) {
+      if (std::abs(ox) > C.Rg[0]) return -1;
+      return zr_at[(size_t)(ox + C.Rg[0]) + (size_t)Wr * (oy + C.Rg[1])];
+    };
+    auto floor4 = [](int v) { return v >= 0 ? v / 4 : -((-v + 3) / 4); };
+    // Runs start at x = 4k + s with s = 0 on even rows and 2 on odd rows, so
+    // that the runs' 8-byte halves in the LDS plane fall on every bank pair,
+    // not only on every other one.
+    auto shift = [](int oy) { return 2 * (oy & 1); };
+    struct Run { int x0, oy, zq; };
+    std::vector<Run> runs;
+    for (int oy = -C.Rg[1]; oy <= C.Rg[1]; ++oy)
+      for (int k = floor4(-C.Rg[0] - shift(oy)); 4 * k + shift(oy) <= C.Rg[0]; ++k) {
+        const int x0 = 4 * k + shift(oy);
+        int zq = -1;
+        for (int j = 0; j < 4; ++j) zq = std::max(zq, zr_of(x0 + j, oy));
+        if (zq >= 0) runs.push_back({x0, oy, zq});
+      }
+    // by run height (descending; plane z is a prefix), then within one height
+    // greedily: each next run takes the 8-byte bank pair used least so far by
+    // its aligned group of 16 threads (ties: row order)
+    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
+      if (a.zq != b.zq) return a.zq > b.zq;
+      if (a.oy != b.oy) return a.oy < b.oy;
+      return a.x0 < b.x0;
+    });
+    auto pair_of = [](const Run& r) { return (((r.x0 + 88 * r.oy) / 2) % 16 + 16) % 16; };
+    std::vector<Run> ordered;
+    ordered.reserve(runs.size());
+    for (size_t g0 = 0; g0 < runs.size();) {
+      size_t g1 = g0;
+      while (g1 < runs.size() && runs[g1].zq == runs[g0].zq) ++g1;
+      std::vector<Run> pending(runs.begin() + g0, runs.begin() + g1);
+      while (!pending.empty()) {
+        int used[16] = {0};
+        for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used[pair_of(ordered[t])];
+        size_t best = 0;
+        for (size_t i = 1; i < pending.size(); ++i)
+          if (used[pair_of(pending[i])] < used[pair_of(pending[best])]) best = i;
+        ordered.push_back(pending[best]);
+        pending.erase(pending.begin() + best);
+      }
+      g0 = g1;
+    }
+    for (const Run& r : ordered)
+      for (int j = 0; j < 4; ++j) lay.push_back({r.x0 + j, r.oy, zr_of(r.x0 + j, r.oy), r.zq});
+  }
+  C.n_cols = (int)lay.size();
+  C.cols.resize(lay.size());
+  for (size_t c = 0; c < lay.size(); ++c) C.cols[c] = make_int4(lay[c].ox, lay[c].oy, lay[c].zr, lay[c].zq);
+
+  // planes: plane z holds the prefix of the layout that reaches it
   C.plane_start.assign(2 * C.Zmax + 2, 0);
   long long acc = 0;
   for (int z = -C.Zmax; z <= C.Zmax; ++z) {
     C.plane_start[z + C.Zmax] = (int)acc;
     int nz = 0;
-    while (nz < C.n_cols && cols[nz].zr >= std::abs(z)) ++nz;
+    while (nz < C.n_cols && lay[nz].zq >= std::abs(z)) ++nz;
     acc += nz;
   }
   C.plane_start[2 * C.Zmax + 1] = (int)acc;
@@ -103,8 +171,9 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   C.zr_map.assign((size_t)W0 * W1, -1);
   C.col_map.assign((size_t)W0 * W1, -1);
   for (int c = 0; c < C.n_cols; ++c) {
-    size_t m = (size_t)(cols[c].ox + cx) + (size_t)W0 * (cols[c].oy + cy);
-    C.zr_map[m] = cols[c].zr;
+    if (lay[c].zr < 0) continue;
+    size_t m = (size_t)(lay[c].ox + cx) + (size_t)W0 * (lay[c].oy + cy);
+    C.zr_map[m] = lay[c].zr;
     C.col_map[m] = c;
   }
   auto in_pe = [&](int ox, int oy, int oz) {
@@ -133,9 +202,17 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
 
   // ME list: PE points in packed order, then the shell
   C.me_off.reserve((size_t)C.n_pe);
+  C.n_real = 0;
   for (int z = -C.Zmax; z <= C.Zmax; ++z) {
     const int nz = C.plane_start[z + C.Zmax + 1] - C.plane_start[z + C.Zmax];
-    for (int c = 0; c < nz; ++c) C.me_off.push_back(make_short4((short)cols[c].ox, (short)cols[c].oy, (short)z, 0));
+    for (int c = 0; c < nz; ++c) {
+      if (lay[c].zr < std::abs(z)) {   // dead slot of a padded run
+        C.me_off.push_back(make_short4(0, 0, 0, 1));
+        continue;
+      }
+      C.me_off.push_back(make_short4((short)lay[c].ox, (short)lay[c].oy, (short)z, 0));
+      ++C.n_real;
+    }
   }
   for (int oz = -K[2]; oz <= K[2]; ++oz)
     for (int oy = -K[1]; oy <= K[1]; ++oy)
@@ -146,7 +223,6 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
         C.me_off.push_back(make_short4((short)ox, (short)oy, (short)oz, 0));
       }
   C.n_me = (long long)C.me_off.size();
-  C.n_real = C.n_pe;
   for (int a = 0; a < 3; ++a) C.Rc[a] = C.Rg[a];
   return std::string();
 }

@@ -60,6 +60,7 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
   // general cell: the NK arms in the CG frame (x', y', z') = o[perm]
   a.gen = in.g.gen;
+  a.quads = in.g.quads;
   std::memset(&a.G, 0, sizeof(a.G));
   if (a.gen) {
     for (int q = 0; q < 4; ++q) a.G.w[q] = in.g.w2[q];

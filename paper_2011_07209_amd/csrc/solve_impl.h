@@ -75,6 +75,7 @@ struct SolveKArgs {
   double delta;           // mixed: update when ||r|| < delta * (residual at the last update)
   StencilT<double> S;
   int gen;                 // general cell: padded columns and the NK arms in G
+  int quads;               // orthorhombic cell in the quad layout (one run of four columns per thread)
   GenStencilT<double> G;
   // G in FP32 for the mixed passes, made on the host: the passes index the
   // arms with a runtime index, which reads kernel arguments with scalar
@@ -883,20 +884,325 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
 #undef EXX_GIDX
 
 
-// Orthorhombic (axis stencil) or general-cell (NK arms) form of the passes.
-template <bool GEN, int CPT>
-using ColsOf = std::conditional_t<GEN, ColsG<CPT>, Cols<CPT>>;
+// ---------------------------------------------------------------------------
+// Quad layout of orthorhombic cells.  The sphere's columns are grouped into
+// runs of four x-adjacent columns of one row (starting at x = 4k on even rows,
+// 4k + 2 on odd rows, so a run starts at an even LDS position), padded to the
+// run's tallest column: plane z holds the runs whose tallest column reaches
+// it, as a prefix of the runs sorted by that height, four slots per run; a
+// slot whose own column is shorter (or lies outside the sphere) is dead and
+// stays zero.  Thread t owns run t.  Its four points of a plane are one
+// 16-byte (FP32) vector in global memory and two 8-byte halves in the LDS
+// plane; the in-plane stencil reads the run's left and right neighbours along
+// x (n <= 3 points each) and the rows y +- q as such halves.  The x neighbours
+// inside the run are the thread's own registers.
 
-template <bool GEN, int CPT, int NT>
-__device__ __forceinline__ void cols_load(const ClassDev& C, const SolveKArgs& a, ColsOf<GEN, CPT>& cl) {
-  if constexpr (GEN) load_cols_gen<CPT, NT>(C, a, cl); else load_cols<CPT, NT>(C, a, cl);
+struct ColsQ {
+  int zr[4];   // half-height of each column, -1 outside the sphere
+  int zq;      // half-height of the run (max zr), -1 for no run
+  int pos;     // LDS plane position of the run's first column (even)
+  int base;    // offset of the run's slots within a plane (4 t)
+};
+
+template <int NT>
+__device__ __forceinline__ void load_cols_quad(const ClassDev& C, const SolveKArgs& a, ColsQ& cl) {
+  const int run = threadIdx.x;
+  cl.zq = -1;
+  cl.pos = 0;
+  cl.base = 4 * run;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) cl.zr[j] = -1;
+  if (4 * run < C.n_cols) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int4 cc = C.cols[4 * run + j];
+      cl.zr[j] = cc.z;
+      cl.zq = max(cl.zq, cc.z);
+    }
+    const int4 c0 = C.cols[4 * run];
+    cl.pos = (c0.x + a.lds_cx) + kLdsWX * (c0.y + a.lds_cy);
+  }
 }
 
-template <int NS, int CPT, int PD, bool GEN, bool TL, typename T>
-__device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T>& G, const ColsOf<GEN, CPT>& cl,
-                                       const int* pst, int Zmax, const T* r, T* p, T beta, bool first, T* pl0,
-                                       T* pl1, double& pq, double& rr) {
-  if constexpr (GEN && TL)
+// A run's four values of one plane.  The passes work on these 4-point vectors
+// throughout, so that global accesses stay whole 16-byte (FP32) or 32-byte
+// (FP64) accesses and the z window is one register tuple per plane.
+template <typename T>
+using V4 = T __attribute__((ext_vector_type(4)));
+
+// Global-memory vectors: element idx (a multiple of 4) of the plane-major
+// vector at base, which is aligned to the vector size.  The accesses name the
+// global address space and take a 32-bit byte offset from the workgroup's
+// uniform base.
+#define EXX_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ V4<T> ld_quad(const T* base, int idx) {
+  return *(const EXX_GLOBAL V4<T>*)((const EXX_GLOBAL char*)base + (unsigned)idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_quad(T* base, int idx, V4<T> v) {
+  *(EXX_GLOBAL V4<T>*)((EXX_GLOBAL char*)base + (unsigned)idx * (unsigned)sizeof(T)) = v;
+}
+
+template <typename T>
+__device__ __forceinline__ double dot4(V4<T> a, V4<T> b) {
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
+         (double)a.w * (double)b.w;
+}
+
+// plane values K points right (xr) and left (xl) of the run's four columns,
+// from the run's own values c and its neighbour vectors lf (x - 4 .. x - 1)
+// and rt (x + 4 .. x + 7)
+template <int K, typename T>
+__device__ __forceinline__ V4<T> shift_right(V4<T> c, V4<T> rt) {
+  return __builtin_shufflevector(c, rt, K, K + 1, K + 2, K + 3);
+}
+template <int K, typename T>
+__device__ __forceinline__ V4<T> shift_left(V4<T> lf, V4<T> c) {
+  return __builtin_shufflevector(lf, c, 4 - K, 5 - K, 6 - K, 7 - K);
+}
+
+// A run's vector in the LDS plane (p even: 8-byte aligned for FP32) as two
+// halves of two points.  The compiler barrier keeps the halves separate
+// accesses: on gfx950 one 16-byte LDS access per thread occupies the LDS
+// longer than two 8-byte ones (measured on the CG).
+template <typename T>
+__device__ __forceinline__ V4<T> lds_quad(const T* p) {
+  using V2 = T __attribute__((ext_vector_type(2)));
+  const V2 a = *reinterpret_cast<const V2*>(p);
+  __asm__ volatile("" ::: "memory");
+  const V2 b = *reinterpret_cast<const V2*>(p + 2);
+  return V4<T>{a.x, a.y, b.x, b.y};
+}
+template <typename T>
+__device__ __forceinline__ void lds_quad_store(T* p, V4<T> v) {
+  using V2 = T __attribute__((ext_vector_type(2)));
+  *reinterpret_cast<V2*>(p) = V2{v.x, v.y};
+  __asm__ volatile("" ::: "memory");
+  *reinterpret_cast<V2*>(p + 2) = V2{v.z, v.w};
+}
+
+template <int K, int NS, typename T>
+__device__ __forceinline__ void quad_terms(const StencilT<T>& S, const V4<T> (&win)[2 * NS + 1], const T* pl,
+                                           int pos, V4<T> lf, V4<T> rt, V4<T>& sx, V4<T>& sy, V4<T>& sz) {
+  if constexpr (K <= NS) {
+    const V4<T> up = lds_quad(pl + pos + K * kLdsWX);
+    const V4<T> dn = lds_quad(pl + pos - K * kLdsWX);
+    sx += S.w[K] * (shift_right<K, T>(win[NS], rt) + shift_left<K, T>(lf, win[NS]));
+    sy += S.w[K] * (up + dn);
+    sz += S.w[K] * (win[NS + K] + win[NS - K]);
+    quad_terms<K + 1, NS, T>(S, win, pl, pos, lf, rt, sx, sy, sz);
+  }
+}
+
+// -(stencil Laplacian) at the run's four points of the staged plane pl, with
+// the z window of the run; per point the arithmetic is that of apply_point.
+template <int NS, typename T>
+__device__ __forceinline__ V4<T> apply_quad(const StencilT<T>& S, const V4<T> (&win)[2 * NS + 1], const T* pl,
+                                            int pos) {
+  const V4<T> lf = lds_quad(pl + pos - 4);
+  const V4<T> rt = lds_quad(pl + pos + 4);
+  V4<T> sx = {0, 0, 0, 0}, sy = {0, 0, 0, 0}, sz = {0, 0, 0, 0};
+  quad_terms<1, NS, T>(S, win, pl, pos, lf, rt, sx, sy, sz);
+  return -(S.diag * win[NS] + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
+}
+
+// v at the run's live slots of plane z, 0 at its dead ones
+template <typename T>
+__device__ __forceinline__ V4<T> live_only(const ColsQ& cl, int z, V4<T> v) {
+  const int az = abs(z);
+  v.x = az <= cl.zr[0] ? v.x : (T)0;
+  v.y = az <= cl.zr[1] ? v.y : (T)0;
+  v.z = az <= cl.zr[2] ? v.z : (T)0;
+  v.w = az <= cl.zr[3] ? v.w : (T)0;
+  return v;
+}
+
+#define EXX_QVALID(zz) (abs(zz) <= cl.zq)
+#define EXX_QIDX(zz) (pst[(zz) + Zmax] + cl.base)
+
+// Pass A (as cg_pass_a) on the quad layout.  Dead slots hold r = p = 0, so p
+// stays zero there and adds nothing to the dot products.
+template <int NS, int PD, typename T>
+__device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax,
+                               const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
+                               double& pq, double& rr) {
+  const V4<T> zero = {0, 0, 0, 0};
+  V4<T> win[2 * NS + 1];
+  V4<T> qr[PD], qp[PD];   // raw r, p of planes z+NS+1 .. z+NS+PD
+  pq = 0.0;
+  rr = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+    V4<T> v = zero;
+    if (EXX_QVALID(zz)) {
+      const int idx = EXX_QIDX(zz);
+      const V4<T> rv = ld_quad(r, idx);
+      v = first ? rv : rv + beta * ld_quad(p, idx);
+      rr += dot4(rv, rv);
+      st_quad(p, idx, v);
+    }
+    win[k] = v;
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+    qr[d] = zero;
+    qp[d] = zero;
+    if (EXX_QVALID(zz)) {
+      qr[d] = ld_quad(r, EXX_QIDX(zz));
+      if (!first) qp[d] = ld_quad(p, EXX_QIDX(zz));
+    }
+  }
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zl = z + NS + PD + 1;   // plane whose loads are issued now
+    V4<T> nr = zero, np = zero;
+    if (EXX_QVALID(zl)) {
+      nr = ld_quad(r, EXX_QIDX(zl));
+      if (!first) np = ld_quad(p, EXX_QIDX(zl));
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+    if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
+    __syncthreads();
+    if (EXX_QVALID(z)) pq += dot4(win[NS], apply_quad<NS, T>(S, win, pl, cl.pos));
+    const int zc = z + NS + 1;        // plane entering the window
+    V4<T> v = zero;
+    if (EXX_QVALID(zc)) {
+      v = first ? qr[0] : qr[0] + beta * qp[0];
+      rr += dot4(qr[0], qr[0]);
+      st_quad(p, EXX_QIDX(zc), v);
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
+    win[2 * NS] = v;
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d) {
+      qr[d] = qr[d + 1];
+      qp[d] = qp[d + 1];
+    }
+    qr[PD - 1] = nr;
+    qp[PD - 1] = np;
+  }
+}
+
+// Pass B (as cg_pass_b) on the quad layout; the new r is kept to the run's
+// live slots, so dead slots keep r = 0 (and x = 0, since p is zero there).
+template <int NS, int PD, typename T>
+__device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
+                                 const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+  const V4<T> zero = {0, 0, 0, 0};
+  V4<T> win[2 * NS + 1];
+  V4<T> qp[PD];              // p of planes z+NS+1 .. z+NS+PD
+  V4<T> cx = zero, cr = zero;   // x, r of plane z
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+    win[k] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+    qp[d] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
+  }
+  if (EXX_QVALID(-Zmax)) {
+    const int idx = EXX_QIDX(-Zmax);
+    cr = ld_quad(r_in, idx);
+    if (!x_zero) cx = ld_quad(x, idx);
+  }
+  double acc = 0.0;
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zl = z + NS + PD + 1;
+    V4<T> np = zero, nx = zero, nr = zero;
+    if (EXX_QVALID(zl)) np = ld_quad(p, EXX_QIDX(zl));
+    if (EXX_QVALID(z + 1)) {
+      const int idx = EXX_QIDX(z + 1);
+      nr = ld_quad(r_in, idx);
+      if (!x_zero) nx = ld_quad(x, idx);
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+    if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
+    __syncthreads();
+    if (EXX_QVALID(z)) {
+      const int idx = EXX_QIDX(z);
+      const V4<T> rn = live_only(cl, z, cr - alpha * apply_quad<NS, T>(S, win, pl, cl.pos));
+      st_quad(x, idx, cx + alpha * win[NS]);
+      st_quad(r, idx, rn);
+      acc += dot4(rn, rn);
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
+    win[2 * NS] = qp[0];
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d) qp[d] = qp[d + 1];
+    qp[PD - 1] = np;
+    cx = nx;
+    cr = nr;
+  }
+  return acc;
+}
+
+// FP64 true residual (as cg_true_residual) on the quad layout, zero at dead
+// slots.
+template <int NS, typename TR>
+__device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& cl, const int* pst, int Zmax,
+                                        const double* __restrict__ x, const double* __restrict__ b,
+                                        TR* __restrict__ r, double rs, double* pl0, double* pl1) {
+  const V4<double> zero = {0, 0, 0, 0};
+  V4<double> win[2 * NS + 1];
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+    win[k] = EXX_QVALID(zz) ? ld_quad(x, EXX_QIDX(zz)) : zero;
+  }
+  double acc = 0.0;
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zc = z + NS + 1;        // plane entering the window
+    const V4<double> nx = EXX_QVALID(zc) ? ld_quad(x, EXX_QIDX(zc)) : zero;
+    const V4<double> cb = EXX_QVALID(z) ? ld_quad(b, EXX_QIDX(z)) : zero;
+    double* pl = (z & 1) ? pl1 : pl0;
+    if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
+    __syncthreads();
+    if (EXX_QVALID(z)) {
+      const V4<double> rt = live_only(cl, z, cb - apply_quad<NS, double>(S, win, pl, cl.pos));
+      const V4<double> ro = rt * rs;
+      V4<TR> o = {(TR)ro.x, (TR)ro.y, (TR)ro.z, (TR)ro.w};
+      st_quad(r, EXX_QIDX(z), o);
+      acc += dot4(rt, rt);
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
+    win[2 * NS] = nx;
+  }
+  return acc;
+}
+
+#undef EXX_QVALID
+#undef EXX_QIDX
+
+// Orthorhombic (axis stencil, column or quad layout) or general-cell (NK
+// arms) form of the passes.
+template <bool GEN, bool QD, int CPT>
+using ColsOf = std::conditional_t<QD, ColsQ, std::conditional_t<GEN, ColsG<CPT>, Cols<CPT>>>;
+
+template <bool GEN, bool QD, int CPT, int NT>
+__device__ __forceinline__ void cols_load(const ClassDev& C, const SolveKArgs& a, ColsOf<GEN, QD, CPT>& cl) {
+  if constexpr (QD)
+    load_cols_quad<NT>(C, a, cl);
+  else if constexpr (GEN)
+    load_cols_gen<CPT, NT>(C, a, cl);
+  else
+    load_cols<CPT, NT>(C, a, cl);
+}
+
+template <int NS, int CPT, int PD, bool GEN, bool TL, bool QD, typename T>
+__device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T>& G,
+                                       const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, const T* r, T* p,
+                                       T beta, bool first, T* pl0, T* pl1, double& pq, double& rr) {
+  if constexpr (QD)
+    cg_pass_a_quad<NS, PD, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+  else if constexpr (GEN && TL)
     cg_pass_a_tl<NS, CPT, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else if constexpr (GEN)
     cg_pass_a_gen<NS, CPT, PD, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
@@ -904,11 +1210,13 @@ __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T
     cg_pass_a<NS, CPT, PD, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
 }
 
-template <int NS, int CPT, int PD, bool GEN, bool TL, typename T>
-__device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT<T>& G, const ColsOf<GEN, CPT>& cl,
-                                         const int* pst, int Zmax, T* x, const T* r_in, T* r, const T* p, T alpha,
-                                         bool x_zero, T* pl0, T* pl1) {
-  if constexpr (GEN && TL)
+template <int NS, int CPT, int PD, bool GEN, bool TL, bool QD, typename T>
+__device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT<T>& G,
+                                         const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, T* x,
+                                         const T* r_in, T* r, const T* p, T alpha, bool x_zero, T* pl0, T* pl1) {
+  if constexpr (QD)
+    return cg_pass_b_quad<NS, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+  else if constexpr (GEN && TL)
     return cg_pass_b_tl<NS, CPT, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
   else if constexpr (GEN)
     return cg_pass_b_gen<NS, CPT, PD, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
@@ -916,11 +1224,13 @@ __device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT
     return cg_pass_b<NS, CPT, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
 }
 
-template <int NS, int CPT, bool GEN, bool TL, typename TR>
-__device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsOf<GEN, CPT>& cl, const int* pst,
+template <int NS, int CPT, bool GEN, bool TL, bool QD, typename TR>
+__device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsOf<GEN, QD, CPT>& cl, const int* pst,
                                                 int Zmax, const double* x, const double* b, TR* r, double rs,
                                                 double* pl0, double* pl1) {
-  if constexpr (GEN && TL)
+  if constexpr (QD)
+    return cg_true_residual_quad<NS, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+  else if constexpr (GEN && TL)
     return cg_true_residual_tl<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else if constexpr (GEN)
     return cg_true_residual_gen<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
@@ -931,7 +1241,7 @@ __device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsO
 // One workgroup solves one pair at a time, taking pairs from a device queue
 // until the batch is exhausted (every workgroup exits when the counter passes
 // the batch size).  Unpreconditioned CG from x = 0, stop at ||r|| <= tol ||b||.
-template <int NS, int CPT, int NT, int PD, bool GEN, bool TL>
+template <int NS, int CPT, int NT, int PD, bool GEN, bool TL, bool QD>
 __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[NT / 64];
@@ -961,8 +1271,8 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
 
     for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
     for (int k = tid; k < 2 * Zmax + 2; k += NT) pst[k] = C.plane_start[k];
-    ColsOf<GEN, CPT> cl;
-    cols_load<GEN, CPT, NT>(C, a, cl);
+    ColsOf<GEN, QD, CPT> cl;
+    cols_load<GEN, QD, CPT, NT>(C, a, cl);
     __syncthreads();
 
     int it = 0;
@@ -986,7 +1296,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       double alpha = 1.0;
       if (!init) {
         double pq_t, rr_t;
-        pass_a<NS, CPT, PD, GEN, TL, double>(a.S, a.G, cl, pst, Zmax, (first && from_b) ? x : r, p, beta, first,
+        pass_a<NS, CPT, PD, GEN, TL, QD, double>(a.S, a.G, cl, pst, Zmax, (first && from_b) ? x : r, p, beta, first,
                                              pl0, pl1, pq_t, rr_t);
         const double pq = block_sum(pq_t, red);
         if (first && from_b) {
@@ -1002,7 +1312,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
         alpha = rr / pq;
       }
       const bool from_b_now = init || (first && from_b);
-      const double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, double>(a.S, a.G, cl, pst, Zmax, x,
+      const double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, double>(a.S, a.G, cl, pst, Zmax, x,
                                                                        from_b_now ? x : r, r, p, alpha, from_b_now,
                                                                        pl0, pl1),
                                   red);
@@ -1041,7 +1351,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
 // van der Vorst and Ye 2000; Clark et al. 2010).  The solution accumulates in
 // FP64 and the stop test is on the FP64 true residual, ||b - A x|| <= tol ||b||,
 // the same criterion as the FP64 path.
-template <int NS, int CPT, int NT, int PD, bool GEN, bool TL>
+template <int NS, int CPT, int NT, int PD, bool GEN, bool TL, bool QD>
 __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[NT / 64];
@@ -1077,8 +1387,8 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
 
     for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
     for (int k = tid; k < 2 * Zmax + 2; k += NT) pst[k] = C.plane_start[k];
-    ColsOf<GEN, CPT> cl;
-    cols_load<GEN, CPT, NT>(C, a, cl);
+    ColsOf<GEN, QD, CPT> cl;
+    cols_load<GEN, QD, CPT, NT>(C, a, cl);
     // ||b|| in FP64; the FP32 recursion runs in units of ||b|| (r = b / ||b||),
     // so its values stay far from the FP32 range limits whatever the pair's
     // overlap, and the solution is x = ||b|| sum y
@@ -1100,7 +1410,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     if (!conv && warm_gather<double>(a, C, pid, x)) {
       for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
       __syncthreads();
-      rr_true = block_sum(true_residual<NS, CPT, GEN, TL, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+      rr_true = block_sum(true_residual<NS, CPT, GEN, TL, QD, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
       for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
       __syncthreads();
       x_zero = false;
@@ -1110,7 +1420,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     }
     while (!conv && it < a.max_iter) {
       double pq_t, rr_t;
-      pass_a<NS, CPT, PD, GEN, TL, float>(S32, a.G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
+      pass_a<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
       const double pq = block_sum(pq_t, red);
       if (!(pq > 0.0) || !(pq < INFINITY)) {
         it = a.max_iter;
@@ -1118,7 +1428,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         break;
       }
       const double alpha = rr / pq;
-      double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
+      double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
                                                                 y_zero, fl0, fl1),
                             red);
       ++it;
@@ -1138,7 +1448,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
-        rr_true = block_sum(true_residual<NS, CPT, GEN, TL, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+        rr_true = block_sum(true_residual<NS, CPT, GEN, TL, QD, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
         for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
         __syncthreads();
         ++upd;
@@ -1169,22 +1479,23 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
 }
 
 // Launch (or occupancy query, when occ is not NULL) of one instance.
-template <int NS, int CPT, int NT, int PD, bool GEN, bool TL>
+template <int NS, int CPT, int NT, int PD, bool GEN, bool TL, bool QD = false>
 hipError_t solve_instance_g(const SolveKArgs& a, bool mixed, int groups, size_t lds, hipStream_t s, int* occ) {
-  const void* fn = mixed ? (const void*)k_solve_mixed<NS, CPT, NT, PD, GEN, TL>
-                         : (const void*)k_solve<NS, CPT, NT, PD, GEN, TL>;
+  const void* fn = mixed ? (const void*)k_solve_mixed<NS, CPT, NT, PD, GEN, TL, QD>
+                         : (const void*)k_solve<NS, CPT, NT, PD, GEN, TL, QD>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   if (occ) {
-    return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve_mixed<NS, CPT, NT, PD, GEN, TL>, NT, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, CPT, NT, PD, GEN, TL>, NT, lds);
+    return mixed
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve_mixed<NS, CPT, NT, PD, GEN, TL, QD>, NT, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_solve<NS, CPT, NT, PD, GEN, TL, QD>, NT, lds);
   }
   if (mixed)
-    k_solve_mixed<NS, CPT, NT, PD, GEN, TL><<<groups, NT, lds, s>>>(a);
+    k_solve_mixed<NS, CPT, NT, PD, GEN, TL, QD><<<groups, NT, lds, s>>>(a);
   else
-    k_solve<NS, CPT, NT, PD, GEN, TL><<<groups, NT, lds, s>>>(a);
+    k_solve<NS, CPT, NT, PD, GEN, TL, QD><<<groups, NT, lds, s>>>(a);
   return hipGetLastError();
 }
 
@@ -1228,6 +1539,11 @@ hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_
 template <int NS>
 hipError_t solve_ns_dispatch(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
                              size_t lds, hipStream_t s, int* occ) {
+  if (a.quads) {   // one run of four columns per thread, 1024 threads
+    if (threads != 1024 || max_cols > 4 * 1024) return hipErrorInvalidValue;
+    if (depth <= 1) return solve_instance_g<NS, 4, 1024, 1, false, false, true>(a, mixed, groups, lds, s, occ);
+    return solve_instance_g<NS, 4, 1024, 2, false, false, true>(a, mixed, groups, lds, s, occ);
+  }
   const int cpt = (max_cols + threads - 1) / threads;
   if (threads == 1024) {
     if (depth <= 1) return solve_cpt<NS, 1024, 1>(a, mixed, cpt, groups, lds, s, occ);

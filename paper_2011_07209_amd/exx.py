@@ -50,6 +50,7 @@ class Options(ctypes.Structure):
         ("R_ME_self", ctypes.c_double),
         ("cell_fluctuation", ctypes.c_int),
         ("reassemble_strain", ctypes.c_double),
+        ("cg_layout", ctypes.c_int),
     ]
 
 
@@ -82,6 +83,7 @@ class Stats(ctypes.Structure):
         ("cell_strain", ctypes.c_double),
         ("reassemblies", ctypes.c_int),
         ("n_arms", ctypes.c_int),
+        ("cg_layout", ctypes.c_int),
     ]
 
     def as_dict(self):

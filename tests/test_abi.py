@@ -55,7 +55,8 @@ def test_default_options(lib):
     assert o.cg_max_iter == 5000 and o.pair_sample_frac == 1.0 and o.R_PE_nclass == 0
 
 
-@pytest.mark.parametrize("case", ["singular", "left_handed", "arm_reach", "rme", "lmax", "stencil", "grid", "tol"])
+@pytest.mark.parametrize("case", ["singular", "left_handed", "arm_reach", "rme", "lmax", "stencil", "grid", "tol",
+                                  "layout", "quad_general", "quad_512"])
 def test_plan_rejects_invalid_arguments(lib, case):
     h = np.diag([12.0, 12.0, 12.0])
     grid, R_pair, R_PE, R_ME, L = (60, 60, 60), 8.0, 5.0, 7.0, 6
@@ -86,6 +87,14 @@ def test_plan_rejects_invalid_arguments(lib, case):
         grid = (60, 0, 60)
     elif case == "tol":
         opt.cg_tol = 0.0
+    elif case == "layout":
+        opt.cg_layout = 3
+    elif case == "quad_general":   # runs of four columns are for orthorhombic cells
+        h[0, 1] = 0.5
+        opt.cg_layout = 2
+    elif case == "quad_512":       # ... and one run per thread of 1024
+        opt.cg_layout = 2
+        opt.solve_threads = 512
     with pytest.raises(exx.ExxError) as ei:
         exx.exx_plan(h, grid, R_pair, R_PE, R_ME, L, opt)
     assert ei.value.status == exx.EXX_EINVAL

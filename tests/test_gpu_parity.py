@@ -180,19 +180,24 @@ def test_mixed_precision_far_pair_with_vanishing_density():
         assert abs(g["pairs"]["E"][k] - Eo[k]) <= 1e-7 * abs(Eo[k]), (k, g["pairs"]["E"][k], Eo[k])
 
 
-@pytest.mark.parametrize("threads,depth", [(1024, 1), (1024, 2), (512, 1), (512, 2)])
+@pytest.mark.parametrize("layout,threads,depth", [(1, 1024, 1), (1, 1024, 2), (1, 512, 1), (1, 512, 2),
+                                                  (2, 1024, 1), (2, 1024, 2)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_every_solve_variant(threads, depth, prec):
-    """Each CG variant the autotuner may pick (workgroup size x load depth, in
-    both precisions) gives the oracle's result."""
-    cfg = synth.custom(key=f"var-{threads}-{depth}-{prec}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=5,
-                       R_pair=7.0, R_PE=3.9, R_ME=5.3, l_max=4, stencil_n=3, cg_tol=1e-12, seed_index=60)
+def test_every_solve_variant(layout, threads, depth, prec):
+    """Each CG variant the autotuner may pick (layout: single columns or runs
+    of four, workgroup size x load depth, in both precisions) gives the
+    oracle's result."""
+    cfg = synth.custom(key=f"var-{layout}-{threads}-{depth}-{prec}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46),
+                       n_orb=5, R_pair=7.0, R_PE=3.9, R_ME=5.3, l_max=4, stencil_n=3, cg_tol=1e-12, seed_index=60)
     orbs = synth.make_orbitals(cfg)
     phi = synth.fill_orbitals(cfg, orbs)
     from paper_2011_07209_amd import exx
     g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64,
-                 solve_threads=threads, solve_depth=depth)
+                 solve_threads=threads, solve_depth=depth, cg_layout=layout)
     o = oracle_eval(cfg, orbs, phi)
+    print(f"[layout {layout} {threads}x{depth} {prec}] E gpu={g['E']:.15g} oracle={o['E']:.15g}", flush=True)
+    assert g["stats"]["cg_layout"] == layout
+    assert (g["stats"]["solve_threads"], g["stats"]["solve_depth"]) == (threads, depth)
     if prec == "mixed":
         _check_mixed(g, o, cfg.n_orb)
         return
@@ -249,3 +254,48 @@ def test_separate_self_radii(prec):
     assert rel1(g["D"], o["D"]) <= TOL_D
     Eo = np.array([p.E for p in o["pairs"]])
     assert np.abs(g["pairs"]["E"] - Eo).sum() <= TOL_E * np.abs(Eo).sum()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_quad_layout_lower_order_stencils(n):
+    """The quad layout with the n = 1 and n = 2 stencils (the run's x
+    neighbours reach 1 or 2 points into the neighbour vectors), FP64 path."""
+    from paper_2011_07209_amd import exx
+    cfg = synth.custom(key=f"quad-n{n}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=5, R_pair=7.0, R_PE=3.9,
+                       R_ME=5.3, l_max=4, stencil_n=n, cg_tol=1e-12, seed_index=70 + n)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g, _ = _compare(cfg, orbs, phi, cg_layout=2)
+    assert g["stats"]["cg_layout"] == 2
+
+
+def test_quad_layout_variable_radius_classes():
+    """Three sphere classes, each in its own padded run layout, mixed path."""
+    from paper_2011_07209_amd import exx
+    cfg = synth.custom(key="quad-classes", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=7, R_pair=7.0, R_PE=3.9,
+                       R_ME=5.3, l_max=4, stencil_n=3, cg_tol=1e-12, seed_index=83, R_PE_classes=(3.0, 0.45, 3),
+                       R_orb_range=(3.0, 3.9))
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    o = oracle_eval(cfg, orbs, phi)
+    assert g["stats"]["cg_layout"] == 2 and g["stats"]["n_classes"] >= 2
+    assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
+    _check_mixed(g, o, cfg.n_orb)
+
+
+def test_quad_layout_falls_back_for_wide_spheres():
+    """A sphere of more than 1024 runs of four columns (R_PE 7.1 at spacing 0.2:
+    3,969 columns in 1,044 runs): the default layout of a mixed plan falls back
+    to single columns, and asking for runs is refused."""
+    from paper_2011_07209_amd import exx
+    h = np.diag([30.0, 30.0, 30.0])
+    with pytest.raises(exx.ExxError):
+        exx.Plan(h, (150, 150, 150), 6.0, 7.1, 8.5, 4, cg_layout=2, precision=exx.EXX_PREC_MIXED)
+    cfg = synth.custom(key="quad-wide", cell=(30.0, 30.0, 30.0), grid=(150, 150, 150), n_orb=2, R_pair=6.0, R_PE=7.1,
+                       R_ME=8.5, l_max=4, stencil_n=3, cg_tol=1e-10, seed_index=84)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g = gpu_eval(cfg, orbs, phi, want_D=False, precision=exx.EXX_PREC_MIXED)
+    assert g["stats"]["cg_layout"] == 1
+    assert g["stats"]["n_unconverged"] == 0
