@@ -120,14 +120,15 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
         if (zq >= 0) runs.push_back({x0, oy, zq});
       }
     // by run height (descending; plane z is a prefix), then within one height
-    // greedily: each next run takes the 8-byte bank pair used least so far by
-    // its aligned group of 16 threads (ties: row order)
+    // greedily: each next run takes the 8-byte bank pair (of 16) used least so
+    // far by its aligned group of 16 threads, then the pair (of 32) used least
+    // by its group of 32 (ties: row order)
     std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
       if (a.zq != b.zq) return a.zq > b.zq;
       if (a.oy != b.oy) return a.oy < b.oy;
       return a.x0 < b.x0;
     });
-    auto pair_of = [](const Run& r) { return (((r.x0 + 88 * r.oy) / 2) % 16 + 16) % 16; };
+    auto pair_of = [](const Run& r) { return (((r.x0 + 88 * r.oy) / 2) % 32 + 32) % 32; };
     std::vector<Run> ordered;
     ordered.reserve(runs.size());
     for (size_t g0 = 0; g0 < runs.size();) {
@@ -135,11 +136,13 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
       while (g1 < runs.size() && runs[g1].zq == runs[g0].zq) ++g1;
       std::vector<Run> pending(runs.begin() + g0, runs.begin() + g1);
       while (!pending.empty()) {
-        int used[16] = {0};
-        for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used[pair_of(ordered[t])];
+        int used16[16] = {0}, used32[32] = {0};
+        for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used16[pair_of(ordered[t]) % 16];
+        for (size_t t = ordered.size() / 32 * 32; t < ordered.size(); ++t) ++used32[pair_of(ordered[t])];
+        auto key = [&](const Run& r) { return 64 * used16[pair_of(r) % 16] + used32[pair_of(r)]; };
         size_t best = 0;
         for (size_t i = 1; i < pending.size(); ++i)
-          if (used[pair_of(pending[i])] < used[pair_of(pending[best])]) best = i;
+          if (key(pending[i]) < key(pending[best])) best = i;
         ordered.push_back(pending[best]);
         pending.erase(pending.begin() + best);
       }
