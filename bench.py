@@ -63,10 +63,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str, precision: str, threads: int, depth: int):
+def stored_traffic(workload: str, precision: str, threads: int, depth: int, layout: int):
     """HBM bytes per solve launch from the committed counter runs, or None when
     the kernels changed since they were taken or the run used another CG
-    variant (workgroup size, load depth) than the one measured."""
+    variant (workgroup size, load depth, column or quad layout) than the one
+    measured."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -76,7 +77,9 @@ def stored_traffic(workload: str, precision: str, threads: int, depth: int):
     if not e or e.get("kernel_hash") != kernel_hash():
         return None
     args = [a.strip() for a in e.get("kernel", "").split("<", 1)[-1].rstrip(">").split(",")]
-    if len(args) < 4 or args[2] != str(threads) or args[3] != str(depth):
+    if len(args) < 7 or args[2] != str(threads) or args[3] != str(depth):
+        return None
+    if (args[6] == "true") != (layout == 2):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -200,7 +203,8 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
         achieved = (alg / max(launches, 1)) / (solve_ms / max(launches, 1) / 1000.0) / 1e9 if solve_ms > 0 else 0.0
         cg = {"bound": "hbm", "kernel": "k_solve_mixed" if precision == "mixed" else "k_solve",
               "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-              "traffic": stored_traffic(cfg.key, precision, s_last["solve_threads"], s_last["solve_depth"]),
+              "traffic": stored_traffic(cfg.key, precision, s_last["solve_threads"], s_last["solve_depth"],
+                                        s_last["cg_layout"]),
               "alg_bytes_per_launch": alg / max(launches, 1),
               "launch_ms": solve_ms / max(launches, 1)}
     print(f"[bench] {cfg.key} {precision} timed {steps} steps: {ms:.1f} ms/step E={E.item():.10f}", file=sys.stderr,
@@ -228,7 +232,7 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
         "cg_iters_mean": s_last["cg_iter_sum"] / max(1, n_pairs), "cg_iters_max": s_last["cg_iter_max"],
         "updates_max": s_last["refine_passes_max"], "max_rel_residual": s_last["max_rel_residual"],
         "solve_variant": {"threads": s_last["solve_threads"], "depth": s_last["solve_depth"],
-                          "tune_ms": s_last["tune_ms"]},
+                          "layout": "quads" if s_last["cg_layout"] == 2 else "columns", "tune_ms": s_last["tune_ms"]},
         "roofline": cg, "moments_roofline": moments,
         "E": E.item(), "sigma": S.cpu().numpy().reshape(3, 3, order="F"),
         "D_rows": D[:D_CHECK_ROWS].double().cpu(),
