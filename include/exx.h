@@ -101,15 +101,15 @@ typedef struct {
      proto-subdomains are rebuilt from scratch at the new cell with the plan's
      radii (0: never)                                                         */
   double reassemble_strain;
-  /* layout of the CG vectors of an orthorhombic cell: 0 picks the quad
-     layout for mixed plans when it fits (and solve_threads is not 512) and
-     single columns otherwise; 1:
-     single columns (each CG thread owns whole columns of the sphere); 2: quad
-     layout (each CG thread owns a run of four x-adjacent columns, padded with
-     zero slots to the run's tallest column, and reads its in-plane neighbours
-     as 4-point vectors; 1024 threads; EXX_EINVAL when the sphere needs more
-     than 1024 runs, for general cells, with cell_fluctuation and with
-     solve_threads 512)                                                      */
+  /* layout of the CG vectors of an orthorhombic cell, per sphere class: 0
+     picks the quad layout for mixed plans (unless solve_threads is 512) for
+     every class where it fits, single columns elsewhere; 1: single columns
+     (each CG thread owns whole columns of the sphere); 2: quad layout for
+     every class (each CG thread owns a run of four x-adjacent columns, padded
+     with zero slots to the run's tallest column, and reads its in-plane
+     neighbours as 2-point vectors; 1024 threads; EXX_EINVAL when a class
+     needs more than 1024 runs, for general cells, with cell_fluctuation and
+     with solve_threads 512)                                                  */
   int cg_layout;
 } exx_options;
 
@@ -209,7 +209,8 @@ typedef struct {
                                   cell the tables were built for                  */
   int reassemblies;            /* proto-subdomain re-assemblies by exx_set_cell    */
   int n_arms;                  /* arms of the Laplacian in use (3 to 6)           */
-  int cg_layout;               /* CG layout in use: 1 columns, 2 quads             */
+  int cg_layout;               /* CG layout in use: 1 columns, 2 quads, 3 both
+                                  (per sphere class)                               */
 } exx_stats;
 
 /* Fluctuating cell (Sec. III B 2): makes h (host [9], column-major,

@@ -189,6 +189,11 @@ exx_status harvest(exx_plan_t P) {
 // variant (class_threads, class_depth; its columns per thread select the
 // kernel instance).  The slot workspace, sized for the largest grid, is
 // resized on the next eval.
+// Elements per CG vector in a workgroup's slot: the largest class's points,
+// rounded up to 8 so that every vector of the slot starts 32-byte aligned (the
+// quad layout reads a run's four values as one vector).
+long long slot_stride(exx_plan_t P) { return (P->max_pe + 7) / 8 * 8; }
+
 exx_status apply_solve_variants(exx_plan_t P) {
   const bool mixed = P->opt.precision == EXX_PREC_MIXED;
   const size_t ncls = P->classes.size();
@@ -196,7 +201,8 @@ exx_status apply_solve_variants(exx_plan_t P) {
   int slots = 0;
   for (size_t k = 0; k < ncls; ++k) {
     const ClassHost& C = P->classes[k];
-    const int per_cu = solve_groups_per_cu(P->geo, C.n_cols, C.Zmax, mixed, P->class_threads[k], P->class_depth[k]);
+    const int per_cu =
+        solve_groups_per_cu(P->geo, C.n_cols, C.Zmax, mixed, C.quads, P->class_threads[k], P->class_depth[k]);
     if (per_cu < 1) return fail(P, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
     P->class_groups[k] = P->opt.solve_groups > 0 ? P->opt.solve_groups : P->n_cus * per_cu;
     slots = std::max(slots, P->class_groups[k]);
@@ -225,7 +231,7 @@ exx_status select_solve(exx_plan_t P, int threads, int depth, int cls) {
 exx_status ensure_slots(exx_plan_t P) {
   if (P->slot_ws) return EXX_OK;
   char* sw = nullptr;
-  const long long sb = solve_slot_bytes(P->opt.precision == EXX_PREC_MIXED, P->max_pe);
+  const long long sb = solve_slot_bytes(P->opt.precision == EXX_PREC_MIXED, slot_stride(P));
   if (dev_alloc(P, &sw, (size_t)P->n_slots * sb, "CG vectors")) return EXX_ENOMEM;
   P->slot_ws = sw;
   return EXX_OK;
@@ -243,6 +249,7 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
     a.cls_id = ncls > 1 ? k : -1;
     a.threads = P->class_threads[k];
     a.depth = P->class_depth[k];
+    a.quads = C.quads;
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
     const int groups = (int)std::min<long long>(P->class_groups[k], a.npair);
     EXX_HIP(P, launch_solve(a, C.n_cols, C.Zmax, groups, s));
@@ -287,7 +294,8 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
       }
     for (int ci = 0; ci < nc; ++ci) {
       const int* c = order[ci];
-      if (solve_groups_per_cu(P->geo, P->classes[k].n_cols, P->classes[k].Zmax, base.mixed, c[0], c[1]) < 1)
+      if (solve_groups_per_cu(P->geo, P->classes[k].n_cols, P->classes[k].Zmax, base.mixed, P->classes[k].quads, c[0],
+                              c[1]) < 1)
         continue;
       exx_status st = select_solve(P, c[0], c[1], k);
       if (st != EXX_OK) return st;
@@ -302,6 +310,7 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
       a.cls_id = ncls > 1 ? k : -1;
       a.threads = c[0];
       a.depth = c[1];
+      a.quads = P->classes[k].quads;
       Batch B;
       B.cls = P->class_dev;
       B.pairs = P->pairs;
@@ -517,46 +526,68 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
       }
     }
   }
-  // CG layout of an orthorhombic cell: runs of four columns per thread (the
-  // quad layout) for mixed plans by default or when asked, if every class's
-  // runs fit one workgroup of 1024 threads and one LDS row of 88 points with
-  // the runs' 4-point neighbour vectors (R / spacing + 7 on both sides of an
-  // origin that is a multiple of 4, so that runs start at even positions);
-  // else one column per thread slot
-  bool quads = !general && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED &&
-                                                  opt.solve_threads != 512));
+  // CG layout of each sphere class of an orthorhombic cell: runs of four
+  // columns per thread (the quad layout) for mixed plans by default or when
+  // asked, if the class's runs fit one workgroup of 1024 threads and its row
+  // fits the LDS plane with the runs' 4-point neighbour vectors (R / spacing + 7
+  // points on both sides of an origin that is a multiple of 4, so that runs
+  // start at even positions); else single columns
+  const bool want_quads =
+      !general && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED && opt.solve_threads != 512));
+  auto quads_fit = [&](const ClassHost& C) {
+    return C.n_cols <= 4 * 1024 && (C.Rc[0] + 7 + 3) / 4 * 4 + C.Rc[0] + 7 <= kLdsWX - 1;
+  };
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
-  int max_zmax = 0, maxRc0 = 0, maxRc1 = 0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    max_pe = max_halo = max_me = max_cols = 0;
-    max_zmax = maxRc0 = maxRc1 = 0;
-    for (size_t k = 0; k < radii.size(); ++k) {
-      std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs,
-                                                    &classes[k])
-                              : build_class(g.L, g.N, radii[k], me_radii[k], n, quads, &classes[k]);
+  int max_zmax = 0, maxRq = -1, maxRc = -1, maxRc1 = 0;
+  for (size_t k = 0; k < radii.size(); ++k) {
+    std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs,
+                                                  &classes[k])
+                            : build_class(g.L, g.N, radii[k], me_radii[k], n, want_quads, &classes[k]);
+    if (!e.empty()) return fail(P, EXX_EINVAL, e);
+    if (classes[k].quads && !quads_fit(classes[k])) {
+      if (opt.cg_layout == 2)
+        return fail(P, EXX_EINVAL, "quad layout: the PE sphere needs more than 1024 runs or a wider LDS row");
+      e = build_class(g.L, g.N, radii[k], me_radii[k], n, false, &classes[k]);
       if (!e.empty()) return fail(P, EXX_EINVAL, e);
-      const ClassHost& C = classes[k];
+    }
+  }
+  auto class_extents = [&]() {
+    max_pe = max_halo = max_me = max_cols = 0;
+    max_zmax = maxRc1 = 0;
+    maxRq = maxRc = -1;
+    for (const ClassHost& C : classes) {
       max_pe = std::max(max_pe, C.n_pe);
       max_halo = std::max(max_halo, C.n_halo);
       max_me = std::max(max_me, C.n_me);
       max_cols = std::max<long long>(max_cols, C.n_cols);
       max_zmax = std::max(max_zmax, C.Zmax);
-      maxRc0 = std::max(maxRc0, C.Rc[0]);
+      if (C.quads) maxRq = std::max(maxRq, C.Rc[0]); else maxRc = std::max(maxRc, C.Rc[0]);
       maxRc1 = std::max(maxRc1, C.Rc[1]);
     }
-    if (!quads) break;
-    const int cx4 = (maxRc0 + 7 + 3) / 4 * 4;
-    if (max_cols <= 4 * 1024 && cx4 + maxRc0 + 7 <= kLdsWX - 1) break;
-    if (opt.cg_layout == 2)
-      return fail(P, EXX_EINVAL, "quad layout: the PE sphere needs more than 1024 runs or a wider LDS row");
-    quads = false;
+  };
+  class_extents();
+  // one LDS plane origin for every class: a multiple of 4 at least R + 7 from
+  // the left edge for quad classes (R + n for column classes), and the row
+  // must hold R + 7 (R + n) points right of it
+  if (maxRq >= 0) {
+    g.lds_cx = (std::max(maxRq + 7, maxRc + n) + 3) / 4 * 4;
+    if (g.lds_cx + maxRq + 7 > kLdsWX - 1 || (maxRc >= 0 && g.lds_cx + maxRc + n > kLdsWX - 1)) {
+      // the classes do not share a plane origin: every class in columns
+      if (opt.cg_layout == 2)
+        return fail(P, EXX_EINVAL, "quad layout: the sphere classes do not fit one LDS row");
+      for (size_t k = 0; k < radii.size(); ++k)
+        if (classes[k].quads) {
+          std::string e = build_class(g.L, g.N, radii[k], me_radii[k], n, false, &classes[k]);
+          if (!e.empty()) return fail(P, EXX_EINVAL, e);
+        }
+      class_extents();
+    }
   }
-  g.quads = quads ? 1 : 0;
-  g.lds_cx = quads ? (maxRc0 + 7 + 3) / 4 * 4 : maxRc0 + n;
+  if (maxRq < 0) g.lds_cx = maxRc + n;
   g.lds_cy = maxRc1 + n;
   g.lds_wx = kLdsWX;
   g.lds_wy = 2 * g.lds_cy + 1;
-  if (!quads && 2 * g.lds_cx + 1 > kLdsWX)
+  if (maxRq < 0 && 2 * g.lds_cx + 1 > kLdsWX)
     return fail(P, EXX_EINVAL, "PE sphere too wide: need 2 (R_PE / spacing + n) + 1 <= 88 grid points");
   if (!solve_supported((int)std::min<long long>(max_cols, 1 << 30), 512))
     return fail(P, EXX_EINVAL, "PE sphere has too many columns for one workgroup (R_PE / spacing too large)");
@@ -684,9 +715,10 @@ void default_solve_variants(exx_plan_t P) {
   const int cpt = P->geo.gen ? 4 : 3;
   P->class_threads.assign(P->classes.size(), 1024);
   P->class_depth.assign(P->classes.size(), dp);
-  if (P->geo.quads) return;   // one run per thread: 1024 threads
-  for (size_t k = 0; k < P->classes.size(); ++k)
+  for (size_t k = 0; k < P->classes.size(); ++k) {
+    if (P->classes[k].quads) continue;   // one run per thread: 1024 threads
     P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= cpt * 1024 ? 1024 : 512);
+  }
 }
 
 // A new cell for the same proto-subdomains (fixed grid offsets, Sec. III B 2):
@@ -1075,7 +1107,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.bx_ws = P->bx_ws;
     a.rstride = P->rstride;
     a.slot_ws = P->slot_ws;
-    a.sstride = P->max_pe;
+    a.sstride = slot_stride(P);
     a.outIt = P->pIt;
     a.outRes = P->pRes;
     a.outUpd = P->pUpd;
@@ -1238,7 +1270,11 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->cell_strain = P->cell_strain;
   out->reassemblies = P->reassemblies;
   out->n_arms = P->geo.gen ? P->geo.n_arms : 3;
-  out->cg_layout = P->geo.quads ? 2 : 1;
+  {
+    int nq = 0;
+    for (const ClassHost& C : P->classes) nq += C.quads ? 1 : 0;
+    out->cg_layout = nq == 0 ? 1 : (nq == (int)P->classes.size() ? 2 : 3);
+  }
   out->solve_threads = P->solve_threads;
   out->solve_depth = P->solve_depth;
   out->tune_ms = P->tune_ms;

@@ -43,9 +43,6 @@ struct Geo {
   // General (non-orthogonal) cells.  gen == 0: orthorhombic, offsets are
   // r = (o_x d_x, o_y d_y, o_z d_z) and the Laplacian is the axis stencil.
   int gen;
-  // Orthorhombic cells only: 1 when the columns are laid out in runs of four
-  // x-adjacent columns (one run per CG thread), 0 for single columns.
-  int quads;
   double A[9];          // r = A o, A[a + 3 al] = h_{a al} / N_al
   int perm[3];          // CG frame: (x', y', z') = (o[perm[0]], o[perm[1]], o[perm[2]])
   int n_arms;           // NK Laplacian: sum over arms of coef * eq. d2_1 along u
@@ -106,7 +103,7 @@ struct ClassHost {
   int Wm[3] = {0, 0, 0};
   int Rc[3] = {0, 0, 0};
   bool general = false;
-  bool quads = false;
+  bool quads = false;         // orthorhombic quad layout (runs of four columns per CG thread)
   int perm[3] = {0, 1, 2};
   std::vector<int4> cols;
   std::vector<int> plane_start;

@@ -87,13 +87,14 @@ struct SolveArgs {
   const PairDev* prev_pairs = nullptr;
   int threads = 1024;          // workgroup size of the solve (512 or 1024)
   int depth = 1;               // planes of loads in flight ahead of their use (1 or 2)
+  bool quads = false;          // the class's vectors are in the quad layout
 };
 
 hipError_t launch_rhs(const Geo& g, const Batch& B, long long max_pe, const double* rho_ws, double* b_ws,
                       long long rstride, const double* halo_ws, long long hstride, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int max_cols, int max_zmax, int groups, hipStream_t s);
 size_t solve_lds_bytes(const Geo& g, int max_zmax);
-int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, int threads, int depth);
+int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, bool quads, int threads, int depth);
 bool solve_supported(int max_cols, int threads);
 long long solve_slot_bytes(bool mixed, long long sstride);
 hipError_t launch_finalize(const Geo& g, const Batch& B, const double* rho_ws, const double* v_ws, long long rstride,

@@ -60,7 +60,7 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
   // general cell: the NK arms in the CG frame (x', y', z') = o[perm]
   a.gen = in.g.gen;
-  a.quads = in.g.quads;
+  a.quads = in.quads ? 1 : 0;
   std::memset(&a.G, 0, sizeof(a.G));
   if (a.gen) {
     for (int q = 0; q < 4; ++q) a.G.w[q] = in.g.w2[q];
@@ -113,11 +113,12 @@ bool solve_supported(int max_cols, int threads) {
   return false;
 }
 
-int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, int threads, int depth) {
+int solve_groups_per_cu(const Geo& g, int max_cols, int max_zmax, bool mixed, bool quads, int threads, int depth) {
   if (!solve_supported(max_cols, threads)) return 0;
   SolveArgs a;
   a.g = g;
   a.mixed = mixed;
+  a.quads = quads;
   a.threads = threads;
   a.depth = depth;
   int occ = 0;

@@ -299,3 +299,27 @@ def test_quad_layout_falls_back_for_wide_spheres():
     g = gpu_eval(cfg, orbs, phi, want_D=False, precision=exx.EXX_PREC_MIXED)
     assert g["stats"]["cg_layout"] == 1
     assert g["stats"]["n_unconverged"] == 0
+
+
+def test_layout_per_sphere_class():
+    """Variable radii where the largest class (R_PE 7.1 at spacing 0.2: 1,044
+    runs) does not fit the quad layout: that class keeps single columns, the
+    others run quads (stats report both).  The mixed result meets the mixed
+    bars against the FP64 path (single columns) on the same inputs."""
+    from paper_2011_07209_amd import exx
+    cfg = synth.custom(key="layout-classes", cell=(30.0, 30.0, 30.0), grid=(150, 150, 150), n_orb=6, R_pair=8.0,
+                       R_PE=6.0, R_ME=9.0, l_max=4, stencil_n=3, cg_tol=1e-10, seed_index=85,
+                       R_PE_classes=(5.0, 1.05, 3), R_orb_range=(5.0, 7.1))
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    m = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    f = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_FP64)
+    radii = sorted({round(r, 6) for r in m["pairs"]["R_PE"]}) if "R_PE" in m["pairs"] else None
+    print(f"[layout classes] layout={m['stats']['cg_layout']} classes={m['stats']['n_classes']} radii={radii} "
+          f"E mixed={m['E']:.12f} fp64={f['E']:.12f}", flush=True)
+    assert m["stats"]["cg_layout"] == 3 and f["stats"]["cg_layout"] == 1
+    assert [tuple(x) for x in m["pairs"]["ij"]] == [tuple(x) for x in f["pairs"]["ij"]]
+    assert m["stats"]["n_unconverged"] == 0 and f["stats"]["n_unconverged"] == 0
+    assert abs(m["E"] - f["E"]) <= MIXED_E_PER_MOLECULE * cfg.n_orb / 4
+    assert rel1(m["sigma"], f["sigma"]) <= MIXED_S
+    assert rel1(m["D"], f["D"]) <= MIXED_D
