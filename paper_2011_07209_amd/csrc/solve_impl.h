@@ -1144,36 +1144,70 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
 }
 
 // FP64 true residual (as cg_true_residual) on the quad layout, zero at dead
-// slots.
+// slots.  It sweeps twice, once per half of the run (columns 2h, 2h+1), with
+// a z window of 2-point FP64 vectors: a window of whole runs in FP64 does not
+// fit the registers of a 1024-thread workgroup, and the spilled version spent
+// more time in the few reliable updates of a solve than in all of its FP32
+// iterations.  Each plane still stages the run's four values in LDS.
 template <int NS, typename TR>
 __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& cl, const int* pst, int Zmax,
                                         const double* __restrict__ x, const double* __restrict__ b,
                                         TR* __restrict__ r, double rs, double* pl0, double* pl1) {
-  const V4<double> zero = {0, 0, 0, 0};
-  V4<double> win[2 * NS + 1];
-#pragma unroll
-  for (int k = 0; k < 2 * NS + 1; ++k) {
-    const int zz = -Zmax - NS + k;
-    win[k] = EXX_QVALID(zz) ? ld_quad(x, EXX_QIDX(zz)) : zero;
-  }
+  using V2d = double __attribute__((ext_vector_type(2)));
+  using V2r = TR __attribute__((ext_vector_type(2)));
+  const V2d zero2 = {0, 0};
+  const V4<double> zero4 = {0, 0, 0, 0};
+  auto ld_half = [](const double* base, int idx) {
+    return *(const EXX_GLOBAL V2d*)((const EXX_GLOBAL char*)base + (unsigned)idx * 8u);
+  };
   double acc = 0.0;
-  for (int z = -Zmax; z <= Zmax; ++z) {
-    const int zc = z + NS + 1;        // plane entering the window
-    const V4<double> nx = EXX_QVALID(zc) ? ld_quad(x, EXX_QIDX(zc)) : zero;
-    const V4<double> cb = EXX_QVALID(z) ? ld_quad(b, EXX_QIDX(z)) : zero;
-    double* pl = (z & 1) ? pl1 : pl0;
-    if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
-    __syncthreads();
-    if (EXX_QVALID(z)) {
-      const V4<double> rt = live_only(cl, z, cb - apply_quad<NS, double>(S, win, pl, cl.pos));
-      const V4<double> ro = rt * rs;
-      V4<TR> o = {(TR)ro.x, (TR)ro.y, (TR)ro.z, (TR)ro.w};
-      st_quad(r, EXX_QIDX(z), o);
-      acc += dot4(rt, rt);
-    }
+  for (int h = 0; h < 2; ++h) {
+    const int off = 2 * h;   // the half's first column within the run
+    V2d win[2 * NS + 1];
 #pragma unroll
-    for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
-    win[2 * NS] = nx;
+    for (int k = 0; k < 2 * NS + 1; ++k) {
+      const int zz = -Zmax - NS + k;
+      win[k] = EXX_QVALID(zz) ? ld_half(x, EXX_QIDX(zz) + off) : zero2;
+    }
+    for (int z = -Zmax; z <= Zmax; ++z) {
+      const int zc = z + NS + 1;        // plane entering the window
+      const V2d nx = EXX_QVALID(zc) ? ld_half(x, EXX_QIDX(zc) + off) : zero2;
+      const V4<double> xq = EXX_QVALID(z) ? ld_quad(x, EXX_QIDX(z)) : zero4;
+      const V2d cb = EXX_QVALID(z) ? ld_half(b, EXX_QIDX(z) + off) : zero2;
+      double* pl = (z & 1) ? pl1 : pl0;
+      if (cl.zq >= 0) lds_quad_store(pl + cl.pos, xq);
+      __syncthreads();
+      if (EXX_QVALID(z)) {
+        // plane values at x offsets -4 .. 5 from the half's first column
+        const int p = cl.pos + off;
+        const V2d l2 = *reinterpret_cast<const V2d*>(pl + p - 4), l1 = *reinterpret_cast<const V2d*>(pl + p - 2);
+        const V2d r1 = *reinterpret_cast<const V2d*>(pl + p + 2), r2 = *reinterpret_cast<const V2d*>(pl + p + 4);
+        const V2d c = win[NS];
+        const double row[10] = {l2.x, l2.y, l1.x, l1.y, c.x, c.y, r1.x, r1.y, r2.x, r2.y};
+        V2d sx = zero2, sy = zero2, sz = zero2;
+#pragma unroll
+        for (int k = 1; k <= NS; ++k) {
+          const V2d up = *reinterpret_cast<const V2d*>(pl + p + k * kLdsWX);
+          const V2d dn = *reinterpret_cast<const V2d*>(pl + p - k * kLdsWX);
+          const V2d xr = {row[4 + k], row[5 + k]}, xl = {row[4 - k], row[5 - k]};
+          sx += S.w[k] * (xr + xl);
+          sy += S.w[k] * (up + dn);
+          sz += S.w[k] * (win[NS + k] + win[NS - k]);
+        }
+        V2d rt = cb - (-(S.diag * c + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz));
+        const int az = abs(z);
+        rt.x = az <= cl.zr[off] ? rt.x : 0.0;
+        rt.y = az <= cl.zr[off + 1] ? rt.y : 0.0;
+        const V2d ro = rt * rs;
+        *(EXX_GLOBAL V2r*)((EXX_GLOBAL char*)r + (unsigned)(EXX_QIDX(z) + off) * (unsigned)sizeof(TR)) =
+            V2r{(TR)ro.x, (TR)ro.y};
+        acc += rt.x * rt.x + rt.y * rt.y;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
+      win[2 * NS] = nx;
+    }
+    __syncthreads();   // the next half's first plane reuses the buffer of this half's last one
   }
   return acc;
 }
