@@ -1146,9 +1146,8 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
 // FP64 true residual (as cg_true_residual) on the quad layout, zero at dead
 // slots.  It sweeps twice, once per half of the run (columns 2h, 2h+1), with
 // a z window of 2-point FP64 vectors: a window of whole runs in FP64 does not
-// fit the registers of a 1024-thread workgroup, and the spilled version spent
-// more time in the few reliable updates of a solve than in all of its FP32
-// iterations.  Each plane still stages the run's four values in LDS.
+// fit the registers of a 1024-thread workgroup (its plane loop spilled to
+// scratch memory).  Each plane still stages the run's four values in LDS.
 template <int NS, typename TR>
 __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& cl, const int* pst, int Zmax,
                                         const double* __restrict__ x, const double* __restrict__ b,
