@@ -343,13 +343,39 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const ClassDev* __restr
     const double rh = rho[k];
     e += rh * x[k];
     double dxi[3] = {0.0, 0.0, 0.0};
-    for (int q = 1; q <= g.n; ++q) {
-      dxi[0] += g.w1[q] * (point_value(C, g.n, x, halo, o.x + q, o.y, o.z, false) -
-                           point_value(C, g.n, x, halo, o.x - q, o.y, o.z, false));
-      dxi[1] += g.w1[q] * (point_value(C, g.n, x, halo, o.x, o.y + q, o.z, false) -
-                           point_value(C, g.n, x, halo, o.x, o.y - q, o.z, false));
-      dxi[2] += g.w1[q] * (point_value(C, g.n, x, halo, o.x, o.y, o.z + q, false) -
-                           point_value(C, g.n, x, halo, o.x, o.y, o.z - q, false));
+    if (!C.pe_map) {
+      // orthorhombic tables: the point's own column and plane serve its z and
+      // its x/y neighbours (the same lookups as point_value, fewer of them)
+      const int mx = o.x + C.Rg[0] + g.n, my = o.y + C.Rg[1] + g.n, mz = o.z + C.Rg[2] + g.n;
+      const int m2 = mx + C.Wm[0] * my;
+      const int plane = C.Wm[0] * C.Wm[1];
+      const int col = C.col_map[m2], zr = C.zr_map[m2];
+      const int ps = C.plane_start[o.z + C.Zmax];
+      auto in_plane = [&](int dm) -> double {
+        const int m = m2 + dm;
+        if (abs(o.z) <= C.zr_map[m]) return x[ps + C.col_map[m]];
+        const int hh = C.halo_map[m + plane * mz];
+        return hh >= 0 ? halo[hh] : 0.0;
+      };
+      auto along_z = [&](int oz) -> double {
+        if (abs(oz) <= zr) return x[C.plane_start[oz + C.Zmax] + col];
+        const int hh = C.halo_map[m2 + plane * (oz + C.Rg[2] + g.n)];
+        return hh >= 0 ? halo[hh] : 0.0;
+      };
+      for (int q = 1; q <= g.n; ++q) {
+        dxi[0] += g.w1[q] * (in_plane(q) - in_plane(-q));
+        dxi[1] += g.w1[q] * (in_plane(q * C.Wm[0]) - in_plane(-q * C.Wm[0]));
+        dxi[2] += g.w1[q] * (along_z(o.z + q) - along_z(o.z - q));
+      }
+    } else {
+      for (int q = 1; q <= g.n; ++q) {
+        dxi[0] += g.w1[q] * (point_value(C, g.n, x, halo, o.x + q, o.y, o.z, false) -
+                             point_value(C, g.n, x, halo, o.x - q, o.y, o.z, false));
+        dxi[1] += g.w1[q] * (point_value(C, g.n, x, halo, o.x, o.y + q, o.z, false) -
+                             point_value(C, g.n, x, halo, o.x, o.y - q, o.z, false));
+        dxi[2] += g.w1[q] * (point_value(C, g.n, x, halo, o.x, o.y, o.z + q, false) -
+                             point_value(C, g.n, x, halo, o.x, o.y, o.z - q, false));
+      }
     }
     for (int al = 0; al < 3; ++al) dxi[al] *= g.inv_d[al];
     double rb[3];
