@@ -101,15 +101,17 @@ typedef struct {
      proto-subdomains are rebuilt from scratch at the new cell with the plan's
      radii (0: never)                                                         */
   double reassemble_strain;
-  /* layout of the CG vectors of an orthorhombic cell, per sphere class: 0
-     picks the quad layout for mixed plans (unless solve_threads is 512) for
-     every class where it fits, single columns elsewhere; 1: single columns
-     (each CG thread owns whole columns of the sphere); 2: quad layout for
-     every class (each CG thread owns a run of four x-adjacent columns, padded
-     with zero slots to the run's tallest column, and reads its in-plane
-     neighbours as 2-point vectors; 1024 threads; EXX_EINVAL when a class
-     needs more than 1024 runs, for general cells, with cell_fluctuation and
-     with solve_threads 512)                                                  */
+  /* layout of the CG vectors, per sphere class: 0 picks the quad layout for
+     mixed plans (unless solve_threads is 512) for every class where it fits,
+     single columns elsewhere; 1: single columns (each CG thread owns whole
+     columns of the sphere); 2: quad layout for every class (each CG thread
+     owns a run of four adjacent columns, padded with zero slots to the run's
+     tallest column, and reads its in-plane neighbours as 2-point vectors;
+     1024 threads).  A general cell takes it when no Laplacian arm leaves the
+     sweep plane, at most one diagonal arm lies in it, and its columns are
+     symmetric about the sweep plane.  With 2, EXX_EINVAL when a class does
+     not fit (more than 1024 runs, other arms or columns), with
+     cell_fluctuation and with solve_threads 512                              */
   int cg_layout;
 } exx_options;
 

@@ -514,7 +514,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     int best_tilt = 0;
     for (int sw = 2; sw >= 0; --sw) {
       ClassHost T;
-      std::string e = build_class_general(h, g.N, sw, radii[big], me_radii[big], n, arms, all_dirs, &T);
+      std::string e = build_class_general(h, g.N, sw, radii[big], me_radii[big], n, arms, all_dirs, false, &T);
       if (!e.empty()) return fail(P, EXX_EINVAL, e);
       int tilt = 0;
       for (const NkArm& A : arms)
@@ -532,22 +532,46 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
   // fits the LDS plane with the runs' 4-point neighbour vectors (R / spacing + 7
   // points on both sides of an origin that is a multiple of 4, so that runs
   // start at even positions); else single columns
-  const bool want_quads =
-      !general && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED && opt.solve_threads != 512));
+  // General cells take the quad layout when no arm leaves the sweep plane and
+  // the in-plane arms are the two axes and at most one diagonal (|u_x'| =
+  // |u_y'| = 1), and the columns need no padding (checked by the builder);
+  // not with cell_fluctuation, whose later cells may bring other arms.
+  bool arms_fit = true;
+  if (general) {
+    int diagonals = 0;
+    for (const NkArm& A : arms) {
+      const int ux = A.u[g.perm[0]], uy = A.u[g.perm[1]], uz = A.u[g.perm[2]];
+      if (uz != 0 && (ux != 0 || uy != 0)) arms_fit = false;
+      if (ux != 0 && uy != 0) {
+        ++diagonals;
+        if (std::abs(ux) != 1 || std::abs(uy) != 1) arms_fit = false;
+      }
+    }
+    arms_fit = arms_fit && diagonals <= 1 && !opt.cell_fluctuation;
+  }
+  const bool want_quads = arms_fit && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED &&
+                                                              opt.solve_threads != 512));
+  if (opt.cg_layout == 2 && !arms_fit)
+    return fail(P, EXX_EINVAL, "quad layout: an arm of the cell's Laplacian leaves the sweep plane, or more than one "
+                               "diagonal arm lies in it");
   auto quads_fit = [&](const ClassHost& C) {
     return C.n_cols <= 4 * 1024 && (C.Rc[0] + 7 + 3) / 4 * 4 + C.Rc[0] + 7 <= kLdsWX - 1;
   };
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
   int max_zmax = 0, maxRq = -1, maxRc = -1, maxRc1 = 0;
   for (size_t k = 0; k < radii.size(); ++k) {
-    std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs,
-                                                  &classes[k])
-                            : build_class(g.L, g.N, radii[k], me_radii[k], n, want_quads, &classes[k]);
+    auto build = [&](bool q) {
+      return general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs, q, &classes[k])
+                     : build_class(g.L, g.N, radii[k], me_radii[k], n, q, &classes[k]);
+    };
+    std::string e = build(want_quads);
     if (!e.empty()) return fail(P, EXX_EINVAL, e);
+    if (want_quads && opt.cg_layout == 2 && !classes[k].quads)
+      return fail(P, EXX_EINVAL, "quad layout: the cell's columns are not symmetric about the sweep plane");
     if (classes[k].quads && !quads_fit(classes[k])) {
       if (opt.cg_layout == 2)
         return fail(P, EXX_EINVAL, "quad layout: the PE sphere needs more than 1024 runs or a wider LDS row");
-      e = build_class(g.L, g.N, radii[k], me_radii[k], n, false, &classes[k]);
+      e = build(false);
       if (!e.empty()) return fail(P, EXX_EINVAL, e);
     }
   }
@@ -577,7 +601,9 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
         return fail(P, EXX_EINVAL, "quad layout: the sphere classes do not fit one LDS row");
       for (size_t k = 0; k < radii.size(); ++k)
         if (classes[k].quads) {
-          std::string e = build_class(g.L, g.N, radii[k], me_radii[k], n, false, &classes[k]);
+          std::string e = general ? build_class_general(h, g.N, g.perm[2], radii[k], me_radii[k], n, arms, all_dirs,
+                                                        false, &classes[k])
+                                  : build_class(g.L, g.N, radii[k], me_radii[k], n, false, &classes[k]);
           if (!e.empty()) return fail(P, EXX_EINVAL, e);
         }
       class_extents();
@@ -814,8 +840,8 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (!(opt.reassemble_strain >= 0.0) || !std::isfinite(opt.reassemble_strain))
     return fail(nullptr, EXX_EINVAL, "reassemble_strain must be >= 0");
   if (opt.cg_layout < 0 || opt.cg_layout > 2) return fail(nullptr, EXX_EINVAL, "cg_layout must be 0, 1 or 2");
-  if (opt.cg_layout == 2 && (general || opt.cell_fluctuation))
-    return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) is for orthorhombic cells without cell_fluctuation");
+  if (opt.cg_layout == 2 && opt.cell_fluctuation)
+    return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) is not combined with cell_fluctuation");
   if (opt.cg_layout == 2 && opt.solve_threads == 512)
     return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) runs 1024 threads per workgroup");
 
@@ -1318,7 +1344,7 @@ exx_status exx_subdomain_counts(const double h[9], const int grid[3], double R_P
     if (!(det3(h) > 0.0)) return fail(nullptr, EXX_EINVAL, "the cell tensor must have a positive determinant");
     std::vector<NkArm> arms;
     e = build_nk_arms(h, N, &arms);
-    if (e.empty()) e = build_class_general(h, N, 2, R_PE, R_ME, stencil_n, arms, false, &C);
+    if (e.empty()) e = build_class_general(h, N, 2, R_PE, R_ME, stencil_n, arms, false, false, &C);
   } else {
     e = build_class(L, N, R_PE, R_ME, stencil_n, false, &C);
   }

@@ -124,8 +124,11 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
 // sweeps along grid axis `sweep`.
 // all_dirs: Dirichlet points along every nearest-neighbour direction (for
 // cells that may change later), else along the arms and the lattice axes.
+// quads: the quad layout when every column is symmetric about the sweep
+// plane z' = 0 (else, and without quads, padded single columns; ClassHost.quads
+// tells which).
 std::string build_class_general(const double h[9], const int N[3], int sweep, double R_PE, double R_ME, int n,
-                                const std::vector<NkArm>& arms, bool all_dirs, ClassHost* out);
+                                const std::vector<NkArm>& arms, bool all_dirs, bool quads, ClassHost* out);
 // The NK Laplacian of cell h on grid N (Algorithm 1 and eq. lapG_mod_nk3d).
 std::string build_nk_arms(const double h[9], const int N[3], std::vector<NkArm>* arms);
 // Unnormalised solid harmonics P_lm(A o) of the class's PE points, laid out

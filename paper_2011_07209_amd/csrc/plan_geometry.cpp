@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 
 #include "exx_internal.h"
 #include "harmonics.h"
@@ -38,6 +39,67 @@ inline double r2_of(const double L[3], const int N[3], int ox, int oy, int oz) {
   double y = L[1] * ((double)oy / N[1]);
   double z = L[2] * ((double)oz / N[2]);
   return x * x + y * y + z * z;
+}
+
+// One column of a vector layout: (x, y) in the CG frame, the column's own
+// half-height zr (-1 outside the sphere) and the half-height zq of the unit
+// (column or run) that the plane prefixes are taken over.
+struct LayCol {
+  int ox, oy, zr, zq;
+};
+
+// The quad layout's columns (see the file comment) for a cross-section whose
+// column (x, y), |x| <= Rx, |y| <= Ry, has half-height zr_of(x, y), or -1
+// outside the sphere: runs of four x-adjacent columns in their processing
+// order, each column with its own half-height and its run's.
+std::vector<LayCol> quad_runs(int Rx, int Ry, const std::function<int(int, int)>& zr_of) {
+  std::vector<LayCol> out;
+  auto floor4 = [](int v) { return v >= 0 ? v / 4 : -((-v + 3) / 4); };
+  // Runs start at x = 4k + s with s = 0 on even rows and 2 on odd rows, so
+  // that the runs' 8-byte halves in the LDS plane fall on every bank pair,
+  // not only on every other one.
+  auto shift = [](int oy) { return 2 * (oy & 1); };
+  struct Run { int x0, oy, zq; };
+  std::vector<Run> runs;
+  for (int oy = -Ry; oy <= Ry; ++oy)
+    for (int k = floor4(-Rx - shift(oy)); 4 * k + shift(oy) <= Rx; ++k) {
+      const int x0 = 4 * k + shift(oy);
+      int zq = -1;
+      for (int j = 0; j < 4; ++j) zq = std::max(zq, zr_of(x0 + j, oy));
+      if (zq >= 0) runs.push_back({x0, oy, zq});
+    }
+  // by run height (descending; plane z is a prefix), then within one height
+  // greedily: each next run takes the 8-byte bank pair (of 16) used least so
+  // far by its aligned group of 16 threads, then the pair (of 32) used least
+  // by its group of 32 (ties: row order)
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
+    if (a.zq != b.zq) return a.zq > b.zq;
+    if (a.oy != b.oy) return a.oy < b.oy;
+    return a.x0 < b.x0;
+  });
+  auto pair_of = [](const Run& r) { return (((r.x0 + 88 * r.oy) / 2) % 32 + 32) % 32; };
+  std::vector<Run> ordered;
+  ordered.reserve(runs.size());
+  for (size_t g0 = 0; g0 < runs.size();) {
+    size_t g1 = g0;
+    while (g1 < runs.size() && runs[g1].zq == runs[g0].zq) ++g1;
+    std::vector<Run> pending(runs.begin() + g0, runs.begin() + g1);
+    while (!pending.empty()) {
+      int used16[16] = {0}, used32[32] = {0};
+      for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used16[pair_of(ordered[t]) % 16];
+      for (size_t t = ordered.size() / 32 * 32; t < ordered.size(); ++t) ++used32[pair_of(ordered[t])];
+      auto key = [&](const Run& r) { return 64 * used16[pair_of(r) % 16] + used32[pair_of(r)]; };
+      size_t best = 0;
+      for (size_t i = 1; i < pending.size(); ++i)
+        if (key(pending[i]) < key(pending[best])) best = i;
+      ordered.push_back(pending[best]);
+      pending.erase(pending.begin() + best);
+    }
+    g0 = g1;
+  }
+  for (const Run& r : ordered)
+    for (int j = 0; j < 4; ++j) out.push_back({r.x0 + j, r.oy, zr_of(r.x0 + j, r.oy), r.zq});
+  return out;
 }
 
 }  // namespace
@@ -96,8 +158,7 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
 
   // the layout's columns: (ox, oy, half-height zr of the column itself or -1
   // outside the sphere, half-height zq of the unit the prefix is taken over)
-  struct Lay { int ox, oy, zr, zq; };
-  std::vector<Lay> lay;
+  std::vector<LayCol> lay;
   if (!quads) {
     for (const Col& c : cols) lay.push_back({c.ox, c.oy, c.zr, c.zr});
   } else {
@@ -105,51 +166,7 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
       if (std::abs(ox) > C.Rg[0]) return -1;
       return zr_at[(size_t)(ox + C.Rg[0]) + (size_t)Wr * (oy + C.Rg[1])];
     };
-    auto floor4 = [](int v) { return v >= 0 ? v / 4 : -((-v + 3) / 4); };
-    // Runs start at x = 4k + s with s = 0 on even rows and 2 on odd rows, so
-    // that the runs' 8-byte halves in the LDS plane fall on every bank pair,
-    // not only on every other one.
-    auto shift = [](int oy) { return 2 * (oy & 1); };
-    struct Run { int x0, oy, zq; };
-    std::vector<Run> runs;
-    for (int oy = -C.Rg[1]; oy <= C.Rg[1]; ++oy)
-      for (int k = floor4(-C.Rg[0] - shift(oy)); 4 * k + shift(oy) <= C.Rg[0]; ++k) {
-        const int x0 = 4 * k + shift(oy);
-        int zq = -1;
-        for (int j = 0; j < 4; ++j) zq = std::max(zq, zr_of(x0 + j, oy));
-        if (zq >= 0) runs.push_back({x0, oy, zq});
-      }
-    // by run height (descending; plane z is a prefix), then within one height
-    // greedily: each next run takes the 8-byte bank pair (of 16) used least so
-    // far by its aligned group of 16 threads, then the pair (of 32) used least
-    // by its group of 32 (ties: row order)
-    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
-      if (a.zq != b.zq) return a.zq > b.zq;
-      if (a.oy != b.oy) return a.oy < b.oy;
-      return a.x0 < b.x0;
-    });
-    auto pair_of = [](const Run& r) { return (((r.x0 + 88 * r.oy) / 2) % 32 + 32) % 32; };
-    std::vector<Run> ordered;
-    ordered.reserve(runs.size());
-    for (size_t g0 = 0; g0 < runs.size();) {
-      size_t g1 = g0;
-      while (g1 < runs.size() && runs[g1].zq == runs[g0].zq) ++g1;
-      std::vector<Run> pending(runs.begin() + g0, runs.begin() + g1);
-      while (!pending.empty()) {
-        int used16[16] = {0}, used32[32] = {0};
-        for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used16[pair_of(ordered[t]) % 16];
-        for (size_t t = ordered.size() / 32 * 32; t < ordered.size(); ++t) ++used32[pair_of(ordered[t])];
-        auto key = [&](const Run& r) { return 64 * used16[pair_of(r) % 16] + used32[pair_of(r)]; };
-        size_t best = 0;
-        for (size_t i = 1; i < pending.size(); ++i)
-          if (key(pending[i]) < key(pending[best])) best = i;
-        ordered.push_back(pending[best]);
-        pending.erase(pending.begin() + best);
-      }
-      g0 = g1;
-    }
-    for (const Run& r : ordered)
-      for (int j = 0; j < 4; ++j) lay.push_back({r.x0 + j, r.oy, zr_of(r.x0 + j, r.oy), r.zq});
+    lay = quad_runs(C.Rg[0], C.Rg[1], zr_of);
   }
   C.n_cols = (int)lay.size();
   C.cols.resize(lay.size());
@@ -286,7 +303,7 @@ void sphere_box(const double h[9], const int N[3], double R, int K[3]) {
 }  // namespace
 
 std::string build_class_general(const double h[9], const int N[3], int sweep, double R_PE, double R_ME, int n,
-                                const std::vector<NkArm>& arms, bool all_dirs, ClassHost* out) {
+                                const std::vector<NkArm>& arms, bool all_dirs, bool quads, ClassHost* out) {
   ClassHost& C = *out;
   C = ClassHost();
   C.R_PE = R_PE;
@@ -347,19 +364,41 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
     if (a.y != b.y) return a.y < b.y;
     return a.x < b.x;
   });
-  C.n_cols = (int)cols.size();
   C.Zmax = 0;
   for (const Col& c : cols) C.Zmax = std::max(C.Zmax, c.zr);
-  C.cols.resize(cols.size());
-  for (size_t c = 0; c < cols.size(); ++c) C.cols[c] = make_int4(cols[c].x, cols[c].y, cols[c].lo, cols[c].hi);
+  // The quad layout takes symmetric columns only (lo = -hi: no padding, as
+  // when the sweep axis is perpendicular to the other two lattice vectors);
+  // its phantom columns (outside the sphere) hold the empty interval [1, 0].
+  bool sym = true;
+  for (const Col& c : cols) sym = sym && c.lo == -c.hi;
+  C.quads = quads && sym;
+  struct GCol { int x, y, lo, hi, zq; };
+  std::vector<GCol> lay;
+  if (!C.quads) {
+    for (const Col& c : cols) lay.push_back({c.x, c.y, c.lo, c.hi, c.zr});
+    C.cols.resize(cols.size());
+    for (size_t c = 0; c < cols.size(); ++c) C.cols[c] = make_int4(cols[c].x, cols[c].y, cols[c].lo, cols[c].hi);
+  } else {
+    auto zr_of = [&](int x, int y) {
+      if (std::abs(x) > C.Rc[0] || std::abs(y) > C.Rc[1]) return -1;
+      const size_t m = (size_t)(x + C.Rc[0]) + (size_t)Wc0 * (y + C.Rc[1]);
+      return cnt[m] ? hi[m] : -1;
+    };
+    for (const LayCol& q : quad_runs(C.Rc[0], C.Rc[1], zr_of))
+      lay.push_back({q.ox, q.oy, q.zr >= 0 ? -q.zr : 1, q.zr >= 0 ? q.zr : 0, q.zq});
+    C.cols.resize(lay.size());
+    for (size_t c = 0; c < lay.size(); ++c)
+      C.cols[c] = make_int4(lay[c].x, lay[c].y, lay[c].lo <= lay[c].hi ? lay[c].hi : -1, lay[c].zq);
+  }
+  C.n_cols = (int)lay.size();
 
-  // planes: prefix of the padded columns; slots outside [lo, hi] are dead
+  // planes: prefix of the padded columns (or runs); slots outside [lo, hi] are dead
   C.plane_start.assign(2 * C.Zmax + 2, 0);
   long long acc = 0;
   for (int z = -C.Zmax; z <= C.Zmax; ++z) {
     C.plane_start[z + C.Zmax] = (int)acc;
     int nz = 0;
-    while (nz < C.n_cols && cols[nz].zr >= std::abs(z)) ++nz;
+    while (nz < C.n_cols && lay[nz].zq >= std::abs(z)) ++nz;
     acc += nz;
   }
   C.plane_start[2 * C.Zmax + 1] = (int)acc;
@@ -381,7 +420,7 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
   for (int z = -C.Zmax; z <= C.Zmax; ++z) {
     const int nz = C.plane_start[z + C.Zmax + 1] - C.plane_start[z + C.Zmax];
     for (int c = 0; c < nz; ++c) {
-      const Col& cc = cols[c];
+      const GCol& cc = lay[c];
       if (z < cc.lo || z > cc.hi) {
         C.me_off.push_back(make_short4(0, 0, 0, 1));
         continue;

@@ -58,6 +58,32 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   for (int q = 0; q < 4; ++q) a.S.w[q] = in.g.w2[q];
   for (int al = 0; al < 3; ++al) a.S.c[al] = in.g.inv_d2[al];
   a.S.diag = in.g.w2[0] * (a.S.c[0] + a.S.c[1] + a.S.c[2]);
+  a.S.cd = 0.0;
+  a.S.sd = 0;
+  if (in.g.gen && in.quads) {
+    // a general cell in the quad layout: its arms in the CG frame are the x',
+    // y' and z' axes and at most one diagonal of the sweep plane
+    double c[3] = {0.0, 0.0, 0.0}, sum = 0.0;
+    for (int m = 0; m < in.g.n_arms; ++m) {
+      const int ux = in.g.arm_u[m][in.g.perm[0]], uy = in.g.arm_u[m][in.g.perm[1]], uz = in.g.arm_u[m][in.g.perm[2]];
+      const double cf = in.g.arm_coef[m];
+      sum += cf;
+      if (uz != 0) {
+        if (ux != 0 || uy != 0) return hipErrorInvalidValue;
+        c[2] += cf;
+      } else if (ux != 0 && uy != 0) {
+        if (a.S.sd != 0 || (ux != 1 && ux != -1) || (uy != 1 && uy != -1)) return hipErrorInvalidValue;
+        a.S.cd = cf;
+        a.S.sd = ux * uy;   // oriented so that one step raises x' by one
+      } else if (ux != 0) {
+        c[0] += cf;
+      } else {
+        c[1] += cf;
+      }
+    }
+    for (int al = 0; al < 3; ++al) a.S.c[al] = c[al];
+    a.S.diag = in.g.w2[0] * sum;
+  }
   // general cell: the NK arms in the CG frame (x', y', z') = o[perm]
   a.gen = in.g.gen;
   a.quads = in.quads ? 1 : 0;

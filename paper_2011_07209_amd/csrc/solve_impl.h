@@ -22,8 +22,10 @@ namespace exx {
 template <typename T>
 struct StencilT {
   T w[4];      // second-derivative weights w_0..w_3
-  T c[3];      // 1 / d_al^2
-  T diag;      // w_0 (c_x + c_y + c_z)
+  T c[3];      // 1 / d_al^2 (general cells in the quad layout: the coefficients of the x', y', z' arms)
+  T cd;        // quad layout of a general cell: coefficient of its diagonal arm in the sweep plane (else 0)
+  int sd;      // that arm's step along y' for one step along +x' (+-1)
+  T diag;      // w_0 times the sum of the arm coefficients
 };
 
 template <typename T>
@@ -31,6 +33,8 @@ __device__ __forceinline__ StencilT<T> stencil_cast(const StencilT<double>& s) {
   StencilT<T> o;
   for (int q = 0; q < 4; ++q) o.w[q] = (T)s.w[q];
   for (int a = 0; a < 3; ++a) o.c[a] = (T)s.c[a];
+  o.cd = (T)s.cd;
+  o.sd = s.sd;
   o.diag = (T)s.diag;
   return o;
 }
@@ -983,28 +987,43 @@ __device__ __forceinline__ void lds_quad_store(T* p, V4<T> v) {
   *reinterpret_cast<V2*>(p + 2) = V2{v.z, v.w};
 }
 
-template <int K, int NS, typename T>
+// Terms of one step K of the stencil.  With DG, the cell's diagonal arm in the
+// sweep plane: step +K reaches (x + K, y + s K), read from the run's vector of
+// row y + s K and the one right of it; step -K reaches (x - K, y - s K), from
+// row y - s K and the vector left of it.
+template <int K, int NS, bool DG, typename T>
 __device__ __forceinline__ void quad_terms(const StencilT<T>& S, const V4<T> (&win)[2 * NS + 1], const T* pl,
-                                           int pos, V4<T> lf, V4<T> rt, V4<T>& sx, V4<T>& sy, V4<T>& sz) {
+                                           int pos, V4<T> lf, V4<T> rt, V4<T>& sx, V4<T>& sy, V4<T>& sz,
+                                           V4<T>& sdg) {
   if constexpr (K <= NS) {
     const V4<T> up = lds_quad(pl + pos + K * kLdsWX);
     const V4<T> dn = lds_quad(pl + pos - K * kLdsWX);
     sx += S.w[K] * (shift_right<K, T>(win[NS], rt) + shift_left<K, T>(lf, win[NS]));
     sy += S.w[K] * (up + dn);
     sz += S.w[K] * (win[NS + K] + win[NS - K]);
-    quad_terms<K + 1, NS, T>(S, win, pl, pos, lf, rt, sx, sy, sz);
+    if constexpr (DG) {
+      const int row = S.sd * K * kLdsWX;
+      const V4<T> fwd = S.sd > 0 ? up : dn;    // row y + s K
+      const V4<T> bwd = S.sd > 0 ? dn : up;    // row y - s K
+      const V4<T> fr = lds_quad(pl + pos + row + 4);
+      const V4<T> bl = lds_quad(pl + pos - row - 4);
+      sdg += S.w[K] * (shift_right<K, T>(fwd, fr) + shift_left<K, T>(bl, bwd));
+    }
+    quad_terms<K + 1, NS, DG, T>(S, win, pl, pos, lf, rt, sx, sy, sz, sdg);
   }
 }
 
 // -(stencil Laplacian) at the run's four points of the staged plane pl, with
-// the z window of the run; per point the arithmetic is that of apply_point.
-template <int NS, typename T>
+// the z window of the run; per point the arithmetic is that of apply_point
+// (of the general passes' arm sum, with DG).
+template <int NS, bool DG, typename T>
 __device__ __forceinline__ V4<T> apply_quad(const StencilT<T>& S, const V4<T> (&win)[2 * NS + 1], const T* pl,
                                             int pos) {
   const V4<T> lf = lds_quad(pl + pos - 4);
   const V4<T> rt = lds_quad(pl + pos + 4);
-  V4<T> sx = {0, 0, 0, 0}, sy = {0, 0, 0, 0}, sz = {0, 0, 0, 0};
-  quad_terms<1, NS, T>(S, win, pl, pos, lf, rt, sx, sy, sz);
+  V4<T> sx = {0, 0, 0, 0}, sy = {0, 0, 0, 0}, sz = {0, 0, 0, 0}, sdg = {0, 0, 0, 0};
+  quad_terms<1, NS, DG, T>(S, win, pl, pos, lf, rt, sx, sy, sz, sdg);
+  if constexpr (DG) return -(S.diag * win[NS] + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz + S.cd * sdg);
   return -(S.diag * win[NS] + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
 }
 
@@ -1024,7 +1043,7 @@ __device__ __forceinline__ V4<T> live_only(const ColsQ& cl, int z, V4<T> v) {
 
 // Pass A (as cg_pass_a) on the quad layout.  Dead slots hold r = p = 0, so p
 // stays zero there and adds nothing to the dot products.
-template <int NS, int PD, typename T>
+template <int NS, int PD, bool DG, typename T>
 __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax,
                                const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
                                double& pq, double& rr) {
@@ -1066,7 +1085,7 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
     T* pl = (z & 1) ? pl1 : pl0;
     if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
     __syncthreads();
-    if (EXX_QVALID(z)) pq += dot4(win[NS], apply_quad<NS, T>(S, win, pl, cl.pos));
+    if (EXX_QVALID(z)) pq += dot4(win[NS], apply_quad<NS, DG, T>(S, win, pl, cl.pos));
     const int zc = z + NS + 1;        // plane entering the window
     V4<T> v = zero;
     if (EXX_QVALID(zc)) {
@@ -1089,7 +1108,7 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
 
 // Pass B (as cg_pass_b) on the quad layout; the new r is kept to the run's
 // live slots, so dead slots keep r = 0 (and x = 0, since p is zero there).
-template <int NS, int PD, typename T>
+template <int NS, int PD, bool DG, typename T>
 __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
                                  const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
   const V4<T> zero = {0, 0, 0, 0};
@@ -1126,7 +1145,7 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
     __syncthreads();
     if (EXX_QVALID(z)) {
       const int idx = EXX_QIDX(z);
-      const V4<T> rn = live_only(cl, z, cr - alpha * apply_quad<NS, T>(S, win, pl, cl.pos));
+      const V4<T> rn = live_only(cl, z, cr - alpha * apply_quad<NS, DG, T>(S, win, pl, cl.pos));
       st_quad(x, idx, cx + alpha * win[NS]);
       st_quad(r, idx, rn);
       acc += dot4(rn, rn);
@@ -1148,7 +1167,7 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
 // a z window of 2-point FP64 vectors: a window of whole runs in FP64 does not
 // fit the registers of a 1024-thread workgroup (its plane loop spilled to
 // scratch memory).  Each plane still stages the run's four values in LDS.
-template <int NS, typename TR>
+template <int NS, bool DG, typename TR>
 __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& cl, const int* pst, int Zmax,
                                         const double* __restrict__ x, const double* __restrict__ b,
                                         TR* __restrict__ r, double rs, double* pl0, double* pl1) {
@@ -1183,7 +1202,7 @@ __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& 
         const V2d r1 = *reinterpret_cast<const V2d*>(pl + p + 2), r2 = *reinterpret_cast<const V2d*>(pl + p + 4);
         const V2d c = win[NS];
         const double row[10] = {l2.x, l2.y, l1.x, l1.y, c.x, c.y, r1.x, r1.y, r2.x, r2.y};
-        V2d sx = zero2, sy = zero2, sz = zero2;
+        V2d sx = zero2, sy = zero2, sz = zero2, sdg = zero2;
 #pragma unroll
         for (int k = 1; k <= NS; ++k) {
           const V2d up = *reinterpret_cast<const V2d*>(pl + p + k * kLdsWX);
@@ -1192,8 +1211,16 @@ __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& 
           sx += S.w[k] * (xr + xl);
           sy += S.w[k] * (up + dn);
           sz += S.w[k] * (win[NS + k] + win[NS - k]);
+          if constexpr (DG) {   // the diagonal arm: (x + k, y + s k) and (x - k, y - s k)
+            const int rs_k = S.sd * k * kLdsWX;
+            const V2d f = {pl[p + k + rs_k], pl[p + 1 + k + rs_k]};
+            const V2d bk = {pl[p - k - rs_k], pl[p + 1 - k - rs_k]};
+            sdg += S.w[k] * (f + bk);
+          }
         }
-        V2d rt = cb - (-(S.diag * c + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz));
+        V2d aq = S.diag * c + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz;
+        if constexpr (DG) aq += S.cd * sdg;
+        V2d rt = cb - (-aq);
         const int az = abs(z);
         rt.x = az <= cl.zr[off] ? rt.x : 0.0;
         rt.y = az <= cl.zr[off + 1] ? rt.y : 0.0;
@@ -1234,7 +1261,7 @@ __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T
                                        const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, const T* r, T* p,
                                        T beta, bool first, T* pl0, T* pl1, double& pq, double& rr) {
   if constexpr (QD)
-    cg_pass_a_quad<NS, PD, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+    cg_pass_a_quad<NS, PD, GEN, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else if constexpr (GEN && TL)
     cg_pass_a_tl<NS, CPT, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else if constexpr (GEN)
@@ -1248,7 +1275,7 @@ __device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT
                                          const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, T* x,
                                          const T* r_in, T* r, const T* p, T alpha, bool x_zero, T* pl0, T* pl1) {
   if constexpr (QD)
-    return cg_pass_b_quad<NS, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+    return cg_pass_b_quad<NS, PD, GEN, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
   else if constexpr (GEN && TL)
     return cg_pass_b_tl<NS, CPT, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
   else if constexpr (GEN)
@@ -1262,7 +1289,7 @@ __device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsO
                                                 int Zmax, const double* x, const double* b, TR* r, double rs,
                                                 double* pl0, double* pl1) {
   if constexpr (QD)
-    return cg_true_residual_quad<NS, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+    return cg_true_residual_quad<NS, GEN, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else if constexpr (GEN && TL)
     return cg_true_residual_tl<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else if constexpr (GEN)
@@ -1572,8 +1599,12 @@ hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_
 template <int NS>
 hipError_t solve_ns_dispatch(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
                              size_t lds, hipStream_t s, int* occ) {
-  if (a.quads) {   // one run of four columns per thread, 1024 threads
+  if (a.quads) {   // one run of four columns per thread, 1024 threads (GEN: with a diagonal arm)
     if (threads != 1024 || max_cols > 4 * 1024) return hipErrorInvalidValue;
+    if (a.gen) {
+      if (depth <= 1) return solve_instance_g<NS, 4, 1024, 1, true, false, true>(a, mixed, groups, lds, s, occ);
+      return solve_instance_g<NS, 4, 1024, 2, true, false, true>(a, mixed, groups, lds, s, occ);
+    }
     if (depth <= 1) return solve_instance_g<NS, 4, 1024, 1, false, false, true>(a, mixed, groups, lds, s, occ);
     return solve_instance_g<NS, 4, 1024, 2, false, false, true>(a, mixed, groups, lds, s, occ);
   }

@@ -89,8 +89,10 @@ def test_plan_rejects_invalid_arguments(lib, case):
         opt.cg_tol = 0.0
     elif case == "layout":
         opt.cg_layout = 3
-    elif case == "quad_general":   # runs of four columns are for orthorhombic cells
-        h[0, 1] = 0.5
+    elif case == "quad_general":   # runs of four columns need arms inside the sweep plane
+        from test_oracle_pins import _cell
+        h = _cell(12.0, 12.5, 11.5, 80, 95, 100)
+        grid = (60, 62, 58)
         opt.cg_layout = 2
     elif case == "quad_512":       # ... and one run per thread of 1024
         opt.cg_layout = 2

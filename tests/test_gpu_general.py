@@ -172,3 +172,26 @@ def test_general_cell_warm_start_over_displaced_steps():
         assert iters[1] < iters[0]
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("name", ["hexagonal", "monoclinic"])
+def test_general_cell_quad_layout(name):
+    """Cells whose one auxiliary direction is a diagonal of the sweep plane and
+    whose columns need no padding run the quad layout (runs of four columns,
+    the diagonal arm read from the neighbouring runs' vectors): mixed by
+    default, FP64 when asked, both against the oracle."""
+    h, N = CELLS[name]
+    cfg = _cfg(f"gen-quad-{name}", h, N, seed_index=77)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    o = oracle_eval(cfg, orbs, phi)
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    print(f"[quad {name}] layout {g['stats']['cg_layout']} E gpu={g['E']:.15g} oracle={o['E']:.15g}", flush=True)
+    assert g["stats"]["cg_layout"] == 2
+    assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
+    _check_mixed(g, o, cfg.n_orb)
+    f = gpu_eval(cfg, orbs, phi, cg_layout=2)
+    assert f["stats"]["cg_layout"] == 2 and f["stats"]["n_unconverged"] == 0
+    assert rel1(f["E"], o["E"]) <= TOL_E
+    assert rel1(f["sigma"], o["sigma"]) <= TOL_S
+    assert rel1(f["D"], o["D"]) <= TOL_D
