@@ -106,6 +106,41 @@ def test_water64_sampled_pairs_match_oracle(water64_run):
     _check_pairs("water64", cfg, orbs, orb_t, pr, _picks(pr, 6, 64))
 
 
+def test_water64_mixed_sampled_pairs_match_oracle():
+    """The headline configuration as the benchmark runs it (mixed precision,
+    autotuned CG variant, quad layout): sampled pairs against the oracle, per
+    pair within the mixed bar (1e-6 relative on E_xx and sigma_xx)."""
+    cfg = synth.CONFIGS["water64"]
+    orbs = synth.make_orbitals(cfg)
+    orb_t = synth.fill_orbitals_device(cfg, orbs, DEV)
+    cen_t = torch.from_numpy(orbs.centres).to(DEV)
+    plan = _plan(cfg, autotune=1, precision=exx.EXX_PREC_MIXED)
+    try:
+        E = torch.zeros(1, dtype=torch.float64, device=DEV)
+        S = torch.zeros(9, dtype=torch.float64, device=DEV)
+        plan.eval(orb_t, cen_t, E, None, S)
+        torch.cuda.synchronize()
+        pr = plan.pair_results()
+        st = plan.stats()
+    finally:
+        plan.close()
+    print(f"[water64 mixed] pairs={st['n_pairs']} layout={st['cg_layout']} variant={st['solve_threads']}x"
+          f"{st['solve_depth']} E={E.item():.12f}", flush=True)
+    assert st["n_unconverged"] == 0 and st["cg_layout"] == 2
+    P = _oracle_params(cfg)
+    for k in _picks(pr, 3, 65):
+        i, j = (int(x) for x in pr["ij"][k])
+        idx = [i] if i == j else [i, j]
+        f = oracle.pair_fields(P, orb_t[idx].to(torch.float64).cpu().numpy(), orbs.centres[idx], 0, len(idx) - 1)
+        r = f["res"]
+        s_o = np.array(list(r.sigma))
+        print(f"[water64 mixed] pair ({i},{j}) gpu E={pr['E'][k]:.15g} oracle={r.E:.15g}", flush=True)
+        assert abs(pr["E"][k] - r.E) <= 1e-6 * abs(r.E) + 1e-14
+        assert np.abs(pr["sigma"][k] - s_o).sum() <= 1e-6 * np.abs(s_o).sum() + 1e-14
+    del orb_t
+    torch.cuda.empty_cache()
+
+
 def test_water64_D_of_one_orbital_matches_oracle(water64_run):
     cfg, orbs, orb_t, D, E, S, pr, st = water64_run
     i = 37
