@@ -5,10 +5,10 @@
 // centre (eq. l2g), so the tables are shared by every pair of the class.
 //
 // Layout of a PE vector ("column-major planes"): the (x,y) columns of the
-// sphere are sorted by half-height zr descending (ties by angle about the z
-// axis, then y, then x).  At plane z the columns with zr >= |z| are therefore
-// a prefix of that order, and the plane is stored as that prefix, planes in
-// ascending z.  A workgroup that assigns column c to a fixed thread then reads
+// sphere are sorted by half-height zr descending; columns of equal half-height
+// are ordered so that the LDS words a wavefront stages spread over the banks.
+// At plane z the columns with zr >= |z| are therefore a prefix of that order,
+// and the plane is stored as that prefix, planes in ascending z.  A workgroup that assigns column c to a fixed thread then reads
 // every plane with consecutive addresses from one per-plane base offset.
 //
 // Quad layout (orthorhombic cells, one CG thread per run): the columns are
@@ -48,6 +48,37 @@ struct LayCol {
   int ox, oy, zr, zq;
 };
 
+// Reorders items already sorted by half-height (descending) within each run
+// of equal half-height, so that the LDS words they stage spread over the
+// banks: each next item takes the word residue (of 16) used least so far by
+// its aligned group of 16 threads, then the residue (of 32) used least by its
+// group of 32 (ties: the given order).  word_of(item) is the item's LDS word
+// index up to a constant; consecutive items go to consecutive threads.
+template <typename Item, typename H, typename W>
+void bank_order(std::vector<Item>& items, H height_of, W word_of) {
+  auto res = [&](const Item& it) { return (word_of(it) % 32 + 32) % 32; };
+  std::vector<Item> ordered;
+  ordered.reserve(items.size());
+  for (size_t g0 = 0; g0 < items.size();) {
+    size_t g1 = g0;
+    while (g1 < items.size() && height_of(items[g1]) == height_of(items[g0])) ++g1;
+    std::vector<Item> pending(items.begin() + g0, items.begin() + g1);
+    while (!pending.empty()) {
+      int used16[16] = {0}, used32[32] = {0};
+      for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used16[res(ordered[t]) % 16];
+      for (size_t t = ordered.size() / 32 * 32; t < ordered.size(); ++t) ++used32[res(ordered[t])];
+      auto key = [&](const Item& it) { return 64 * used16[res(it) % 16] + used32[res(it)]; };
+      size_t best = 0;
+      for (size_t i = 1; i < pending.size(); ++i)
+        if (key(pending[i]) < key(pending[best])) best = i;
+      ordered.push_back(pending[best]);
+      pending.erase(pending.begin() + best);
+    }
+    g0 = g1;
+  }
+  items.swap(ordered);
+}
+
 // The quad layout's columns (see the file comment) for a cross-section whose
 // column (x, y), |x| <= Rx, |y| <= Ry, has half-height zr_of(x, y), or -1
 // outside the sphere: runs of four x-adjacent columns in their processing
@@ -69,35 +100,14 @@ std::vector<LayCol> quad_runs(int Rx, int Ry, const std::function<int(int, int)>
       if (zq >= 0) runs.push_back({x0, oy, zq});
     }
   // by run height (descending; plane z is a prefix), then within one height
-  // greedily: each next run takes the 8-byte bank pair (of 16) used least so
-  // far by its aligned group of 16 threads, then the pair (of 32) used least
-  // by its group of 32 (ties: row order)
+  // over the banks of the 8-byte halves the runs stage (row order first)
   std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
     if (a.zq != b.zq) return a.zq > b.zq;
     if (a.oy != b.oy) return a.oy < b.oy;
     return a.x0 < b.x0;
   });
-  auto pair_of = [](const Run& r) { return (((r.x0 + 88 * r.oy) / 2) % 32 + 32) % 32; };
-  std::vector<Run> ordered;
-  ordered.reserve(runs.size());
-  for (size_t g0 = 0; g0 < runs.size();) {
-    size_t g1 = g0;
-    while (g1 < runs.size() && runs[g1].zq == runs[g0].zq) ++g1;
-    std::vector<Run> pending(runs.begin() + g0, runs.begin() + g1);
-    while (!pending.empty()) {
-      int used16[16] = {0}, used32[32] = {0};
-      for (size_t t = ordered.size() / 16 * 16; t < ordered.size(); ++t) ++used16[pair_of(ordered[t]) % 16];
-      for (size_t t = ordered.size() / 32 * 32; t < ordered.size(); ++t) ++used32[pair_of(ordered[t])];
-      auto key = [&](const Run& r) { return 64 * used16[pair_of(r) % 16] + used32[pair_of(r)]; };
-      size_t best = 0;
-      for (size_t i = 1; i < pending.size(); ++i)
-        if (key(pending[i]) < key(pending[best])) best = i;
-      ordered.push_back(pending[best]);
-      pending.erase(pending.begin() + best);
-    }
-    g0 = g1;
-  }
-  for (const Run& r : ordered)
+  bank_order(runs, [](const Run& r) { return r.zq; }, [](const Run& r) { return (r.x0 + kLdsWX * r.oy) / 2; });
+  for (const Run& r : runs)
     for (int j = 0; j < 4; ++j) out.push_back({r.x0 + j, r.oy, zr_of(r.x0 + j, r.oy), r.zq});
   return out;
 }
@@ -160,6 +170,7 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   // outside the sphere, half-height zq of the unit the prefix is taken over)
   std::vector<LayCol> lay;
   if (!quads) {
+    bank_order(cols, [](const Col& c) { return c.zr; }, [](const Col& c) { return c.ox + kLdsWX * c.oy; });
     for (const Col& c : cols) lay.push_back({c.ox, c.oy, c.zr, c.zr});
   } else {
     auto zr_of = [&](int ox, int oy) {
@@ -375,6 +386,7 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
   struct GCol { int x, y, lo, hi, zq; };
   std::vector<GCol> lay;
   if (!C.quads) {
+    bank_order(cols, [](const Col& c) { return c.zr; }, [](const Col& c) { return c.x + kLdsWX * c.y; });
     for (const Col& c : cols) lay.push_back({c.x, c.y, c.lo, c.hi, c.zr});
     C.cols.resize(cols.size());
     for (size_t c = 0; c < cols.size(); ++c) C.cols[c] = make_int4(cols[c].x, cols[c].y, cols[c].lo, cols[c].hi);
