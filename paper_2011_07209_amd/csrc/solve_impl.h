@@ -889,8 +889,10 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
 
 
 // ---------------------------------------------------------------------------
-// Quad layout of orthorhombic cells.  The sphere's columns are grouped into
-// runs of four x-adjacent columns of one row (starting at x = 4k on even rows,
+// Quad layout (orthorhombic cells, and general cells whose arms stay in the
+// sweep plane with at most one diagonal among them and whose columns are
+// symmetric about it; coordinates in the CG frame).  The sphere's columns are
+// grouped into runs of four x-adjacent columns of one row (starting at x = 4k on even rows,
 // 4k + 2 on odd rows, so a run starts at an even LDS position), padded to the
 // run's tallest column: plane z holds the runs whose tallest column reaches
 // it, as a prefix of the runs sorted by that height, four slots per run; a
