@@ -195,3 +195,44 @@ def test_general_cell_quad_layout(name):
     assert rel1(f["E"], o["E"]) <= TOL_E
     assert rel1(f["sigma"], o["sigma"]) <= TOL_S
     assert rel1(f["D"], o["D"]) <= TOL_D
+
+
+def test_quad_layout_warm_start_over_displaced_steps():
+    """Warm start on a general cell in the quad layout (hexagonal, mixed): the
+    previous solution is moved through the 3D slot map, dead slots start at
+    zero, and each step meets the mixed bars against the oracle."""
+    h, N = CELLS["hexagonal"]
+    cfg = _cfg("gen-quad-warm", h, N, seed_index=96)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    dev = torch.device("cuda:0")
+    orb_t = torch.from_numpy(phi).to(dev)
+    cen_t = torch.from_numpy(np.ascontiguousarray(orbs.centres)).to(dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    S = torch.zeros(9, dtype=torch.float64, device=dev)
+    D = torch.empty_like(orb_t)
+    plan = exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, stencil_n=cfg.stencil_n,
+                    cg_tol=cfg.cg_tol, max_pairs=64, warm_start=1, precision=exx.EXX_PREC_MIXED)
+    try:
+        iters = []
+        for step in range(2):
+            if step:
+                orbs = synth.displace(cfg, orbs, step, amplitude=0.05)
+                phi = synth.fill_orbitals(cfg, orbs)
+                orb_t.copy_(torch.from_numpy(phi).to(dev))
+                cen_t.copy_(torch.from_numpy(np.ascontiguousarray(orbs.centres)).to(dev))
+            plan.eval(orb_t, cen_t, E, D, S)
+            torch.cuda.synchronize()
+            st = plan.stats()
+            o = oracle_eval(cfg, orbs, phi)
+            iters.append(st["cg_iter_sum"])
+            print(f"[quad warm] step {step}: layout {st['cg_layout']} warm {st['warm_pairs']}/{st['n_pairs']} "
+                  f"iters {st['cg_iter_sum']}", flush=True)
+            assert st["cg_layout"] == 2 and st["n_unconverged"] == 0
+            assert (st["warm_pairs"] == 0) if step == 0 else (st["warm_pairs"] >= 0.75 * st["n_pairs"])
+            assert abs(E.item() - o["E"]) <= 1e-6 * cfg.n_orb / 4
+            assert rel1(S.cpu().numpy().reshape(3, 3, order="F"), o["sigma"]) <= 1e-6
+            assert rel1(D.cpu().numpy(), o["D"]) <= 1e-6
+        assert iters[1] < iters[0]
+    finally:
+        plan.close()
