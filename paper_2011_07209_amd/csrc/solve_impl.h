@@ -56,6 +56,23 @@ struct GenStencilT {
   T tl_coef[3];
 };
 
+// Loads and stores of the CG vectors (global memory) at a 32-bit element
+// index from the workgroup's uniform base: the address is one 32-bit offset
+// register on top of the base held in scalar registers.
+#define EXX_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gload(const T* base, unsigned idx) {
+  return *(const EXX_GLOBAL T*)((const EXX_GLOBAL char*)base + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* base, unsigned idx, T v) {
+  *(EXX_GLOBAL T*)((EXX_GLOBAL char*)base + idx * (unsigned)sizeof(T)) = v;
+}
+// plane start of plane index k (the same for every thread)
+__device__ __forceinline__ unsigned plane_base(const int* pst, int k) {
+  return (unsigned)__builtin_amdgcn_readfirstlane(pst[k]);
+}
+
 struct SolveKArgs {
   const ClassDev* cls;
   const PairDev* pairs;
@@ -202,7 +219,7 @@ __device__ __forceinline__ void solve_range(const SolveKArgs& a, long long* lo, 
 }
 
 #define EXX_VALID(c, zz) (abs(zz) <= cl.zr[c])
-#define EXX_IDX(c, zz) (pst[(zz) + Zmax] + cl.col[c])
+#define EXX_IDX(c, zz) (plane_base(pst, (zz) + Zmax) + (unsigned)cl.col[c])
 
 // Pass A of a CG iteration: p = r + beta p (p = r on the first iteration) is
 // stored, q = A p is formed on the fly; accumulates p.q and r.r in FP64.
@@ -220,10 +237,10 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
     for (int c = 0; c < CPT; ++c) {
       T v = 0;
       if (EXX_VALID(c, zz)) {
-        const int idx = EXX_IDX(c, zz);
-        const T rv = r[idx];
-        v = first ? rv : rv + beta * p[idx];
-        p[idx] = v;
+        const unsigned idx = EXX_IDX(c, zz);
+        const T rv = gload(r, idx);
+        v = first ? rv : rv + beta * gload(p, idx);
+        gstore(p, idx, v);
         rr += (double)rv * (double)rv;
       }
       win[c][k] = v;
@@ -237,9 +254,9 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
       qr[d][c] = 0;
       qp[d][c] = 0;
       if (EXX_VALID(c, zz)) {
-        const int idx = EXX_IDX(c, zz);
-        qr[d][c] = r[idx];
-        if (!first) qp[d][c] = p[idx];
+        const unsigned idx = EXX_IDX(c, zz);
+        qr[d][c] = gload(r, idx);
+        if (!first) qp[d][c] = gload(p, idx);
       }
     }
   }
@@ -251,9 +268,9 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
       nr[c] = 0;
       np[c] = 0;
       if (EXX_VALID(c, zl)) {
-        const int idx = EXX_IDX(c, zl);
-        nr[c] = r[idx];
-        if (!first) np[c] = p[idx];
+        const unsigned idx = EXX_IDX(c, zl);
+        nr[c] = gload(r, idx);
+        if (!first) np[c] = gload(p, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -274,7 +291,7 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
       T v = 0;
       if (EXX_VALID(c, zc)) {
         v = first ? qr[0][c] : qr[0][c] + beta * qp[0][c];
-        p[EXX_IDX(c, zc)] = v;
+        gstore(p, EXX_IDX(c, zc), v);
         rr += (double)qr[0][c] * (double)qr[0][c];
       }
       win[c][2 * NS] = v;
@@ -304,22 +321,22 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_VALID(c, zz) ? p[EXX_IDX(c, zz)] : (T)0;
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_VALID(c, zz) ? gload(p, EXX_IDX(c, zz)) : (T)0;
   }
 #pragma unroll
   for (int d = 0; d < PD; ++d) {
     const int zz = -Zmax + NS + 1 + d;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_VALID(c, zz) ? p[EXX_IDX(c, zz)] : (T)0;
+    for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_VALID(c, zz) ? gload(p, EXX_IDX(c, zz)) : (T)0;
   }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     cx[c] = 0;
     cr[c] = 0;
     if (EXX_VALID(c, -Zmax)) {
-      const int idx = EXX_IDX(c, -Zmax);
-      cr[c] = r_in[idx];
-      if (!x_zero) cx[c] = x[idx];
+      const unsigned idx = EXX_IDX(c, -Zmax);
+      cr[c] = gload(r_in, idx);
+      if (!x_zero) cx[c] = gload(x, idx);
     }
   }
   double acc = 0.0;
@@ -328,13 +345,13 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
     T np[CPT], nx[CPT], nr[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      np[c] = EXX_VALID(c, zl) ? p[EXX_IDX(c, zl)] : (T)0;
+      np[c] = EXX_VALID(c, zl) ? gload(p, EXX_IDX(c, zl)) : (T)0;
       nx[c] = 0;
       nr[c] = 0;
       if (EXX_VALID(c, z + 1)) {
-        const int idx = EXX_IDX(c, z + 1);
-        nr[c] = r_in[idx];
-        if (!x_zero) nx[c] = x[idx];
+        const unsigned idx = EXX_IDX(c, z + 1);
+        nr[c] = gload(r_in, idx);
+        if (!x_zero) nx[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -345,11 +362,11 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (EXX_VALID(c, z)) {
-        const int idx = EXX_IDX(c, z);
+        const unsigned idx = EXX_IDX(c, z);
         const T q = apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
         const T rn = cr[c] - alpha * q;
-        x[idx] = cx[c] + alpha * win[c][NS];
-        r[idx] = rn;
+        gstore(x, idx, cx[c] + alpha * win[c][NS]);
+        gstore(r, idx, rn);
         acc += (double)rn * (double)rn;
       }
     }
@@ -383,7 +400,7 @@ __device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& c
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_VALID(c, zz) ? x[EXX_IDX(c, zz)] : 0.0;
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_VALID(c, zz) ? gload(x, EXX_IDX(c, zz)) : 0.0;
   }
   double acc = 0.0;
   for (int z = -Zmax; z <= Zmax; ++z) {
@@ -391,8 +408,8 @@ __device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& c
     double nx[CPT], cb[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      nx[c] = EXX_VALID(c, zc) ? x[EXX_IDX(c, zc)] : 0.0;
-      cb[c] = EXX_VALID(c, z) ? b[EXX_IDX(c, z)] : 0.0;
+      nx[c] = EXX_VALID(c, zc) ? gload(x, EXX_IDX(c, zc)) : 0.0;
+      cb[c] = EXX_VALID(c, z) ? gload(b, EXX_IDX(c, z)) : 0.0;
     }
     double* pl = (z & 1) ? pl1 : pl0;
 #pragma unroll
@@ -403,7 +420,7 @@ __device__ double cg_true_residual(const StencilT<double>& S, const Cols<CPT>& c
     for (int c = 0; c < CPT; ++c) {
       if (EXX_VALID(c, z)) {
         const double rt = cb[c] - apply_point<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
-        r[EXX_IDX(c, z)] = (TR)(rt * rs);
+        gstore(r, EXX_IDX(c, z), (TR)(rt * rs));
         acc += rt * rt;
       }
     }
@@ -454,7 +471,7 @@ __device__ __forceinline__ void load_cols_gen(const ClassDev& C, const SolveKArg
 
 #define EXX_GVALID(c, zz) ((zz) >= cl.lo[c] && (zz) <= cl.hi[c])
 #define EXX_GHAS(c) (cl.lo[c] <= cl.hi[c])
-#define EXX_GIDX(c, zz) (pst[(zz) + Zmax] + cl.col[c])
+#define EXX_GIDX(c, zz) (plane_base(pst, (zz) + Zmax) + (unsigned)cl.col[c])
 
 // Laplacian sum at a point from its own column (z' arm, centre) and the
 // in-plane arms (staged plane pl)
@@ -509,10 +526,10 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
     for (int c = 0; c < CPT; ++c) {
       T v = 0;
       if (EXX_GVALID(c, zz)) {
-        const int idx = EXX_GIDX(c, zz);
-        const T rv = r[idx];
-        v = first ? rv : rv + beta * p[idx];
-        p[idx] = v;
+        const unsigned idx = EXX_GIDX(c, zz);
+        const T rv = gload(r, idx);
+        v = first ? rv : rv + beta * gload(p, idx);
+        gstore(p, idx, v);
         rr += (double)rv * (double)rv;
       }
       win[c][k] = v;
@@ -526,9 +543,9 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
       qr[d][c] = 0;
       qp[d][c] = 0;
       if (EXX_GVALID(c, zz)) {
-        const int idx = EXX_GIDX(c, zz);
-        qr[d][c] = r[idx];
-        if (!first) qp[d][c] = p[idx];
+        const unsigned idx = EXX_GIDX(c, zz);
+        qr[d][c] = gload(r, idx);
+        if (!first) qp[d][c] = gload(p, idx);
       }
     }
   }
@@ -540,9 +557,9 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
       nr[c] = 0;
       np[c] = 0;
       if (EXX_GVALID(c, zl)) {
-        const int idx = EXX_GIDX(c, zl);
-        nr[c] = r[idx];
-        if (!first) np[c] = p[idx];
+        const unsigned idx = EXX_GIDX(c, zl);
+        nr[c] = gload(r, idx);
+        if (!first) np[c] = gload(p, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -562,7 +579,7 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
       T v = 0;
       if (EXX_GVALID(c, zc)) {
         v = first ? qr[0][c] : qr[0][c] + beta * qp[0][c];
-        p[EXX_GIDX(c, zc)] = v;
+        gstore(p, EXX_GIDX(c, zc), v);
         rr += (double)qr[0][c] * (double)qr[0][c];
       }
       win[c][2 * NS] = v;
@@ -590,13 +607,13 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? p[EXX_GIDX(c, zz)] : (T)0;
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? gload(p, EXX_GIDX(c, zz)) : (T)0;
   }
 #pragma unroll
   for (int d = 0; d < PD; ++d) {
     const int zz = -Zmax + NS + 1 + d;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_GVALID(c, zz) ? p[EXX_GIDX(c, zz)] : (T)0;
+    for (int c = 0; c < CPT; ++c) qp[d][c] = EXX_GVALID(c, zz) ? gload(p, EXX_GIDX(c, zz)) : (T)0;
   }
   double sum = 0.0;
   for (int z = -Zmax; z <= Zmax; ++z) {
@@ -604,13 +621,13 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
     T np[CPT], ox[CPT], orr[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      np[c] = EXX_GVALID(c, zl) ? p[EXX_GIDX(c, zl)] : (T)0;
+      np[c] = EXX_GVALID(c, zl) ? gload(p, EXX_GIDX(c, zl)) : (T)0;
       ox[c] = 0;
       orr[c] = 0;
       if (EXX_GVALID(c, z)) {
-        const int idx = EXX_GIDX(c, z);
-        orr[c] = r_in[idx];
-        if (!x_zero) ox[c] = x[idx];
+        const unsigned idx = EXX_GIDX(c, z);
+        orr[c] = gload(r_in, idx);
+        if (!x_zero) ox[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -621,11 +638,11 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (EXX_GVALID(c, z)) {
-        const int idx = EXX_GIDX(c, z);
+        const unsigned idx = EXX_GIDX(c, z);
         const T lap = gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
         const T rn = orr[c] + alpha * lap;   // r - alpha A p, A p = -lap
-        x[idx] = ox[c] + alpha * win[c][NS];
-        r[idx] = rn;
+        gstore(x, idx, ox[c] + alpha * win[c][NS]);
+        gstore(r, idx, rn);
         sum += (double)rn * (double)rn;
       }
     }
@@ -653,7 +670,7 @@ __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? x[EXX_GIDX(c, zz)] : 0.0;
+    for (int c = 0; c < CPT; ++c) win[c][k] = EXX_GVALID(c, zz) ? gload(x, EXX_GIDX(c, zz)) : 0.0;
   }
   double sum = 0.0;
   for (int z = -Zmax; z <= Zmax; ++z) {
@@ -661,8 +678,8 @@ __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG
     double nx[CPT], cb[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      nx[c] = EXX_GVALID(c, zc) ? x[EXX_GIDX(c, zc)] : 0.0;
-      cb[c] = EXX_GVALID(c, z) ? b[EXX_GIDX(c, z)] : 0.0;
+      nx[c] = EXX_GVALID(c, zc) ? gload(x, EXX_GIDX(c, zc)) : 0.0;
+      cb[c] = EXX_GVALID(c, z) ? gload(b, EXX_GIDX(c, z)) : 0.0;
     }
     double* pl = (z & 1) ? pl1 : pl0;
 #pragma unroll
@@ -673,7 +690,7 @@ __device__ double cg_true_residual_gen(const GenStencilT<double>& S, const ColsG
     for (int c = 0; c < CPT; ++c) {
       if (EXX_GVALID(c, z)) {
         const double rt = cb[c] + gen_inplane<NS, double>(S, win[c][NS], pl, cl.pos[c], win[c]);
-        r[EXX_GIDX(c, z)] = (TR)(rt * rs);
+        gstore(r, EXX_GIDX(c, z), (TR)(rt * rs));
         sum += rt * rt;
       }
     }
@@ -737,9 +754,9 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
     cr[c] = 0;
     cp[c] = 0;
     if (EXX_GVALID(c, -Zmax)) {
-      const int idx = EXX_GIDX(c, -Zmax);
-      cr[c] = r[idx];
-      if (!first) cp[c] = p[idx];
+      const unsigned idx = EXX_GIDX(c, -Zmax);
+      cr[c] = gload(r, idx);
+      if (!first) cp[c] = gload(p, idx);
     }
   }
   for (int z = -Zmax; z <= Zmax + NS; ++z) {
@@ -749,9 +766,9 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
       nr[c] = 0;
       np[c] = 0;
       if (EXX_GVALID(c, z + 1)) {
-        const int idx = EXX_GIDX(c, z + 1);
-        nr[c] = r[idx];
-        if (!first) np[c] = p[idx];
+        const unsigned idx = EXX_GIDX(c, z + 1);
+        nr[c] = gload(r, idx);
+        if (!first) np[c] = gload(p, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -760,7 +777,7 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
       T v = 0;
       if (EXX_GVALID(c, z)) {
         v = first ? cr[c] : cr[c] + beta * cp[c];
-        p[EXX_GIDX(c, z)] = v;
+        gstore(p, EXX_GIDX(c, z), v);
         rr += (double)cr[c] * (double)cr[c];
       }
       pd[c][NS] = v;
@@ -795,7 +812,7 @@ __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, co
     for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0;
 #pragma unroll
     for (int k = 0; k < NS + 1; ++k) pd[c][k] = 0;
-    cp[c] = EXX_GVALID(c, -Zmax) ? p[EXX_GIDX(c, -Zmax)] : (T)0;
+    cp[c] = EXX_GVALID(c, -Zmax) ? gload(p, EXX_GIDX(c, -Zmax)) : (T)0;
   }
   double sum = 0.0;
   for (int z = -Zmax; z <= Zmax + NS; ++z) {
@@ -803,13 +820,13 @@ __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, co
     T np[CPT], ox[CPT], orr[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      np[c] = EXX_GVALID(c, z + 1) ? p[EXX_GIDX(c, z + 1)] : (T)0;
+      np[c] = EXX_GVALID(c, z + 1) ? gload(p, EXX_GIDX(c, z + 1)) : (T)0;
       ox[c] = 0;
       orr[c] = 0;
       if (EXX_GVALID(c, zo)) {   // read before the same thread writes them below
-        const int idx = EXX_GIDX(c, zo);
-        orr[c] = r_in[idx];
-        if (!x_zero) ox[c] = x[idx];
+        const unsigned idx = EXX_GIDX(c, zo);
+        orr[c] = gload(r_in, idx);
+        if (!x_zero) ox[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -823,10 +840,10 @@ __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, co
     for (int c = 0; c < CPT; ++c) {
       if (EXX_GHAS(c)) tl_scatter<NS, T>(S, pd[c][NS], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
       if (EXX_GVALID(c, zo)) {
-        const int idx = EXX_GIDX(c, zo);
+        const unsigned idx = EXX_GIDX(c, zo);
         const T rn = orr[c] + alpha * acc[c][0];   // r - alpha A p, A p = -acc
-        x[idx] = ox[c] + alpha * pd[c][0];
-        r[idx] = rn;
+        gstore(x, idx, ox[c] + alpha * pd[c][0]);
+        gstore(r, idx, rn);
         sum += (double)rn * (double)rn;
       }
 #pragma unroll
@@ -850,7 +867,7 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
   for (int c = 0; c < CPT; ++c) {
 #pragma unroll
     for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0.0;
-    cx[c] = EXX_GVALID(c, -Zmax) ? x[EXX_GIDX(c, -Zmax)] : 0.0;
+    cx[c] = EXX_GVALID(c, -Zmax) ? gload(x, EXX_GIDX(c, -Zmax)) : 0.0;
   }
   double sum = 0.0;
   for (int z = -Zmax; z <= Zmax + NS; ++z) {
@@ -858,8 +875,8 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
     double nx[CPT], ob[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      nx[c] = EXX_GVALID(c, z + 1) ? x[EXX_GIDX(c, z + 1)] : 0.0;
-      ob[c] = EXX_GVALID(c, zo) ? b[EXX_GIDX(c, zo)] : 0.0;
+      nx[c] = EXX_GVALID(c, z + 1) ? gload(x, EXX_GIDX(c, z + 1)) : 0.0;
+      ob[c] = EXX_GVALID(c, zo) ? gload(b, EXX_GIDX(c, zo)) : 0.0;
     }
     double* pl = (z & 1) ? pl1 : pl0;
 #pragma unroll
@@ -871,7 +888,7 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
       if (EXX_GHAS(c)) tl_scatter<NS, double>(S, cx[c], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
       if (EXX_GVALID(c, zo)) {
         const double rt = ob[c] + acc[c][0];   // b - A x, A x = -acc
-        r[EXX_GIDX(c, zo)] = (TR)(rt * rs);
+        gstore(r, EXX_GIDX(c, zo), (TR)(rt * rs));
         sum += rt * rt;
       }
 #pragma unroll
@@ -940,8 +957,6 @@ using V4 = T __attribute__((ext_vector_type(4)));
 // vector at base, which is aligned to the vector size.  The accesses name the
 // global address space and take a 32-bit byte offset from the workgroup's
 // uniform base.
-#define EXX_GLOBAL __attribute__((address_space(1)))
-
 template <typename T>
 __device__ __forceinline__ V4<T> ld_quad(const T* base, int idx) {
   return *(const EXX_GLOBAL V4<T>*)((const EXX_GLOBAL char*)base + (unsigned)idx * (unsigned)sizeof(T));
