@@ -107,7 +107,10 @@ typedef struct {
      columns of the sphere); 2: quad layout for every class (each CG thread
      owns a run of four adjacent columns, padded with zero slots to the run's
      tallest column, and reads its in-plane neighbours as 2-point vectors;
-     1024 threads).  A general cell takes it when no Laplacian arm leaves the
+     1024 threads, or 768 for mixed plans where the class has at most 768
+     runs and solve_threads is not 1024: their CG sweeps each pass B together
+     with the next pass A, six vector accesses per point and iteration in
+     place of eight).  A general cell takes it when no Laplacian arm leaves the
      sweep plane, at most one diagonal arm lies in it, and its columns are
      symmetric about the sweep plane.  With 2, EXX_EINVAL when a class does
      not fit (more than 1024 runs, other arms or columns), with
@@ -188,15 +191,19 @@ typedef struct {
   double max_rel_residual;     /* max over pairs of ||b - A x|| / ||b||            */
   double solve_ms;             /* device time of the solve kernels (last eval)     */
   double eval_ms;              /* device time of the whole evaluation              */
-  double cg_alg_bytes;         /* algorithmic CG bytes: sum_pairs iters 8 N_PE b   */
+  double cg_alg_bytes;         /* algorithmic CG bytes: sum_pairs (8 iters - 2
+                                  fused sweeps) N_PE b                              */
   double moment_flops;         /* algorithmic moment flops: 2 N_lm N_PE per pair   */
   /* running totals since the plan was made (every completed exx_eval):       */
   long long n_evals;
   long long solve_launches;    /* launches of the persistent CG kernel           */
   double solve_ms_total;       /* their summed device time (HIP events)          */
-  double cg_alg_bytes_total;   /* their summed algorithmic CG bytes              */
+  double cg_alg_bytes_total;   /* their summed algorithmic CG bytes (eight vector
+                                  accesses per point and iteration, six in a
+                                  fused sweep)                                      */
   double eval_ms_total;
-  int solve_threads;           /* CG variant in use: workgroup size ...            */
+  int solve_threads;           /* CG variant in use: workgroup size (768: quad
+                                  layout with fused sweeps) ...                     */
   int solve_depth;             /* ... and load depth (chosen by the autotuner)     */
   double tune_ms;              /* time spent by the autotuner (first eval only)    */
   double moment_ms;            /* device time of the moment kernels (last eval)    */

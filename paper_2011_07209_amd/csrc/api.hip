@@ -126,7 +126,7 @@ struct CaptureGuard {
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
+                  P->pRes, P->pUpd, P->pFus, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
                   P->warm_map, P->prev_pairs, P->prev_offs, P->warm_state, P->slot_ws, P->queue,
                   P->stats_dev};
   for (void* p : ptrs)
@@ -266,7 +266,7 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
 // sides are rebuilt before each trial (the solve overwrites them) and once
 // more by the caller.
 exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hipStream_t s) {
-  static const int cand[4][2] = {{1024, 1}, {1024, 2}, {512, 1}, {512, 2}};
+  static const int cand[6][2] = {{1024, 1}, {1024, 2}, {768, 1}, {768, 2}, {512, 1}, {512, 2}};
   hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
   EXX_HIP(P, hipEventCreate(&e0));
   EXX_HIP(P, hipEventCreate(&e1));
@@ -284,7 +284,7 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
     if (hi <= lo) continue;
     float best = 1e30f;
     int bt = P->class_threads[k], bd = P->class_depth[k];
-    int order[5][2] = {{bt, bd}};
+    int order[7][2] = {{bt, bd}};
     int nc = 1;
     for (const auto& c : cand)
       if (c[0] != bt || c[1] != bd) {
@@ -742,7 +742,13 @@ void default_solve_variants(exx_plan_t P) {
   P->class_threads.assign(P->classes.size(), 1024);
   P->class_depth.assign(P->classes.size(), dp);
   for (size_t k = 0; k < P->classes.size(); ++k) {
-    if (P->classes[k].quads) continue;   // one run per thread: 1024 threads
+    if (P->classes[k].quads) {
+      // one run per thread; mixed plans take 768 threads where the runs fit
+      // (their CG then fuses each pass B with the next pass A), else 1024
+      if (opt.precision == EXX_PREC_MIXED && opt.solve_threads != 1024 && P->classes[k].n_cols <= 4 * 768)
+        P->class_threads[k] = 768;
+      continue;
+    }
     P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= cpt * 1024 ? 1024 : 512);
   }
 }
@@ -1019,7 +1025,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     if (dev_alloc(P, &P->pairs, (size_t)cap, "pairs") || dev_alloc(P, &P->order, (size_t)cap, "order") ||
         dev_alloc(P, &P->pE, (size_t)cap, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * cap, "pair sigma") ||
         dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res") ||
-        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates"))
+        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates") || dev_alloc(P, &P->pFus, (size_t)cap, "pair fused sweeps"))
       return EXX_ENOMEM;
     P->pair_cap = cap;
     return EXX_OK;
@@ -1137,6 +1143,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.outIt = P->pIt;
     a.outRes = P->pRes;
     a.outUpd = P->pUpd;
+    a.outFus = P->pFus;
     a.mixed = mixed;
     a.delta = 0.1;
     a.threads = P->solve_threads;
@@ -1169,7 +1176,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
       EXX_HIP(P, launch_dscatter(g, B, P->max_me, orbitals, D_xx, d_slot, (int)dt, P->bx_ws, P->rstride, P->Q_ws, s));
   }
   EXX_HIP(P, event(P->ev[2]));
-  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pairs, P->class_dev, P->pair_count, n_orb,
+  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pFus, P->pairs, P->class_dev, P->pair_count, n_orb,
                            P->n_eff, P->opt.warm_start ? P->warm_map : nullptr, P->opt.cg_max_iter, E_xx, sigma,
                            P->stats_dev, s));
   if (P->opt.warm_start)

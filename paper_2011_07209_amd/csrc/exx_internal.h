@@ -191,6 +191,7 @@ struct exx_plan_s {
   int* pIt = nullptr;
   double* pRes = nullptr;
   int* pUpd = nullptr;
+  int* pFus = nullptr;   // fused CG sweeps per pair (each saves two vector accesses per point)
 
   // batch workspace
   long long batch_cap = 0;

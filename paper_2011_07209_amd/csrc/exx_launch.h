@@ -75,6 +75,7 @@ struct SolveArgs {
   int* outIt = nullptr;
   double* outRes = nullptr;
   int* outUpd = nullptr;       // reliable updates per pair (mixed)
+  int* outFus = nullptr;       // fused sweeps per pair (pass B with the next pass A)
   double tol = 0;
   int max_iter = 0;
   bool mixed = false;
@@ -123,6 +124,7 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s);
 // capacity), sum iters*N_PE, refinement passes max, sum N_PE, warm-started
 // pairs) as doubles.  warm_map may be null.
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
+                         const int* pFus,
                          const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
                          const int* warm_map, int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
 

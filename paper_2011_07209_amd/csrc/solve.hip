@@ -52,6 +52,7 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.outIt = in.outIt;
   a.outRes = in.outRes;
   a.outUpd = in.outUpd;
+  a.outFus = in.outFus;
   a.tol = in.tol;
   a.max_iter = in.max_iter;
   a.delta = in.delta;
@@ -135,6 +136,7 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
 
 bool solve_supported(int max_cols, int threads) {
   if (threads == 1024) return max_cols <= 4 * 1024;
+  if (threads == 768) return max_cols <= 4 * 768;   // quad layout only
   if (threads == 512) return max_cols <= 8 * 512;
   return false;
 }

@@ -91,6 +91,7 @@ struct SolveKArgs {
   int* outIt;
   double* outRes;
   int* outUpd;            // mixed: reliable updates per pair
+  int* outFus;            // sweeps that fused pass B with the next pass A, per pair
   double tol;
   int max_iter;
   double delta;           // mixed: update when ||r|| < delta * (residual at the last update)
@@ -921,8 +922,8 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
 // inside the run are the thread's own registers.
 
 struct ColsQ {
-  int zr[4];   // half-height of each column, -1 outside the sphere
-  int zq;      // half-height of the run (max zr), -1 for no run
+  unsigned zu; // per column j, bits 8j .. 8j+7: its half-height plus one (0 outside the sphere)
+  int zq;      // half-height of the run (max of the columns'), -1 for no run
   int pos;     // LDS plane position of the run's first column (even)
   int base;    // offset of the run's slots within a plane (4 t)
 };
@@ -933,13 +934,12 @@ __device__ __forceinline__ void load_cols_quad(const ClassDev& C, const SolveKAr
   cl.zq = -1;
   cl.pos = 0;
   cl.base = 4 * run;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) cl.zr[j] = -1;
+  cl.zu = 0;
   if (4 * run < C.n_cols) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int4 cc = C.cols[4 * run + j];
-      cl.zr[j] = cc.z;
+      cl.zu |= (unsigned)(cc.z + 1) << (8 * j);
       cl.zq = max(cl.zq, cc.z);
     }
     const int4 c0 = C.cols[4 * run];
@@ -970,6 +970,19 @@ template <typename T>
 __device__ __forceinline__ double dot4(V4<T> a, V4<T> b) {
   return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
          (double)a.w * (double)b.w;
+}
+
+// p.a, r.a and a.a of 4-point vectors added to pq, ra and aa in FP64, one
+// point at a time (one FP64 value of a live at once)
+template <typename T>
+__device__ __forceinline__ void dots3(V4<T> p, V4<T> r, V4<T> a, double& pq, double& ra, double& aa) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double aj = (double)a[j];
+    pq += (double)p[j] * aj;
+    ra += (double)r[j] * aj;
+    aa += aj * aj;
+  }
 }
 
 // plane values K points right (xr) and left (xl) of the run's four columns,
@@ -1048,10 +1061,10 @@ __device__ __forceinline__ V4<T> apply_quad(const StencilT<T>& S, const V4<T> (&
 template <typename T>
 __device__ __forceinline__ V4<T> live_only(const ColsQ& cl, int z, V4<T> v) {
   const int az = abs(z);
-  v.x = az <= cl.zr[0] ? v.x : (T)0;
-  v.y = az <= cl.zr[1] ? v.y : (T)0;
-  v.z = az <= cl.zr[2] ? v.z : (T)0;
-  v.w = az <= cl.zr[3] ? v.w : (T)0;
+  v.x = az < (int)(cl.zu & 255u) ? v.x : (T)0;
+  v.y = az < (int)((cl.zu >> 8) & 255u) ? v.y : (T)0;
+  v.z = az < (int)((cl.zu >> 16) & 255u) ? v.z : (T)0;
+  v.w = az < (int)(cl.zu >> 24) ? v.w : (T)0;
   return v;
 }
 
@@ -1059,28 +1072,37 @@ __device__ __forceinline__ V4<T> live_only(const ColsQ& cl, int z, V4<T> v) {
 #define EXX_QIDX(zz) (pst[(zz) + Zmax] + cl.base)
 
 // Pass A (as cg_pass_a) on the quad layout.  Dead slots hold r = p = 0, so p
-// stays zero there and adds nothing to the dot products.
-template <int NS, int PD, bool DG, typename T>
+// stays zero there and adds nothing to the dot products.  With RA it also
+// returns r.Ap and |Ap|^2 (Ap kept to the live slots), from which the next
+// residual norm |r - alpha Ap|^2 follows before r is updated; r of the planes
+// z .. z+NS is then kept in registers for the product with Ap of plane z.
+template <int NS, int PD, bool DG, bool RA, typename T>
 __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax,
                                const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
-                               double& pq, double& rr) {
+                               double& pq, double& rr, double& ra, double& aa) {
   const V4<T> zero = {0, 0, 0, 0};
   V4<T> win[2 * NS + 1];
   V4<T> qr[PD], qp[PD];   // raw r, p of planes z+NS+1 .. z+NS+PD
+  V4<T> rw[RA ? NS + 1 : 1];   // with RA: r of planes z .. z+NS
   pq = 0.0;
   rr = 0.0;
+  ra = 0.0;
+  aa = 0.0;
 #pragma unroll
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
-    V4<T> v = zero;
+    V4<T> v = zero, rv = zero;
     if (EXX_QVALID(zz)) {
       const int idx = EXX_QIDX(zz);
-      const V4<T> rv = ld_quad(r, idx);
+      rv = ld_quad(r, idx);
       v = first ? rv : rv + beta * ld_quad(p, idx);
       rr += dot4(rv, rv);
       st_quad(p, idx, v);
     }
     win[k] = v;
+    if constexpr (RA) {
+      if (k >= NS) rw[k - NS] = rv;
+    }
   }
 #pragma unroll
   for (int d = 0; d < PD; ++d) {
@@ -1102,7 +1124,15 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
     T* pl = (z & 1) ? pl1 : pl0;
     if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
     __syncthreads();
-    if (EXX_QVALID(z)) pq += dot4(win[NS], apply_quad<NS, DG, T>(S, win, pl, cl.pos));
+    if (EXX_QVALID(z)) {
+      const V4<T> ap = apply_quad<NS, DG, T>(S, win, pl, cl.pos);
+      pq += dot4(win[NS], ap);
+      if constexpr (RA) {
+        const V4<T> al = live_only(cl, z, ap);
+        ra += dot4(rw[0], al);
+        aa += dot4(al, al);
+      }
+    }
     const int zc = z + NS + 1;        // plane entering the window
     V4<T> v = zero;
     if (EXX_QVALID(zc)) {
@@ -1113,6 +1143,11 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
 #pragma unroll
     for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
     win[2 * NS] = v;
+    if constexpr (RA) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) rw[k] = rw[k + 1];
+      rw[NS] = EXX_QVALID(zc) ? qr[0] : zero;
+    }
 #pragma unroll
     for (int d = 0; d + 1 < PD; ++d) {
       qr[d] = qr[d + 1];
@@ -1179,6 +1214,95 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
   return acc;
 }
 
+// Pass B of one iteration and pass A of the next in one sweep on the quad
+// layout.  With the step alpha of p (= p_k) and the next beta (which the
+// caller takes from |r - alpha Ap|^2, known before r is updated): along the
+// sweep, Ap_k of plane c is recomputed from the z window of p_k, then
+// x += alpha p_k, r -= alpha Ap_k and p_k+1 = r + beta p_k are written over
+// the same slots; NS planes behind, Ap_k+1 is taken from the z window of the
+// new p, for p_k+1.Ap_k+1, r_k+1.Ap_k+1 and |Ap_k+1|^2 (r_k+1 restated as
+// p_k+1 - beta p_k from the two windows).  Each plane is read and written once
+// per iteration (p, r, x in; p, r, x out) instead of twice for p.  Each step
+// stages the planes of both stencils (la*, lb*) behind one barrier.
+// The two z windows take 56 registers per thread (FP32, n = 3), which fit
+// beside the rest only with at most three waves per SIMD (768 threads).
+// Returns |r_k+1|^2 and writes the products of iteration k+1 to out3.
+template <int NS, int PD, bool DG, typename T>
+__device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
+                                     T* r, T* p, T alpha, T beta, bool x_zero, T* la0, T* la1, T* lb0, T* lb1,
+                                     double (&out3)[3]) {
+  const V4<T> zero = {0, 0, 0, 0};
+  V4<T> wk[2 * NS + 1];      // p_k of planes c - NS .. c + NS
+  V4<T> wn[2 * NS + 1];      // p_k+1 of planes c - 2 NS .. c (the top one formed in the step)
+  V4<T> qp[PD];              // p_k of planes c+NS+1 .. c+NS+PD
+  V4<T> cx = zero, cr = zero;   // x, r of plane c
+#pragma unroll
+  for (int k = 0; k < 2 * NS + 1; ++k) {
+    const int zz = -Zmax - NS + k;
+    wk[k] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
+    wn[k] = zero;
+  }
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int zz = -Zmax + NS + 1 + d;
+    qp[d] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
+  }
+  if (EXX_QVALID(-Zmax)) {
+    const int idx = EXX_QIDX(-Zmax);
+    cr = ld_quad(r, idx);
+    if (!x_zero) cx = ld_quad(x, idx);
+  }
+  double rn = 0.0, pq = 0.0, ra = 0.0, aa = 0.0;
+  for (int c = -Zmax; c <= Zmax + NS; ++c) {
+    const int zl = c + NS + PD + 1;
+    V4<T> np = zero, nx = zero, nr = zero;
+    if (EXX_QVALID(zl)) np = ld_quad(p, EXX_QIDX(zl));
+    if (EXX_QVALID(c + 1)) {
+      const int idx = EXX_QIDX(c + 1);
+      nr = ld_quad(r, idx);
+      if (!x_zero) nx = ld_quad(x, idx);
+    }
+    T* la = (c & 1) ? la1 : la0;
+    T* lb = (c & 1) ? lb1 : lb0;
+    if (cl.zq >= 0) {
+      lds_quad_store(la + cl.pos, wk[NS]);
+      lds_quad_store(lb + cl.pos, wn[NS]);
+    }
+    __syncthreads();
+    V4<T> pn = zero;
+    if (EXX_QVALID(c)) {
+      const int idx = EXX_QIDX(c);
+      const V4<T> rn1 = live_only(cl, c, cr - alpha * apply_quad<NS, DG, T>(S, wk, la, cl.pos));
+      pn = rn1 + beta * wk[NS];
+      st_quad(x, idx, cx + alpha * wk[NS]);
+      st_quad(r, idx, rn1);
+      st_quad(p, idx, pn);
+      rn += dot4(rn1, rn1);
+    }
+    wn[2 * NS] = pn;
+    const int c2 = c - NS;
+    if (EXX_QVALID(c2)) {
+      const V4<T> ap = live_only(cl, c2, apply_quad<NS, DG, T>(S, wn, lb, cl.pos));
+      dots3(wn[NS], wn[NS] - beta * wk[0], ap, pq, ra, aa);
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NS; ++k) {
+      wk[k] = wk[k + 1];
+      wn[k] = wn[k + 1];
+    }
+    wk[2 * NS] = qp[0];
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d) qp[d] = qp[d + 1];
+    qp[PD - 1] = np;
+    cx = nx;
+    cr = nr;
+  }
+  out3[0] = pq;
+  out3[1] = ra;
+  out3[2] = aa;
+  return rn;
+}
+
 // FP64 true residual (as cg_true_residual) on the quad layout, zero at dead
 // slots.  It sweeps twice, once per half of the run (columns 2h, 2h+1), with
 // a z window of 2-point FP64 vectors: a window of whole runs in FP64 does not
@@ -1239,8 +1363,8 @@ __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& 
         if constexpr (DG) aq += S.cd * sdg;
         V2d rt = cb - (-aq);
         const int az = abs(z);
-        rt.x = az <= cl.zr[off] ? rt.x : 0.0;
-        rt.y = az <= cl.zr[off + 1] ? rt.y : 0.0;
+        rt.x = az < (int)((cl.zu >> (8 * off)) & 255u) ? rt.x : 0.0;
+        rt.y = az < (int)((cl.zu >> (8 * off + 8)) & 255u) ? rt.y : 0.0;
         const V2d ro = rt * rs;
         *(EXX_GLOBAL V2r*)((EXX_GLOBAL char*)r + (unsigned)(EXX_QIDX(z) + off) * (unsigned)sizeof(TR)) =
             V2r{(TR)ro.x, (TR)ro.y};
@@ -1277,8 +1401,10 @@ template <int NS, int CPT, int PD, bool GEN, bool TL, bool QD, typename T>
 __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T>& G,
                                        const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, const T* r, T* p,
                                        T beta, bool first, T* pl0, T* pl1, double& pq, double& rr) {
-  if constexpr (QD)
-    cg_pass_a_quad<NS, PD, GEN, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
+  if constexpr (QD) {
+    double ra, aa;
+    cg_pass_a_quad<NS, PD, GEN, false, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr, ra, aa);
+  }
   else if constexpr (GEN && TL)
     cg_pass_a_tl<NS, CPT, T>(G, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr);
   else if constexpr (GEN)
@@ -1313,6 +1439,26 @@ __device__ __forceinline__ double true_residual(const SolveKArgs& a, const ColsO
     return cg_true_residual_gen<NS, CPT, TR>(a.G, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
   else
     return cg_true_residual<NS, CPT, TR>(a.S, cl, pst, Zmax, x, b, r, rs, pl0, pl1);
+}
+
+// block_sum of four values at once (two barriers for the four); red must hold
+// 4 blockDim/64 doubles.
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[4 * wave + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[4 * w + i];
+    v[i] = t;
+  }
+  __syncthreads();
 }
 
 // One workgroup solves one pair at a time, taking pairs from a device queue
@@ -1418,6 +1564,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       a.outIt[pid] = it;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
       a.outUpd[pid] = 0;
+      a.outFus[pid] = 0;
     }
     __syncthreads();
   }
@@ -1432,13 +1579,16 @@ template <int NS, int CPT, int NT, int PD, bool GEN, bool TL, bool QD>
 __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[NT / 64];
+  __shared__ double red4[QD ? 4 * (NT / 64) : 1];
   __shared__ int s_item;
   const int tid = threadIdx.x;
   const int plane = kLdsWX * a.lds_wy;
   double* pl0 = lds;
   double* pl1 = lds + plane;
-  float* fl0 = reinterpret_cast<float*>(lds);
+  float* fl0 = reinterpret_cast<float*>(lds);   // four FP32 planes in the space of two FP64 ones
   float* fl1 = fl0 + plane;
+  float* fl2 = fl1 + plane;
+  float* fl3 = fl2 + plane;
   int* pst = reinterpret_cast<int*>(lds + 2 * plane);
   // slot: x (FP64), then r, p, y (FP32)
   double* x = (double*)((char*)a.slot_ws + (long long)blockIdx.x * a.slot_bytes);
@@ -1446,6 +1596,11 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   float* p = r + a.sstride;
   float* y = p + a.sstride;
   const StencilT<float> S32 = stencil_cast<float>(a.S);
+  // Quad layout: pass B and the next pass A share a sweep (cg_pass_fused_quad)
+  // in workgroups of up to 768 threads.  Its two z windows need the registers
+  // of at most three waves per SIMD; with four (1024 threads) the sweep spills
+  // to scratch memory and runs slower than the two passes.
+  constexpr bool FUSE = QD && NT <= 768;
 
   long long lo, hi;
   solve_range(a, &lo, &hi);
@@ -1480,7 +1635,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     for (long long k = tid; k < npe; k += NT) r[k] = (float)(bx[k] * inv_b);
     __syncthreads();
 
-    int it = 0, upd = 0;
+    int it = 0, upd = 0, nfus = 0;
     double rr = 1.0, rr_true = bb, rmax = 1.0, beta = 0.0;
     bool first = true, x_zero = true, y_zero = true, conv = !(bnorm > 0.0);
     // warm start: x = x0 (FP64) and the working residual (b - A x0) / ||b||
@@ -1495,16 +1650,66 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       rmax = sqrt(rr);
       conv = sqrt(rr_true) <= a.tol * bnorm;
     }
+    // quad layout: p of the iteration and its products already formed by a
+    // fused sweep (cg_pass_fused_quad)
+    bool have_p = false;
+    double pq = 0.0, ra = 0.0, aa = 0.0;
     while (!conv && it < a.max_iter) {
-      double pq_t, rr_t;
-      pass_a<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t, rr_t);
-      const double pq = block_sum(pq_t, red);
+      if (!have_p) {
+        if constexpr (QD) {
+          double t[4], rr_t;
+          cg_pass_a_quad<NS, PD, GEN, FUSE, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, t[0], rr_t,
+                                                   t[1], t[2]);
+          t[3] = 0.0;
+          block_sum4(t, red4);
+          pq = t[0];
+          ra = t[1];
+          aa = t[2];
+        } else {
+          double pq_t, rr_t;
+          pass_a<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t,
+                                                  rr_t);
+          pq = block_sum(pq_t, red);
+        }
+      }
       if (!(pq > 0.0) || !(pq < INFINITY)) {
         it = a.max_iter;
         rr_true = NAN;
         break;
       }
       const double alpha = rr / pq;
+      if constexpr (FUSE) {
+        // |r - alpha Ap|^2 before r is updated; the sweep is fused only where
+        // this next norm stays clear of the reliable-update and stop thresholds
+        // (2% margin), so that every update and stop test follows a pass B
+        const double rn_next = rr - 2.0 * alpha * ra + alpha * alpha * aa;
+        const double thr = 1.02 * fmax(a.delta * rmax, a.tol);
+        if (rn_next > thr * thr && it + 1 < a.max_iter) {
+          double o3[3], t[4];
+          t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, (float)alpha,
+                                                        (float)(rn_next / rr), y_zero, fl0, fl1, fl2, fl3, o3);
+          t[1] = o3[0];
+          t[2] = o3[1];
+          t[3] = o3[2];
+          block_sum4(t, red4);
+          ++it;
+          ++nfus;
+          first = false;
+          y_zero = false;
+          if (!(t[0] == t[0])) {
+            it = a.max_iter;
+            rr_true = NAN;
+            break;
+          }
+          rr = t[0];
+          pq = t[1];
+          ra = t[2];
+          aa = t[3];
+          have_p = true;
+          continue;
+        }
+        have_p = false;
+      }
       double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
                                                                 y_zero, fl0, fl1),
                             red);
@@ -1550,6 +1755,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       a.outIt[pid] = conv ? it : a.max_iter;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr_true) / bnorm : 0.0;
       a.outUpd[pid] = upd;
+      a.outFus[pid] = nfus;
     }
     __syncthreads();
   }
@@ -1616,8 +1822,16 @@ hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_
 template <int NS>
 hipError_t solve_ns_dispatch(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
                              size_t lds, hipStream_t s, int* occ) {
-  if (a.quads) {   // one run of four columns per thread, 1024 threads (GEN: with a diagonal arm)
-    if (threads != 1024 || max_cols > 4 * 1024) return hipErrorInvalidValue;
+  if (a.quads) {   // one run of four columns per thread, 768 or 1024 threads (GEN: with a diagonal arm)
+    if ((threads != 768 && threads != 1024) || max_cols > 4 * threads) return hipErrorInvalidValue;
+    if (threads == 768) {
+      if (a.gen) {
+        if (depth <= 1) return solve_instance_g<NS, 4, 768, 1, true, false, true>(a, mixed, groups, lds, s, occ);
+        return solve_instance_g<NS, 4, 768, 2, true, false, true>(a, mixed, groups, lds, s, occ);
+      }
+      if (depth <= 1) return solve_instance_g<NS, 4, 768, 1, false, false, true>(a, mixed, groups, lds, s, occ);
+      return solve_instance_g<NS, 4, 768, 2, false, false, true>(a, mixed, groups, lds, s, occ);
+    }
     if (a.gen) {
       if (depth <= 1) return solve_instance_g<NS, 4, 1024, 1, true, false, true>(a, mixed, groups, lds, s, occ);
       return solve_instance_g<NS, 4, 1024, 2, true, false, true>(a, mixed, groups, lds, s, occ);

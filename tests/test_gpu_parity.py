@@ -218,7 +218,7 @@ def test_autotuned_solve(prec):
     g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED if prec == "mixed" else exx.EXX_PREC_FP64,
                  autotune=1)
     o = oracle_eval(cfg, orbs, phi)
-    assert g["stats"]["solve_threads"] in (512, 1024) and g["stats"]["solve_depth"] in (1, 2)
+    assert g["stats"]["solve_threads"] in (512, 768, 1024) and g["stats"]["solve_depth"] in (1, 2)
     assert g["stats"]["tune_ms"] > 0
     if prec == "mixed":
         _check_mixed(g, o, cfg.n_orb)
@@ -282,6 +282,34 @@ def test_quad_layout_variable_radius_classes():
     assert g["stats"]["cg_layout"] == 2 and g["stats"]["n_classes"] >= 2
     assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
     _check_mixed(g, o, cfg.n_orb)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_quad_layout_fused_sweeps(n):
+    """Mixed quad layout in a 768-thread workgroup (the default where a sphere
+    has at most 768 runs): pass B and the next pass A share one sweep, whose
+    beta comes from |r - alpha Ap|^2 = |r|^2 - 2 alpha r.Ap + alpha^2 |Ap|^2.
+    Same oracle result and nearly the same iteration count as the two passes
+    of the 1024-thread kernel; the algorithmic bytes per iteration, which count
+    six vector accesses per point for a fused sweep and eight for two passes,
+    shrink by about a quarter."""
+    from paper_2011_07209_amd import exx
+    cfg = synth.custom(key=f"fused-n{n}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=7, R_pair=7.0, R_PE=3.9,
+                       R_ME=5.3, l_max=4, stencil_n=n, cg_tol=1e-12, seed_index=90 + n)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED)
+    g2 = gpu_eval(cfg, orbs, phi, precision=exx.EXX_PREC_MIXED, solve_threads=1024)
+    o = oracle_eval(cfg, orbs, phi)
+    s, s2 = g["stats"], g2["stats"]
+    print(f"[fused n={n}] iters {s['cg_iter_sum']} vs {s2['cg_iter_sum']} bytes/iter "
+          f"{s['cg_alg_bytes'] / s['cg_iter_sum']:.4g} vs {s2['cg_alg_bytes'] / s2['cg_iter_sum']:.4g}", flush=True)
+    assert s["cg_layout"] == 2 and s["solve_threads"] == 768
+    assert s2["cg_layout"] == 2 and s2["solve_threads"] == 1024
+    _check_mixed(g, o, cfg.n_orb)
+    _check_mixed(g2, o, cfg.n_orb)
+    assert abs(s["cg_iter_sum"] - s2["cg_iter_sum"]) <= 0.02 * s2["cg_iter_sum"] + s["n_pairs"]
+    assert s["cg_alg_bytes"] / s["cg_iter_sum"] < 0.85 * s2["cg_alg_bytes"] / s2["cg_iter_sum"]
 
 
 def test_quad_layout_falls_back_for_wide_spheres():
