@@ -554,9 +554,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
   if (opt.cg_layout == 2 && !arms_fit)
     return fail(P, EXX_EINVAL, "quad layout: an arm of the cell's Laplacian leaves the sweep plane, or more than one "
                                "diagonal arm lies in it");
-  // a run's column half-heights are kept plus one in 8-bit fields (ColsQ)
   auto quads_fit = [&](const ClassHost& C) {
-    return C.n_cols <= 4 * 1024 && (C.Rc[0] + 7 + 3) / 4 * 4 + C.Rc[0] + 7 <= kLdsWX - 1 && C.Zmax <= 254;
+    return C.n_cols <= 4 * 1024 && (C.Rc[0] + 7 + 3) / 4 * 4 + C.Rc[0] + 7 <= kLdsWX - 1;
   };
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
   int max_zmax = 0, maxRq = -1, maxRc = -1, maxRc1 = 0;
@@ -571,9 +570,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
       return fail(P, EXX_EINVAL, "quad layout: the cell's columns are not symmetric about the sweep plane");
     if (classes[k].quads && !quads_fit(classes[k])) {
       if (opt.cg_layout == 2)
-        return fail(P, EXX_EINVAL,
-                    "quad layout: the PE sphere needs more than 1024 runs, a wider LDS row or more than 254 planes "
-                    "each side of its centre");
+        return fail(P, EXX_EINVAL, "quad layout: the PE sphere needs more than 1024 runs or a wider LDS row");
       e = build(false);
       if (!e.empty()) return fail(P, EXX_EINVAL, e);
     }

@@ -922,8 +922,8 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
 // inside the run are the thread's own registers.
 
 struct ColsQ {
-  unsigned zu; // per column j, bits 8j .. 8j+7: its half-height plus one (0 outside the sphere)
-  int zq;      // half-height of the run (max of the columns'), -1 for no run
+  int zr[4];   // half-height of each column, -1 outside the sphere
+  int zq;      // half-height of the run (max zr), -1 for no run
   int pos;     // LDS plane position of the run's first column (even)
   int base;    // offset of the run's slots within a plane (4 t)
 };
@@ -934,12 +934,13 @@ __device__ __forceinline__ void load_cols_quad(const ClassDev& C, const SolveKAr
   cl.zq = -1;
   cl.pos = 0;
   cl.base = 4 * run;
-  cl.zu = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) cl.zr[j] = -1;
   if (4 * run < C.n_cols) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int4 cc = C.cols[4 * run + j];
-      cl.zu |= (unsigned)(cc.z + 1) << (8 * j);
+      cl.zr[j] = cc.z;
       cl.zq = max(cl.zq, cc.z);
     }
     const int4 c0 = C.cols[4 * run];
@@ -970,19 +971,6 @@ template <typename T>
 __device__ __forceinline__ double dot4(V4<T> a, V4<T> b) {
   return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
          (double)a.w * (double)b.w;
-}
-
-// p.a, r.a and a.a of 4-point vectors added to pq, ra and aa in FP64, one
-// point at a time (one FP64 value of a live at once)
-template <typename T>
-__device__ __forceinline__ void dots3(V4<T> p, V4<T> r, V4<T> a, double& pq, double& ra, double& aa) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double aj = (double)a[j];
-    pq += (double)p[j] * aj;
-    ra += (double)r[j] * aj;
-    aa += aj * aj;
-  }
 }
 
 // plane values K points right (xr) and left (xl) of the run's four columns,
@@ -1061,10 +1049,10 @@ __device__ __forceinline__ V4<T> apply_quad(const StencilT<T>& S, const V4<T> (&
 template <typename T>
 __device__ __forceinline__ V4<T> live_only(const ColsQ& cl, int z, V4<T> v) {
   const int az = abs(z);
-  v.x = az < (int)(cl.zu & 255u) ? v.x : (T)0;
-  v.y = az < (int)((cl.zu >> 8) & 255u) ? v.y : (T)0;
-  v.z = az < (int)((cl.zu >> 16) & 255u) ? v.z : (T)0;
-  v.w = az < (int)(cl.zu >> 24) ? v.w : (T)0;
+  v.x = az <= cl.zr[0] ? v.x : (T)0;
+  v.y = az <= cl.zr[1] ? v.y : (T)0;
+  v.z = az <= cl.zr[2] ? v.z : (T)0;
+  v.w = az <= cl.zr[3] ? v.w : (T)0;
   return v;
 }
 
@@ -1283,7 +1271,9 @@ __device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, cons
     const int c2 = c - NS;
     if (EXX_QVALID(c2)) {
       const V4<T> ap = live_only(cl, c2, apply_quad<NS, DG, T>(S, wn, lb, cl.pos));
-      dots3(wn[NS], wn[NS] - beta * wk[0], ap, pq, ra, aa);
+      pq += dot4(wn[NS], ap);
+      ra += dot4(wn[NS] - beta * wk[0], ap);
+      aa += dot4(ap, ap);
     }
 #pragma unroll
     for (int k = 0; k < 2 * NS; ++k) {
@@ -1363,8 +1353,8 @@ __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& 
         if constexpr (DG) aq += S.cd * sdg;
         V2d rt = cb - (-aq);
         const int az = abs(z);
-        rt.x = az < (int)((cl.zu >> (8 * off)) & 255u) ? rt.x : 0.0;
-        rt.y = az < (int)((cl.zu >> (8 * off + 8)) & 255u) ? rt.y : 0.0;
+        rt.x = az <= cl.zr[off] ? rt.x : 0.0;
+        rt.y = az <= cl.zr[off + 1] ? rt.y : 0.0;
         const V2d ro = rt * rs;
         *(EXX_GLOBAL V2r*)((EXX_GLOBAL char*)r + (unsigned)(EXX_QIDX(z) + off) * (unsigned)sizeof(TR)) =
             V2r{(TR)ro.x, (TR)ro.y};
