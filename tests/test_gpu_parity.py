@@ -312,6 +312,43 @@ def test_quad_layout_fused_sweeps(n):
     assert s["cg_alg_bytes"] / s["cg_iter_sum"] < 0.85 * s2["cg_alg_bytes"] / s2["cg_iter_sum"]
 
 
+@pytest.mark.parametrize("threads", [0, 1024])
+def test_mixed_quad_iteration_cap(threads):
+    """With cg_max_iter below what the pairs need, the mixed quad-layout CG
+    (768-thread fused sweeps by default, two passes at 1024 threads) stops
+    every pair at the cap.  No fused sweep takes the last iteration, so the cap
+    ends in a pass B and an FP64 true residual: every pair reports the cap,
+    and the plan reports them unconverged (EXX_ENOCONV)."""
+    import torch
+    from paper_2011_07209_amd import exx
+    cfg = synth.custom(key=f"cap-{threads}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46), n_orb=5, R_pair=7.0,
+                       R_PE=3.9, R_ME=5.3, l_max=4, stencil_n=3, cg_tol=1e-12, seed_index=97)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    dev = torch.device("cuda:0")
+    cap = 30
+    plan = exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, stencil_n=cfg.stencil_n,
+                    cg_tol=cfg.cg_tol, precision=exx.EXX_PREC_MIXED, cg_max_iter=cap, solve_threads=threads)
+    try:
+        orb_t = torch.from_numpy(phi).to(dev)
+        cen_t = torch.from_numpy(orbs.centres).to(dev)
+        plan.eval(orb_t, cen_t)
+        torch.cuda.synchronize()
+        with pytest.raises(exx.ExxError):
+            plan.stats()
+        st = plan.stats(allow_noconv=True)
+        res = plan.pair_results()
+    finally:
+        plan.close()
+    print(f"[cap {threads}] variant {st['solve_threads']} pairs {st['n_pairs']} unconverged {st['n_unconverged']} "
+          f"iters max {st['cg_iter_max']} residual max {st['max_rel_residual']:.3e}", flush=True)
+    assert st["cg_layout"] == 2 and st["solve_threads"] == (768 if threads == 0 else 1024)
+    assert st["n_unconverged"] == st["n_pairs"] > 0
+    assert st["cg_iter_max"] == cap and st["cg_iter_sum"] == cap * st["n_pairs"]
+    assert np.all(np.asarray(res["iters"]) == cap)
+    assert st["max_rel_residual"] > cfg.cg_tol
+
+
 def test_quad_layout_falls_back_for_wide_spheres():
     """A sphere of more than 1024 runs of four columns (R_PE 7.1 at spacing 0.2:
     3,969 columns in 1,044 runs): the default layout of a mixed plan falls back
