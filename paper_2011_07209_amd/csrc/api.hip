@@ -732,9 +732,10 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
 
 // Default CG variant of each class (measured on MI355X): 1024 threads up to
 // three columns each for orthorhombic cells (1024 x 4 spills), up to four for
-// general cells (whose passes keep fewer values per column), else 512; FP64
-// loads one plane ahead, mixed two (cells with arms leaving the sweep plane
-// always load one ahead).
+// general cells (whose passes keep fewer values per column), else 512; quad
+// layout classes one run per thread, 768 threads for mixed plans where the
+// runs fit (fused sweeps), else 1024; FP64 loads one plane ahead, mixed two
+// (cells with arms leaving the sweep plane always load one ahead).
 void default_solve_variants(exx_plan_t P) {
   const exx_options& opt = P->opt;
   const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
