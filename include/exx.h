@@ -35,12 +35,27 @@ typedef enum {
   EXX_OK = 0,
   EXX_EINVAL = 1,      /* an argument is out of range or inconsistent            */
   EXX_ENOMEM = 2,      /* a device or host allocation failed                     */
-  EXX_ENOCONV = 3,     /* at least one pair's CG hit cg_max_iter (outputs kept)  */
+  EXX_ENOCONV = 3,     /* at least one pair's CG did not converge: it hit
+                          cg_max_iter, broke down, or met a non-finite norm
+                          (exx_stats tells which; outputs are kept, each such
+                          pair with its last FP64 solution)                    */
   EXX_EDEVICE = 4,     /* a HIP runtime call failed                              */
   EXX_ECAPACITY = 5    /* more pairs than the plan's fixed capacity              */
 } exx_status;
 
 typedef enum { EXX_F64 = 0, EXX_F32 = 1 } exx_dtype;
+
+/* Why a pair's CG stopped (exx_pair_results exit_code, low byte; the bits
+   above it count the mixed solve's restarts). */
+typedef enum {
+  EXX_CG_CONVERGED = 0,   /* ||b - A x|| <= cg_tol ||b|| (or b = 0)                  */
+  EXX_CG_CAP = 1,         /* cg_max_iter iterations without converging                */
+  EXX_CG_BREAKDOWN = 2,   /* p.Ap not positive and finite (in FP64 only a non-finite
+                             input does this; the mixed solve first restarts from
+                             its last FP64 solution, at most 3 times)                 */
+  EXX_CG_NONFINITE = 3    /* a NaN or infinity in the right-hand side or in a
+                             residual norm (mixed: after its restarts)                */
+} exx_cg_exit;
 
 typedef enum {
   EXX_PREC_FP64 = 0,   /* every step in double precision                          */
@@ -53,7 +68,9 @@ typedef struct {
                                  eq. d2_1; the paper's default is 3)               */
   int precision;              /* exx_precision                                      */
   double cg_tol;              /* stop when ||r||_2 <= cg_tol ||b||_2 (FP64 residual)  */
-  int cg_max_iter;            /* per solve; hitting it is reported as EXX_ENOCONV   */
+  int cg_max_iter;            /* per solve; hitting it is reported as EXX_ENOCONV
+                                 (a pair that converges on its last permitted
+                                 iteration counts as converged)                     */
   /* variable sphere radii: with per-orbital radii passed to exx_eval, the pair
      radius is the rung R_PE_min + k R_PE_step (k < R_PE_nclass) nearest to
      (R_i + R_j)/2; R_PE_nclass <= 0 keeps the single plan radius R_PE          */
@@ -72,7 +89,8 @@ typedef struct {
                                  returns EXX_ECAPACITY                              */
   double workspace_gb;        /* cap on per-batch pair workspace (0: 24 GB)        */
   int solve_groups;           /* persistent solve workgroups (0: as many as fit)   */
-  int solve_threads;          /* CG workgroup size, 512 or 1024 (0: tuned/default) */
+  int solve_threads;          /* CG workgroup size, 512, 768 (quad layout only) or
+                                 1024 (0: tuned/default)                            */
   int solve_depth;            /* planes of loads in flight ahead of use, 1 or 2
                                  (0: tuned/default)                                */
   int autotune;               /* 1: the first exx_eval times the CG variants on a
@@ -175,11 +193,14 @@ exx_status exx_count_pairs(exx_plan_t plan, int n_orb, const double* centres, co
 
 /* Per-pair results of the last exx_eval, copied to host arrays of capacity
    cap (any may be NULL): ij [2*cap] (i, j), E [cap] (weighted contribution),
-   sigma [9*cap], iters [cap], rel_res [cap] (final recursive ||r||/||b||).
-   Pairs come in i-major, j-ascending order.  Synchronizes the bound stream.
-   Returns the number of pairs of the last evaluation in *n_pairs. */
+   sigma [9*cap], iters [cap] (CG iterations; mixed: FP32 iterations),
+   rel_res [cap] (final ||b - A x|| / ||b||; FP64: the recursive residual at
+   the stop), exit_code [cap] (exx_cg_exit in the low byte, the mixed solve's
+   restarts << 8), updates [cap] (mixed: FP64 reliable updates).  Pairs come
+   in i-major, j-ascending order.  Synchronizes the bound stream.  Returns the
+   number of pairs of the last evaluation in *n_pairs. */
 exx_status exx_pair_results(exx_plan_t plan, long long cap, int* ij, double* E, double* sigma, int* iters,
-                            double* rel_res, long long* n_pairs);
+                            double* rel_res, int* exit_code, int* updates, long long* n_pairs);
 
 typedef struct {
   long long n_pairs;
@@ -220,6 +241,21 @@ typedef struct {
   int n_arms;                  /* arms of the Laplacian in use (3 to 6)           */
   int cg_layout;               /* CG layout in use: 1 columns, 2 quads, 3 both
                                   (per sphere class)                               */
+  /* why pairs of the last exx_eval did not converge (they sum to n_unconverged) */
+  int n_cg_cap;                /* stopped at cg_max_iter                           */
+  int n_cg_breakdown;          /* p.Ap not positive and finite (after restarts)     */
+  int n_cg_nonfinite;          /* a non-finite right-hand side or residual norm     */
+  long long cg_restarts;       /* mixed: restarts from the last FP64 solution after
+                                  a breakdown or a non-finite FP32 norm              */
+  double t_pairlist_ms;        /* device time of the pair list and its order       */
+  double t_reduce_ms;          /* device time of the E, sigma and stats reduction  */
+  /* CG variant of each sphere class (classes beyond n_classes are 0): workgroup
+     size, load depth, layout (1 columns, 2 quads) and the class's pairs in the
+     last exx_eval */
+  int class_threads[16];
+  int class_depth[16];
+  int class_layout[16];
+  long long class_pairs[16];
 } exx_stats;
 
 /* Fluctuating cell (Sec. III B 2): makes h (host [9], column-major,

@@ -126,7 +126,7 @@ struct CaptureGuard {
 void free_plan(exx_plan_t P) {
   if (!P) return;
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->pFus, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
+                  P->pRes, P->pUpd, P->pFus, P->pExit, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
                   P->warm_map, P->prev_pairs, P->prev_offs, P->warm_state, P->slot_ws, P->queue,
                   P->stats_dev};
   for (void* p : ptrs)
@@ -143,9 +143,9 @@ void free_plan(exx_plan_t P) {
 // Copies the device statistics of the last evaluation (k_reduce's eight
 // values and the per-class pair counts).  The caller has synchronized.
 exx_status read_device_stats(exx_plan_t P) {
-  double st[9] = {0};
+  double st[kStatsLen] = {0};
   EXX_HIP(P, hipMemcpy(st, P->stats_dev, sizeof(st), hipMemcpyDeviceToHost));
-  for (int k = 0; k < 9; ++k) P->last_stats[k] = st[k];
+  for (int k = 0; k < kStatsLen; ++k) P->last_stats[k] = st[k];
   int cc[kMaxClasses] = {0};
   const int ncls = (int)P->classes.size();
   EXX_HIP(P, hipMemcpy(cc, P->pair_count + 2 * P->last_n_orb + 1, sizeof(int) * ncls, hipMemcpyDeviceToHost));
@@ -169,6 +169,11 @@ exx_status harvest(exx_plan_t P) {
     mom += ms;
   }
   P->last_moment_ms = mom;
+  float pl_ms = 0, red_ms = 0;
+  EXX_HIP(P, hipEventElapsedTime(&pl_ms, P->ev[0], P->ev[4]));
+  EXX_HIP(P, hipEventElapsedTime(&red_ms, P->ev[2], P->ev[3]));
+  P->last_pairlist_ms = pl_ms;
+  P->last_reduce_ms = red_ms;
   EXX_HIP(P, hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
   exx_status ds = read_device_stats(P);
   if (ds != EXX_OK) return ds;
@@ -884,7 +889,7 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
       free_plan(P);
       return fail(nullptr, EXX_EDEVICE, "event creation failed");
     }
-  if (hipMalloc(&P->queue, sizeof(int)) != hipSuccess || hipMalloc(&P->stats_dev, 9 * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&P->queue, sizeof(int)) != hipSuccess || hipMalloc(&P->stats_dev, kStatsLen * sizeof(double)) != hipSuccess) {
     free_plan(P);
     return fail(nullptr, EXX_ENOMEM, "device allocation failed");
   }
@@ -1026,7 +1031,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     if (dev_alloc(P, &P->pairs, (size_t)cap, "pairs") || dev_alloc(P, &P->order, (size_t)cap, "order") ||
         dev_alloc(P, &P->pE, (size_t)cap, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * cap, "pair sigma") ||
         dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res") ||
-        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates") || dev_alloc(P, &P->pFus, (size_t)cap, "pair fused sweeps"))
+        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates") || dev_alloc(P, &P->pFus, (size_t)cap, "pair fused sweeps") ||
+        dev_alloc(P, &P->pExit, (size_t)cap, "pair exit reasons"))
       return EXX_ENOMEM;
     P->pair_cap = cap;
     return EXX_OK;
@@ -1052,6 +1058,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   P->last_n_orb = n_orb;
   const int ncls = (int)P->classes.size();
   EXX_HIP(P, launch_order(P->pairs, P->pair_count, n_orb, ncls, P->order, P->pair_cap, P->n_eff, s));
+  EXX_HIP(P, event(P->ev[4]));
   if (P->opt.warm_start) {
     // the stores and the previous list keep their contents between calls;
     // they are (re)made only when the capacity grows, which drops the history
@@ -1145,6 +1152,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.outRes = P->pRes;
     a.outUpd = P->pUpd;
     a.outFus = P->pFus;
+    a.outExit = P->pExit;
     a.mixed = mixed;
     a.delta = 0.1;
     a.threads = P->solve_threads;
@@ -1177,8 +1185,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
       EXX_HIP(P, launch_dscatter(g, B, P->max_me, orbitals, D_xx, d_slot, (int)dt, P->bx_ws, P->rstride, P->Q_ws, s));
   }
   EXX_HIP(P, event(P->ev[2]));
-  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pFus, P->pairs, P->class_dev, P->pair_count, n_orb,
-                           P->n_eff, P->opt.warm_start ? P->warm_map : nullptr, P->opt.cg_max_iter, E_xx, sigma,
+  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pFus, P->pExit, P->pairs, P->class_dev,
+                           P->pair_count, n_orb, P->n_eff, P->opt.warm_start ? P->warm_map : nullptr, E_xx, sigma,
                            P->stats_dev, s));
   if (P->opt.warm_start)
     EXX_HIP(P, launch_warm_commit(P->pairs, P->pair_count, n_orb, P->n_eff, P->pair_cap, P->prev_pairs, P->prev_offs,
@@ -1234,7 +1242,7 @@ exx_status exx_count_pairs(exx_plan_t P, int n_orb, const double* centres, const
 }
 
 exx_status exx_pair_results(exx_plan_t P, long long cap, int* ij, double* E, double* sigma, int* iters,
-                            double* rel_res, long long* n_pairs) {
+                            double* rel_res, int* exit_code, int* updates, long long* n_pairs) {
   if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
   EXX_HIP(P, hipStreamSynchronize(P->stream));
   int stored = 0;
@@ -1254,6 +1262,8 @@ exx_status exx_pair_results(exx_plan_t P, long long cap, int* ij, double* E, dou
   if (sigma) EXX_HIP(P, hipMemcpy(sigma, P->pS, sizeof(double) * 9 * n, hipMemcpyDeviceToHost));
   if (iters) EXX_HIP(P, hipMemcpy(iters, P->pIt, sizeof(int) * n, hipMemcpyDeviceToHost));
   if (rel_res) EXX_HIP(P, hipMemcpy(rel_res, P->pRes, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (exit_code) EXX_HIP(P, hipMemcpy(exit_code, P->pExit, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (updates) EXX_HIP(P, hipMemcpy(updates, P->pUpd, sizeof(int) * n, hipMemcpyDeviceToHost));
   return EXX_OK;
 }
 
@@ -1315,6 +1325,18 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
   out->pairs_kept = (long long)st[4];
   out->graph_recorded = P->last_captured ? 1 : 0;
   out->warm_pairs = (long long)st[8];
+  out->n_cg_cap = (int)st[9];
+  out->n_cg_breakdown = (int)st[10];
+  out->n_cg_nonfinite = (int)st[11];
+  out->cg_restarts = (long long)st[12];
+  out->t_pairlist_ms = P->last_pairlist_ms;
+  out->t_reduce_ms = P->last_reduce_ms;
+  for (int k = 0; k < (int)P->classes.size() && k < kMaxClasses; ++k) {
+    out->class_threads[k] = P->class_threads[k];
+    out->class_depth[k] = P->class_depth[k];
+    out->class_layout[k] = P->classes[k].quads ? 2 : 1;
+    out->class_pairs[k] = P->last_class_pairs[k];
+  }
   if (st[4] > (double)P->pair_cap)
     return fail(P, EXX_ECAPACITY, "more pairs than the fixed capacity (max_pairs); results cover the first ones");
   return out->n_unconverged > 0 ? fail(P, EXX_ENOCONV, "CG did not converge for some pairs") : EXX_OK;

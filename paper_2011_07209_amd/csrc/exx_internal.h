@@ -15,6 +15,8 @@ namespace exx {
 constexpr int kMaxL = 8;                       // l_max limit of the multipole expansion
 constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
 constexpr int kMaxClasses = 16;
+// values k_reduce writes per evaluation (see launch_reduce)
+constexpr int kStatsLen = 13;
 constexpr double kSlack = 1e-12;               // relative slack of sphere membership on |r|^2
 // Row stride of the LDS planes of the CG, a compile-time constant so that the
 // y-neighbour reads use immediate offsets.  It bounds the sphere:
@@ -192,6 +194,7 @@ struct exx_plan_s {
   double* pRes = nullptr;
   int* pUpd = nullptr;
   int* pFus = nullptr;   // fused CG sweeps per pair (each saves two vector accesses per point)
+  int* pExit = nullptr;  // CG exit reason per pair (EXX_CG_*) | restarts << 8
 
   // batch workspace
   long long batch_cap = 0;
@@ -215,7 +218,8 @@ struct exx_plan_s {
   double* stats_dev = nullptr;     // the eight values of k_reduce (see launch_reduce)
   int last_n_orb = 0;
 
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // eval begin, workspace ready, reductions begin, eval end, pair list done
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> solve_ev;   // begin/end pairs around each solve launch of the last eval
   int solve_ev_used = 0;
   std::vector<hipEvent_t> mom_ev;     // begin/end pairs around each moment launch of the last eval
@@ -224,8 +228,8 @@ struct exx_plan_s {
   long long last_class_pairs[exx::kMaxClasses] = {0};
   bool timing_valid = false;
   bool harvested = true;              // last eval's events already added to the totals
-  double last_solve_ms = 0, last_eval_ms = 0, last_alg_bytes = 0;
-  double last_stats[9] = {0};
+  double last_solve_ms = 0, last_eval_ms = 0, last_alg_bytes = 0, last_pairlist_ms = 0, last_reduce_ms = 0;
+  double last_stats[exx::kStatsLen] = {0};
   long long n_evals = 0, solve_launches = 0;
   double solve_ms_total = 0, eval_ms_total = 0, alg_bytes_total = 0;
   std::string err;

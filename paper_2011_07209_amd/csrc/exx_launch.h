@@ -76,6 +76,7 @@ struct SolveArgs {
   double* outRes = nullptr;
   int* outUpd = nullptr;       // reliable updates per pair (mixed)
   int* outFus = nullptr;       // fused sweeps per pair (pass B with the next pass A)
+  int* outExit = nullptr;      // per pair: exit reason (EXX_CG_*) | restarts << 8
   double tol = 0;
   int max_iter = 0;
   bool mixed = false;
@@ -119,13 +120,15 @@ hipError_t launch_warm_commit(const PairDev* pairs, const int* counts, int n_orb
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
-// E_xx and sigma from per-pair results in canonical order; stats[9] receives
-// (iter_sum, iter_max, n_unconverged, max_res, n_pairs kept (also beyond the
-// capacity), sum iters*N_PE, refinement passes max, sum N_PE, warm-started
-// pairs) as doubles.  warm_map may be null.
+// E_xx and sigma from per-pair results in canonical order; stats[kStatsLen]
+// receives (iter_sum, iter_max, n_unconverged, max_res, n_pairs kept (also
+// beyond the capacity), sum iters*N_PE, refinement passes max, sum N_PE,
+// warm-started pairs, pairs stopped at the iteration cap, by a breakdown, by a
+// non-finite norm, restarts) as doubles.  A pair is unconverged when its exit
+// reason (pExit, low byte) is not EXX_CG_CONVERGED.  warm_map may be null.
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
-                         const int* pFus,
-                         const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
-                         const int* warm_map, int max_iter, double* E, double* sigma, double* stats, hipStream_t s);
+                         const int* pFus, const int* pExit, const PairDev* pairs, const ClassDev* cls,
+                         const int* counts, int n_orb, const int* n_eff, const int* warm_map, double* E, double* sigma,
+                         double* stats, hipStream_t s);
 
 }  // namespace exx

@@ -515,15 +515,16 @@ __global__ void k_dslot_fill(int* slot, int n_orb, const int* __restrict__ subse
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, const double* __restrict__ pS,
                                                 const int* __restrict__ pIt, const double* __restrict__ pRes,
                                                 const int* __restrict__ pUpd, const int* __restrict__ pFus,
+                                                const int* __restrict__ pExit,
                                                 const PairDev* __restrict__ pairs, const ClassDev* __restrict__ cls,
                                                 const int* __restrict__ cnt, int n_orb, const int* __restrict__ n_eff,
-                                                const int* __restrict__ warm_map, int max_iter,
+                                                const int* __restrict__ warm_map,
                                                 double* __restrict__ E, double* __restrict__ sigma,
                                                 double* __restrict__ stats) {
   __shared__ double red[4];
   const long long np = *n_eff;
   double e = 0.0, s[9], isum = 0.0, imax = 0.0, nunc = 0.0, rmax = 0.0, work = 0.0, pts = 0.0, umax = 0.0,
-         warm = 0.0;
+         warm = 0.0, ncap = 0.0, nbrk = 0.0, nnan = 0.0, nrst = 0.0;
   for (int t = 0; t < 9; ++t) s[t] = 0.0;
   for (long long k = threadIdx.x; k < np; k += blockDim.x) {
     e += pE[k];
@@ -531,7 +532,14 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     isum += pIt[k];
     imax = fmax(imax, (double)pIt[k]);
     umax = fmax(umax, (double)pUpd[k]);
-    nunc += (pIt[k] >= max_iter) ? 1.0 : 0.0;
+    // the solve's own exit reason, not the iteration count, says whether a
+    // pair converged (a pair may converge on its last permitted iteration)
+    const int ex = pExit[k] & 0xff;
+    nunc += ex != EXX_CG_CONVERGED ? 1.0 : 0.0;
+    ncap += ex == EXX_CG_CAP ? 1.0 : 0.0;
+    nbrk += ex == EXX_CG_BREAKDOWN ? 1.0 : 0.0;
+    nnan += ex == EXX_CG_NONFINITE ? 1.0 : 0.0;
+    nrst += (double)(pExit[k] >> 8);
     rmax = fmax(rmax, pRes[k]);
     const double npe = (double)cls[pairs[k].cls].n_real;
     work += (pIt[k] - 0.25 * pFus[k]) * npe;   // a fused sweep moves 6 of 8 vector accesses per point
@@ -545,6 +553,10 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
   work = block_sum(work, red);
   pts = block_sum(pts, red);
   warm = block_sum(warm, red);
+  ncap = block_sum(ncap, red);
+  nbrk = block_sum(nbrk, red);
+  nnan = block_sum(nnan, red);
+  nrst = block_sum(nrst, red);
   // max via shuffles
   for (int o = 32; o > 0; o >>= 1) {
     imax = fmax(imax, __shfl_xor(imax, o, 64));
@@ -576,6 +588,10 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     stats[6] = umax;
     stats[7] = pts;
     stats[8] = warm;
+    stats[9] = ncap;
+    stats[10] = nbrk;
+    stats[11] = nnan;
+    stats[12] = nrst;
   }
 }
 
@@ -711,9 +727,10 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
-                         const int* pFus, const PairDev* pairs, const ClassDev* cls, const int* counts, int n_orb, const int* n_eff,
-                         const int* warm_map, int max_iter, double* E, double* sigma, double* stats, hipStream_t s) {
-  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pFus, pairs, cls, counts, n_orb, n_eff, warm_map, max_iter, E, sigma,
+                         const int* pFus, const int* pExit, const PairDev* pairs, const ClassDev* cls,
+                         const int* counts, int n_orb, const int* n_eff, const int* warm_map, double* E, double* sigma,
+                         double* stats, hipStream_t s) {
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pFus, pExit, pairs, cls, counts, n_orb, n_eff, warm_map, E, sigma,
                              stats);
   return hipGetLastError();
 }

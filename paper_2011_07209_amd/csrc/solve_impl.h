@@ -19,6 +19,16 @@
 
 namespace exx {
 
+// Exit reasons of a pair's CG (low byte of SolveKArgs::outExit; the mixed
+// solve keeps its restarts above it).
+constexpr int kCgConverged = EXX_CG_CONVERGED;
+constexpr int kCgCap = EXX_CG_CAP;
+constexpr int kCgBreakdown = EXX_CG_BREAKDOWN;
+constexpr int kCgNonFinite = EXX_CG_NONFINITE;
+// Restarts the mixed solve allows from its last FP64 solution after a
+// breakdown or a non-finite norm of its FP32 recursion.
+constexpr int kCgMaxRestarts = 3;
+
 template <typename T>
 struct StencilT {
   T w[4];      // second-derivative weights w_0..w_3
@@ -92,6 +102,7 @@ struct SolveKArgs {
   double* outRes;
   int* outUpd;            // mixed: reliable updates per pair
   int* outFus;            // sweeps that fused pass B with the next pass A, per pair
+  int* outExit;           // per pair: exit reason (kCg*) | restarts << 8
   double tol;
   int max_iter;
   double delta;           // mixed: update when ||r|| < delta * (residual at the last update)
@@ -1488,7 +1499,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
     cols_load<GEN, QD, CPT, NT>(C, a, cl);
     __syncthreads();
 
-    int it = 0;
+    int it = 0, code = kCgConverged;
     double rr = 0.0, bnorm = 0.0, beta = 0.0;
     bool first = true;
     // Warm start: with x0 gathered into p, a first half-iteration runs pass B
@@ -1505,6 +1516,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       __syncthreads();
     }
     const bool from_b = !init;   // cold: the first pass reads b from x, and x starts at zero
+    bool conv = false;
     while (it < a.max_iter) {
       double alpha = 1.0;
       if (!init) {
@@ -1515,11 +1527,19 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
         if (first && from_b) {
           rr = block_sum(rr_t, red);
           bnorm = sqrt(rr);
-          if (!(bnorm > 0.0)) break;   // b == 0: x = b = 0 already
+          if (bnorm == 0.0) {   // b == 0: x = b = 0 already
+            conv = true;
+            break;
+          }
+          if (!(bnorm < INFINITY)) {   // b holds a NaN or an infinity
+            code = kCgNonFinite;
+            break;
+          }
         }
-        if (!(pq > 0.0) || !(pq < INFINITY)) {   // breakdown: A is SPD, so only NaN/inf input gets here
-          it = a.max_iter;
-          rr = NAN;
+        // breakdown: A is SPD, so in FP64 only non-finite input gets here;
+        // the solution is left as it stands (b is no longer held)
+        if (!(pq > 0.0) || !(pq < INFINITY)) {
+          code = kCgBreakdown;
           break;
         }
         alpha = rr / pq;
@@ -1532,29 +1552,35 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       if (init) {   // the warm start's residual
         init = false;
         rr = rn;
-        if (!(bnorm > 0.0) || sqrt(rn) <= a.tol * bnorm) break;
+        if (!(bnorm > 0.0) || sqrt(rn) <= a.tol * bnorm) {
+          conv = true;
+          break;
+        }
         continue;
       }
       ++it;
       first = false;
       if (sqrt(rn) <= a.tol * bnorm) {
         rr = rn;
+        conv = true;
         break;
       }
       if (!(rn == rn)) {
-        it = a.max_iter;
         rr = NAN;
+        code = kCgNonFinite;
         break;
       }
       beta = rn / rr;
       rr = rn;
     }
+    if (!conv && code == kCgConverged) code = kCgCap;
     warm_store_solution(a, npe, pid, x);
     if (tid == 0) {
       a.outIt[pid] = it;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
       a.outUpd[pid] = 0;
       a.outFus[pid] = 0;
+      a.outExit[pid] = code;
     }
     __syncthreads();
   }
@@ -1625,11 +1651,13 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     for (long long k = tid; k < npe; k += NT) r[k] = (float)(bx[k] * inv_b);
     __syncthreads();
 
-    int it = 0, upd = 0, nfus = 0;
+    int it = 0, upd = 0, nfus = 0, rst = 0, code = kCgConverged;
     double rr = 1.0, rr_true = bb, rmax = 1.0, beta = 0.0;
-    bool first = true, x_zero = true, y_zero = true, conv = !(bnorm > 0.0);
+    bool first = true, x_zero = true, y_zero = true;
+    bool conv = bnorm == 0.0;
+    if (!conv && !(bnorm < INFINITY)) code = kCgNonFinite;   // b holds a NaN or an infinity
     // warm start: x = x0 (FP64) and the working residual (b - A x0) / ||b||
-    if (!conv && warm_gather<double>(a, C, pid, x)) {
+    if (!conv && code == kCgConverged && warm_gather<double>(a, C, pid, x)) {
       for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
       __syncthreads();
       rr_true = block_sum(true_residual<NS, CPT, GEN, TL, QD, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
@@ -1644,7 +1672,12 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     // fused sweep (cg_pass_fused_quad)
     bool have_p = false;
     double pq = 0.0, ra = 0.0, aa = 0.0;
-    while (!conv && it < a.max_iter) {
+    while (!conv && code == kCgConverged && it < a.max_iter) {
+      // bad: the FP32 recursion broke down (p.Ap not positive and finite) or
+      // produced a non-finite norm; the CG then restarts from the last FP64
+      // solution (its FP32 correction y is dropped), up to kCgMaxRestarts times
+      int bad = kCgConverged;
+      double rn = 0.0;
       if (!have_p) {
         if constexpr (QD) {
           double t[4], rr_t;
@@ -1662,77 +1695,96 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
           pq = block_sum(pq_t, red);
         }
       }
-      if (!(pq > 0.0) || !(pq < INFINITY)) {
-        it = a.max_iter;
-        rr_true = NAN;
-        break;
-      }
-      const double alpha = rr / pq;
-      if constexpr (FUSE) {
-        // |r - alpha Ap|^2 before r is updated; the sweep is fused only where
-        // this next norm stays clear of the reliable-update and stop thresholds
-        // (2% margin), so that every update and stop test follows a pass B
-        const double rn_next = rr - 2.0 * alpha * ra + alpha * alpha * aa;
-        const double thr = 1.02 * fmax(a.delta * rmax, a.tol);
-        if (rn_next > thr * thr && it + 1 < a.max_iter) {
-          double o3[3], t[4];
-          t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, (float)alpha,
-                                                        (float)(rn_next / rr), y_zero, fl0, fl1, fl2, fl3, o3);
-          t[1] = o3[0];
-          t[2] = o3[1];
-          t[3] = o3[2];
-          block_sum4(t, red4);
+      if (!(pq > 0.0) || !(pq < INFINITY)) bad = kCgBreakdown;
+      if (bad == kCgConverged) {
+        const double alpha = rr / pq;
+        bool fused = false;
+        if constexpr (FUSE) {
+          // |r - alpha Ap|^2 before r is updated; the sweep is fused only where
+          // this next norm stays clear of the reliable-update and stop thresholds
+          // (2% margin), so that every update and stop test follows a pass B
+          const double rn_next = rr - 2.0 * alpha * ra + alpha * alpha * aa;
+          const double thr = 1.02 * fmax(a.delta * rmax, a.tol);
+          if (rn_next > thr * thr && it + 1 < a.max_iter) {
+            double o3[3], t[4];
+            t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, (float)alpha,
+                                                          (float)(rn_next / rr), y_zero, fl0, fl1, fl2, fl3, o3);
+            t[1] = o3[0];
+            t[2] = o3[1];
+            t[3] = o3[2];
+            block_sum4(t, red4);
+            ++it;
+            ++nfus;
+            first = false;
+            y_zero = false;
+            fused = true;
+            if (!(t[0] == t[0]) || !(t[0] < INFINITY)) {
+              bad = kCgNonFinite;
+            } else {
+              rr = t[0];
+              pq = t[1];
+              ra = t[2];
+              aa = t[3];
+              have_p = true;
+              continue;
+            }
+          }
+          have_p = false;
+        }
+        if (!fused) {
+          rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
+                                                                 y_zero, fl0, fl1),
+                         red);
           ++it;
-          ++nfus;
           first = false;
           y_zero = false;
-          if (!(t[0] == t[0])) {
-            it = a.max_iter;
-            rr_true = NAN;
-            break;
-          }
-          rr = t[0];
-          pq = t[1];
-          ra = t[2];
-          aa = t[3];
-          have_p = true;
-          continue;
+          if (!(rn == rn) || !(rn < INFINITY)) bad = kCgNonFinite;
         }
-        have_p = false;
       }
-      double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
-                                                                y_zero, fl0, fl1),
-                            red);
-      ++it;
-      first = false;
-      y_zero = false;
       const double rnorm = sqrt(rn);
-      if (!(rn == rn)) {
-        it = a.max_iter;
-        rr_true = NAN;
+      const bool restart = bad != kCgConverged;
+      if (restart && rst >= kCgMaxRestarts) {
+        code = bad;
         break;
       }
-      if (rnorm < a.delta * rmax || rnorm <= a.tol || it >= a.max_iter) {
-        // fold the FP32 correction into the FP64 solution, x = x + ||b|| y
-        // (a flat pass over the points), then the FP64 true residual; the
-        // FP64 and FP32 plane views share LDS, so it is cleared around the
-        // FP64 pass (the barrier also orders the fold before the sweep)
-        for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
-        for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
-        __syncthreads();
-        rr_true = block_sum(true_residual<NS, CPT, GEN, TL, QD, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
-        for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
-        __syncthreads();
-        ++upd;
-        x_zero = false;
+      if (restart || rnorm < a.delta * rmax || rnorm <= a.tol || it >= a.max_iter) {
+        // A reliable update folds the FP32 correction into the FP64 solution,
+        // x = x + ||b|| y (a flat pass over the points); a restart drops it.
+        // Then the FP64 true residual replaces the working one (or, with no
+        // FP64 solution yet, b / ||b|| does).  The FP64 and FP32 plane views
+        // share LDS, so it is cleared around the FP64 pass (the barrier also
+        // orders the fold before the sweep).
+        if (!restart) {
+          for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
+          x_zero = false;
+          ++upd;
+        } else {
+          ++rst;
+          have_p = false;
+        }
+        if (x_zero) {
+          for (long long k = tid; k < npe; k += NT) r[k] = (float)(bx[k] * inv_b);
+          __syncthreads();
+          rr_true = bb;
+        } else {
+          for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+          __syncthreads();
+          rr_true =
+              block_sum(true_residual<NS, CPT, GEN, TL, QD, float>(a, cl, pst, Zmax, x, bx, r, inv_b, pl0, pl1), red);
+          for (int k = tid; k < 2 * plane; k += NT) lds[k] = 0.0;
+          __syncthreads();
+        }
         y_zero = true;
         rn = rr_true * inv_b * inv_b;
         rmax = sqrt(rn);
         if (sqrt(rr_true) <= a.tol * bnorm) conv = true;
+        if (!(rn < INFINITY)) code = kCgNonFinite;   // the FP64 solution itself is not finite
+        if (restart) first = true;   // steepest descent from the refreshed residual
       }
       beta = rn / rr;
       rr = rn;
     }
+    if (!conv && code == kCgConverged) code = kCgCap;
     // the FP64 solution replaces the right-hand side
     if (!x_zero) {
       for (long long k = tid; k < npe; k += NT) bx[k] = x[k];
@@ -1742,10 +1794,11 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     __syncthreads();
     warm_store_solution(a, npe, pid, bx);
     if (tid == 0) {
-      a.outIt[pid] = conv ? it : a.max_iter;
+      a.outIt[pid] = it;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr_true) / bnorm : 0.0;
       a.outUpd[pid] = upd;
       a.outFus[pid] = nfus;
+      a.outExit[pid] = code | (rst << 8);
     }
     __syncthreads();
   }

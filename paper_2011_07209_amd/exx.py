@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libexx.so")
 EXX_OK, EXX_EINVAL, EXX_ENOMEM, EXX_ENOCONV, EXX_EDEVICE, EXX_ECAPACITY = range(6)
 EXX_F64, EXX_F32 = 0, 1
 EXX_PREC_FP64, EXX_PREC_MIXED = 0, 1
+EXX_CG_CONVERGED, EXX_CG_CAP, EXX_CG_BREAKDOWN, EXX_CG_NONFINITE = range(4)
+CG_EXIT_NAMES = {0: "converged", 1: "cap", 2: "breakdown", 3: "nonfinite"}
 _STATUS = {0: "EXX_OK", 1: "EXX_EINVAL", 2: "EXX_ENOMEM", 3: "EXX_ENOCONV", 4: "EXX_EDEVICE", 5: "EXX_ECAPACITY"}
 
 
@@ -84,10 +86,24 @@ class Stats(ctypes.Structure):
         ("reassemblies", ctypes.c_int),
         ("n_arms", ctypes.c_int),
         ("cg_layout", ctypes.c_int),
+        ("n_cg_cap", ctypes.c_int),
+        ("n_cg_breakdown", ctypes.c_int),
+        ("n_cg_nonfinite", ctypes.c_int),
+        ("cg_restarts", ctypes.c_longlong),
+        ("t_pairlist_ms", ctypes.c_double),
+        ("t_reduce_ms", ctypes.c_double),
+        ("class_threads", ctypes.c_int * 16),
+        ("class_depth", ctypes.c_int * 16),
+        ("class_layout", ctypes.c_int * 16),
+        ("class_pairs", ctypes.c_longlong * 16),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v)[:self.n_classes] if isinstance(v, ctypes.Array) else v
+        return d
 
 
 SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_count_pairs", "exx_pair_results",
@@ -119,7 +135,7 @@ def load():
     lib.exx_count_pairs.restype = ctypes.c_int
     lib.exx_count_pairs.argtypes = [vp, ctypes.c_int, vp, vp, llp]
     lib.exx_pair_results.restype = ctypes.c_int
-    lib.exx_pair_results.argtypes = [vp, ctypes.c_longlong, ip, dp, dp, ip, dp, llp]
+    lib.exx_pair_results.argtypes = [vp, ctypes.c_longlong, ip, dp, dp, ip, dp, ip, ip, llp]
     lib.exx_stats_fetch.restype = ctypes.c_int
     lib.exx_stats_fetch.argtypes = [vp, P(Stats)]
     lib.exx_plan_geometry.restype = ctypes.c_int
@@ -228,19 +244,23 @@ def exx_pair_results(plan):
     import numpy as np
     n = ctypes.c_longlong(0)
     lib = load()
-    _check(lib.exx_pair_results(plan, 0, None, None, None, None, None, ctypes.byref(n)), plan)
+    _check(lib.exx_pair_results(plan, 0, None, None, None, None, None, None, None, ctypes.byref(n)), plan)
     m = n.value
     ij = np.zeros(2 * max(m, 1), dtype=np.int32)
     E = np.zeros(max(m, 1))
     S = np.zeros(9 * max(m, 1))
     it = np.zeros(max(m, 1), dtype=np.int32)
     res = np.zeros(max(m, 1))
+    ex = np.zeros(max(m, 1), dtype=np.int32)
+    upd = np.zeros(max(m, 1), dtype=np.int32)
     P = ctypes.POINTER
-    _check(lib.exx_pair_results(plan, m, ij.ctypes.data_as(P(ctypes.c_int)), E.ctypes.data_as(P(ctypes.c_double)),
-                                S.ctypes.data_as(P(ctypes.c_double)), it.ctypes.data_as(P(ctypes.c_int)),
-                                res.ctypes.data_as(P(ctypes.c_double)), ctypes.byref(n)), plan)
+    ip = P(ctypes.c_int)
+    _check(lib.exx_pair_results(plan, m, ij.ctypes.data_as(ip), E.ctypes.data_as(P(ctypes.c_double)),
+                                S.ctypes.data_as(P(ctypes.c_double)), it.ctypes.data_as(ip),
+                                res.ctypes.data_as(P(ctypes.c_double)), ex.ctypes.data_as(ip), upd.ctypes.data_as(ip),
+                                ctypes.byref(n)), plan)
     return {"ij": ij[:2 * m].reshape(m, 2), "E": E[:m], "sigma": S[:9 * m].reshape(m, 9), "iters": it[:m],
-            "rel_res": res[:m]}
+            "rel_res": res[:m], "exit": ex[:m] & 0xff, "restarts": ex[:m] >> 8, "updates": upd[:m]}
 
 
 def exx_stats_fetch(plan, allow_noconv: bool = False, allow_capacity: bool = False) -> dict:

@@ -344,8 +344,11 @@ def test_mixed_quad_iteration_cap(threads):
           f"iters max {st['cg_iter_max']} residual max {st['max_rel_residual']:.3e}", flush=True)
     assert st["cg_layout"] == 2 and st["solve_threads"] == (768 if threads == 0 else 1024)
     assert st["n_unconverged"] == st["n_pairs"] > 0
+    assert st["n_cg_cap"] == st["n_pairs"] and st["n_cg_breakdown"] == 0 and st["n_cg_nonfinite"] == 0
+    assert st["cg_restarts"] == 0
     assert st["cg_iter_max"] == cap and st["cg_iter_sum"] == cap * st["n_pairs"]
     assert np.all(np.asarray(res["iters"]) == cap)
+    assert np.all(res["exit"] == exx.EXX_CG_CAP) and np.all(res["restarts"] == 0)
     assert st["max_rel_residual"] > cfg.cg_tol
 
 

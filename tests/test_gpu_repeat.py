@@ -1,0 +1,114 @@
+"""Repeated mixed-precision evaluations of the 64-molecule set at full size,
+as the benchmark runs them: one plan, several evaluations in a row, made after
+an FP64 plan of the same set was used and closed (its freed device memory is
+what the mixed plan's workspace then receives).
+
+For each CG variant that can run the set's sphere in the quad layout (780 runs
+of four columns: 1024 threads, load depth 1 or 2), forced, three evaluations
+must each converge every pair (no iteration cap, breakdown or non-finite
+norm), give bitwise the same E_xx and sigma_xx, and match the FP64 oracle on
+sampled pairs (the strongest non-self pairs among them) within the mixed bar
+(1e-6 relative per pair, the PE solve of eq. pe)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2011_07209_amd import exx, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = torch.device("cuda:0")
+
+
+def _plan(cfg, **kw):
+    opt = dict(stencil_n=cfg.stencil_n, cg_tol=cfg.cg_tol, workspace_gb=48.0)
+    opt.update(kw)
+    return exx.Plan(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, **opt)
+
+
+def _sample(pr, n_random, n_strong, seed):
+    """Random pairs, one self pair and the n_strong non-self pairs of largest |E|."""
+    rng = np.random.default_rng(seed)
+    m = len(pr["E"])
+    ij = pr["ij"]
+    self_idx = np.flatnonzero(ij[:, 0] == ij[:, 1])
+    cross = np.flatnonzero(ij[:, 0] != ij[:, 1])
+    strong = cross[np.argsort(-np.abs(pr["E"][cross]))[:n_strong]]
+    picks = set(rng.choice(m, n_random, replace=False).tolist()) | {int(self_idx[len(self_idx) // 2])}
+    return sorted(picks | set(strong.tolist()))
+
+
+@pytest.fixture(scope="module")
+def water64():
+    cfg = synth.CONFIGS["water64"]
+    orbs = synth.make_orbitals(cfg)
+    orb_t = synth.fill_orbitals_device(cfg, orbs, DEV)
+    cen_t = torch.from_numpy(orbs.centres).to(DEV)
+    # an FP64 plan used and closed first
+    plan = _plan(cfg)
+    E = torch.zeros(1, dtype=torch.float64, device=DEV)
+    D = torch.empty_like(orb_t)
+    plan.eval(orb_t, cen_t, E, D)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    plan.close()
+    del D
+    print(f"[repeat] fp64 first: pairs {st['n_pairs']} E={E.item():.12f}", flush=True)
+    yield cfg, orbs, orb_t, cen_t
+    del orb_t
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def oracle_cache():
+    return {}
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_water64_mixed_repeated_evaluations(water64, oracle_cache, depth):
+    cfg, orbs, orb_t, cen_t = water64
+    plan = _plan(cfg, precision=exx.EXX_PREC_MIXED, solve_threads=1024, solve_depth=depth)
+    runs = []
+    try:
+        E = torch.zeros(1, dtype=torch.float64, device=DEV)
+        S = torch.zeros(9, dtype=torch.float64, device=DEV)
+        D = torch.empty_like(orb_t)
+        for k in range(3):
+            plan.eval(orb_t, cen_t, E, D, S)
+            torch.cuda.synchronize()
+            st = plan.stats(allow_noconv=True)
+            pr = plan.pair_results()
+            print(f"[repeat 1024x{depth}] eval {k + 1}: pairs {st['n_pairs']} E={E.item():.12f} unconverged "
+                  f"{st['n_unconverged']} (cap {st['n_cg_cap']}, breakdown {st['n_cg_breakdown']}, non-finite "
+                  f"{st['n_cg_nonfinite']}), restarts {st['cg_restarts']}, iterations mean "
+                  f"{st['cg_iter_sum'] / st['n_pairs']:.1f} max {st['cg_iter_max']}, updates max "
+                  f"{st['refine_passes_max']}, variants {st['class_threads']}x{st['class_depth']} layout "
+                  f"{st['class_layout']}", flush=True)
+            bad = np.flatnonzero(pr["exit"] != exx.EXX_CG_CONVERGED)
+            for b in bad[:16]:
+                print(f"[repeat 1024x{depth}]   pair {tuple(pr['ij'][b])} exit {pr['exit'][b]} iterations "
+                      f"{pr['iters'][b]} rel_res {pr['rel_res'][b]:.3e} updates {pr['updates'][b]}", flush=True)
+            assert st["class_threads"] == [1024] and st["class_depth"] == [depth] and st["class_layout"] == [2]
+            assert st["n_unconverged"] == 0 and st["n_cg_breakdown"] == 0 and st["n_cg_nonfinite"] == 0
+            assert np.all(pr["exit"] == exx.EXX_CG_CONVERGED)
+            assert st["max_rel_residual"] <= cfg.cg_tol
+            runs.append((E.item(), S.cpu().numpy(), pr))
+    finally:
+        plan.close()
+    # deterministic: every evaluation gives the same E and sigma, bit for bit
+    for Ek, Sk, _ in runs[1:]:
+        assert Ek == runs[0][0] and np.array_equal(Sk, runs[0][1])
+    pr = runs[-1][2]
+    picks = _sample(pr, 10, 6, 640 + depth)
+    P = oracle.make_params(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, cfg.stencil_n, cfg.cg_tol)
+    for k in picks:
+        i, j = (int(x) for x in pr["ij"][k])
+        if (i, j) not in oracle_cache:
+            idx = [i] if i == j else [i, j]
+            f = oracle.pair_fields(P, orb_t[idx].to(torch.float64).cpu().numpy(), orbs.centres[idx], 0, len(idx) - 1)
+            oracle_cache[(i, j)] = (f["res"].E, np.array(list(f["res"].sigma)))
+        Eo, So = oracle_cache[(i, j)]
+        print(f"[repeat 1024x{depth}] pair ({i},{j}) gpu E={pr['E'][k]:.15g} oracle={Eo:.15g}", flush=True)
+        assert abs(pr["E"][k] - Eo) <= 1e-6 * abs(Eo) + 1e-14
+        assert np.abs(pr["sigma"][k] - So).sum() <= 1e-6 * np.abs(So).sum() + 1e-14
