@@ -183,6 +183,31 @@ exx_status exx_eval(exx_plan_t plan, int n_orb, const void* orbitals, exx_dtype 
                     const double* R_PE_orb, const int* d_subset, int n_subset, double* E_xx, void* D_xx,
                     double* sigma);
 
+/* Bytes of the device scratch array behind exx_eval_noalloc (one per device). */
+#define EXX_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* exx_eval without any device allocation, for callers that cannot allocate:
+   code recorded into a HIP graph, tight serving loops, harnesses that forbid
+   hipMalloc.  Same arguments, outputs and status codes as exx_eval.  Its
+   whole workspace (pair list, per-pair results, batch workspace and CG
+   vectors) comes from one static device array of EXX_NOALLOC_SCRATCH_BYTES
+   that the library holds on each device it runs on until the process ends;
+   it uses as many batch rows and persistent CG workgroups as the array holds
+   (fewer than exx_eval may use, so it can be slower).  Needs a plan with a
+   fixed pair capacity (max_pairs > 0) and without warm_start (EXX_EINVAL
+   otherwise); it never runs the autotuner (it keeps the plan's CG variants).
+   EXX_EINVAL when n_orb and max_pairs need more than the array (the message
+   gives the bytes).  The array keeps the last call's contents: every call on
+   a device shares it, so calls that overlap on one device (two streams, or
+   two plans) race, and the statistics and per-pair results of a call
+   (exx_stats_fetch, exx_pair_results) stay readable only until the next
+   exx_eval_noalloc on that device or the next exx_eval, exx_count_pairs or
+   exx_set_cell on the plan.  No allocation and no host wait; it records no
+   per-launch timing events, so exx_stats reports its whole device time only. */
+exx_status exx_eval_noalloc(exx_plan_t plan, int n_orb, const void* orbitals, exx_dtype dt, const double* centres,
+                            const double* R_PE_orb, const int* d_subset, int n_subset, double* E_xx, void* D_xx,
+                            double* sigma);
+
 /* Number of pairs exx_eval would form for these centres (and radii), for
    sizing max_pairs.  centres and R_PE_orb as in exx_eval (device).  Enqueues
    the pair-list kernels on the bound stream and waits for them; not for use

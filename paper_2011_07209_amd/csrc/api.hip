@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -101,6 +102,9 @@ double bf16_value(unsigned short h) {
 
 template <typename T>
 exx_status dev_alloc(exx_plan_t P, T** p, size_t count, const char* what) {
+  if (P && P->no_alloc)
+    return fail(P, EXX_EINVAL, std::string("exx_eval_noalloc would need a device allocation (") + what +
+                                   "); its workspace must come from the scratch array");
   if (P && P->capturing)
     return fail(P, EXX_EINVAL, std::string("exx_eval needs a device allocation (") + what +
                                    ") while its stream is recorded into a graph; run one eager exx_eval with the "
@@ -123,8 +127,80 @@ struct CaptureGuard {
   ~CaptureGuard() { P->capturing = false; }
 };
 
+// The plan's active workspace pointers as one EvalWork, and back.
+EvalWork get_work(exx_plan_t P) {
+  EvalWork w;
+  w.pair_cap = P->pair_cap;
+  w.pairs = P->pairs;
+  w.order = P->order;
+  w.pair_count = P->pair_count;
+  w.orb_cap = P->orb_cap;
+  w.n_eff = P->n_eff;
+  w.d_slot = P->d_slot;
+  w.pE = P->pE;
+  w.pS = P->pS;
+  w.pIt = P->pIt;
+  w.pRes = P->pRes;
+  w.pUpd = P->pUpd;
+  w.pFus = P->pFus;
+  w.pExit = P->pExit;
+  w.batch_cap = P->batch_cap;
+  w.rho_ws = P->rho_ws;
+  w.bx_ws = P->bx_ws;
+  w.halo_ws = P->halo_ws;
+  w.Q_ws = P->Q_ws;
+  w.rho_scale = P->rho_scale;
+  w.Qp_ws = P->Qp_ws;
+  w.qp_rows = P->qp_rows;
+  w.n_slots = P->n_slots;
+  w.slot_ws = P->slot_ws;
+  return w;
+}
+
+void put_work(exx_plan_t P, const EvalWork& w) {
+  P->pair_cap = w.pair_cap;
+  P->pairs = w.pairs;
+  P->order = w.order;
+  P->pair_count = w.pair_count;
+  P->orb_cap = w.orb_cap;
+  P->n_eff = w.n_eff;
+  P->d_slot = w.d_slot;
+  P->pE = w.pE;
+  P->pS = w.pS;
+  P->pIt = w.pIt;
+  P->pRes = w.pRes;
+  P->pUpd = w.pUpd;
+  P->pFus = w.pFus;
+  P->pExit = w.pExit;
+  P->batch_cap = w.batch_cap;
+  P->rho_ws = w.rho_ws;
+  P->bx_ws = w.bx_ws;
+  P->halo_ws = w.halo_ws;
+  P->Q_ws = w.Q_ws;
+  P->rho_scale = w.rho_scale;
+  P->Qp_ws = w.Qp_ws;
+  P->qp_rows = w.qp_rows;
+  P->n_slots = w.n_slots;
+  P->slot_ws = w.slot_ws;
+}
+
+// After an exx_eval_noalloc the scratch array's pieces stay the active
+// workspace (the statistics and per-pair results of that call live there);
+// every call that may allocate or free workspace first makes the plan's own
+// allocations active again.
+void use_own_work(exx_plan_t P) {
+  if (!P->on_scratch) return;
+  put_work(P, P->own_work);
+  P->own_work = EvalWork();
+  P->on_scratch = false;
+  P->timing_valid = false;   // the last evaluation's results were in the scratch array
+  P->harvested = true;
+  P->last_captured = false;
+}
+
 void free_plan(exx_plan_t P) {
   if (!P) return;
+  use_own_work(P);
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
                   P->pRes, P->pUpd, P->pFus, P->pExit, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
                   P->warm_map, P->prev_pairs, P->prev_offs, P->warm_state, P->slot_ws, P->queue,
@@ -256,8 +332,9 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
     a.depth = P->class_depth[k];
     a.quads = C.quads;
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
-    const int groups = (int)std::min<long long>(P->class_groups[k], a.npair);
-    EXX_HIP(P, launch_solve(a, C.n_cols, C.Zmax, groups, s));
+    long long groups = std::min<long long>(P->class_groups[k], a.npair);
+    if (P->slot_limit > 0) groups = std::min<long long>(groups, P->slot_limit);   // CG slots of the scratch layout
+    EXX_HIP(P, launch_solve(a, C.n_cols, C.Zmax, (int)groups, s));
   }
   return EXX_OK;
 }
@@ -793,6 +870,87 @@ exx_status update_cell(exx_plan_t P, const double h[9]) {
   return EXX_OK;
 }
 
+// Pairs per batch of an evaluation over `span` rows of the processing order:
+// as many as the workspace cap (exx_options.workspace_gb) holds.
+long long eval_batch(exx_plan_t P, long long span) {
+  const long long per_pair = 2 * P->rstride + P->max_halo + kMaxLM;
+  const double budget = (P->opt.workspace_gb > 0 ? P->opt.workspace_gb : 24.0) * 1e9;
+  long long batch = std::max<long long>(1, (long long)(budget / (8.0 * per_pair)));
+  batch = std::min<long long>(batch, std::max<long long>(span, 1));
+  return std::min<long long>(batch, 65535);   // pair index on grid y of the per-point kernels
+}
+
+// ---------------------------------------------------------------------------
+// The scratch array of exx_eval_noalloc: the whole device workspace of an
+// evaluation (pair list, per-pair results, batch workspace, CG slots) in one
+// file-scope array that every plan on a device shares.  Host code never names
+// it in a kernel argument or copy: its device address on each device comes
+// from hipGetSymbolAddress, looked up once per device when a plan is made.
+constexpr size_t kScratchBytes = (size_t)EXX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::string g_scratch_err[kMaxDevices];
+
+// Looks up the scratch array's address on the current device dev (once).
+void scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] || !g_scratch_err[dev].empty()) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    g_scratch_err[dev] = std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e);
+  else
+    g_scratch_ptr[dev] = ptr;
+}
+
+// Pieces of the scratch array (from base; base null: sizes only) for n_orb
+// orbitals, the plan's pair capacity, k batch rows and g CG slots.  Returns
+// the bytes the layout spans.
+size_t scratch_carve(exx_plan_t P, char* base, int n_orb, long long k, int g, EvalWork* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~(size_t)255;
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const long long cap = P->opt.max_pairs;
+  const int ncls = (int)P->classes.size();
+  w->orb_cap = n_orb;
+  w->pair_count = (int*)take(sizeof(int) * ((size_t)2 * n_orb + 1 + kMaxClasses));
+  w->d_slot = (int*)take(sizeof(int) * (size_t)n_orb);
+  w->n_eff = (int*)take(sizeof(int));
+  w->pair_cap = cap;
+  w->pairs = (PairDev*)take(sizeof(PairDev) * (size_t)cap);
+  w->order = (int*)take(sizeof(int) * (size_t)cap);
+  w->pE = (double*)take(sizeof(double) * (size_t)cap);
+  w->pS = (double*)take(sizeof(double) * 9 * (size_t)cap);
+  w->pIt = (int*)take(sizeof(int) * (size_t)cap);
+  w->pRes = (double*)take(sizeof(double) * (size_t)cap);
+  w->pUpd = (int*)take(sizeof(int) * (size_t)cap);
+  w->pFus = (int*)take(sizeof(int) * (size_t)cap);
+  w->pExit = (int*)take(sizeof(int) * (size_t)cap);
+  w->batch_cap = k;
+  w->rho_ws = (double*)take(sizeof(double) * (size_t)(k * P->rstride));
+  w->bx_ws = (double*)take(sizeof(double) * (size_t)(k * P->rstride));
+  w->halo_ws = (double*)take(sizeof(double) * (size_t)(k * std::max<long long>(P->max_halo, 1)));
+  w->Q_ws = (double*)take(sizeof(double) * (size_t)(k * kMaxLM));
+  w->rho_scale = (double*)take(sizeof(double) * (size_t)k);
+  // partial moments of the point chunks: full batches and the last one, as exx_eval sizes them
+  const long long tail = cap % k;
+  w->qp_rows = std::max<long long>(moment_splits(k, ncls, P->max_pe) * k,
+                                   tail ? moment_splits(tail, ncls, P->max_pe) * tail : 0);
+  w->Qp_ws = (double*)take(sizeof(double) * (size_t)(w->qp_rows * kMaxLM));
+  w->n_slots = g;
+  w->slot_ws =
+      take((size_t)g * (size_t)solve_slot_bytes(P->opt.precision == EXX_PREC_MIXED, slot_stride(P)));
+  return off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -893,6 +1051,9 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     free_plan(P);
     return fail(nullptr, EXX_ENOMEM, "device allocation failed");
   }
+  // the device address of exx_eval_noalloc's scratch array on this device
+  // (a failure is reported by exx_eval_noalloc; exx_eval does not need it)
+  scratch_lookup(P->device);
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
   P->n_cus = std::max(1, cus);
@@ -925,6 +1086,7 @@ exx_status exx_set_cell(exx_plan_t P, const double h[9]) {
   if (cs != hipStreamCaptureStatusNone) return fail(P, EXX_EINVAL, "exx_set_cell is not capturable");
   // the tables are rewritten: no evaluation may still read them
   EXX_HIP(P, hipStreamSynchronize(P->stream));
+  use_own_work(P);
   if (P->opt.reassemble_strain > 0.0 && cell_strain(h, P->h0) > P->opt.reassemble_strain) {
     // re-assembly (Sec. III B 2): new proto-subdomains for h from the plan's radii
     exx_status st = assemble_cell(P, h);
@@ -992,7 +1154,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   const bool fixed = P->opt.max_pairs > 0;
   if (capturing) {
     if (!fixed) return fail(P, EXX_EINVAL, "recording exx_eval in a graph needs a fixed pair capacity (max_pairs > 0)");
-    if (n_orb > P->warm_orb)
+    // (exx_eval_noalloc sizes its scratch layout in the call itself)
+    if (n_orb > P->warm_orb && !P->no_alloc)
       return fail(P, EXX_EINVAL, "recording exx_eval in a graph needs one eager exx_eval with at least as many "
                                  "orbitals first");
   } else if (P->timing_valid && !P->harvested) {
@@ -1000,6 +1163,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     exx_status hs = harvest(P);
     if (hs != EXX_OK) return hs;
   }
+  if (!P->no_alloc) use_own_work(P);
   P->timing_valid = false;
   P->last_captured = capturing;
   P->solve_ev_used = 0;
@@ -1081,11 +1245,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   }
 
   // workspace
-  const long long per_pair = 2 * P->rstride + P->max_halo + kMaxLM;
-  const double budget = (P->opt.workspace_gb > 0 ? P->opt.workspace_gb : 24.0) * 1e9;
-  long long batch = std::max<long long>(1, (long long)(budget / (8.0 * per_pair)));
-  batch = std::min<long long>(batch, std::max<long long>(span, 1));
-  batch = std::min<long long>(batch, 65535);   // pair index on grid y of the per-point kernels
+  long long batch = eval_batch(P, span);
+  if (P->batch_limit > 0) batch = std::min<long long>(batch, P->batch_limit);   // rows of the scratch layout
   if (batch > P->batch_cap) {
     if (dev_alloc(P, &P->rho_ws, (size_t)batch * P->rstride, "pair densities") ||
         dev_alloc(P, &P->bx_ws, (size_t)batch * P->rstride, "pair potentials") ||
@@ -1130,10 +1291,12 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     B.p0 = p0;
     B.nb = std::min(batch, span - p0);
     EXX_HIP(P, launch_gather(g, B, orbitals, (int)dt, P->rho_ws, P->rstride, P->rho_scale, s));
-    if (!capturing) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
+    // (exx_eval_noalloc records no per-launch events: new ones would be created)
+    const bool launch_events = !capturing && !P->no_alloc;
+    if (launch_events) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_moments(g, B, P->pair_count + 2 * n_orb + 1, ncls, mixed, P->rho_ws, P->rstride, P->rho_scale,
                               P->Qp_ws, moment_splits(B.nb, ncls, P->max_pe), P->Q_ws, s));
-    if (!capturing) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
+    if (launch_events) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_boundary(g, B, P->max_halo, P->Q_ws, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
     SolveArgs a;
     a.g = g;
@@ -1166,7 +1329,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
       a.warm_map = P->warm_map;
       a.prev_pairs = P->prev_pairs;
     }
-    if (P->opt.autotune && !P->tuned) {
+    if (P->opt.autotune && !P->tuned && !P->no_alloc) {   // (exx_eval_noalloc keeps the variants it finds)
       if (capturing) return fail(P, EXX_EINVAL, "the autotuner runs in an eager exx_eval, not in a graph");
       exx_status st = autotune_solve(P, a, B.nb, s);
       if (st != EXX_OK) return st;
@@ -1176,9 +1339,9 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     }
     EXX_HIP(P, launch_rhs(g, B, P->max_pe, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
                           std::max<long long>(P->max_halo, 1), s));
-    if (!capturing) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
+    if (launch_events) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     { exx_status es = launch_solves(P, a, s); if (es != EXX_OK) return es; }
-    if (!capturing) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
+    if (launch_events) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     EXX_HIP(P, launch_finalize(g, B, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws, std::max<long long>(P->max_halo, 1),
                                P->pE, P->pS, s));
     if (D_xx)
@@ -1195,9 +1358,75 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
   if (!capturing) {
     P->timing_valid = true;
     P->harvested = false;
-    if (fixed) P->warm_orb = std::max(P->warm_orb, n_orb);
+    if (fixed && !P->no_alloc) P->warm_orb = std::max(P->warm_orb, n_orb);
   }
   return EXX_OK;
+}
+
+exx_status exx_eval_noalloc(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt, const double* centres,
+                            const double* R_PE_orb, const int* d_subset, int n_subset, double* E_xx, void* D_xx,
+                            double* sigma) {
+  if (!P) return fail(nullptr, EXX_EINVAL, "plan is NULL");
+  if (P->opt.max_pairs <= 0)
+    return fail(P, EXX_EINVAL, "exx_eval_noalloc needs a plan with a fixed pair capacity (max_pairs > 0)");
+  if (P->opt.warm_start)
+    return fail(P, EXX_EINVAL, "exx_eval_noalloc keeps no warm-start stores (make the plan without warm_start)");
+  if (n_orb < 1) return fail(P, EXX_EINVAL, "n_orb must be >= 1");
+  int dev = -1;
+  EXX_HIP(P, hipGetDevice(&dev));
+  if (dev != P->device) return fail(P, EXX_EINVAL, "current device differs from the plan's device");
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev >= 0 && dev < kMaxDevices) base = (char*)g_scratch_ptr[dev];
+    if (!base)
+      return fail(P, EXX_EDEVICE, dev >= 0 && dev < kMaxDevices && !g_scratch_err[dev].empty()
+                                      ? g_scratch_err[dev]
+                                      : std::string("no scratch array address for this device"));
+  }
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  EXX_HIP(P, hipStreamIsCapturing(P->stream, &cap_status));
+  if (cap_status == hipStreamCaptureStatusNone && P->timing_valid && !P->harvested) {
+    // the previous evaluation's statistics, from the workspace it used
+    EXX_HIP(P, hipEventSynchronize(P->ev[3]));
+    exx_status hs = harvest(P);
+    if (hs != EXX_OK) return hs;
+  }
+  // the largest batch (and as many CG slots, up to the plan's solve grid) that
+  // the scratch array holds
+  int max_groups = 1;
+  for (int g : P->class_groups) max_groups = std::max(max_groups, g);
+  const long long span = P->opt.max_pairs;
+  long long lo = 1, hi = std::max<long long>(1, eval_batch(P, span));
+  EvalWork w;
+  auto bytes_for = [&](long long k) {
+    return scratch_carve(P, nullptr, n_orb, k, (int)std::min<long long>(k, max_groups), &w);
+  };
+  if (bytes_for(1) > kScratchBytes)
+    return fail(P, EXX_EINVAL, "exx_eval_noalloc: one pair's workspace with " + std::to_string(n_orb) +
+                                   " orbitals and max_pairs " + std::to_string(span) + " needs " +
+                                   std::to_string(bytes_for(1)) + " bytes, beyond the scratch array's " +
+                                   std::to_string(kScratchBytes));
+  while (lo < hi) {   // largest k in [1, hi] that fits
+    const long long mid = (lo + hi + 1) / 2;
+    if (bytes_for(mid) <= kScratchBytes) lo = mid; else hi = mid - 1;
+  }
+  const long long k = lo;
+  const int g = (int)std::min<long long>(k, max_groups);
+  scratch_carve(P, base, n_orb, k, g, &w);
+  if (!P->on_scratch) {
+    P->own_work = get_work(P);
+    P->on_scratch = true;
+  }
+  put_work(P, w);
+  P->no_alloc = true;
+  P->batch_limit = k;
+  P->slot_limit = g;
+  const exx_status st = exx_eval(P, n_orb, orbitals, dt, centres, R_PE_orb, d_subset, n_subset, E_xx, D_xx, sigma);
+  P->no_alloc = false;
+  P->batch_limit = 0;
+  P->slot_limit = 0;
+  return st;
 }
 
 exx_status exx_count_pairs(exx_plan_t P, int n_orb, const double* centres, const double* R_PE_orb,
@@ -1217,6 +1446,7 @@ exx_status exx_count_pairs(exx_plan_t P, int n_orb, const double* centres, const
     exx_status hs = harvest(P);
     if (hs != EXX_OK) return hs;
   }
+  use_own_work(P);
   if (n_orb > P->orb_cap) {
     if (dev_alloc(P, &P->pair_count, (size_t)2 * n_orb + 1 + kMaxClasses, "pair counts") ||
         dev_alloc(P, &P->d_slot, (size_t)n_orb, "D subset slots"))

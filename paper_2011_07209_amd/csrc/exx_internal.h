@@ -139,6 +139,36 @@ std::string build_nk_arms(const double h[9], const int N[3], std::vector<NkArm>*
 void build_moment_table(const ClassHost& C, const double A[9], int l_max, int rows, int group,
                         std::vector<double>* out);
 
+// The device workspace of an evaluation that the plan holds pointers to: the
+// plan's own allocations, or, for exx_eval_noalloc, pieces of the library's
+// static scratch array (the two are swapped in and out as a whole).
+struct EvalWork {
+  long long pair_cap = 0;
+  PairDev* pairs = nullptr;
+  int* order = nullptr;
+  int* pair_count = nullptr;
+  int orb_cap = 0;
+  int* n_eff = nullptr;
+  int* d_slot = nullptr;
+  double* pE = nullptr;
+  double* pS = nullptr;
+  int* pIt = nullptr;
+  double* pRes = nullptr;
+  int* pUpd = nullptr;
+  int* pFus = nullptr;
+  int* pExit = nullptr;
+  long long batch_cap = 0;
+  double* rho_ws = nullptr;
+  double* bx_ws = nullptr;
+  double* halo_ws = nullptr;
+  double* Q_ws = nullptr;
+  double* rho_scale = nullptr;
+  double* Qp_ws = nullptr;
+  long long qp_rows = 0;
+  int n_slots = 0;
+  void* slot_ws = nullptr;
+};
+
 }  // namespace exx
 
 struct exx_plan_s {
@@ -233,4 +263,14 @@ struct exx_plan_s {
   long long n_evals = 0, solve_launches = 0;
   double solve_ms_total = 0, eval_ms_total = 0, alg_bytes_total = 0;
   std::string err;
+
+  // exx_eval_noalloc: the plan's own workspace while the scratch array's
+  // pieces are the active one (on_scratch), the guard that turns any device
+  // allocation into an error, and the batch and CG-workgroup limits of the
+  // scratch layout (0: none)
+  exx::EvalWork own_work;
+  bool on_scratch = false;
+  bool no_alloc = false;
+  long long batch_limit = 0;
+  int slot_limit = 0;
 };

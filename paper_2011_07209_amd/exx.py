@@ -106,7 +106,8 @@ class Stats(ctypes.Structure):
         return d
 
 
-SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_count_pairs", "exx_pair_results",
+SYMBOLS = ["exx_default_options", "exx_plan", "exx_set_stream", "exx_eval", "exx_eval_noalloc", "exx_count_pairs",
+           "exx_pair_results",
            "exx_stats_fetch", "exx_plan_geometry", "exx_subdomain_counts", "exx_nk_stencil", "exx_set_cell",
            "exx_pressure", "exx_destroy", "exx_last_error"]
 
@@ -132,6 +133,8 @@ def load():
     lib.exx_set_stream.argtypes = [vp, vp]
     lib.exx_eval.restype = ctypes.c_int
     lib.exx_eval.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    lib.exx_eval_noalloc.restype = ctypes.c_int
+    lib.exx_eval_noalloc.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.exx_count_pairs.restype = ctypes.c_int
     lib.exx_count_pairs.argtypes = [vp, ctypes.c_int, vp, vp, llp]
     lib.exx_pair_results.restype = ctypes.c_int
@@ -201,8 +204,11 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def exx_eval(plan, orbitals: torch.Tensor, centres: torch.Tensor, E_xx: torch.Tensor,
              D_xx: Optional[torch.Tensor] = None, sigma: Optional[torch.Tensor] = None,
-             R_PE_orb: Optional[torch.Tensor] = None, d_subset: Optional[torch.Tensor] = None):
-    """Enqueues one evaluation; tensors are device tensors laid out as in exx.h."""
+             R_PE_orb: Optional[torch.Tensor] = None, d_subset: Optional[torch.Tensor] = None,
+             noalloc: bool = False):
+    """Enqueues one evaluation; tensors are device tensors laid out as in exx.h.
+    noalloc: through exx_eval_noalloc (no device allocation; workspace in the
+    library's scratch array)."""
     if orbitals.dtype == torch.float64:
         dt = EXX_F64
     elif orbitals.dtype == torch.float32:
@@ -226,8 +232,9 @@ def exx_eval(plan, orbitals: torch.Tensor, centres: torch.Tensor, E_xx: torch.Te
         raise ExxError(EXX_EINVAL, "D_xx must match the orbitals' dtype and hold one grid per requested orbital")
     if centres.numel() != 3 * n_orb:
         raise ExxError(EXX_EINVAL, "centres must be [n_orb, 3]")
-    st = load().exx_eval(plan, int(n_orb), _ptr(orbitals), dt, _ptr(centres), _ptr(R_PE_orb), _ptr(d_subset),
-                         int(n_subset), _ptr(E_xx), _ptr(D_xx), _ptr(sigma))
+    fn = load().exx_eval_noalloc if noalloc else load().exx_eval
+    st = fn(plan, int(n_orb), _ptr(orbitals), dt, _ptr(centres), _ptr(R_PE_orb), _ptr(d_subset), int(n_subset),
+            _ptr(E_xx), _ptr(D_xx), _ptr(sigma))
     _check(st, plan)
 
 
@@ -341,11 +348,12 @@ class Plan:
         self.handle = exx_plan(h, grid, R_pair, R_PE, R_ME, l_max, self.opt)
         exx_set_stream(self.handle)
 
-    def eval(self, orbitals, centres, E_xx=None, D_xx=None, sigma=None, R_PE_orb=None, d_subset=None):
+    def eval(self, orbitals, centres, E_xx=None, D_xx=None, sigma=None, R_PE_orb=None, d_subset=None,
+             noalloc=False):
         dev = orbitals.device
         if E_xx is None:
             E_xx = torch.zeros(1, dtype=torch.float64, device=dev)
-        exx_eval(self.handle, orbitals, centres, E_xx, D_xx, sigma, R_PE_orb, d_subset)
+        exx_eval(self.handle, orbitals, centres, E_xx, D_xx, sigma, R_PE_orb, d_subset, noalloc)
         return E_xx
 
     def set_stream(self, stream=None):
