@@ -237,16 +237,18 @@ typedef struct {
   double max_rel_residual;     /* max over pairs of ||b - A x|| / ||b||            */
   double solve_ms;             /* device time of the solve kernels (last eval)     */
   double eval_ms;              /* device time of the whole evaluation              */
-  double cg_alg_bytes;         /* algorithmic CG bytes: sum_pairs (8 iters - 2
-                                  fused sweeps) N_PE b                              */
+  double cg_alg_bytes;         /* algorithmic CG bytes: sum over pairs of (8 iters
+                                  - 2 fused sweeps - 2 passes that left x alone)
+                                  N_PE b                                            */
   double moment_flops;         /* algorithmic moment flops: 2 N_lm N_PE per pair   */
   /* running totals since the plan was made (every completed exx_eval):       */
   long long n_evals;
   long long solve_launches;    /* launches of the persistent CG kernel           */
   double solve_ms_total;       /* their summed device time (HIP events)          */
   double cg_alg_bytes_total;   /* their summed algorithmic CG bytes (eight vector
-                                  accesses per point and iteration, six in a
-                                  fused sweep)                                      */
+                                  accesses per point and iteration, two fewer in
+                                  a fused sweep and in a pass B that leaves x
+                                  alone, which every other pass B does)            */
   double eval_ms_total;
   int solve_threads;           /* CG variant in use: workgroup size (768: quad
                                   layout with fused sweeps) ...                     */

@@ -142,7 +142,7 @@ EvalWork get_work(exx_plan_t P) {
   w.pIt = P->pIt;
   w.pRes = P->pRes;
   w.pUpd = P->pUpd;
-  w.pFus = P->pFus;
+  w.pSav = P->pSav;
   w.pExit = P->pExit;
   w.batch_cap = P->batch_cap;
   w.rho_ws = P->rho_ws;
@@ -170,7 +170,7 @@ void put_work(exx_plan_t P, const EvalWork& w) {
   P->pIt = w.pIt;
   P->pRes = w.pRes;
   P->pUpd = w.pUpd;
-  P->pFus = w.pFus;
+  P->pSav = w.pSav;
   P->pExit = w.pExit;
   P->batch_cap = w.batch_cap;
   P->rho_ws = w.rho_ws;
@@ -202,7 +202,7 @@ void free_plan(exx_plan_t P) {
   if (!P) return;
   use_own_work(P);
   void* ptrs[] = {P->class_dev, P->class_block, P->pairs, P->order, P->pair_count, P->pE, P->pS, P->pIt,
-                  P->pRes, P->pUpd, P->pFus, P->pExit, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
+                  P->pRes, P->pUpd, P->pSav, P->pExit, P->rho_ws, P->bx_ws, P->halo_ws, P->Q_ws, P->Qp_ws, P->rho_scale, P->n_eff, P->d_slot, P->warm_store,
                   P->warm_map, P->prev_pairs, P->prev_offs, P->warm_state, P->slot_ws, P->queue,
                   P->stats_dev};
   for (void* p : ptrs)
@@ -932,7 +932,7 @@ size_t scratch_carve(exx_plan_t P, char* base, int n_orb, long long k, int g, Ev
   w->pIt = (int*)take(sizeof(int) * (size_t)cap);
   w->pRes = (double*)take(sizeof(double) * (size_t)cap);
   w->pUpd = (int*)take(sizeof(int) * (size_t)cap);
-  w->pFus = (int*)take(sizeof(int) * (size_t)cap);
+  w->pSav = (int*)take(sizeof(int) * (size_t)cap);
   w->pExit = (int*)take(sizeof(int) * (size_t)cap);
   w->batch_cap = k;
   w->rho_ws = (double*)take(sizeof(double) * (size_t)(k * P->rstride));
@@ -1195,7 +1195,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     if (dev_alloc(P, &P->pairs, (size_t)cap, "pairs") || dev_alloc(P, &P->order, (size_t)cap, "order") ||
         dev_alloc(P, &P->pE, (size_t)cap, "pair E") || dev_alloc(P, &P->pS, (size_t)9 * cap, "pair sigma") ||
         dev_alloc(P, &P->pIt, (size_t)cap, "pair iters") || dev_alloc(P, &P->pRes, (size_t)cap, "pair res") ||
-        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates") || dev_alloc(P, &P->pFus, (size_t)cap, "pair fused sweeps") ||
+        dev_alloc(P, &P->pUpd, (size_t)cap, "pair updates") || dev_alloc(P, &P->pSav, (size_t)cap, "pair saved sweeps") ||
         dev_alloc(P, &P->pExit, (size_t)cap, "pair exit reasons"))
       return EXX_ENOMEM;
     P->pair_cap = cap;
@@ -1314,7 +1314,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.outIt = P->pIt;
     a.outRes = P->pRes;
     a.outUpd = P->pUpd;
-    a.outFus = P->pFus;
+    a.outSav = P->pSav;
     a.outExit = P->pExit;
     a.mixed = mixed;
     a.delta = 0.1;
@@ -1348,7 +1348,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
       EXX_HIP(P, launch_dscatter(g, B, P->max_me, orbitals, D_xx, d_slot, (int)dt, P->bx_ws, P->rstride, P->Q_ws, s));
   }
   EXX_HIP(P, event(P->ev[2]));
-  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pFus, P->pExit, P->pairs, P->class_dev,
+  EXX_HIP(P, launch_reduce(P->pE, P->pS, P->pIt, P->pRes, P->pUpd, P->pSav, P->pExit, P->pairs, P->class_dev,
                            P->pair_count, n_orb, P->n_eff, P->opt.warm_start ? P->warm_map : nullptr, E_xx, sigma,
                            P->stats_dev, s));
   if (P->opt.warm_start)

@@ -155,7 +155,7 @@ struct EvalWork {
   int* pIt = nullptr;
   double* pRes = nullptr;
   int* pUpd = nullptr;
-  int* pFus = nullptr;
+  int* pSav = nullptr;
   int* pExit = nullptr;
   long long batch_cap = 0;
   double* rho_ws = nullptr;
@@ -223,7 +223,7 @@ struct exx_plan_s {
   int* pIt = nullptr;
   double* pRes = nullptr;
   int* pUpd = nullptr;
-  int* pFus = nullptr;   // fused CG sweeps per pair (each saves two vector accesses per point)
+  int* pSav = nullptr;   // per pair: CG sweeps that saved two vector accesses per point (fused, or x left alone)
   int* pExit = nullptr;  // CG exit reason per pair (EXX_CG_*) | restarts << 8
 
   // batch workspace

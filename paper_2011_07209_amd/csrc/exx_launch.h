@@ -75,7 +75,7 @@ struct SolveArgs {
   int* outIt = nullptr;
   double* outRes = nullptr;
   int* outUpd = nullptr;       // reliable updates per pair (mixed)
-  int* outFus = nullptr;       // fused sweeps per pair (pass B with the next pass A)
+  int* outSav = nullptr;       // per pair: sweeps that saved two vector accesses per point
   int* outExit = nullptr;      // per pair: exit reason (EXX_CG_*) | restarts << 8
   double tol = 0;
   int max_iter = 0;
@@ -127,7 +127,7 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s);
 // non-finite norm, restarts) as doubles.  A pair is unconverged when its exit
 // reason (pExit, low byte) is not EXX_CG_CONVERGED.  warm_map may be null.
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
-                         const int* pFus, const int* pExit, const PairDev* pairs, const ClassDev* cls,
+                         const int* pSav, const int* pExit, const PairDev* pairs, const ClassDev* cls,
                          const int* counts, int n_orb, const int* n_eff, const int* warm_map, double* E, double* sigma,
                          double* stats, hipStream_t s);
 

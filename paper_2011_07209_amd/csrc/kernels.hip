@@ -514,7 +514,7 @@ __global__ void k_dslot_fill(int* slot, int n_orb, const int* __restrict__ subse
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, const double* __restrict__ pS,
                                                 const int* __restrict__ pIt, const double* __restrict__ pRes,
-                                                const int* __restrict__ pUpd, const int* __restrict__ pFus,
+                                                const int* __restrict__ pUpd, const int* __restrict__ pSav,
                                                 const int* __restrict__ pExit,
                                                 const PairDev* __restrict__ pairs, const ClassDev* __restrict__ cls,
                                                 const int* __restrict__ cnt, int n_orb, const int* __restrict__ n_eff,
@@ -542,7 +542,9 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pE, c
     nrst += (double)(pExit[k] >> 8);
     rmax = fmax(rmax, pRes[k]);
     const double npe = (double)cls[pairs[k].cls].n_real;
-    work += (pIt[k] - 0.25 * pFus[k]) * npe;   // a fused sweep moves 6 of 8 vector accesses per point
+    // 8 vector accesses per point and iteration, two fewer for each fused
+    // sweep and each pass B that left x alone
+    work += (pIt[k] - 0.25 * pSav[k]) * npe;
     pts += npe;
     if (warm_map && warm_map[k] >= 0) warm += 1.0;
   }
@@ -727,10 +729,10 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const double* pE, const double* pS, const int* pIt, const double* pRes, const int* pUpd,
-                         const int* pFus, const int* pExit, const PairDev* pairs, const ClassDev* cls,
+                         const int* pSav, const int* pExit, const PairDev* pairs, const ClassDev* cls,
                          const int* counts, int n_orb, const int* n_eff, const int* warm_map, double* E, double* sigma,
                          double* stats, hipStream_t s) {
-  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pFus, pExit, pairs, cls, counts, n_orb, n_eff, warm_map, E, sigma,
+  k_reduce<<<1, 256, 0, s>>>(pE, pS, pIt, pRes, pUpd, pSav, pExit, pairs, cls, counts, n_orb, n_eff, warm_map, E, sigma,
                              stats);
   return hipGetLastError();
 }

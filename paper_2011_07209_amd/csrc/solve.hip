@@ -52,7 +52,7 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
   a.outIt = in.outIt;
   a.outRes = in.outRes;
   a.outUpd = in.outUpd;
-  a.outFus = in.outFus;
+  a.outSav = in.outSav;
   a.outExit = in.outExit;
   a.tol = in.tol;
   a.max_iter = in.max_iter;

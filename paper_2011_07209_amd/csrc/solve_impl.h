@@ -49,6 +49,36 @@ __device__ __forceinline__ StencilT<T> stencil_cast(const StencilT<double>& s) {
   return o;
 }
 
+// The solution update of a pass B: x = x + ap p + ar r_in, with r_in the
+// residual before the pass's own update.  With `zero` the old x is taken as
+// zero; with `skip` x is neither read nor written, and the update is deferred
+// to the next pass B: p_k = (p_k+1 - r_k+1) / beta_k, so the two steps
+// alpha_k p_k + alpha_k+1 p_k+1 make ap = alpha_k+1 + alpha_k / beta_k and
+// ar = -alpha_k / beta_k.  x is then read and written every other iteration
+// (seven vector accesses per point and iteration in place of eight).
+template <typename T>
+struct XStep {
+  T ap, ar;
+  bool zero, skip;
+};
+
+// A value that is the same in every lane (the CG's step lengths, from block
+// sums), moved to scalar registers so that the plane loops keep their vector
+// registers for the vectors.
+__device__ __forceinline__ float uniform(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename T>
+__device__ __forceinline__ XStep<T> uniform(XStep<T> s) {
+  return XStep<T>{uniform(s.ap), uniform(s.ar), s.zero, s.skip};
+}
+
 // The NK Laplacian of a general cell in the CG frame (x', y' in the LDS plane,
 // z' the sweep axis).  Arms inside the sweep plane read the staged plane at
 // one LDS step off per grid step; arms that leave it (oriented so that one
@@ -101,7 +131,8 @@ struct SolveKArgs {
   int* outIt;
   double* outRes;
   int* outUpd;            // mixed: reliable updates per pair
-  int* outFus;            // sweeps that fused pass B with the next pass A, per pair
+  int* outSav;            // sweeps that saved two vector accesses per point, per pair (a fused
+                          // sweep, or a pass B that left x alone; both in one sweep count twice)
   int* outExit;           // per pair: exit reason (kCg*) | restarts << 8
   double tol;
   int max_iter;
@@ -320,12 +351,12 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
 
 // Pass B: q = A p again (same arithmetic as pass A), x += alpha p,
 // r -= alpha q; returns this thread's FP64 sum of r^2 after the update.  The
-// residual is read from r_in and written to r (they may alias); with x_zero
-// the old x is taken as zero (and x may alias r_in: each point is read before
-// it is written, by the same thread).
+// residual is read from r_in and written to r (they may alias); x is updated
+// as xs says (see XStep); with xs.zero the old x is taken as zero (and x may
+// alias r_in: each point is read before it is written, by the same thread).
 template <int NS, int CPT, int PD, typename T>
 __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, T* x,
-                            const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+                            const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
   T win[CPT][2 * NS + 1];
   T qp[PD][CPT];           // p of planes z+NS+1 .. z+NS+PD
   T cx[CPT], cr[CPT];      // x, r of plane z
@@ -348,7 +379,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
     if (EXX_VALID(c, -Zmax)) {
       const unsigned idx = EXX_IDX(c, -Zmax);
       cr[c] = gload(r_in, idx);
-      if (!x_zero) cx[c] = gload(x, idx);
+      if (!xs.zero && !xs.skip) cx[c] = gload(x, idx);
     }
   }
   double acc = 0.0;
@@ -363,7 +394,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
       if (EXX_VALID(c, z + 1)) {
         const unsigned idx = EXX_IDX(c, z + 1);
         nr[c] = gload(r_in, idx);
-        if (!x_zero) nx[c] = gload(x, idx);
+        if (!xs.zero && !xs.skip) nx[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -377,7 +408,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
         const unsigned idx = EXX_IDX(c, z);
         const T q = apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
         const T rn = cr[c] - alpha * q;
-        gstore(x, idx, cx[c] + alpha * win[c][NS]);
+        if (!xs.skip) gstore(x, idx, cx[c] + xs.ap * win[c][NS] + xs.ar * cr[c]);
         gstore(r, idx, rn);
         acc += (double)rn * (double)rn;
       }
@@ -612,7 +643,7 @@ __device__ void cg_pass_a_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, con
 // x are read before the same thread writes them.
 template <int NS, int CPT, int PD, typename T>
 __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax, T* x,
-                                const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+                                const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
   T win[CPT][2 * NS + 1];
   T qp[PD][CPT];
 #pragma unroll
@@ -639,7 +670,7 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
       if (EXX_GVALID(c, z)) {
         const unsigned idx = EXX_GIDX(c, z);
         orr[c] = gload(r_in, idx);
-        if (!x_zero) ox[c] = gload(x, idx);
+        if (!xs.zero && !xs.skip) ox[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -653,7 +684,7 @@ __device__ double cg_pass_b_gen(const GenStencilT<T>& S, const ColsG<CPT>& cl, c
         const unsigned idx = EXX_GIDX(c, z);
         const T lap = gen_inplane<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
         const T rn = orr[c] + alpha * lap;   // r - alpha A p, A p = -lap
-        gstore(x, idx, ox[c] + alpha * win[c][NS]);
+        if (!xs.skip) gstore(x, idx, ox[c] + xs.ap * win[c][NS] + xs.ar * orr[c]);
         gstore(r, idx, rn);
         sum += (double)rn * (double)rn;
       }
@@ -814,7 +845,7 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
 
 template <int NS, int CPT, typename T>
 __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax, T* x,
-                               const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+                               const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
   T pd[CPT][NS + 1];
   T acc[CPT][2 * NS + 1];
   T cp[CPT];               // p of plane z
@@ -838,7 +869,7 @@ __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, co
       if (EXX_GVALID(c, zo)) {   // read before the same thread writes them below
         const unsigned idx = EXX_GIDX(c, zo);
         orr[c] = gload(r_in, idx);
-        if (!x_zero) ox[c] = gload(x, idx);
+        if (!xs.zero && !xs.skip) ox[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -854,7 +885,7 @@ __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, co
       if (EXX_GVALID(c, zo)) {
         const unsigned idx = EXX_GIDX(c, zo);
         const T rn = orr[c] + alpha * acc[c][0];   // r - alpha A p, A p = -acc
-        gstore(x, idx, ox[c] + alpha * pd[c][0]);
+        if (!xs.skip) gstore(x, idx, ox[c] + xs.ap * pd[c][0] + xs.ar * orr[c]);
         gstore(r, idx, rn);
         sum += (double)rn * (double)rn;
       }
@@ -1159,9 +1190,9 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
 
 // Pass B (as cg_pass_b) on the quad layout; the new r is kept to the run's
 // live slots, so dead slots keep r = 0 (and x = 0, since p is zero there).
-template <int NS, int PD, bool DG, typename T>
-__device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
-                                 const T* r_in, T* r, const T* __restrict__ p, T alpha, bool x_zero, T* pl0, T* pl1) {
+template <int NS, int PD, bool DG, bool SKIP, typename T>
+__device__ double cg_pass_b_quad_x(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
+                                 const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
   const V4<T> zero = {0, 0, 0, 0};
   V4<T> win[2 * NS + 1];
   V4<T> qp[PD];              // p of planes z+NS+1 .. z+NS+PD
@@ -1179,7 +1210,7 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
   if (EXX_QVALID(-Zmax)) {
     const int idx = EXX_QIDX(-Zmax);
     cr = ld_quad(r_in, idx);
-    if (!x_zero) cx = ld_quad(x, idx);
+    if (!SKIP && !xs.zero) cx = ld_quad(x, idx);
   }
   double acc = 0.0;
   for (int z = -Zmax; z <= Zmax; ++z) {
@@ -1189,7 +1220,7 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
     if (EXX_QVALID(z + 1)) {
       const int idx = EXX_QIDX(z + 1);
       nr = ld_quad(r_in, idx);
-      if (!x_zero) nx = ld_quad(x, idx);
+      if (!SKIP && !xs.zero) nx = ld_quad(x, idx);
     }
     T* pl = (z & 1) ? pl1 : pl0;
     if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
@@ -1197,7 +1228,7 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
     if (EXX_QVALID(z)) {
       const int idx = EXX_QIDX(z);
       const V4<T> rn = live_only(cl, z, cr - alpha * apply_quad<NS, DG, T>(S, win, pl, cl.pos));
-      st_quad(x, idx, cx + alpha * win[NS]);
+      if constexpr (!SKIP) st_quad(x, idx, cx + xs.ap * win[NS] + xs.ar * cr);
       st_quad(r, idx, rn);
       acc += dot4(rn, rn);
     }
@@ -1213,22 +1244,33 @@ __device__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const in
   return acc;
 }
 
+// The two forms of pass B as separate loops: one that leaves x alone keeps no
+// x vectors live across the plane loop.
+template <int NS, int PD, bool DG, typename T>
+__device__ __forceinline__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax,
+                                                 T* x, const T* r_in, T* r, const T* __restrict__ p, T alpha,
+                                                 XStep<T> xs, T* pl0, T* pl1) {
+  if (xs.skip) return cg_pass_b_quad_x<NS, PD, DG, true, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
+  return cg_pass_b_quad_x<NS, PD, DG, false, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
+}
+
 // Pass B of one iteration and pass A of the next in one sweep on the quad
 // layout.  With the step alpha of p (= p_k) and the next beta (which the
 // caller takes from |r - alpha Ap|^2, known before r is updated): along the
 // sweep, Ap_k of plane c is recomputed from the z window of p_k, then
-// x += alpha p_k, r -= alpha Ap_k and p_k+1 = r + beta p_k are written over
-// the same slots; NS planes behind, Ap_k+1 is taken from the z window of the
+// x is updated as xs says (with p_k), r -= alpha Ap_k and p_k+1 = r + beta p_k
+// are written over the same slots; NS planes behind, Ap_k+1 is taken from the z window of the
 // new p, for p_k+1.Ap_k+1, r_k+1.Ap_k+1 and |Ap_k+1|^2 (r_k+1 restated as
 // p_k+1 - beta p_k from the two windows).  Each plane is read and written once
-// per iteration (p, r, x in; p, r, x out) instead of twice for p.  Each step
+// per iteration (p, r, x in; p, r, x out; x only every other iteration when
+// its updates are paired, see XStep) instead of twice for p.  Each step
 // stages the planes of both stencils (la*, lb*) behind one barrier.
 // The two z windows take 56 registers per thread (FP32, n = 3), which fit
 // beside the rest only with at most three waves per SIMD (768 threads).
 // Returns |r_k+1|^2 and writes the products of iteration k+1 to out3.
 template <int NS, int PD, bool DG, typename T>
 __device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
-                                     T* r, T* p, T alpha, T beta, bool x_zero, T* la0, T* la1, T* lb0, T* lb1,
+                                     T* r, T* p, T alpha, T beta, XStep<T> xs, T* la0, T* la1, T* lb0, T* lb1,
                                      double (&out3)[3]) {
   const V4<T> zero = {0, 0, 0, 0};
   V4<T> wk[2 * NS + 1];      // p_k of planes c - NS .. c + NS
@@ -1249,7 +1291,7 @@ __device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, cons
   if (EXX_QVALID(-Zmax)) {
     const int idx = EXX_QIDX(-Zmax);
     cr = ld_quad(r, idx);
-    if (!x_zero) cx = ld_quad(x, idx);
+    if (!xs.zero && !xs.skip) cx = ld_quad(x, idx);
   }
   double rn = 0.0, pq = 0.0, ra = 0.0, aa = 0.0;
   for (int c = -Zmax; c <= Zmax + NS; ++c) {
@@ -1259,7 +1301,7 @@ __device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, cons
     if (EXX_QVALID(c + 1)) {
       const int idx = EXX_QIDX(c + 1);
       nr = ld_quad(r, idx);
-      if (!x_zero) nx = ld_quad(x, idx);
+      if (!xs.zero && !xs.skip) nx = ld_quad(x, idx);
     }
     T* la = (c & 1) ? la1 : la0;
     T* lb = (c & 1) ? lb1 : lb0;
@@ -1273,7 +1315,7 @@ __device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, cons
       const int idx = EXX_QIDX(c);
       const V4<T> rn1 = live_only(cl, c, cr - alpha * apply_quad<NS, DG, T>(S, wk, la, cl.pos));
       pn = rn1 + beta * wk[NS];
-      st_quad(x, idx, cx + alpha * wk[NS]);
+      if (!xs.skip) st_quad(x, idx, cx + xs.ap * wk[NS] + xs.ar * cr);
       st_quad(r, idx, rn1);
       st_quad(p, idx, pn);
       rn += dot4(rn1, rn1);
@@ -1402,6 +1444,7 @@ template <int NS, int CPT, int PD, bool GEN, bool TL, bool QD, typename T>
 __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T>& G,
                                        const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, const T* r, T* p,
                                        T beta, bool first, T* pl0, T* pl1, double& pq, double& rr) {
+  beta = uniform(beta);
   if constexpr (QD) {
     double ra, aa;
     cg_pass_a_quad<NS, PD, GEN, false, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr, ra, aa);
@@ -1417,15 +1460,17 @@ __device__ __forceinline__ void pass_a(const StencilT<T>& S, const GenStencilT<T
 template <int NS, int CPT, int PD, bool GEN, bool TL, bool QD, typename T>
 __device__ __forceinline__ double pass_b(const StencilT<T>& S, const GenStencilT<T>& G,
                                          const ColsOf<GEN, QD, CPT>& cl, const int* pst, int Zmax, T* x,
-                                         const T* r_in, T* r, const T* p, T alpha, bool x_zero, T* pl0, T* pl1) {
+                                         const T* r_in, T* r, const T* p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
+  alpha = uniform(alpha);
+  xs = uniform(xs);
   if constexpr (QD)
-    return cg_pass_b_quad<NS, PD, GEN, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+    return cg_pass_b_quad<NS, PD, GEN, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
   else if constexpr (GEN && TL)
-    return cg_pass_b_tl<NS, CPT, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+    return cg_pass_b_tl<NS, CPT, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
   else if constexpr (GEN)
-    return cg_pass_b_gen<NS, CPT, PD, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+    return cg_pass_b_gen<NS, CPT, PD, T>(G, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
   else
-    return cg_pass_b<NS, CPT, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, x_zero, pl0, pl1);
+    return cg_pass_b<NS, CPT, PD, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
 }
 
 template <int NS, int CPT, bool GEN, bool TL, bool QD, typename TR>
@@ -1517,6 +1562,10 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
     }
     const bool from_b = !init;   // cold: the first pass reads b from x, and x starts at zero
     bool conv = false;
+    // a pass B that left x alone (its step alpha_k p_k deferred, see XStep)
+    bool pend = false;
+    double a_pend = 0.0, b_pend = 1.0;
+    int nsav = 0;
     while (it < a.max_iter) {
       double alpha = 1.0;
       if (!init) {
@@ -1545,9 +1594,19 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
         alpha = rr / pq;
       }
       const bool from_b_now = init || (first && from_b);
+      XStep<double> xs{alpha, 0.0, from_b_now, false};
+      if (pend) {   // this pass also takes the deferred step
+        xs.ap = alpha + a_pend / b_pend;
+        xs.ar = -a_pend / b_pend;
+        pend = false;
+      } else if (!from_b_now) {   // x holds the solution: defer this step to the next pass B
+        xs.skip = true;
+        pend = true;
+        a_pend = alpha;
+        ++nsav;
+      }
       const double rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, double>(a.S, a.G, cl, pst, Zmax, x,
-                                                                       from_b_now ? x : r, r, p, alpha, from_b_now,
-                                                                       pl0, pl1),
+                                                                       from_b_now ? x : r, r, p, alpha, xs, pl0, pl1),
                                   red);
       if (init) {   // the warm start's residual
         init = false;
@@ -1572,6 +1631,11 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       }
       beta = rn / rr;
       rr = rn;
+      b_pend = beta;
+    }
+    if (pend) {   // the last pass B deferred its step; p still holds its p
+      for (long long k = tid; k < npe; k += NT) x[k] += a_pend * p[k];
+      __syncthreads();
     }
     if (!conv && code == kCgConverged) code = kCgCap;
     warm_store_solution(a, npe, pid, x);
@@ -1579,7 +1643,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveKArgs a) {
       a.outIt[pid] = it;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
       a.outUpd[pid] = 0;
-      a.outFus[pid] = 0;
+      a.outSav[pid] = nsav;
       a.outExit[pid] = code;
     }
     __syncthreads();
@@ -1651,7 +1715,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     for (long long k = tid; k < npe; k += NT) r[k] = (float)(bx[k] * inv_b);
     __syncthreads();
 
-    int it = 0, upd = 0, nfus = 0, rst = 0, code = kCgConverged;
+    int it = 0, upd = 0, nsav = 0, rst = 0, code = kCgConverged;
     double rr = 1.0, rr_true = bb, rmax = 1.0, beta = 0.0;
     bool first = true, x_zero = true, y_zero = true;
     bool conv = bnorm == 0.0;
@@ -1672,6 +1736,11 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
     // fused sweep (cg_pass_fused_quad)
     bool have_p = false;
     double pq = 0.0, ra = 0.0, aa = 0.0;
+    // the correction y is updated by every other pass B (see XStep): pend
+    // marks a pass that deferred its step a_pend p; b_pend is the FP32 beta
+    // that formed the next p from it
+    bool pend = false;
+    double a_pend = 0.0, b_pend = 1.0;
     while (!conv && code == kCgConverged && it < a.max_iter) {
       // bad: the FP32 recursion broke down (p.Ap not positive and finite) or
       // produced a non-finite norm; the CG then restarts from the last FP64
@@ -1681,8 +1750,8 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       if (!have_p) {
         if constexpr (QD) {
           double t[4], rr_t;
-          cg_pass_a_quad<NS, PD, GEN, FUSE, float>(S32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, t[0], rr_t,
-                                                   t[1], t[2]);
+          cg_pass_a_quad<NS, PD, GEN, FUSE, float>(S32, cl, pst, Zmax, r, p, uniform((float)beta), first, fl0, fl1,
+                                                   t[0], rr_t, t[1], t[2]);
           t[3] = 0.0;
           block_sum4(t, red4);
           pq = t[0];
@@ -1698,6 +1767,13 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       if (!(pq > 0.0) || !(pq < INFINITY)) bad = kCgBreakdown;
       if (bad == kCgConverged) {
         const double alpha = rr / pq;
+        XStep<float> xs{(float)alpha, 0.0f, y_zero, false};
+        if (pend) {   // this pass also takes the deferred step
+          xs.ap = (float)(alpha + a_pend / b_pend);
+          xs.ar = (float)(-a_pend / b_pend);
+        } else {
+          xs.skip = true;
+        }
         bool fused = false;
         if constexpr (FUSE) {
           // |r - alpha Ap|^2 before r is updated; the sweep is fused only where
@@ -1707,16 +1783,20 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
           const double thr = 1.02 * fmax(a.delta * rmax, a.tol);
           if (rn_next > thr * thr && it + 1 < a.max_iter) {
             double o3[3], t[4];
-            t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, (float)alpha,
-                                                          (float)(rn_next / rr), y_zero, fl0, fl1, fl2, fl3, o3);
+            const float bnext = (float)(rn_next / rr);
+            t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, uniform((float)alpha),
+                                                          uniform(bnext), uniform(xs), fl0, fl1, fl2, fl3, o3);
             t[1] = o3[0];
             t[2] = o3[1];
             t[3] = o3[2];
             block_sum4(t, red4);
             ++it;
-            ++nfus;
+            nsav += xs.skip ? 2 : 1;
             first = false;
-            y_zero = false;
+            if (!xs.skip) y_zero = false;
+            pend = xs.skip;
+            a_pend = alpha;
+            b_pend = (double)bnext;
             fused = true;
             if (!(t[0] == t[0]) || !(t[0] < INFINITY)) {
               bad = kCgNonFinite;
@@ -1733,11 +1813,14 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         }
         if (!fused) {
           rn = block_sum(pass_b<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, y, r, r, p, (float)alpha,
-                                                                 y_zero, fl0, fl1),
+                                                                 xs, fl0, fl1),
                          red);
           ++it;
+          nsav += xs.skip ? 1 : 0;
           first = false;
-          y_zero = false;
+          if (!xs.skip) y_zero = false;
+          pend = xs.skip;
+          a_pend = alpha;
           if (!(rn == rn) || !(rn < INFINITY)) bad = kCgNonFinite;
         }
       }
@@ -1755,13 +1838,18 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
         // share LDS, so it is cleared around the FP64 pass (the barrier also
         // orders the fold before the sweep).
         if (!restart) {
-          for (long long k = tid; k < npe; k += NT) x[k] = (x_zero ? 0.0 : x[k]) + bnorm * (double)y[k];
+          // (with a deferred step, p still holds that pass's p: a reliable
+          // update always follows a plain pass B, which leaves p alone)
+          const double ap = pend ? a_pend : 0.0;
+          for (long long k = tid; k < npe; k += NT)
+            x[k] = (x_zero ? 0.0 : x[k]) + bnorm * ((y_zero ? 0.0 : (double)y[k]) + ap * (double)p[k]);
           x_zero = false;
           ++upd;
         } else {
           ++rst;
           have_p = false;
         }
+        pend = false;
         if (x_zero) {
           for (long long k = tid; k < npe; k += NT) r[k] = (float)(bx[k] * inv_b);
           __syncthreads();
@@ -1783,6 +1871,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       }
       beta = rn / rr;
       rr = rn;
+      if (pend) b_pend = (double)(float)beta;   // the FP32 beta of the next pass A
     }
     if (!conv && code == kCgConverged) code = kCgCap;
     // the FP64 solution replaces the right-hand side
@@ -1797,7 +1886,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
       a.outIt[pid] = it;
       a.outRes[pid] = bnorm > 0.0 ? sqrt(rr_true) / bnorm : 0.0;
       a.outUpd[pid] = upd;
-      a.outFus[pid] = nfus;
+      a.outSav[pid] = nsav;
       a.outExit[pid] = code | (rst << 8);
     }
     __syncthreads();
