@@ -134,6 +134,13 @@ typedef struct {
      not fit (more than 1024 runs, other arms or columns), with
      cell_fluctuation and with solve_threads 512                              */
   int cg_layout;
+  /* mixed precision: a reliable update (the FP32 correction folded into the
+     FP64 solution and the FP64 true residual recomputed) happens when the
+     working residual falls below refine_delta times the residual of the last
+     update (0: 0.01); values in (0, 1).  Each update is an FP64 sweep that
+     costs about three CG iterations' worth of memory traffic; smaller values
+     mean fewer updates and a few more FP32 iterations */
+  double refine_delta;
 } exx_options;
 
 /* Fills *opt with the defaults: n = 3, FP64, tol 1e-10, 5000 iterations,

@@ -988,6 +988,8 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (l_max < 0 || l_max > kMaxL) return fail(nullptr, EXX_EINVAL, "l_max must be in [0, 8]");
   if (opt.stencil_n < 1 || opt.stencil_n > 3) return fail(nullptr, EXX_EINVAL, "stencil_n must be 1, 2 or 3");
   if (!(opt.cg_tol > 0.0) || opt.cg_max_iter < 1) return fail(nullptr, EXX_EINVAL, "CG tolerance/iterations invalid");
+  if (!(opt.refine_delta >= 0.0 && opt.refine_delta < 1.0))
+    return fail(nullptr, EXX_EINVAL, "refine_delta must lie in [0, 1)");
   if (opt.precision != EXX_PREC_FP64 && opt.precision != EXX_PREC_MIXED)
     return fail(nullptr, EXX_EINVAL, "unknown precision");
   if (opt.R_PE_nclass < 0 || opt.R_PE_nclass > kMaxClasses) return fail(nullptr, EXX_EINVAL, "R_PE_nclass out of range");
@@ -1317,7 +1319,7 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     a.outSav = P->pSav;
     a.outExit = P->pExit;
     a.mixed = mixed;
-    a.delta = 0.1;
+    a.delta = P->opt.refine_delta > 0.0 ? P->opt.refine_delta : 0.01;
     a.threads = P->solve_threads;
     a.depth = P->solve_depth;
     a.tol = P->opt.cg_tol;

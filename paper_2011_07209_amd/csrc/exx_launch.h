@@ -80,7 +80,7 @@ struct SolveArgs {
   double tol = 0;
   int max_iter = 0;
   bool mixed = false;
-  double delta = 0.1;          // mixed: reliable-update threshold
+  double delta = 0.01;         // mixed: reliable-update threshold
   // warm start (warm_store null: every solve starts from zero)
   const float* warm_store = nullptr;   // [2][warm_cap][rstride] FP32 solutions
   long long warm_cap = 0;

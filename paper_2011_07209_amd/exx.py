@@ -53,6 +53,7 @@ class Options(ctypes.Structure):
         ("cell_fluctuation", ctypes.c_int),
         ("reassemble_strain", ctypes.c_double),
         ("cg_layout", ctypes.c_int),
+        ("refine_delta", ctypes.c_double),
     ]
 
 
