@@ -10,8 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexx.so")
-SOURCES = ["plan_geometry.cpp", "nk_stencil.cpp", "kernels.hip", "moments.hip", "solve.hip", "solve_n1.hip", "solve_n2.hip", "solve_n3.hip",
-           "api.hip"]
+SOURCES = ["plan_geometry.cpp", "nk_stencil.cpp", "kernels.hip", "moments.hip", "finalize.hip", "solve.hip", "solve_n1.hip",
+           "solve_n2.hip", "solve_n3.hip", "api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

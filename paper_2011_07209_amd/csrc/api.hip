@@ -711,12 +711,31 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     const size_t entries = (size_t)((C.n_pe + 31) / 32 * 32) * mom_rows;
     return mixed ? 2 * align(entries * sizeof(unsigned short)) : align(entries * sizeof(double));
   };
+  // orthorhombic classes: the Dirichlet points grouped by plane (for the
+  // plane-sweep E/sigma kernel, which stages each plane's far-field values)
+  for (ClassHost& C : classes) {
+    C.halo_zidx.clear();
+    C.halo_zstart.clear();
+    if (general) continue;
+    const int Zh = C.Zmax + n;
+    C.halo_zstart.assign(2 * Zh + 2, 0);
+    for (const short4& o : C.halo_off) C.halo_zstart[o.z + Zh + 1]++;
+    for (int z = 0; z < 2 * Zh + 1; ++z) C.halo_zstart[z + 1] += C.halo_zstart[z];
+    std::vector<int> fill(C.halo_zstart.begin(), C.halo_zstart.end() - 1);
+    C.halo_zidx.assign(C.halo_off.size(), 0);
+    for (size_t h = 0; h < C.halo_off.size(); ++h) C.halo_zidx[fill[C.halo_off[h].z + Zh]++] = (int)h;
+    C.fin_cols.clear();
+    for (int c = 0; c < C.n_cols; ++c)
+      if (C.cols[c].z >= 0) C.fin_cols.push_back(make_int4(c, C.cols[c].z, C.cols[c].x, C.cols[c].y));
+  }
   size_t total = 0;
   for (const ClassHost& C : classes) {
     total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
              align(C.halo_off.size() * sizeof(short4)) + align(C.me_off.size() * sizeof(short4)) +
              align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
-             align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) + mom_bytes(C);
+             align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) +
+             align(C.halo_zidx.size() * sizeof(int)) + align(C.halo_zstart.size() * sizeof(int)) +
+             align(C.fin_cols.size() * sizeof(int4)) + mom_bytes(C);
   }
   void* block = nullptr;
   ClassDev* class_dev = nullptr;
@@ -761,6 +780,11 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.col_map = (const int*)put(C.col_map.data(), C.col_map.size() * sizeof(int));
     D.zr_map = (const int*)put(C.zr_map.data(), C.zr_map.size() * sizeof(int));
     D.pe_map = general ? (const int*)put(C.pe_map.data(), C.pe_map.size() * sizeof(int)) : nullptr;
+    D.halo_zidx = (const int*)put(C.halo_zidx.data(), C.halo_zidx.size() * sizeof(int));
+    D.halo_zstart = (const int*)put(C.halo_zstart.data(), C.halo_zstart.size() * sizeof(int));
+    D.Zh = general ? 0 : C.Zmax + n;
+    D.fin_cols = (const int4*)put(C.fin_cols.data(), C.fin_cols.size() * sizeof(int4));
+    D.n_fin = (int)C.fin_cols.size();
     D.mom_rows = mom_rows;
     std::vector<double> tab;
     build_moment_table(C, g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);
@@ -802,6 +826,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
   P->max_halo = max_halo;
   P->max_me = max_me;
   P->max_cols = max_cols;
+  P->max_fin = 0;
+  for (const ClassHost& C : P->classes) P->max_fin = std::max<long long>(P->max_fin, (long long)C.fin_cols.size());
   P->max_zmax = max_zmax;
   std::memcpy(P->h, h, sizeof(P->h));
   std::memcpy(P->h0, h, sizeof(P->h0));
@@ -1344,8 +1370,12 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     if (launch_events) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
     { exx_status es = launch_solves(P, a, s); if (es != EXX_OK) return es; }
     if (launch_events) { exx_status es = record_solve_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_finalize(g, B, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws, std::max<long long>(P->max_halo, 1),
-                               P->pE, P->pS, s));
+    if (finalize_sweep_supported(g, P->max_fin))
+      EXX_HIP(P, launch_finalize_sweep(g, B, P->max_fin, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
+                                       std::max<long long>(P->max_halo, 1), P->pE, P->pS, s));
+    else
+      EXX_HIP(P, launch_finalize(g, B, P->rho_ws, P->bx_ws, P->rstride, P->halo_ws,
+                                 std::max<long long>(P->max_halo, 1), P->pE, P->pS, s));
     if (D_xx)
       EXX_HIP(P, launch_dscatter(g, B, P->max_me, orbitals, D_xx, d_slot, (int)dt, P->bx_ws, P->rstride, P->Q_ws, s));
   }

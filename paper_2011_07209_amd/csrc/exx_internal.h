@@ -82,6 +82,15 @@ struct ClassDev {
   const int* halo_map;       // [Wm2][Wm1][Wm0] -> halo index or -1
   const int* col_map;        // [Wm1][Wm0] -> column index or -1
   const int* zr_map;         // [Wm1][Wm0] -> column half-height or -1
+  // orthorhombic cells: the Dirichlet points plane by plane, halo_zidx[halo_zstart[z + Zh] ..
+  // halo_zstart[z + Zh + 1]) the halo indices of plane z, Zh = Zmax + n (null for general cells)
+  const int* halo_zidx;
+  const int* halo_zstart;
+  int Zh;
+  // orthorhombic cells: the sphere's columns without the quad layout's padding columns,
+  // (slot in the layout, half-height, x, y) each; n_fin of them
+  const int4* fin_cols;
+  int n_fin;
   // moment table: unnormalised solid harmonics P_lm of the PE offsets over
   // mom_rows rows and n_pe rounded up to 32 points (zeros beyond); FP64 in
   // layout [k/4][row][4] for FP64 plans, split BF16 (hi, lo) in layout
@@ -112,6 +121,8 @@ struct ClassHost {
   std::vector<short4> halo_off;
   std::vector<short4> me_off;
   std::vector<int> halo_map, col_map, zr_map, pe_map;
+  std::vector<int> halo_zidx, halo_zstart;   // orthorhombic: the Dirichlet points by plane
+  std::vector<int4> fin_cols;                // orthorhombic: the real columns (slot, zr, x, y)
   long long n_pe = 0, n_halo = 0, n_me = 0, n_real = 0;
 };
 
@@ -191,6 +202,7 @@ struct exx_plan_s {
   void* class_block = nullptr;                 // device block holding every class table
   int self_class = -1;   // class of the self pairs when they have their own radii
   long long max_pe = 0, max_halo = 0, max_me = 0, max_cols = 0;
+  long long max_fin = 0;   // most real columns of a class (orthorhombic; the E/sigma sweep)
   long long rstride = 0;   // row stride of the per-pair workspaces: max_pe rounded up to 32
   int max_zmax = 0;
 

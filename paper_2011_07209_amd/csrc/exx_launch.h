@@ -101,6 +101,13 @@ bool solve_supported(int max_cols, int threads);
 long long solve_slot_bytes(bool mixed, long long sstride);
 hipError_t launch_finalize(const Geo& g, const Batch& B, const double* rho_ws, const double* v_ws, long long rstride,
                            const double* halo_ws, long long hstride, double* outE, double* outS, hipStream_t s);
+// E_xx and sigma_xx of the batch's pairs as one plane sweep per pair
+// (finalize.hip): orthorhombic cells whose classes have at most 4096 columns
+// (finalize_sweep_supported); launch_finalize serves the others.
+bool finalize_sweep_supported(const Geo& g, long long max_cols);
+hipError_t launch_finalize_sweep(const Geo& g, const Batch& B, long long max_cols, const double* rho_ws,
+                                 const double* v_ws, long long rstride, const double* halo_ws, long long hstride,
+                                 double* outE, double* outS, hipStream_t s);
 // D^i += v phi_j (and D^j += v phi_i) into row d_slot[i] of D, or row i when
 // d_slot is null; rows with d_slot = -1 are not written.
 hipError_t launch_dscatter(const Geo& g, const Batch& B, long long max_me, const void* orb, void* D,
