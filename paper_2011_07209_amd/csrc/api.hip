@@ -727,6 +727,32 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     C.fin_cols.clear();
     for (int c = 0; c < C.n_cols; ++c)
       if (C.cols[c].z >= 0) C.fin_cols.push_back(make_int4(c, C.cols[c].z, C.cols[c].x, C.cols[c].y));
+    // the Dirichlet terms of each PE slot's right-hand side: every axis
+    // neighbour within n steps that is not a PE point is a Dirichlet point
+    C.rhs_ptr.assign((size_t)C.n_pe + 1, 0);
+    C.rhs_ent.clear();
+    const int W0 = C.Wm[0], W1 = C.Wm[1];
+    const int cx = C.Rg[0] + n, cy = C.Rg[1] + n, cz = C.Rg[2] + n;
+    auto in_pe = [&](int ox, int oy, int oz) {
+      if (std::abs(ox) > C.Rg[0] || std::abs(oy) > C.Rg[1]) return false;
+      const int zr = C.zr_map[(size_t)(ox + cx) + (size_t)W0 * (oy + cy)];
+      return zr >= 0 && std::abs(oz) <= zr;
+    };
+    for (long long k = 0; k < C.n_pe; ++k) {
+      const short4 o = C.me_off[(size_t)k];
+      if (!o.w) {
+        for (int al = 0; al < 3; ++al)
+          for (int q = 1; q <= n; ++q)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+              int u[3] = {o.x, o.y, o.z};
+              u[al] += sgn * q;
+              if (in_pe(u[0], u[1], u[2])) continue;
+              const int h = C.halo_map[(size_t)(u[0] + cx) + (size_t)W0 * ((u[1] + cy) + (size_t)W1 * (u[2] + cz))];
+              if (h >= 0) C.rhs_ent.push_back(make_int2(h, 4 * al + q));
+            }
+      }
+      C.rhs_ptr[(size_t)k + 1] = (int)C.rhs_ent.size();
+    }
   }
   size_t total = 0;
   for (const ClassHost& C : classes) {
@@ -735,7 +761,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
              align(C.halo_map.size() * sizeof(int)) + align(C.col_map.size() * sizeof(int)) +
              align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) +
              align(C.halo_zidx.size() * sizeof(int)) + align(C.halo_zstart.size() * sizeof(int)) +
-             align(C.fin_cols.size() * sizeof(int4)) + mom_bytes(C);
+             align(C.fin_cols.size() * sizeof(int4)) + align(C.rhs_ptr.size() * sizeof(int)) +
+             align(C.rhs_ent.size() * sizeof(int2)) + mom_bytes(C);
   }
   void* block = nullptr;
   ClassDev* class_dev = nullptr;
@@ -785,6 +812,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.Zh = general ? 0 : C.Zmax + n;
     D.fin_cols = (const int4*)put(C.fin_cols.data(), C.fin_cols.size() * sizeof(int4));
     D.n_fin = (int)C.fin_cols.size();
+    D.rhs_ptr = (const int*)put(C.rhs_ptr.data(), C.rhs_ptr.size() * sizeof(int));
+    D.rhs_ent = (const int2*)put(C.rhs_ent.data(), C.rhs_ent.size() * sizeof(int2));
     D.mom_rows = mom_rows;
     std::vector<double> tab;
     build_moment_table(C, g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);

@@ -91,6 +91,11 @@ struct ClassDev {
   // (slot in the layout, half-height, x, y) each; n_fin of them
   const int4* fin_cols;
   int n_fin;
+  // orthorhombic cells: the Dirichlet terms of the right-hand side as a CSR
+  // table over the PE slots: slot k takes w_q / d_al^2 v_h for the entries
+  // rhs_ent[rhs_ptr[k] .. rhs_ptr[k + 1]) = (halo index h, 4 al + q)
+  const int* rhs_ptr;
+  const int2* rhs_ent;
   // moment table: unnormalised solid harmonics P_lm of the PE offsets over
   // mom_rows rows and n_pe rounded up to 32 points (zeros beyond); FP64 in
   // layout [k/4][row][4] for FP64 plans, split BF16 (hi, lo) in layout
@@ -123,6 +128,8 @@ struct ClassHost {
   std::vector<int> halo_map, col_map, zr_map, pe_map;
   std::vector<int> halo_zidx, halo_zstart;   // orthorhombic: the Dirichlet points by plane
   std::vector<int4> fin_cols;                // orthorhombic: the real columns (slot, zr, x, y)
+  std::vector<int> rhs_ptr;                  // orthorhombic: CSR of the Dirichlet terms per PE slot
+  std::vector<int2> rhs_ent;
   long long n_pe = 0, n_halo = 0, n_me = 0, n_real = 0;
 };
 

@@ -280,8 +280,18 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= C.n_pe) return;
   const double* halo = halo_ws + (long long)bq * hstride;
-  const short4 o = C.me_off[k];
   double acc = 4.0 * kPi * rho_ws[(long long)bq * rstride + k];
+  if (C.rhs_ptr) {
+    // orthorhombic tables: the slot's Dirichlet terms from the plan's CSR
+    // table (dead slots have none, and their density is zero)
+    for (int e = C.rhs_ptr[k]; e < C.rhs_ptr[k + 1]; ++e) {
+      const int2 t = C.rhs_ent[e];
+      acc += g.inv_d2[t.y >> 2] * g.w2[t.y & 3] * halo[t.x];
+    }
+    b_ws[(long long)bq * rstride + k] = acc;
+    return;
+  }
+  const short4 o = C.me_off[k];
   if (g.gen) {
     // every arm of the NK Laplacian (eq. lapG_mod_nk3d), eq. d2_1 along it
     if (!o.w) {
