@@ -94,7 +94,10 @@ typedef struct {
   int solve_depth;            /* planes of loads in flight ahead of use, 1 or 2
                                  (0: tuned/default)                                */
   int autotune;               /* 1: the first exx_eval times the CG variants on a
-                                 sample of its pairs and keeps the fastest          */
+                                 sample of each sphere class's pairs and keeps
+                                 the fastest per class (threads x depth; for
+                                 mixed plans with refine_delta 0 also the
+                                 reliable-update threshold)                        */
   int warm_start;             /* 1: each exx_eval starts a pair's CG from that
                                  pair's solution in the previous exx_eval of the
                                  plan (same i, j and sphere class, shifted by the
@@ -137,7 +140,9 @@ typedef struct {
   /* mixed precision: a reliable update (the FP32 correction folded into the
      FP64 solution and the FP64 true residual recomputed) happens when the
      working residual falls below refine_delta times the residual of the last
-     update (0: 0.01); values in (0, 1).  Each update is an FP64 sweep that
+     update (0: 0.01, or with autotune the fastest of 0.1, 0.01 and 0.001 on
+     each class's sample, reported in exx_stats.class_refine_delta); values
+     in (0, 1).  Each update is an FP64 sweep that
      costs about three CG iterations' worth of memory traffic; smaller values
      mean fewer updates and a few more FP32 iterations */
   double refine_delta;
@@ -290,6 +295,8 @@ typedef struct {
   int class_depth[16];
   int class_layout[16];
   long long class_pairs[16];
+  double class_refine_delta[16];   /* mixed: reliable-update threshold of each class
+                                      (tuned, when the plan leaves it at 0)     */
 } exx_stats;
 
 /* Fluctuating cell (Sec. III B 2): makes h (host [9], column-major,

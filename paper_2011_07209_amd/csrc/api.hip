@@ -330,6 +330,7 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
     a.cls_id = ncls > 1 ? k : -1;
     a.threads = P->class_threads[k];
     a.depth = P->class_depth[k];
+    if (P->class_delta[k] > 0.0) a.delta = P->class_delta[k];   // chosen by the autotuner
     a.quads = C.quads;
     EXX_HIP(P, launch_set_int(P->queue, 0, s));
     long long groups = std::min<long long>(P->class_groups[k], a.npair);
@@ -342,13 +343,17 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
 // Autotuner: for each sphere class with pairs in this batch, times every CG
 // variant (workgroup size x load depth) that can run it on a sample of the
 // class's pairs (one per workgroup of the grid), and keeps the fastest for
-// that class.  The class's current (default) variant is timed first and is
-// replaced only by one at least 3% faster, so that repeated plans settle on
-// the same variant when timings are close.  Densities and boundary values are in the workspace; right-hand
-// sides are rebuilt before each trial (the solve overwrites them) and once
-// more by the caller.
+// that class; mixed plans without a fixed refine_delta then time the chosen
+// variant with reliable-update thresholds of 0.1 and 0.001 beside the default
+// 0.01 (fewer FP64 updates against a few more FP32 iterations).  The class's
+// current (default) choice is timed first and is replaced only by one at
+// least 3% faster, so that repeated plans settle on the same choice when
+// timings are close.  Densities and boundary values are in the workspace;
+// right-hand sides are rebuilt before each trial (the solve overwrites them)
+// and once more by the caller.
 exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hipStream_t s) {
   static const int cand[6][2] = {{1024, 1}, {1024, 2}, {768, 1}, {768, 2}, {512, 1}, {512, 2}};
+  static const double deltas[2] = {0.1, 0.001};
   hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
   EXX_HIP(P, hipEventCreate(&e0));
   EXX_HIP(P, hipEventCreate(&e1));
@@ -364,22 +369,14 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
     const long long lo = std::max(start, base.p0), hi = std::min(start + cc[k], base.p0 + nb);
     start += cc[k];
     if (hi <= lo) continue;
-    float best = 1e30f;
-    int bt = P->class_threads[k], bd = P->class_depth[k];
-    int order[7][2] = {{bt, bd}};
-    int nc = 1;
-    for (const auto& c : cand)
-      if (c[0] != bt || c[1] != bd) {
-        order[nc][0] = c[0];
-        order[nc][1] = c[1];
-        ++nc;
-      }
-    for (int ci = 0; ci < nc; ++ci) {
-      const int* c = order[ci];
-      if (solve_groups_per_cu(P->geo, P->classes[k].n_cols, P->classes[k].Zmax, base.mixed, P->classes[k].quads, c[0],
-                              c[1]) < 1)
-        continue;
-      exx_status st = select_solve(P, c[0], c[1], k);
+    // one trial: the sample's solve time per pair with variant (threads,
+    // depth) and threshold delta, or a negative value when it cannot run
+    auto trial = [&](int threads, int depth, double delta, float* per_pair) -> exx_status {
+      *per_pair = -1.0f;
+      if (solve_groups_per_cu(P->geo, P->classes[k].n_cols, P->classes[k].Zmax, base.mixed, P->classes[k].quads,
+                              threads, depth) < 1)
+        return EXX_OK;
+      exx_status st = select_solve(P, threads, depth, k);
       if (st != EXX_OK) return st;
       st = ensure_slots(P);
       if (st != EXX_OK) return st;
@@ -390,8 +387,9 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
       a.ncls = ncls;
       a.class_cnt = P->pair_count + 2 * P->last_n_orb + 1;
       a.cls_id = ncls > 1 ? k : -1;
-      a.threads = c[0];
-      a.depth = c[1];
+      a.threads = threads;
+      a.depth = depth;
+      a.delta = delta;
       a.quads = P->classes[k].quads;
       Batch B;
       B.cls = P->class_dev;
@@ -410,13 +408,44 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
       EXX_HIP(P, hipEventSynchronize(e1));
       float ms = 0;
       EXX_HIP(P, hipEventElapsedTime(&ms, e0, e1));
-      const float per_pair = ms / (float)sample;
+      *per_pair = ms / (float)sample;
+      return EXX_OK;
+    };
+    const double d0 = P->class_delta[k] > 0.0 ? P->class_delta[k] : base.delta;
+    float best = 1e30f;
+    int bt = P->class_threads[k], bd = P->class_depth[k];
+    int order[7][2] = {{bt, bd}};
+    int nc = 1;
+    for (const auto& c : cand)
+      if (c[0] != bt || c[1] != bd) {
+        order[nc][0] = c[0];
+        order[nc][1] = c[1];
+        ++nc;
+      }
+    for (int ci = 0; ci < nc; ++ci) {
+      float per_pair;
+      exx_status st = trial(order[ci][0], order[ci][1], d0, &per_pair);
+      if (st != EXX_OK) return st;
+      if (per_pair < 0.0f) continue;
       if (ci == 0 ? per_pair < best : per_pair < 0.97f * best) {
         best = per_pair;
-        bt = c[0];
-        bd = c[1];
+        bt = order[ci][0];
+        bd = order[ci][1];
       }
     }
+    double bdelta = d0;
+    if (base.mixed && P->opt.refine_delta <= 0.0) {
+      for (double dl : deltas) {
+        float per_pair;
+        exx_status st = trial(bt, bd, dl, &per_pair);
+        if (st != EXX_OK) return st;
+        if (per_pair >= 0.0f && per_pair < 0.97f * best) {
+          best = per_pair;
+          bdelta = dl;
+        }
+      }
+    }
+    P->class_delta[k] = bdelta;
     exx_status st = select_solve(P, bt, bd, k);
     if (st != EXX_OK) return st;
   }
@@ -711,49 +740,6 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     const size_t entries = (size_t)((C.n_pe + 31) / 32 * 32) * mom_rows;
     return mixed ? 2 * align(entries * sizeof(unsigned short)) : align(entries * sizeof(double));
   };
-  // orthorhombic classes: the Dirichlet points grouped by plane (for the
-  // plane-sweep E/sigma kernel, which stages each plane's far-field values)
-  for (ClassHost& C : classes) {
-    C.halo_zidx.clear();
-    C.halo_zstart.clear();
-    if (general) continue;
-    const int Zh = C.Zmax + n;
-    C.halo_zstart.assign(2 * Zh + 2, 0);
-    for (const short4& o : C.halo_off) C.halo_zstart[o.z + Zh + 1]++;
-    for (int z = 0; z < 2 * Zh + 1; ++z) C.halo_zstart[z + 1] += C.halo_zstart[z];
-    std::vector<int> fill(C.halo_zstart.begin(), C.halo_zstart.end() - 1);
-    C.halo_zidx.assign(C.halo_off.size(), 0);
-    for (size_t h = 0; h < C.halo_off.size(); ++h) C.halo_zidx[fill[C.halo_off[h].z + Zh]++] = (int)h;
-    C.fin_cols.clear();
-    for (int c = 0; c < C.n_cols; ++c)
-      if (C.cols[c].z >= 0) C.fin_cols.push_back(make_int4(c, C.cols[c].z, C.cols[c].x, C.cols[c].y));
-    // the Dirichlet terms of each PE slot's right-hand side: every axis
-    // neighbour within n steps that is not a PE point is a Dirichlet point
-    C.rhs_ptr.assign((size_t)C.n_pe + 1, 0);
-    C.rhs_ent.clear();
-    const int W0 = C.Wm[0], W1 = C.Wm[1];
-    const int cx = C.Rg[0] + n, cy = C.Rg[1] + n, cz = C.Rg[2] + n;
-    auto in_pe = [&](int ox, int oy, int oz) {
-      if (std::abs(ox) > C.Rg[0] || std::abs(oy) > C.Rg[1]) return false;
-      const int zr = C.zr_map[(size_t)(ox + cx) + (size_t)W0 * (oy + cy)];
-      return zr >= 0 && std::abs(oz) <= zr;
-    };
-    for (long long k = 0; k < C.n_pe; ++k) {
-      const short4 o = C.me_off[(size_t)k];
-      if (!o.w) {
-        for (int al = 0; al < 3; ++al)
-          for (int q = 1; q <= n; ++q)
-            for (int sgn = -1; sgn <= 1; sgn += 2) {
-              int u[3] = {o.x, o.y, o.z};
-              u[al] += sgn * q;
-              if (in_pe(u[0], u[1], u[2])) continue;
-              const int h = C.halo_map[(size_t)(u[0] + cx) + (size_t)W0 * ((u[1] + cy) + (size_t)W1 * (u[2] + cz))];
-              if (h >= 0) C.rhs_ent.push_back(make_int2(h, 4 * al + q));
-            }
-      }
-      C.rhs_ptr[(size_t)k + 1] = (int)C.rhs_ent.size();
-    }
-  }
   size_t total = 0;
   for (const ClassHost& C : classes) {
     total += align(C.cols.size() * sizeof(int4)) + align(C.plane_start.size() * sizeof(int)) +
@@ -879,6 +865,7 @@ void default_solve_variants(exx_plan_t P) {
   const int cpt = P->geo.gen ? 4 : 3;
   P->class_threads.assign(P->classes.size(), 1024);
   P->class_depth.assign(P->classes.size(), dp);
+  P->class_delta.assign(P->classes.size(), 0.0);
   for (size_t k = 0; k < P->classes.size(); ++k) {
     if (P->classes[k].quads) {
       // one run per thread; mixed plans take 768 threads where the runs fit
@@ -1627,6 +1614,10 @@ exx_status exx_stats_fetch(exx_plan_t P, exx_stats* out) {
     out->class_depth[k] = P->class_depth[k];
     out->class_layout[k] = P->classes[k].quads ? 2 : 1;
     out->class_pairs[k] = P->last_class_pairs[k];
+    out->class_refine_delta[k] = P->opt.precision != EXX_PREC_MIXED ? 0.0
+                                 : P->class_delta[k] > 0.0       ? P->class_delta[k]
+                                 : P->opt.refine_delta > 0.0     ? P->opt.refine_delta
+                                                                 : 0.01;
   }
   if (st[4] > (double)P->pair_cap)
     return fail(P, EXX_ECAPACITY, "more pairs than the fixed capacity (max_pairs); results cover the first ones");

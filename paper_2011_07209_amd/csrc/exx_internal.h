@@ -140,6 +140,11 @@ struct ClassHost {
 // its tallest column with dead slots, the runs sorted by that height.
 std::string build_class(const double L[3], const int N[3], double R_PE, double R_ME, int n, bool quads,
                         ClassHost* out);
+// The tables of an orthorhombic class's plane-sweep kernels (build_class
+// calls it): the Dirichlet points by plane (halo_zidx, halo_zstart), the real
+// columns (fin_cols) and the CSR of each PE slot's Dirichlet couplings
+// (rhs_ptr, rhs_ent: halo index and 4 * axis + step).
+void build_sweep_tables(int n, ClassHost* out);
 // The same for a general cell h with the NK arms of its Laplacian; the CG
 // sweeps along grid axis `sweep`.
 // all_dirs: Dirichlet points along every nearest-neighbour direction (for
@@ -258,6 +263,7 @@ struct exx_plan_s {
   std::vector<int> class_groups;   // persistent solve workgroups of each class's launch
   std::vector<int> class_threads;  // CG variant of each class: workgroup size ...
   std::vector<int> class_depth;    // ... and load depth
+  std::vector<double> class_delta; // ... and (mixed) reliable-update threshold; 0: the plan's
   int n_cus = 1;
   int solve_threads = 1024, solve_depth = 1;   // CG variant in use
   bool tuned = false;

@@ -97,6 +97,7 @@ class Stats(ctypes.Structure):
         ("class_depth", ctypes.c_int * 16),
         ("class_layout", ctypes.c_int * 16),
         ("class_pairs", ctypes.c_longlong * 16),
+        ("class_refine_delta", ctypes.c_double * 16),
     ]
 
     def as_dict(self):

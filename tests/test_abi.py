@@ -39,16 +39,18 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "exx.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(exx_options), sizeof(exx_stats),'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(exx_options), sizeof(exx_stats),'
                     ' offsetof(exx_options, pair_sample_seed), offsetof(exx_options, solve_groups),'
                     ' offsetof(exx_stats, moment_flops), offsetof(exx_stats, cg_restarts),'
-                    ' offsetof(exx_stats, class_pairs)); return 0;}\n')
+                    ' offsetof(exx_stats, class_pairs), offsetof(exx_options, refine_delta),'
+                    ' offsetof(exx_stats, class_refine_delta)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert out == [ctypes.sizeof(exx.Options), ctypes.sizeof(exx.Stats), exx.Options.pair_sample_seed.offset,
                    exx.Options.solve_groups.offset, exx.Stats.moment_flops.offset, exx.Stats.cg_restarts.offset,
-                   exx.Stats.class_pairs.offset]
+                   exx.Stats.class_pairs.offset, exx.Options.refine_delta.offset,
+                   exx.Stats.class_refine_delta.offset]
 
 
 def test_default_options(lib):
