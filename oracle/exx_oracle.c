@@ -909,7 +909,8 @@ void oracle_box_dims(const oracle_params* P, int* K) {
   for (int a = 0; a < 3; ++a) K[a] = bx.K[a];
 }
 
-/* Fields of a single pair (i, j) on the local box of oracle_box_dims:
+/* Fields of a single pair (i, j) on the local box of oracle_box_dims (half-widths
+   K, so (2K_0+1)(2K_1+1)(2K_2+1) points, x fastest, offset = index - K):
    rho_box (PE only), v_box (PE: CG solution, shell: far field, elsewhere 0),
    mask_box (0 outside ME, 1 shell, 2 PE).  res receives E, sigma and the CG
    diagnostics. */
@@ -1026,7 +1027,8 @@ long oracle_eval(const oracle_params* P, int n_orb, const double* orb, const dou
 }
 
 /* Operator pieces exposed for the stencil and CG checks: A applied on a box
-   with a membership mask (2 = unknown point), and CG on that mask. */
+   with a membership mask (2 = unknown point), and CG on that mask.  K holds
+   the box's half-widths: 2K_a+1 points along axis a, x fastest. */
 static int box_from_dims(const int* K, box_t* bx) {
   for (int a = 0; a < 3; ++a) {
     if (K[a] < 0) return -1;

@@ -255,7 +255,51 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
       }
   C.n_me = (long long)C.me_off.size();
   for (int a = 0; a < 3; ++a) C.Rc[a] = C.Rg[a];
+  build_sweep_tables(n, &C);
   return std::string();
+}
+
+void build_sweep_tables(int n, ClassHost* out) {
+  ClassHost& C = *out;
+  // the Dirichlet points grouped by plane (the plane-sweep E/sigma kernel
+  // stages each plane's far-field values beside its PE values)
+  const int Zh = C.Zmax + n;
+  C.halo_zstart.assign(2 * Zh + 2, 0);
+  for (const short4& o : C.halo_off) C.halo_zstart[o.z + Zh + 1]++;
+  for (int z = 0; z < 2 * Zh + 1; ++z) C.halo_zstart[z + 1] += C.halo_zstart[z];
+  std::vector<int> fill(C.halo_zstart.begin(), C.halo_zstart.end() - 1);
+  C.halo_zidx.assign(C.halo_off.size(), 0);
+  for (size_t h = 0; h < C.halo_off.size(); ++h) C.halo_zidx[fill[C.halo_off[h].z + Zh]++] = (int)h;
+  // the real columns (without the quad layout's padding columns)
+  C.fin_cols.clear();
+  for (int c = 0; c < C.n_cols; ++c)
+    if (C.cols[c].z >= 0) C.fin_cols.push_back(make_int4(c, C.cols[c].z, C.cols[c].x, C.cols[c].y));
+  // the Dirichlet terms of each PE slot's right-hand side: every axis
+  // neighbour within n steps that is not a PE point is a Dirichlet point
+  C.rhs_ptr.assign((size_t)C.n_pe + 1, 0);
+  C.rhs_ent.clear();
+  const int W0 = C.Wm[0], W1 = C.Wm[1];
+  const int cx = C.Rg[0] + n, cy = C.Rg[1] + n, cz = C.Rg[2] + n;
+  auto in_pe = [&](int ox, int oy, int oz) {
+    if (std::abs(ox) > C.Rg[0] || std::abs(oy) > C.Rg[1]) return false;
+    const int zr = C.zr_map[(size_t)(ox + cx) + (size_t)W0 * (oy + cy)];
+    return zr >= 0 && std::abs(oz) <= zr;
+  };
+  for (long long k = 0; k < C.n_pe; ++k) {
+    const short4 o = C.me_off[(size_t)k];
+    if (!o.w) {
+      for (int al = 0; al < 3; ++al)
+        for (int q = 1; q <= n; ++q)
+          for (int sgn = -1; sgn <= 1; sgn += 2) {
+            int u[3] = {o.x, o.y, o.z};
+            u[al] += sgn * q;
+            if (in_pe(u[0], u[1], u[2])) continue;
+            const int h = C.halo_map[(size_t)(u[0] + cx) + (size_t)W0 * ((u[1] + cy) + (size_t)W1 * (u[2] + cz))];
+            if (h >= 0) C.rhs_ent.push_back(make_int2(h, 4 * al + q));
+          }
+    }
+    C.rhs_ptr[(size_t)k + 1] = (int)C.rhs_ent.size();
+  }
 }
 
 void build_moment_table(const ClassHost& C, const double A[9], int l_max, int rows, int group,
