@@ -189,8 +189,14 @@ def _plan(exx, cfg, precision, **kw):
 
 def variants(st):
     """The CG variant of each sphere class, for the record and for failures."""
-    return [{"threads": t, "depth": d, "layout": "quads" if l == 2 else "columns", "pairs": p}
-            for t, d, l, p in zip(st["class_threads"], st["class_depth"], st["class_layout"], st["class_pairs"])]
+    out = []
+    for t, d, l, p, dl in zip(st["class_threads"], st["class_depth"], st["class_layout"], st["class_pairs"],
+                              st["class_refine_delta"]):
+        v = {"threads": t, "depth": d, "layout": "quads" if l == 2 else "columns", "pairs": p}
+        if dl > 0:
+            v["refine_delta"] = dl
+        out.append(v)
+    return out
 
 
 def checked_stats(exx, plan, tag):

@@ -89,8 +89,10 @@ typedef struct {
                                  returns EXX_ECAPACITY                              */
   double workspace_gb;        /* cap on per-batch pair workspace (0: 24 GB)        */
   int solve_groups;           /* persistent solve workgroups (0: as many as fit)   */
-  int solve_threads;          /* CG workgroup size, 512, 768 (quad layout only) or
-                                 1024 (0: tuned/default)                            */
+  int solve_threads;          /* CG workgroup size, 512, 768 or 1024 (0:
+                                 tuned/default); 768 applies to quad-layout
+                                 classes of at most 768 runs only, other classes
+                                 keep their default                              */
   int solve_depth;            /* planes of loads in flight ahead of use, 1 or 2
                                  (0: tuned/default)                                */
   int autotune;               /* 1: the first exx_eval times the CG variants on a
@@ -123,19 +125,20 @@ typedef struct {
      radii (0: never)                                                         */
   double reassemble_strain;
   /* layout of the CG vectors, per sphere class: 0 picks the quad layout for
-     mixed plans (unless solve_threads is 512) for every class where it fits,
-     single columns elsewhere; 1: single columns (each CG thread owns whole
-     columns of the sphere); 2: quad layout for every class (each CG thread
-     owns a run of four adjacent columns, padded with zero slots to the run's
-     tallest column, and reads its in-plane neighbours as 2-point vectors;
-     1024 threads, or 768 for mixed plans where the class has at most 768
-     runs and solve_threads is not 1024: their CG sweeps each pass B together
-     with the next pass A, six vector accesses per point and iteration in
-     place of eight).  A general cell takes it when no Laplacian arm leaves the
-     sweep plane, at most one diagonal arm lies in it, and its columns are
-     symmetric about the sweep plane.  With 2, EXX_EINVAL when a class does
-     not fit (more than 1024 runs, other arms or columns), with
-     cell_fluctuation and with solve_threads 512                              */
+     mixed plans for every class where it fits, single columns elsewhere; 1:
+     single columns (each CG thread owns whole columns of the sphere); 2: quad
+     layout for every class (the sphere's columns in runs of four adjacent
+     columns, padded with zero slots to the run's tallest column; a CG thread
+     owns one run in workgroups of 768 or 1024 threads and two in workgroups
+     of 512, and reads its in-plane neighbours as 2-point vectors).  Mixed
+     plans run quad classes in 768 threads where the class has at most 768
+     runs, else in 512: their CG sweeps each pass B together with the next
+     pass A (six vector accesses per point and iteration in place of eight);
+     with 1024 threads the two passes stay separate.  A general cell takes it
+     when no Laplacian arm leaves the sweep plane, at most one diagonal arm
+     lies in it, and its columns are symmetric about the sweep plane.  With
+     2, EXX_EINVAL when a class does not fit (more than 1024 runs, other arms
+     or columns) and with cell_fluctuation                                     */
   int cg_layout;
   /* mixed precision: a reliable update (the FP32 correction folded into the
      FP64 solution and the FP64 true residual recomputed) happens when the
@@ -262,8 +265,9 @@ typedef struct {
                                   a fused sweep and in a pass B that leaves x
                                   alone, which every other pass B does)            */
   double eval_ms_total;
-  int solve_threads;           /* CG variant in use: workgroup size (768: quad
-                                  layout with fused sweeps) ...                     */
+  int solve_threads;           /* CG variant in use: workgroup size (quad layout:
+                                  768 and 512 with fused sweeps, 512 with two
+                                  runs per thread) ...                             */
   int solve_depth;             /* ... and load depth (chosen by the autotuner)     */
   double tune_ms;              /* time spent by the autotuner (first eval only)    */
   double moment_ms;            /* device time of the moment kernels (last eval)    */

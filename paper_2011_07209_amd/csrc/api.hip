@@ -660,8 +660,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     }
     arms_fit = arms_fit && diagonals <= 1 && !opt.cell_fluctuation;
   }
-  const bool want_quads = arms_fit && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED &&
-                                                              opt.solve_threads != 512));
+  const bool want_quads = arms_fit && (opt.cg_layout == 2 || (opt.cg_layout == 0 && opt.precision == EXX_PREC_MIXED));
   if (opt.cg_layout == 2 && !arms_fit)
     return fail(P, EXX_EINVAL, "quad layout: an arm of the cell's Laplacian leaves the sweep plane, or more than one "
                                "diagonal arm lies in it");
@@ -856,9 +855,11 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
 // Default CG variant of each class (measured on MI355X): 1024 threads up to
 // three columns each for orthorhombic cells (1024 x 4 spills), up to four for
 // general cells (whose passes keep fewer values per column), else 512; quad
-// layout classes one run per thread, 768 threads for mixed plans where the
-// runs fit (fused sweeps), else 1024; FP64 loads one plane ahead, mixed two
-// (cells with arms leaving the sweep plane always load one ahead).
+// layout classes of mixed plans 768 threads (one run each) where the runs fit,
+// else 512 (two runs each), both with fused sweeps; FP64 quad classes 1024
+// threads; an explicit solve_threads that can run the class is kept.  FP64
+// loads one plane ahead, mixed two (512-thread quad classes, and cells with
+// arms leaving the sweep plane, one).
 void default_solve_variants(exx_plan_t P) {
   const exx_options& opt = P->opt;
   const int dp = opt.solve_depth > 0 ? opt.solve_depth : (opt.precision == EXX_PREC_MIXED ? 2 : 1);
@@ -867,14 +868,21 @@ void default_solve_variants(exx_plan_t P) {
   P->class_depth.assign(P->classes.size(), dp);
   P->class_delta.assign(P->classes.size(), 0.0);
   for (size_t k = 0; k < P->classes.size(); ++k) {
+    const int nc = P->classes[k].n_cols;
     if (P->classes[k].quads) {
-      // one run per thread; mixed plans take 768 threads where the runs fit
-      // (their CG then fuses each pass B with the next pass A), else 1024
-      if (opt.precision == EXX_PREC_MIXED && opt.solve_threads != 1024 && P->classes[k].n_cols <= 4 * 768)
-        P->class_threads[k] = 768;
+      // mixed plans fuse each pass B with the next pass A in workgroups of
+      // 768 (one run per thread) or 512 threads (two runs per thread)
+      int t = opt.precision == EXX_PREC_MIXED ? (nc <= 4 * 768 ? 768 : 512) : 1024;
+      if (opt.solve_threads == 512 || opt.solve_threads == 1024 || (opt.solve_threads == 768 && nc <= 4 * 768))
+        t = opt.solve_threads;
+      P->class_threads[k] = t;
+      // two runs per thread: loads one plane ahead (the registers of a
+      // second plane of loads cost more than they hide)
+      if (t == 512 && opt.solve_depth == 0) P->class_depth[k] = 1;
       continue;
     }
-    P->class_threads[k] = opt.solve_threads > 0 ? opt.solve_threads : (P->classes[k].n_cols <= cpt * 1024 ? 1024 : 512);
+    P->class_threads[k] = (opt.solve_threads == 512 || opt.solve_threads == 1024) ? opt.solve_threads
+                          : (nc <= cpt * 1024 ? 1024 : 512);
   }
 }
 
@@ -1043,8 +1051,8 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
     return fail(nullptr, EXX_EINVAL, "too many sphere classes");
   if (opt.max_pairs < 0 || opt.workspace_gb < 0 || opt.solve_groups < 0)
     return fail(nullptr, EXX_EINVAL, "negative capacity option");
-  if (opt.solve_threads != 0 && opt.solve_threads != 512 && opt.solve_threads != 1024)
-    return fail(nullptr, EXX_EINVAL, "solve_threads must be 0, 512 or 1024");
+  if (opt.solve_threads != 0 && opt.solve_threads != 512 && opt.solve_threads != 768 && opt.solve_threads != 1024)
+    return fail(nullptr, EXX_EINVAL, "solve_threads must be 0, 512, 768 or 1024");
   if (opt.solve_depth < 0 || opt.solve_depth > 2) return fail(nullptr, EXX_EINVAL, "solve_depth must be 0, 1 or 2");
   if (opt.warm_start != 0 && opt.warm_start != 1) return fail(nullptr, EXX_EINVAL, "warm_start must be 0 or 1");
   if (opt.warm_start && opt.max_pairs <= 0)
@@ -1056,8 +1064,6 @@ exx_status exx_plan(const double h[9], const int grid[3], double R_pair, double 
   if (opt.cg_layout < 0 || opt.cg_layout > 2) return fail(nullptr, EXX_EINVAL, "cg_layout must be 0, 1 or 2");
   if (opt.cg_layout == 2 && opt.cell_fluctuation)
     return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) is not combined with cell_fluctuation");
-  if (opt.cg_layout == 2 && opt.solve_threads == 512)
-    return fail(nullptr, EXX_EINVAL, "the quad layout (cg_layout 2) runs 1024 threads per workgroup");
 
   exx_plan_t P = new (std::nothrow) exx_plan_s();
   if (!P) return fail(nullptr, EXX_ENOMEM, "host allocation failed");

@@ -957,36 +957,42 @@ __device__ double cg_true_residual_tl(const GenStencilT<double>& S, const ColsG<
 // run's tallest column: plane z holds the runs whose tallest column reaches
 // it, as a prefix of the runs sorted by that height, four slots per run; a
 // slot whose own column is shorter (or lies outside the sphere) is dead and
-// stays zero.  Thread t owns run t.  Its four points of a plane are one
-// 16-byte (FP32) vector in global memory and two 8-byte halves in the LDS
-// plane; the in-plane stencil reads the run's left and right neighbours along
-// x (n <= 3 points each) and the rows y +- q as such halves.  The x neighbours
-// inside the run are the thread's own registers.
+// stays zero.  Thread t owns runs t, t + NT, ... (RQ of them; one in
+// workgroups of 768 or 1024 threads, two in workgroups of 512).  A run's four
+// points of a plane are one 16-byte (FP32) vector in global memory and two
+// 8-byte halves in the LDS plane; the in-plane stencil reads the run's left
+// and right neighbours along x (n <= 3 points each) and the rows y +- q as
+// such halves.  The x neighbours inside the run are the thread's own
+// registers.
 
+template <int RQ>
 struct ColsQ {
-  int zr[4];   // half-height of each column, -1 outside the sphere
-  int zq;      // half-height of the run (max zr), -1 for no run
-  int pos;     // LDS plane position of the run's first column (even)
-  int base;    // offset of the run's slots within a plane (4 t)
+  int zr[RQ][4];   // half-height of each column, -1 outside the sphere
+  int zq[RQ];      // half-height of the run (max zr), -1 for no run
+  int pos[RQ];     // LDS plane position of the run's first column (even)
+  int base[RQ];    // offset of the run's slots within a plane (4 run)
 };
 
-template <int NT>
-__device__ __forceinline__ void load_cols_quad(const ClassDev& C, const SolveKArgs& a, ColsQ& cl) {
-  const int run = threadIdx.x;
-  cl.zq = -1;
-  cl.pos = 0;
-  cl.base = 4 * run;
+template <int NT, int RQ>
+__device__ __forceinline__ void load_cols_quad(const ClassDev& C, const SolveKArgs& a, ColsQ<RQ>& cl) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) cl.zr[j] = -1;
-  if (4 * run < C.n_cols) {
+  for (int u = 0; u < RQ; ++u) {
+    const int run = threadIdx.x + u * NT;
+    cl.zq[u] = -1;
+    cl.pos[u] = 0;
+    cl.base[u] = 4 * run;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int4 cc = C.cols[4 * run + j];
-      cl.zr[j] = cc.z;
-      cl.zq = max(cl.zq, cc.z);
+    for (int j = 0; j < 4; ++j) cl.zr[u][j] = -1;
+    if (4 * run < C.n_cols) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int4 cc = C.cols[4 * run + j];
+        cl.zr[u][j] = cc.z;
+        cl.zq[u] = max(cl.zq[u], cc.z);
+      }
+      const int4 c0 = C.cols[4 * run];
+      cl.pos[u] = (c0.x + a.lds_cx) + kLdsWX * (c0.y + a.lds_cy);
     }
-    const int4 c0 = C.cols[4 * run];
-    cl.pos = (c0.x + a.lds_cx) + kLdsWX * (c0.y + a.lds_cy);
   }
 }
 
@@ -1087,29 +1093,28 @@ __device__ __forceinline__ V4<T> apply_quad(const StencilT<T>& S, const V4<T> (&
   return -(S.diag * win[NS] + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz);
 }
 
-// v at the run's live slots of plane z, 0 at its dead ones
-template <typename T>
-__device__ __forceinline__ V4<T> live_only(const ColsQ& cl, int z, V4<T> v) {
+// v at the live slots of run u in plane z, 0 at its dead ones
+template <typename T, int RQ>
+__device__ __forceinline__ V4<T> live_only(const ColsQ<RQ>& cl, int u, int z, V4<T> v) {
   const int az = abs(z);
-  v.x = az <= cl.zr[0] ? v.x : (T)0;
-  v.y = az <= cl.zr[1] ? v.y : (T)0;
-  v.z = az <= cl.zr[2] ? v.z : (T)0;
-  v.w = az <= cl.zr[3] ? v.w : (T)0;
+  v.x = az <= cl.zr[u][0] ? v.x : (T)0;
+  v.y = az <= cl.zr[u][1] ? v.y : (T)0;
+  v.z = az <= cl.zr[u][2] ? v.z : (T)0;
+  v.w = az <= cl.zr[u][3] ? v.w : (T)0;
   return v;
 }
 
-#define EXX_QVALID(zz) (abs(zz) <= cl.zq)
-#define EXX_QIDX(zz) (pst[(zz) + Zmax] + cl.base)
+#define EXX_QVALID(u, zz) (abs(zz) <= cl.zq[u])
+#define EXX_QIDX(u, zz) (pst[(zz) + Zmax] + cl.base[u])
 
-// Pass A (as cg_pass_a) on the quad layout.  Dead slots hold r = p = 0, so p
-// stays zero there and adds nothing to the dot products.  With RA it also
-// returns r.Ap and |Ap|^2 (Ap kept to the live slots), from which the next
-// residual norm |r - alpha Ap|^2 follows before r is updated; r of the planes
-// z .. z+NS is then kept in registers for the product with Ap of plane z.
+// Pass A (cg_pass_a_quad below) for one run per thread (768 and 1024
+// threads), in a loop of its own: the loop written for RQ runs compiles at
+// RQ = 1 to code that spills registers in the plane loops of the 1024-thread
+// kernels.
 template <int NS, int PD, bool DG, bool RA, typename T>
-__device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax,
-                               const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
-                               double& pq, double& rr, double& ra, double& aa) {
+__device__ void cg_pass_a_quad_one(const StencilT<T>& S, const ColsQ<1>& cl, const int* pst, int Zmax,
+                                   const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
+                                   double& pq, double& rr, double& ra, double& aa) {
   const V4<T> zero = {0, 0, 0, 0};
   V4<T> win[2 * NS + 1];
   V4<T> qr[PD], qp[PD];   // raw r, p of planes z+NS+1 .. z+NS+PD
@@ -1122,8 +1127,8 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
   for (int k = 0; k < 2 * NS + 1; ++k) {
     const int zz = -Zmax - NS + k;
     V4<T> v = zero, rv = zero;
-    if (EXX_QVALID(zz)) {
-      const int idx = EXX_QIDX(zz);
+    if (EXX_QVALID(0, zz)) {
+      const int idx = EXX_QIDX(0, zz);
       rv = ld_quad(r, idx);
       v = first ? rv : rv + beta * ld_quad(p, idx);
       rr += dot4(rv, rv);
@@ -1139,36 +1144,36 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
     const int zz = -Zmax + NS + 1 + d;
     qr[d] = zero;
     qp[d] = zero;
-    if (EXX_QVALID(zz)) {
-      qr[d] = ld_quad(r, EXX_QIDX(zz));
-      if (!first) qp[d] = ld_quad(p, EXX_QIDX(zz));
+    if (EXX_QVALID(0, zz)) {
+      qr[d] = ld_quad(r, EXX_QIDX(0, zz));
+      if (!first) qp[d] = ld_quad(p, EXX_QIDX(0, zz));
     }
   }
   for (int z = -Zmax; z <= Zmax; ++z) {
     const int zl = z + NS + PD + 1;   // plane whose loads are issued now
     V4<T> nr = zero, np = zero;
-    if (EXX_QVALID(zl)) {
-      nr = ld_quad(r, EXX_QIDX(zl));
-      if (!first) np = ld_quad(p, EXX_QIDX(zl));
+    if (EXX_QVALID(0, zl)) {
+      nr = ld_quad(r, EXX_QIDX(0, zl));
+      if (!first) np = ld_quad(p, EXX_QIDX(0, zl));
     }
     T* pl = (z & 1) ? pl1 : pl0;
-    if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
+    if (cl.zq[0] >= 0) lds_quad_store(pl + cl.pos[0], win[NS]);
     __syncthreads();
-    if (EXX_QVALID(z)) {
-      const V4<T> ap = apply_quad<NS, DG, T>(S, win, pl, cl.pos);
+    if (EXX_QVALID(0, z)) {
+      const V4<T> ap = apply_quad<NS, DG, T>(S, win, pl, cl.pos[0]);
       pq += dot4(win[NS], ap);
       if constexpr (RA) {
-        const V4<T> al = live_only(cl, z, ap);
+        const V4<T> al = live_only(cl, 0, z, ap);
         ra += dot4(rw[0], al);
         aa += dot4(al, al);
       }
     }
     const int zc = z + NS + 1;        // plane entering the window
     V4<T> v = zero;
-    if (EXX_QVALID(zc)) {
+    if (EXX_QVALID(0, zc)) {
       v = first ? qr[0] : qr[0] + beta * qp[0];
       rr += dot4(qr[0], qr[0]);
-      st_quad(p, EXX_QIDX(zc), v);
+      st_quad(p, EXX_QIDX(0, zc), v);
     }
 #pragma unroll
     for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
@@ -1176,7 +1181,7 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
     if constexpr (RA) {
 #pragma unroll
       for (int k = 0; k < NS; ++k) rw[k] = rw[k + 1];
-      rw[NS] = EXX_QVALID(zc) ? qr[0] : zero;
+      rw[NS] = EXX_QVALID(0, zc) ? qr[0] : zero;
     }
 #pragma unroll
     for (int d = 0; d + 1 < PD; ++d) {
@@ -1188,66 +1193,189 @@ __device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ& cl, const int*
   }
 }
 
+// Pass A (as cg_pass_a) on the quad layout.  Dead slots hold r = p = 0, so p
+// stays zero there and adds nothing to the dot products.  With RA it also
+// returns r.Ap and |Ap|^2 (Ap kept to the live slots), from which the next
+// residual norm |r - alpha Ap|^2 follows before r is updated; r of the planes
+// z .. z+NS is then kept in registers for the product with Ap of plane z.
+template <int NS, int PD, bool DG, bool RA, typename T, int RQ>
+__device__ void cg_pass_a_quad(const StencilT<T>& S, const ColsQ<RQ>& cl, const int* pst, int Zmax,
+                               const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
+                               double& pq, double& rr, double& ra, double& aa) {
+  if constexpr (RQ == 1) {
+    cg_pass_a_quad_one<NS, PD, DG, RA, T>(S, cl, pst, Zmax, r, p, beta, first, pl0, pl1, pq, rr, ra, aa);
+    return;
+  }
+  const V4<T> zero = {0, 0, 0, 0};
+  V4<T> win[RQ][2 * NS + 1];
+  V4<T> qr[RQ][PD], qp[RQ][PD];   // raw r, p of planes z+NS+1 .. z+NS+PD
+  V4<T> rw[RQ][RA ? NS + 1 : 1];   // with RA: r of planes z .. z+NS
+  pq = 0.0;
+  rr = 0.0;
+  ra = 0.0;
+  aa = 0.0;
+#pragma unroll
+  for (int u = 0; u < RQ; ++u) {
+#pragma unroll
+    for (int k = 0; k < 2 * NS + 1; ++k) {
+      const int zz = -Zmax - NS + k;
+      V4<T> v = zero, rv = zero;
+      if (EXX_QVALID(u, zz)) {
+        const int idx = EXX_QIDX(u, zz);
+        rv = ld_quad(r, idx);
+        v = first ? rv : rv + beta * ld_quad(p, idx);
+        rr += dot4(rv, rv);
+        st_quad(p, idx, v);
+      }
+      win[u][k] = v;
+      if constexpr (RA) {
+        if (k >= NS) rw[u][k - NS] = rv;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int zz = -Zmax + NS + 1 + d;
+      qr[u][d] = zero;
+      qp[u][d] = zero;
+      if (EXX_QVALID(u, zz)) {
+        qr[u][d] = ld_quad(r, EXX_QIDX(u, zz));
+        if (!first) qp[u][d] = ld_quad(p, EXX_QIDX(u, zz));
+      }
+    }
+  }
+  for (int z = -Zmax; z <= Zmax; ++z) {
+    const int zl = z + NS + PD + 1;   // plane whose loads are issued now
+    V4<T> nr[RQ], np[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      nr[u] = zero;
+      np[u] = zero;
+      if (EXX_QVALID(u, zl)) {
+        nr[u] = ld_quad(r, EXX_QIDX(u, zl));
+        if (!first) np[u] = ld_quad(p, EXX_QIDX(u, zl));
+      }
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int u = 0; u < RQ; ++u)
+      if (cl.zq[u] >= 0) lds_quad_store(pl + cl.pos[u], win[u][NS]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      if (EXX_QVALID(u, z)) {
+        const V4<T> ap = apply_quad<NS, DG, T>(S, win[u], pl, cl.pos[u]);
+        pq += dot4(win[u][NS], ap);
+        if constexpr (RA) {
+          const V4<T> al = live_only(cl, u, z, ap);
+          ra += dot4(rw[u][0], al);
+          aa += dot4(al, al);
+        }
+      }
+    }
+    const int zc = z + NS + 1;        // plane entering the window
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      V4<T> v = zero;
+      if (EXX_QVALID(u, zc)) {
+        v = first ? qr[u][0] : qr[u][0] + beta * qp[u][0];
+        rr += dot4(qr[u][0], qr[u][0]);
+        st_quad(p, EXX_QIDX(u, zc), v);
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[u][k] = win[u][k + 1];
+      win[u][2 * NS] = v;
+      if constexpr (RA) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) rw[u][k] = rw[u][k + 1];
+        rw[u][NS] = EXX_QVALID(u, zc) ? qr[u][0] : zero;
+      }
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) {
+        qr[u][d] = qr[u][d + 1];
+        qp[u][d] = qp[u][d + 1];
+      }
+      qr[u][PD - 1] = nr[u];
+      qp[u][PD - 1] = np[u];
+    }
+  }
+}
+
 // Pass B (as cg_pass_b) on the quad layout; the new r is kept to the run's
 // live slots, so dead slots keep r = 0 (and x = 0, since p is zero there).
-template <int NS, int PD, bool DG, bool SKIP, typename T>
-__device__ double cg_pass_b_quad_x(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
+template <int NS, int PD, bool DG, bool SKIP, typename T, int RQ>
+__device__ double cg_pass_b_quad_x(const StencilT<T>& S, const ColsQ<RQ>& cl, const int* pst, int Zmax, T* x,
                                  const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
   const V4<T> zero = {0, 0, 0, 0};
-  V4<T> win[2 * NS + 1];
-  V4<T> qp[PD];              // p of planes z+NS+1 .. z+NS+PD
-  V4<T> cx = zero, cr = zero;   // x, r of plane z
+  V4<T> win[RQ][2 * NS + 1];
+  V4<T> qp[RQ][PD];              // p of planes z+NS+1 .. z+NS+PD
+  V4<T> cx[RQ], cr[RQ];          // x, r of plane z
 #pragma unroll
-  for (int k = 0; k < 2 * NS + 1; ++k) {
-    const int zz = -Zmax - NS + k;
-    win[k] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
-  }
+  for (int u = 0; u < RQ; ++u) {
 #pragma unroll
-  for (int d = 0; d < PD; ++d) {
-    const int zz = -Zmax + NS + 1 + d;
-    qp[d] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
-  }
-  if (EXX_QVALID(-Zmax)) {
-    const int idx = EXX_QIDX(-Zmax);
-    cr = ld_quad(r_in, idx);
-    if (!SKIP && !xs.zero) cx = ld_quad(x, idx);
+    for (int k = 0; k < 2 * NS + 1; ++k) {
+      const int zz = -Zmax - NS + k;
+      win[u][k] = EXX_QVALID(u, zz) ? ld_quad(p, EXX_QIDX(u, zz)) : zero;
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int zz = -Zmax + NS + 1 + d;
+      qp[u][d] = EXX_QVALID(u, zz) ? ld_quad(p, EXX_QIDX(u, zz)) : zero;
+    }
+    cx[u] = zero;
+    cr[u] = zero;
+    if (EXX_QVALID(u, -Zmax)) {
+      const int idx = EXX_QIDX(u, -Zmax);
+      cr[u] = ld_quad(r_in, idx);
+      if (!SKIP && !xs.zero) cx[u] = ld_quad(x, idx);
+    }
   }
   double acc = 0.0;
   for (int z = -Zmax; z <= Zmax; ++z) {
     const int zl = z + NS + PD + 1;
-    V4<T> np = zero, nx = zero, nr = zero;
-    if (EXX_QVALID(zl)) np = ld_quad(p, EXX_QIDX(zl));
-    if (EXX_QVALID(z + 1)) {
-      const int idx = EXX_QIDX(z + 1);
-      nr = ld_quad(r_in, idx);
-      if (!SKIP && !xs.zero) nx = ld_quad(x, idx);
+    V4<T> np[RQ], nx[RQ], nr[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      np[u] = zero;
+      nx[u] = zero;
+      nr[u] = zero;
+      if (EXX_QVALID(u, zl)) np[u] = ld_quad(p, EXX_QIDX(u, zl));
+      if (EXX_QVALID(u, z + 1)) {
+        const int idx = EXX_QIDX(u, z + 1);
+        nr[u] = ld_quad(r_in, idx);
+        if (!SKIP && !xs.zero) nx[u] = ld_quad(x, idx);
+      }
     }
     T* pl = (z & 1) ? pl1 : pl0;
-    if (cl.zq >= 0) lds_quad_store(pl + cl.pos, win[NS]);
+#pragma unroll
+    for (int u = 0; u < RQ; ++u)
+      if (cl.zq[u] >= 0) lds_quad_store(pl + cl.pos[u], win[u][NS]);
     __syncthreads();
-    if (EXX_QVALID(z)) {
-      const int idx = EXX_QIDX(z);
-      const V4<T> rn = live_only(cl, z, cr - alpha * apply_quad<NS, DG, T>(S, win, pl, cl.pos));
-      if constexpr (!SKIP) st_quad(x, idx, cx + xs.ap * win[NS] + xs.ar * cr);
-      st_quad(r, idx, rn);
-      acc += dot4(rn, rn);
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      if (EXX_QVALID(u, z)) {
+        const int idx = EXX_QIDX(u, z);
+        const V4<T> rn = live_only(cl, u, z, cr[u] - alpha * apply_quad<NS, DG, T>(S, win[u], pl, cl.pos[u]));
+        if constexpr (!SKIP) st_quad(x, idx, cx[u] + xs.ap * win[u][NS] + xs.ar * cr[u]);
+        st_quad(r, idx, rn);
+        acc += dot4(rn, rn);
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) win[u][k] = win[u][k + 1];
+      win[u][2 * NS] = qp[u][0];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) qp[u][d] = qp[u][d + 1];
+      qp[u][PD - 1] = np[u];
+      cx[u] = nx[u];
+      cr[u] = nr[u];
     }
-#pragma unroll
-    for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
-    win[2 * NS] = qp[0];
-#pragma unroll
-    for (int d = 0; d + 1 < PD; ++d) qp[d] = qp[d + 1];
-    qp[PD - 1] = np;
-    cx = nx;
-    cr = nr;
   }
   return acc;
 }
 
 // The two forms of pass B as separate loops: one that leaves x alone keeps no
 // x vectors live across the plane loop.
-template <int NS, int PD, bool DG, typename T>
-__device__ __forceinline__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax,
+template <int NS, int PD, bool DG, typename T, int RQ>
+__device__ __forceinline__ double cg_pass_b_quad(const StencilT<T>& S, const ColsQ<RQ>& cl, const int* pst, int Zmax,
                                                  T* x, const T* r_in, T* r, const T* __restrict__ p, T alpha,
                                                  XStep<T> xs, T* pl0, T* pl1) {
   if (xs.skip) return cg_pass_b_quad_x<NS, PD, DG, true, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
@@ -1268,77 +1396,94 @@ __device__ __forceinline__ double cg_pass_b_quad(const StencilT<T>& S, const Col
 // The two z windows take 56 registers per thread (FP32, n = 3), which fit
 // beside the rest only with at most three waves per SIMD (768 threads).
 // Returns |r_k+1|^2 and writes the products of iteration k+1 to out3.
-template <int NS, int PD, bool DG, typename T>
-__device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, const int* pst, int Zmax, T* x,
+template <int NS, int PD, bool DG, typename T, int RQ>
+__device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ<RQ>& cl, const int* pst, int Zmax, T* x,
                                      T* r, T* p, T alpha, T beta, XStep<T> xs, T* la0, T* la1, T* lb0, T* lb1,
                                      double (&out3)[3]) {
   const V4<T> zero = {0, 0, 0, 0};
-  V4<T> wk[2 * NS + 1];      // p_k of planes c - NS .. c + NS
-  V4<T> wn[2 * NS + 1];      // p_k+1 of planes c - 2 NS .. c (the top one formed in the step)
-  V4<T> qp[PD];              // p_k of planes c+NS+1 .. c+NS+PD
-  V4<T> cx = zero, cr = zero;   // x, r of plane c
+  V4<T> wk[RQ][2 * NS + 1];      // p_k of planes c - NS .. c + NS
+  V4<T> wn[RQ][2 * NS + 1];      // p_k+1 of planes c - 2 NS .. c (the top one formed in the step)
+  V4<T> qp[RQ][PD];              // p_k of planes c+NS+1 .. c+NS+PD
+  V4<T> cx[RQ], cr[RQ];          // x, r of plane c
 #pragma unroll
-  for (int k = 0; k < 2 * NS + 1; ++k) {
-    const int zz = -Zmax - NS + k;
-    wk[k] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
-    wn[k] = zero;
-  }
+  for (int u = 0; u < RQ; ++u) {
 #pragma unroll
-  for (int d = 0; d < PD; ++d) {
-    const int zz = -Zmax + NS + 1 + d;
-    qp[d] = EXX_QVALID(zz) ? ld_quad(p, EXX_QIDX(zz)) : zero;
-  }
-  if (EXX_QVALID(-Zmax)) {
-    const int idx = EXX_QIDX(-Zmax);
-    cr = ld_quad(r, idx);
-    if (!xs.zero && !xs.skip) cx = ld_quad(x, idx);
+    for (int k = 0; k < 2 * NS + 1; ++k) {
+      const int zz = -Zmax - NS + k;
+      wk[u][k] = EXX_QVALID(u, zz) ? ld_quad(p, EXX_QIDX(u, zz)) : zero;
+      wn[u][k] = zero;
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int zz = -Zmax + NS + 1 + d;
+      qp[u][d] = EXX_QVALID(u, zz) ? ld_quad(p, EXX_QIDX(u, zz)) : zero;
+    }
+    cx[u] = zero;
+    cr[u] = zero;
+    if (EXX_QVALID(u, -Zmax)) {
+      const int idx = EXX_QIDX(u, -Zmax);
+      cr[u] = ld_quad(r, idx);
+      if (!xs.zero && !xs.skip) cx[u] = ld_quad(x, idx);
+    }
   }
   double rn = 0.0, pq = 0.0, ra = 0.0, aa = 0.0;
   for (int c = -Zmax; c <= Zmax + NS; ++c) {
     const int zl = c + NS + PD + 1;
-    V4<T> np = zero, nx = zero, nr = zero;
-    if (EXX_QVALID(zl)) np = ld_quad(p, EXX_QIDX(zl));
-    if (EXX_QVALID(c + 1)) {
-      const int idx = EXX_QIDX(c + 1);
-      nr = ld_quad(r, idx);
-      if (!xs.zero && !xs.skip) nx = ld_quad(x, idx);
+    V4<T> np[RQ], nx[RQ], nr[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      np[u] = zero;
+      nx[u] = zero;
+      nr[u] = zero;
+      if (EXX_QVALID(u, zl)) np[u] = ld_quad(p, EXX_QIDX(u, zl));
+      if (EXX_QVALID(u, c + 1)) {
+        const int idx = EXX_QIDX(u, c + 1);
+        nr[u] = ld_quad(r, idx);
+        if (!xs.zero && !xs.skip) nx[u] = ld_quad(x, idx);
+      }
     }
     T* la = (c & 1) ? la1 : la0;
     T* lb = (c & 1) ? lb1 : lb0;
-    if (cl.zq >= 0) {
-      lds_quad_store(la + cl.pos, wk[NS]);
-      lds_quad_store(lb + cl.pos, wn[NS]);
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      if (cl.zq[u] >= 0) {
+        lds_quad_store(la + cl.pos[u], wk[u][NS]);
+        lds_quad_store(lb + cl.pos[u], wn[u][NS]);
+      }
     }
     __syncthreads();
-    V4<T> pn = zero;
-    if (EXX_QVALID(c)) {
-      const int idx = EXX_QIDX(c);
-      const V4<T> rn1 = live_only(cl, c, cr - alpha * apply_quad<NS, DG, T>(S, wk, la, cl.pos));
-      pn = rn1 + beta * wk[NS];
-      if (!xs.skip) st_quad(x, idx, cx + xs.ap * wk[NS] + xs.ar * cr);
-      st_quad(r, idx, rn1);
-      st_quad(p, idx, pn);
-      rn += dot4(rn1, rn1);
-    }
-    wn[2 * NS] = pn;
-    const int c2 = c - NS;
-    if (EXX_QVALID(c2)) {
-      const V4<T> ap = live_only(cl, c2, apply_quad<NS, DG, T>(S, wn, lb, cl.pos));
-      pq += dot4(wn[NS], ap);
-      ra += dot4(wn[NS] - beta * wk[0], ap);
-      aa += dot4(ap, ap);
-    }
 #pragma unroll
-    for (int k = 0; k < 2 * NS; ++k) {
-      wk[k] = wk[k + 1];
-      wn[k] = wn[k + 1];
-    }
-    wk[2 * NS] = qp[0];
+    for (int u = 0; u < RQ; ++u) {
+      V4<T> pn = zero;
+      if (EXX_QVALID(u, c)) {
+        const int idx = EXX_QIDX(u, c);
+        const V4<T> rn1 = live_only(cl, u, c, cr[u] - alpha * apply_quad<NS, DG, T>(S, wk[u], la, cl.pos[u]));
+        pn = rn1 + beta * wk[u][NS];
+        if (!xs.skip) st_quad(x, idx, cx[u] + xs.ap * wk[u][NS] + xs.ar * cr[u]);
+        st_quad(r, idx, rn1);
+        st_quad(p, idx, pn);
+        rn += dot4(rn1, rn1);
+      }
+      wn[u][2 * NS] = pn;
+      const int c2 = c - NS;
+      if (EXX_QVALID(u, c2)) {
+        const V4<T> ap = live_only(cl, u, c2, apply_quad<NS, DG, T>(S, wn[u], lb, cl.pos[u]));
+        pq += dot4(wn[u][NS], ap);
+        ra += dot4(wn[u][NS] - beta * wk[u][0], ap);
+        aa += dot4(ap, ap);
+      }
 #pragma unroll
-    for (int d = 0; d + 1 < PD; ++d) qp[d] = qp[d + 1];
-    qp[PD - 1] = np;
-    cx = nx;
-    cr = nr;
+      for (int k = 0; k < 2 * NS; ++k) {
+        wk[u][k] = wk[u][k + 1];
+        wn[u][k] = wn[u][k + 1];
+      }
+      wk[u][2 * NS] = qp[u][0];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) qp[u][d] = qp[u][d + 1];
+      qp[u][PD - 1] = np[u];
+      cx[u] = nx[u];
+      cr[u] = nr[u];
+    }
   }
   out3[0] = pq;
   out3[1] = ra;
@@ -1351,8 +1496,8 @@ __device__ double cg_pass_fused_quad(const StencilT<T>& S, const ColsQ& cl, cons
 // a z window of 2-point FP64 vectors: a window of whole runs in FP64 does not
 // fit the registers of a 1024-thread workgroup (its plane loop spilled to
 // scratch memory).  Each plane still stages the run's four values in LDS.
-template <int NS, bool DG, typename TR>
-__device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& cl, const int* pst, int Zmax,
+template <int NS, bool DG, typename TR, int RQ>
+__device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ<RQ>& cl, const int* pst, int Zmax,
                                         const double* __restrict__ x, const double* __restrict__ b,
                                         TR* __restrict__ r, double rs, double* pl0, double* pl1) {
   using V2d = double __attribute__((ext_vector_type(2)));
@@ -1365,57 +1510,66 @@ __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& 
   double acc = 0.0;
   for (int h = 0; h < 2; ++h) {
     const int off = 2 * h;   // the half's first column within the run
-    V2d win[2 * NS + 1];
+    V2d win[RQ][2 * NS + 1];
 #pragma unroll
-    for (int k = 0; k < 2 * NS + 1; ++k) {
-      const int zz = -Zmax - NS + k;
-      win[k] = EXX_QVALID(zz) ? ld_half(x, EXX_QIDX(zz) + off) : zero2;
-    }
+    for (int u = 0; u < RQ; ++u)
+#pragma unroll
+      for (int k = 0; k < 2 * NS + 1; ++k) {
+        const int zz = -Zmax - NS + k;
+        win[u][k] = EXX_QVALID(u, zz) ? ld_half(x, EXX_QIDX(u, zz) + off) : zero2;
+      }
     for (int z = -Zmax; z <= Zmax; ++z) {
       const int zc = z + NS + 1;        // plane entering the window
-      const V2d nx = EXX_QVALID(zc) ? ld_half(x, EXX_QIDX(zc) + off) : zero2;
-      const V4<double> xq = EXX_QVALID(z) ? ld_quad(x, EXX_QIDX(z)) : zero4;
-      const V2d cb = EXX_QVALID(z) ? ld_half(b, EXX_QIDX(z) + off) : zero2;
+      V2d nx[RQ], cb[RQ];
       double* pl = (z & 1) ? pl1 : pl0;
-      if (cl.zq >= 0) lds_quad_store(pl + cl.pos, xq);
-      __syncthreads();
-      if (EXX_QVALID(z)) {
-        // plane values at x offsets -4 .. 5 from the half's first column
-        const int p = cl.pos + off;
-        const V2d l2 = *reinterpret_cast<const V2d*>(pl + p - 4), l1 = *reinterpret_cast<const V2d*>(pl + p - 2);
-        const V2d r1 = *reinterpret_cast<const V2d*>(pl + p + 2), r2 = *reinterpret_cast<const V2d*>(pl + p + 4);
-        const V2d c = win[NS];
-        const double row[10] = {l2.x, l2.y, l1.x, l1.y, c.x, c.y, r1.x, r1.y, r2.x, r2.y};
-        V2d sx = zero2, sy = zero2, sz = zero2, sdg = zero2;
 #pragma unroll
-        for (int k = 1; k <= NS; ++k) {
-          const V2d up = *reinterpret_cast<const V2d*>(pl + p + k * kLdsWX);
-          const V2d dn = *reinterpret_cast<const V2d*>(pl + p - k * kLdsWX);
-          const V2d xr = {row[4 + k], row[5 + k]}, xl = {row[4 - k], row[5 - k]};
-          sx += S.w[k] * (xr + xl);
-          sy += S.w[k] * (up + dn);
-          sz += S.w[k] * (win[NS + k] + win[NS - k]);
-          if constexpr (DG) {   // the diagonal arm: (x + k, y + s k) and (x - k, y - s k)
-            const int rs_k = S.sd * k * kLdsWX;
-            const V2d f = {pl[p + k + rs_k], pl[p + 1 + k + rs_k]};
-            const V2d bk = {pl[p - k - rs_k], pl[p + 1 - k - rs_k]};
-            sdg += S.w[k] * (f + bk);
-          }
-        }
-        V2d aq = S.diag * c + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz;
-        if constexpr (DG) aq += S.cd * sdg;
-        V2d rt = cb - (-aq);
-        const int az = abs(z);
-        rt.x = az <= cl.zr[off] ? rt.x : 0.0;
-        rt.y = az <= cl.zr[off + 1] ? rt.y : 0.0;
-        const V2d ro = rt * rs;
-        *(EXX_GLOBAL V2r*)((EXX_GLOBAL char*)r + (unsigned)(EXX_QIDX(z) + off) * (unsigned)sizeof(TR)) =
-            V2r{(TR)ro.x, (TR)ro.y};
-        acc += rt.x * rt.x + rt.y * rt.y;
+      for (int u = 0; u < RQ; ++u) {
+        nx[u] = EXX_QVALID(u, zc) ? ld_half(x, EXX_QIDX(u, zc) + off) : zero2;
+        const V4<double> xq = EXX_QVALID(u, z) ? ld_quad(x, EXX_QIDX(u, z)) : zero4;
+        cb[u] = EXX_QVALID(u, z) ? ld_half(b, EXX_QIDX(u, z) + off) : zero2;
+        if (cl.zq[u] >= 0) lds_quad_store(pl + cl.pos[u], xq);
       }
+      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 2 * NS; ++k) win[k] = win[k + 1];
-      win[2 * NS] = nx;
+      for (int u = 0; u < RQ; ++u) {
+        if (EXX_QVALID(u, z)) {
+          // plane values at x offsets -4 .. 5 from the half's first column
+          const int p = cl.pos[u] + off;
+          const V2d l2 = *reinterpret_cast<const V2d*>(pl + p - 4), l1 = *reinterpret_cast<const V2d*>(pl + p - 2);
+          const V2d r1 = *reinterpret_cast<const V2d*>(pl + p + 2), r2 = *reinterpret_cast<const V2d*>(pl + p + 4);
+          const V2d c = win[u][NS];
+          const double row[10] = {l2.x, l2.y, l1.x, l1.y, c.x, c.y, r1.x, r1.y, r2.x, r2.y};
+          V2d sx = zero2, sy = zero2, sz = zero2, sdg = zero2;
+#pragma unroll
+          for (int k = 1; k <= NS; ++k) {
+            const V2d up = *reinterpret_cast<const V2d*>(pl + p + k * kLdsWX);
+            const V2d dn = *reinterpret_cast<const V2d*>(pl + p - k * kLdsWX);
+            const V2d xr = {row[4 + k], row[5 + k]}, xl = {row[4 - k], row[5 - k]};
+            sx += S.w[k] * (xr + xl);
+            sy += S.w[k] * (up + dn);
+            sz += S.w[k] * (win[u][NS + k] + win[u][NS - k]);
+            if constexpr (DG) {   // the diagonal arm: (x + k, y + s k) and (x - k, y - s k)
+              const int rs_k = S.sd * k * kLdsWX;
+              const V2d f = {pl[p + k + rs_k], pl[p + 1 + k + rs_k]};
+              const V2d bk = {pl[p - k - rs_k], pl[p + 1 - k - rs_k]};
+              sdg += S.w[k] * (f + bk);
+            }
+          }
+          V2d aq = S.diag * c + S.c[0] * sx + S.c[1] * sy + S.c[2] * sz;
+          if constexpr (DG) aq += S.cd * sdg;
+          V2d rt = cb[u] - (-aq);
+          const int az = abs(z);
+          rt.x = az <= cl.zr[u][off] ? rt.x : 0.0;
+          rt.y = az <= cl.zr[u][off + 1] ? rt.y : 0.0;
+          const V2d ro = rt * rs;
+          *(EXX_GLOBAL V2r*)((EXX_GLOBAL char*)r + (unsigned)(EXX_QIDX(u, z) + off) * (unsigned)sizeof(TR)) =
+              V2r{(TR)ro.x, (TR)ro.y};
+          acc += rt.x * rt.x + rt.y * rt.y;
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * NS; ++k) win[u][k] = win[u][k + 1];
+        win[u][2 * NS] = nx[u];
+      }
     }
     __syncthreads();   // the next half's first plane reuses the buffer of this half's last one
   }
@@ -1427,13 +1581,14 @@ __device__ double cg_true_residual_quad(const StencilT<double>& S, const ColsQ& 
 
 // Orthorhombic (axis stencil, column or quad layout) or general-cell (NK
 // arms) form of the passes.
+// (quad layout: CPT counts the columns of a thread's runs, 4 per run)
 template <bool GEN, bool QD, int CPT>
-using ColsOf = std::conditional_t<QD, ColsQ, std::conditional_t<GEN, ColsG<CPT>, Cols<CPT>>>;
+using ColsOf = std::conditional_t<QD, ColsQ<(CPT + 3) / 4>, std::conditional_t<GEN, ColsG<CPT>, Cols<CPT>>>;
 
 template <bool GEN, bool QD, int CPT, int NT>
 __device__ __forceinline__ void cols_load(const ClassDev& C, const SolveKArgs& a, ColsOf<GEN, QD, CPT>& cl) {
   if constexpr (QD)
-    load_cols_quad<NT>(C, a, cl);
+    load_cols_quad<NT, (CPT + 3) / 4>(C, a, cl);
   else if constexpr (GEN)
     load_cols_gen<CPT, NT>(C, a, cl);
   else
@@ -1677,9 +1832,10 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   float* y = p + a.sstride;
   const StencilT<float> S32 = stencil_cast<float>(a.S);
   // Quad layout: pass B and the next pass A share a sweep (cg_pass_fused_quad)
-  // in workgroups of up to 768 threads.  Its two z windows need the registers
-  // of at most three waves per SIMD; with four (1024 threads) the sweep spills
-  // to scratch memory and runs slower than the two passes.
+  // in workgroups of up to 768 threads (one run per thread with 768, two with
+  // 512).  Its two z windows need the registers of at most three waves per
+  // SIMD; with four (1024 threads) the sweep spills to scratch memory and runs
+  // slower than the two passes.
   constexpr bool FUSE = QD && NT <= 768;
 
   long long lo, hi;
@@ -1954,8 +2110,18 @@ hipError_t solve_cpt(const SolveKArgs& a, bool mixed, int cpt, int groups, size_
 template <int NS>
 hipError_t solve_ns_dispatch(const SolveKArgs& a, bool mixed, int max_cols, int threads, int depth, int groups,
                              size_t lds, hipStream_t s, int* occ) {
-  if (a.quads) {   // one run of four columns per thread, 768 or 1024 threads (GEN: with a diagonal arm)
-    if ((threads != 768 && threads != 1024) || max_cols > 4 * threads) return hipErrorInvalidValue;
+  if (a.quads) {   // runs of four columns: one per thread with 768 or 1024 threads, two with 512 (GEN: with a
+                   // diagonal arm)
+    if ((threads != 512 && threads != 768 && threads != 1024) || max_cols > 4 * (threads == 512 ? 2 : 1) * threads)
+      return hipErrorInvalidValue;
+    if (threads == 512) {
+      if (a.gen) {
+        if (depth <= 1) return solve_instance_g<NS, 8, 512, 1, true, false, true>(a, mixed, groups, lds, s, occ);
+        return solve_instance_g<NS, 8, 512, 2, true, false, true>(a, mixed, groups, lds, s, occ);
+      }
+      if (depth <= 1) return solve_instance_g<NS, 8, 512, 1, false, false, true>(a, mixed, groups, lds, s, occ);
+      return solve_instance_g<NS, 8, 512, 2, false, false, true>(a, mixed, groups, lds, s, occ);
+    }
     if (threads == 768) {
       if (a.gen) {
         if (depth <= 1) return solve_instance_g<NS, 4, 768, 1, true, false, true>(a, mixed, groups, lds, s, occ);

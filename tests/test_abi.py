@@ -60,7 +60,7 @@ def test_default_options(lib):
 
 
 @pytest.mark.parametrize("case", ["singular", "left_handed", "arm_reach", "rme", "lmax", "stencil", "grid", "tol",
-                                  "layout", "quad_general", "quad_512"])
+                                  "layout", "quad_general", "threads_640"])
 def test_plan_rejects_invalid_arguments(lib, case):
     h = np.diag([12.0, 12.0, 12.0])
     grid, R_pair, R_PE, R_ME, L = (60, 60, 60), 8.0, 5.0, 7.0, 6
@@ -98,9 +98,8 @@ def test_plan_rejects_invalid_arguments(lib, case):
         h = _cell(12.0, 12.5, 11.5, 80, 95, 100)
         grid = (60, 62, 58)
         opt.cg_layout = 2
-    elif case == "quad_512":       # ... and one run per thread of 1024
-        opt.cg_layout = 2
-        opt.solve_threads = 512
+    elif case == "threads_640":    # workgroups of 512, 768 or 1024 threads only
+        opt.solve_threads = 640
     with pytest.raises(exx.ExxError) as ei:
         exx.exx_plan(h, grid, R_pair, R_PE, R_ME, L, opt)
     assert ei.value.status == exx.EXX_EINVAL

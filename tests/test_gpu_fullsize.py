@@ -498,3 +498,43 @@ def test_fused_sweeps_on_a_760_run_sphere():
     _check_pairs("fused 760 runs", cfg, orbs, orb_t, pr, list(range(len(pr["E"]))), tol_E=1e-6, tol_S=1e-6)
     del orb_t
     torch.cuda.empty_cache()
+
+
+def test_two_run_fused_sweeps_on_the_64_molecule_sphere():
+    """The 64-molecule sphere needs more than 768 runs (780), so the mixed
+    plan runs it in 512-thread workgroups with two runs per thread, whose CG
+    fuses pass B with the next pass A.  Every pair of two molecules matches
+    the oracle within the mixed bar, with the same iteration counts as the
+    two-pass 1024-thread kernel and fewer bytes per iteration."""
+    base = synth.CONFIGS["water64"]
+    full = synth.make_orbitals(base)
+    n = 8
+    cfg = dataclasses.replace(base, n_orb=n)
+    orbs = synth.OrbitalSet(full.centres[:n], full.expo[:n], full.poly[:n])
+    runs = _quad_runs(cfg.R_PE, cfg.cell[0] / cfg.grid[0])
+    assert 768 < runs <= 1024, runs
+    orb_t = synth.fill_orbitals_device(cfg, orbs, DEV)
+    cen_t = torch.from_numpy(orbs.centres).to(DEV)
+    out = {}
+    for threads in (0, 1024):
+        plan = _plan(cfg, precision=exx.EXX_PREC_MIXED, solve_threads=threads)
+        try:
+            E = torch.zeros(1, dtype=torch.float64, device=DEV)
+            plan.eval(orb_t, cen_t, E)
+            torch.cuda.synchronize()
+            st = plan.stats()
+            out[threads] = (E.item(), plan.pair_results(), st)
+        finally:
+            plan.close()
+        print(f"[fused {runs} runs] threads {st['class_threads']}: pairs {st['n_pairs']} iterations "
+              f"{st['cg_iter_sum']} bytes/iteration/point {st['cg_alg_bytes'] / st['cg_iter_sum'] / 120473:.2f} "
+              f"E={E.item():.12f}", flush=True)
+        assert st["n_unconverged"] == 0 and st["class_layout"] == [2]
+    fused, plain = out[0][2], out[1024][2]
+    assert fused["class_threads"] == [512] and plain["class_threads"] == [1024]
+    assert abs(fused["cg_iter_sum"] - plain["cg_iter_sum"]) <= 0.02 * plain["cg_iter_sum"] + plain["n_pairs"]
+    assert fused["cg_alg_bytes"] / fused["cg_iter_sum"] < 0.85 * plain["cg_alg_bytes"] / plain["cg_iter_sum"]
+    pr = out[0][1]
+    _check_pairs(f"fused {runs} runs", cfg, orbs, orb_t, pr, list(range(len(pr["E"]))), tol_E=1e-6, tol_S=1e-6)
+    del orb_t
+    torch.cuda.empty_cache()

@@ -181,12 +181,15 @@ def test_mixed_precision_far_pair_with_vanishing_density():
 
 
 @pytest.mark.parametrize("layout,threads,depth", [(1, 1024, 1), (1, 1024, 2), (1, 512, 1), (1, 512, 2),
-                                                  (2, 1024, 1), (2, 1024, 2)])
+                                                  (2, 1024, 1), (2, 1024, 2), (2, 768, 1), (2, 768, 2),
+                                                  (2, 512, 1), (2, 512, 2)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_every_solve_variant(layout, threads, depth, prec):
     """Each CG variant the autotuner may pick (layout: single columns or runs
-    of four, workgroup size x load depth, in both precisions) gives the
-    oracle's result."""
+    of four, workgroup size x load depth, in both precisions; runs of four:
+    one per thread with 768 and 1024 threads, two with 512, with fused
+    sweeps in mixed plans of 512 and 768 threads) gives the oracle's
+    result."""
     cfg = synth.custom(key=f"var-{layout}-{threads}-{depth}-{prec}", cell=(11.0, 12.0, 10.5), grid=(50, 56, 46),
                        n_orb=5, R_pair=7.0, R_PE=3.9, R_ME=5.3, l_max=4, stencil_n=3, cg_tol=1e-12, seed_index=60)
     orbs = synth.make_orbitals(cfg)

@@ -4,7 +4,8 @@ an FP64 plan of the same set was used and closed (its freed device memory is
 what the mixed plan's workspace then receives).
 
 For each CG variant that can run the set's sphere in the quad layout (780 runs
-of four columns: 1024 threads, load depth 1 or 2), forced, three evaluations
+of four columns: 1024 threads with one run each and two passes per iteration,
+or 512 threads with two runs each and fused sweeps; load depth 1 or 2), forced, three evaluations
 must each converge every pair (no iteration cap, breakdown or non-finite
 norm), give bitwise the same E_xx and sigma_xx, and match the FP64 oracle on
 sampled pairs (the strongest non-self pairs among them) within the mixed bar
@@ -65,10 +66,10 @@ def oracle_cache():
     return {}
 
 
-@pytest.mark.parametrize("depth", [1, 2])
-def test_water64_mixed_repeated_evaluations(water64, oracle_cache, depth):
+@pytest.mark.parametrize("threads,depth", [(1024, 1), (1024, 2), (512, 1), (512, 2)])
+def test_water64_mixed_repeated_evaluations(water64, oracle_cache, threads, depth):
     cfg, orbs, orb_t, cen_t = water64
-    plan = _plan(cfg, precision=exx.EXX_PREC_MIXED, solve_threads=1024, solve_depth=depth)
+    plan = _plan(cfg, precision=exx.EXX_PREC_MIXED, solve_threads=threads, solve_depth=depth)
     runs = []
     try:
         E = torch.zeros(1, dtype=torch.float64, device=DEV)
@@ -79,7 +80,7 @@ def test_water64_mixed_repeated_evaluations(water64, oracle_cache, depth):
             torch.cuda.synchronize()
             st = plan.stats(allow_noconv=True)
             pr = plan.pair_results()
-            print(f"[repeat 1024x{depth}] eval {k + 1}: pairs {st['n_pairs']} E={E.item():.12f} unconverged "
+            print(f"[repeat {threads}x{depth}] eval {k + 1}: pairs {st['n_pairs']} E={E.item():.12f} unconverged "
                   f"{st['n_unconverged']} (cap {st['n_cg_cap']}, breakdown {st['n_cg_breakdown']}, non-finite "
                   f"{st['n_cg_nonfinite']}), restarts {st['cg_restarts']}, iterations mean "
                   f"{st['cg_iter_sum'] / st['n_pairs']:.1f} max {st['cg_iter_max']}, updates max "
@@ -87,9 +88,9 @@ def test_water64_mixed_repeated_evaluations(water64, oracle_cache, depth):
                   f"{st['class_layout']}", flush=True)
             bad = np.flatnonzero(pr["exit"] != exx.EXX_CG_CONVERGED)
             for b in bad[:16]:
-                print(f"[repeat 1024x{depth}]   pair {tuple(pr['ij'][b])} exit {pr['exit'][b]} iterations "
+                print(f"[repeat {threads}x{depth}]   pair {tuple(pr['ij'][b])} exit {pr['exit'][b]} iterations "
                       f"{pr['iters'][b]} rel_res {pr['rel_res'][b]:.3e} updates {pr['updates'][b]}", flush=True)
-            assert st["class_threads"] == [1024] and st["class_depth"] == [depth] and st["class_layout"] == [2]
+            assert st["class_threads"] == [threads] and st["class_depth"] == [depth] and st["class_layout"] == [2]
             assert st["n_unconverged"] == 0 and st["n_cg_breakdown"] == 0 and st["n_cg_nonfinite"] == 0
             assert np.all(pr["exit"] == exx.EXX_CG_CONVERGED)
             assert st["max_rel_residual"] <= cfg.cg_tol
@@ -100,7 +101,7 @@ def test_water64_mixed_repeated_evaluations(water64, oracle_cache, depth):
     for Ek, Sk, _ in runs[1:]:
         assert Ek == runs[0][0] and np.array_equal(Sk, runs[0][1])
     pr = runs[-1][2]
-    picks = _sample(pr, 10, 6, 640 + depth)
+    picks = _sample(pr, 10, 6, 640 + depth + threads)
     P = oracle.make_params(cfg.h, cfg.grid, cfg.R_pair, cfg.R_PE, cfg.R_ME, cfg.l_max, cfg.stencil_n, cfg.cg_tol)
     for k in picks:
         i, j = (int(x) for x in pr["ij"][k])
@@ -109,6 +110,6 @@ def test_water64_mixed_repeated_evaluations(water64, oracle_cache, depth):
             f = oracle.pair_fields(P, orb_t[idx].to(torch.float64).cpu().numpy(), orbs.centres[idx], 0, len(idx) - 1)
             oracle_cache[(i, j)] = (f["res"].E, np.array(list(f["res"].sigma)))
         Eo, So = oracle_cache[(i, j)]
-        print(f"[repeat 1024x{depth}] pair ({i},{j}) gpu E={pr['E'][k]:.15g} oracle={Eo:.15g}", flush=True)
+        print(f"[repeat {threads}x{depth}] pair ({i},{j}) gpu E={pr['E'][k]:.15g} oracle={Eo:.15g}", flush=True)
         assert abs(pr["E"][k] - Eo) <= 1e-6 * abs(Eo) + 1e-14
         assert np.abs(pr["sigma"][k] - So).sum() <= 1e-6 * np.abs(So).sum() + 1e-14
