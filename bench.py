@@ -66,7 +66,8 @@ KERNEL_SOURCES = ["paper_2011_07209_amd/csrc/solve_impl.h", "paper_2011_07209_am
                   "paper_2011_07209_amd/csrc/solve_n1.hip", "paper_2011_07209_amd/csrc/solve_n2.hip",
                   "paper_2011_07209_amd/csrc/solve_n3.hip", "paper_2011_07209_amd/csrc/exx_internal.h",
                   "paper_2011_07209_amd/csrc/plan_geometry.cpp"]
-MOLECULES = {"water64": 64, "water128": 128, "water256": 256, "water512": 512, "hex64": 64, "tri64": 64}
+MOLECULES = {"tiny16": 4, "water64": 64, "water128": 128, "water256": 256, "water512": 512, "hex64": 64,
+             "tri64": 64}   # molecule-equivalents (4 orbitals each)
 D_CHECK_ROWS = 16   # orbitals whose D the mixed/FP64 comparison uses
 CPU_SAMPLE_ORBITALS = 32
 DTYPE = {"fp64": "f64", "mixed": "f32+f64 (FP32 CG, FP64 dots and reliable updates; split-bf16 MFMA moments)"}
@@ -125,7 +126,9 @@ def describe(cfg) -> str:
         cell += " (angles " + "/".join(f"{x:.0f}" for x in ang) + " deg, NK Laplacian)"
     radii = (f"R_PE {cfg.R_orb_range[0]:g}-{cfg.R_orb_range[1]:g} per orbital ({cfg.R_PE_classes[2]} classes)"
              if cfg.R_PE_classes else f"R_PE {cfg.R_PE:g}")
-    return (f"{cfg.key}: water-like {MOLECULES[cfg.key]}-molecule set, {cfg.lattice} lattice, cell {cell} bohr, "
+    kind = (f"water-like {MOLECULES[cfg.key]}-molecule set, {cfg.lattice} lattice" if cfg.lattice else
+            "Gaussian-times-polynomial orbitals at uniform random centres")
+    return (f"{cfg.key}: {kind}, cell {cell} bohr, "
             f"{grid} grid, {cfg.n_orb} orbitals ({cfg.orb_dtype}), R_pair {cfg.R_pair:g}, {radii}, "
             f"R_ME {cfg.R_ME:g}, l_max {cfg.l_max}, n {cfg.stencil_n}, CG tol {cfg.cg_tol:g}")
 
