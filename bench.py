@@ -223,10 +223,13 @@ def checked_stats(exx, plan, tag):
     raise CgFailure(f"{tag}: {st['n_unconverged']} pairs did not converge")
 
 
-def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, graph, deadline, warm=False):
+def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, graph, deadline, warm=False,
+                  cmp_step=None):
     """Times up to `steps` evaluations (after up to `warmup`) in one precision,
     cut to what fits before `deadline` (perf_counter seconds); returns the
-    measurement and the outputs of the last evaluation."""
+    measurement and the outputs of the last evaluation (of trajectory step
+    `cmp_step` in graph mode when given, so that two precisions are compared
+    at the same centres)."""
     orb_t, cen_t, R_t, D = bufs
     dev = orb_t.device
     E = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -261,6 +264,7 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
     n_steps = plan_steps(time.perf_counter(), deadline, t_eval, steps)
     step_ms, step_pairs, step_iters, step_warm = [], [], [], []
     s_last = None
+    snap = None
     if graph:
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -289,6 +293,8 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
             step_iters.append(st["cg_iter_sum"] / max(1, st["n_pairs"]))
             step_warm.append(st["warm_pairs"])
             s_last = st
+            if k + 1 == (cmp_step or n_steps):
+                snap = (k + 1, E.item(), S.cpu().numpy().reshape(3, 3, order="F"), D[:D_CHECK_ROWS].double().cpu())
             print(f"[bench] {cfg.key} {precision} replay {k + 1}/{n_steps}: {step_ms[-1]:.1f} ms, {st['n_pairs']} pairs "
                   f"({st['warm_pairs']} warm-started), mean iterations {step_iters[-1]:.1f}, E={E.item():.10f}",
                   file=sys.stderr, flush=True)
@@ -341,7 +347,7 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
                    "launch_ms": s_last["moment_ms"]}
     plan.close()
     n_pairs = s_last["n_pairs"]
-    return {
+    out = {
         "value": value, "ms_per_step": ms, "n_pairs": n_pairs, "n_pe": geo["n_pe"],
         "steps": n_steps, "warmup": n_warm,
         "eval_ms_median": statistics.median(step_ms), "eval_ms_steps": step_ms,
@@ -357,6 +363,11 @@ def run_precision(exx, torch, synth, cfg, orbs, bufs, precision, steps, warmup, 
         "E": E.item(), "sigma": S.cpu().numpy().reshape(3, 3, order="F"),
         "D_rows": D[:D_CHECK_ROWS].double().cpu(),
     }
+    if graph:   # the outputs of the compared trajectory step (None: this run did not reach it)
+        out["compared_step"] = snap[0] if snap else None
+        if snap:
+            out["E"], out["sigma"], out["D_rows"] = snap[1], snap[2], snap[3]
+    return out
 
 
 def main(argv=None):
@@ -425,8 +436,10 @@ def main(argv=None):
             # the FP64 phase takes half of what is left; the mixed phase the rest
             now = time.perf_counter()
             deadline = now + (deadline_all - now) * (0.5 if k + 1 < len(precs) else 1.0)
+            # graph mode: compare the precisions at the trajectory step the first one ended on
+            cmp = res[precs[0]]["steps"] if graph and k > 0 else None
             res[p] = run_precision(exx, torch, synth, cfg, orbs, (orb_t, cen_t, R_t, D), p, steps, args.warmup,
-                                   graph, deadline, warm=graph and not args.no_warm_start)
+                                   graph, deadline, warm=graph and not args.no_warm_start, cmp_step=cmp)
     except CgFailure as e:
         print(f"[bench] FAILED: {e}", file=sys.stderr, flush=True)
         return 3
@@ -434,7 +447,7 @@ def main(argv=None):
     r = res[main_p]
 
     accuracy = None
-    if "fp64" in res and "mixed" in res:
+    if "fp64" in res and "mixed" in res and (not graph or res["mixed"].get("compared_step")):
         a, b = res["mixed"], res["fp64"]
         n_mol = MOLECULES[cfg.key]
         dd = (a["D_rows"] - b["D_rows"]).abs().reshape(D_CHECK_ROWS, -1)
@@ -448,6 +461,8 @@ def main(argv=None):
             "D_rows_compared": D_CHECK_ROWS,
             "targets": {"dE_Ha_per_molecule": 1e-6, "sigma_rel_1norm": 1e-6},
         }
+        if graph:
+            accuracy["trajectory_step"] = a["compared_step"]
 
     if args.copy_probe_gib > 0:
         nbytes = int(args.copy_probe_gib * (1 << 30))

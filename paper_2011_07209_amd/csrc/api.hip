@@ -747,7 +747,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
              align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) +
              align(C.halo_zidx.size() * sizeof(int)) + align(C.halo_zstart.size() * sizeof(int)) +
              align(C.fin_cols.size() * sizeof(int4)) + align(C.rhs_ptr.size() * sizeof(int)) +
-             align(C.rhs_ent.size() * sizeof(int2)) + mom_bytes(C);
+             align(C.rhs_ent.size() * sizeof(int2)) + align(C.me_scan.size() * sizeof(int)) + mom_bytes(C);
   }
   void* block = nullptr;
   ClassDev* class_dev = nullptr;
@@ -799,6 +799,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.n_fin = (int)C.fin_cols.size();
     D.rhs_ptr = (const int*)put(C.rhs_ptr.data(), C.rhs_ptr.size() * sizeof(int));
     D.rhs_ent = (const int2*)put(C.rhs_ent.data(), C.rhs_ent.size() * sizeof(int2));
+    D.me_scan = (const int*)put(C.me_scan.data(), C.me_scan.size() * sizeof(int));
+    D.n_scan = (long long)C.me_scan.size();
     D.mom_rows = mom_rows;
     std::vector<double> tab;
     build_moment_table(C, g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);
@@ -816,7 +818,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
       D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
       tab_ok = D.mom_f64 != nullptr;
     }
-    if (!D.cols || !D.plane_start || !D.me_off || !D.halo_map || (!general && (!D.col_map || !D.zr_map)) ||
+    if (!D.cols || !D.plane_start || !D.me_off || !D.me_scan || !D.halo_map || (!general && (!D.col_map || !D.zr_map)) ||
         (general != (D.pe_map != nullptr)) || !tab_ok)
       return give_up(EXX_EDEVICE, "upload of the subdomain tables failed");
     class_dev_host.push_back(D);

@@ -96,6 +96,10 @@ struct ClassDev {
   // rhs_ent[rhs_ptr[k] .. rhs_ptr[k + 1]) = (halo index h, 4 al + q)
   const int* rhs_ptr;
   const int2* rhs_ent;
+  // the live entries of me_off (no dead slots) in grid raster order of their
+  // offsets (z, then y, then x), n_scan of them: the D scatter's order
+  const int* me_scan;
+  long long n_scan;
   // moment table: unnormalised solid harmonics P_lm of the PE offsets over
   // mom_rows rows and n_pe rounded up to 32 points (zeros beyond); FP64 in
   // layout [k/4][row][4] for FP64 plans, split BF16 (hi, lo) in layout
@@ -130,6 +134,7 @@ struct ClassHost {
   std::vector<int4> fin_cols;                // orthorhombic: the real columns (slot, zr, x, y)
   std::vector<int> rhs_ptr;                  // orthorhombic: CSR of the Dirichlet terms per PE slot
   std::vector<int2> rhs_ent;
+  std::vector<int> me_scan;                  // the live ME entries in grid raster order (z, y, x)
   long long n_pe = 0, n_halo = 0, n_me = 0, n_real = 0;
 };
 
@@ -145,6 +150,8 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
 // columns (fin_cols) and the CSR of each PE slot's Dirichlet couplings
 // (rhs_ptr, rhs_ent: halo index and 4 * axis + step).
 void build_sweep_tables(int n, ClassHost* out);
+// The D scatter's order of a class (both builders call it): me_scan.
+void build_scan_order(ClassHost* out);
 // The same for a general cell h with the NK arms of its Laplacian; the CG
 // sweeps along grid axis `sweep`.
 // all_dirs: Dirichlet points along every nearest-neighbour direction (for

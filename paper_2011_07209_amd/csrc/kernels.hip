@@ -428,13 +428,15 @@ __global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restr
   const ClassDev& C = cls[P.cls];
   if (threadIdx.x < NLM) Q[threadIdx.x] = Q_ws[(long long)b * kMaxLM + threadIdx.x];
   __syncthreads();
+  // the ME points in grid raster order, so that a wavefront's orbital reads
+  // and D updates fall on consecutive addresses along x
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= C.n_me) return;
-  const short4 o = C.me_off[k];
-  if (o.w) return;   // dead slot
+  if (k >= C.n_scan) return;
+  const int e = C.me_scan[k];
+  const short4 o = C.me_off[e];
   double rx, ry, rz;
   rbar_of(g, o, &rx, &ry, &rz);
-  const double v = (k < C.n_pe) ? v_ws[(long long)b * rstride + k] : far_field<L>(rx, ry, rz, g.ylm_norm, Q);
+  const double v = (e < C.n_pe) ? v_ws[(long long)b * rstride + e] : far_field<L>(rx, ry, rz, g.ylm_norm, Q);
   const int gx = wrapi(P.c[0] + o.x, g.N[0]);
   const int gy = wrapi(P.c[1] + o.y, g.N[1]);
   const int gz = wrapi(P.c[2] + o.z, g.N[2]);

@@ -256,7 +256,22 @@ std::string build_class(const double L[3], const int N[3], double R_PE, double R
   C.n_me = (long long)C.me_off.size();
   for (int a = 0; a < 3; ++a) C.Rc[a] = C.Rg[a];
   build_sweep_tables(n, &C);
+  build_scan_order(&C);
   return std::string();
+}
+
+void build_scan_order(ClassHost* out) {
+  ClassHost& C = *out;
+  C.me_scan.clear();
+  C.me_scan.reserve(C.me_off.size());
+  for (size_t k = 0; k < C.me_off.size(); ++k)
+    if (!C.me_off[k].w) C.me_scan.push_back((int)k);
+  std::sort(C.me_scan.begin(), C.me_scan.end(), [&](int a, int b) {
+    const short4 p = C.me_off[(size_t)a], q = C.me_off[(size_t)b];
+    if (p.z != q.z) return p.z < q.z;
+    if (p.y != q.y) return p.y < q.y;
+    return p.x < q.x;
+  });
 }
 
 void build_sweep_tables(int n, ClassHost* out) {
@@ -540,6 +555,7 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
         C.me_off.push_back(make_short4((short)o0, (short)o1, (short)o2, 0));
       }
   C.n_me = (long long)C.me_off.size();
+  build_scan_order(&C);
   return std::string();
 }
 

@@ -354,8 +354,8 @@ __device__ void cg_pass_a(const StencilT<T>& S, const Cols<CPT>& cl, const int* 
 // residual is read from r_in and written to r (they may alias); x is updated
 // as xs says (see XStep); with xs.zero the old x is taken as zero (and x may
 // alias r_in: each point is read before it is written, by the same thread).
-template <int NS, int CPT, int PD, typename T>
-__device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, T* x,
+template <int NS, int CPT, int PD, bool SKIP, typename T>
+__device__ double cg_pass_b_x(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax, T* x,
                             const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs, T* pl0, T* pl1) {
   T win[CPT][2 * NS + 1];
   T qp[PD][CPT];           // p of planes z+NS+1 .. z+NS+PD
@@ -379,7 +379,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
     if (EXX_VALID(c, -Zmax)) {
       const unsigned idx = EXX_IDX(c, -Zmax);
       cr[c] = gload(r_in, idx);
-      if (!xs.zero && !xs.skip) cx[c] = gload(x, idx);
+      if (!SKIP && !xs.zero) cx[c] = gload(x, idx);
     }
   }
   double acc = 0.0;
@@ -394,7 +394,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
       if (EXX_VALID(c, z + 1)) {
         const unsigned idx = EXX_IDX(c, z + 1);
         nr[c] = gload(r_in, idx);
-        if (!xs.zero && !xs.skip) nx[c] = gload(x, idx);
+        if (!SKIP && !xs.zero) nx[c] = gload(x, idx);
       }
     }
     T* pl = (z & 1) ? pl1 : pl0;
@@ -408,7 +408,7 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
         const unsigned idx = EXX_IDX(c, z);
         const T q = apply_point<NS, T>(S, win[c][NS], pl, cl.pos[c], win[c]);
         const T rn = cr[c] - alpha * q;
-        if (!xs.skip) gstore(x, idx, cx[c] + xs.ap * win[c][NS] + xs.ar * cr[c]);
+        if constexpr (!SKIP) gstore(x, idx, cx[c] + xs.ap * win[c][NS] + xs.ar * cr[c]);
         gstore(r, idx, rn);
         acc += (double)rn * (double)rn;
       }
@@ -426,6 +426,16 @@ __device__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int
     }
   }
   return acc;
+}
+
+// The two forms of pass B as separate loops (as on the quad layout): one
+// that leaves x alone keeps no x values live across the plane loop.
+template <int NS, int CPT, int PD, typename T>
+__device__ __forceinline__ double cg_pass_b(const StencilT<T>& S, const Cols<CPT>& cl, const int* pst, int Zmax,
+                                            T* x, const T* r_in, T* r, const T* __restrict__ p, T alpha, XStep<T> xs,
+                                            T* pl0, T* pl1) {
+  if (xs.skip) return cg_pass_b_x<NS, CPT, PD, true, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
+  return cg_pass_b_x<NS, CPT, PD, false, T>(S, cl, pst, Zmax, x, r_in, r, p, alpha, xs, pl0, pl1);
 }
 
 // Reliable update of the mixed-precision solve, in FP64, second half: with the

@@ -2,8 +2,9 @@
 // general cells in both layouts, the NK arms, the moment tables) for a build
 // with AddressSanitizer and UndefinedBehaviorSanitizer, and checks the
 // invariants every table entry must satisfy on the way: indices in range,
-// planes stored as prefixes, each PE point once.  Exits non-zero on a failed
-// check (the sanitizers abort on their own findings).
+// planes stored as prefixes, each PE point once, the D scatter's raster
+// order.  Exits non-zero on a failed check (the sanitizers abort on their own
+// findings).
 #include <cmath>
 #include <cstdio>
 #include <set>
@@ -43,6 +44,20 @@ void check_class(const exx::ClassHost& C, int n, const char* name) {
     check(seen.insert(((long long)o.x * 4096 + o.y) * 4096 + o.z).second, "PE point stored once", name);
   }
   check(real == C.n_real || C.n_real == 0, "real point count", name);
+  // the D scatter's order: every live ME entry once, in raster order (z, y, x)
+  long long live = 0;
+  for (const short4& o : C.me_off) live += o.w ? 0 : 1;
+  check((long long)C.me_scan.size() == live, "scan order holds every live ME entry", name);
+  std::set<int> scanned;
+  for (size_t k = 0; k < C.me_scan.size(); ++k) {
+    const int e = C.me_scan[k];
+    check(e >= 0 && e < (int)C.me_off.size() && !C.me_off[e].w, "scan entry is a live ME entry", name);
+    check(scanned.insert(e).second, "scan entry once", name);
+    if (k > 0) {
+      const short4 p = C.me_off[C.me_scan[k - 1]], q = C.me_off[e];
+      check(p.z < q.z || (p.z == q.z && (p.y < q.y || (p.y == q.y && p.x < q.x))), "scan in raster order", name);
+    }
+  }
   if (!C.general) {
     check((int)C.halo_zstart.size() == 2 * (C.Zmax + n) + 2, "halo_zstart size", name);
     check((long long)C.halo_zidx.size() == C.n_halo, "halo_zidx holds every Dirichlet point", name);
