@@ -111,6 +111,14 @@ static hipError_t solve_dispatch(const SolveArgs& in, int max_cols, int max_zmax
     }
     a.G.diag = in.g.w2[0] * sum;
   }
+  for (int q = 0; q < 4; ++q) {
+    a.G.czw[q] = a.G.cz * a.G.w[q];
+    for (int k = 0; k < 3; ++k) a.G.tl_cw[k][q] = a.G.tl_coef[k] * a.G.w[q];
+  }
+  for (int q = 0; q < 4; ++q) {
+    a.G32.czw[q] = (float)a.G.czw[q];
+    for (int k = 0; k < 3; ++k) a.G32.tl_cw[k][q] = (float)a.G.tl_cw[k][q];
+  }
   for (int q = 0; q < 4; ++q) a.G32.w[q] = (float)a.G.w[q];
   a.G32.cz = (float)a.G.cz;
   a.G32.diag = (float)a.G.diag;

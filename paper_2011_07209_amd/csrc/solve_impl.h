@@ -94,6 +94,8 @@ struct GenStencilT {
   T in_coef[3];
   int tl_off[3];  // arms leaving the plane: LDS offset of one step (with z' + 1)
   T tl_coef[3];
+  T tl_cw[3][4];  // tl_coef[k] * w[q], and cz * w[q] (made on the host, rounded once)
+  T czw[4];
 };
 
 // Loads and stores of the CG vectors (global memory) at a 32-bit element
@@ -534,11 +536,12 @@ __device__ __forceinline__ T gen_inplane(const GenStencilT<T>& S, T ctr, const T
 #pragma unroll
   for (int q = 1; q <= NS; ++q) sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
   T s = S.diag * ctr + S.cz * sz;
+  const T* bp = pl + pos;   // the point's slot: each neighbour is one add of a uniform offset
   for (int k = 0; k < S.n_in; ++k) {
     const int off = S.in_off[k];
     T t = 0;
 #pragma unroll
-    for (int q = 1; q <= NS; ++q) t += S.w[q] * (pl[pos + q * off] + pl[pos - q * off]);
+    for (int q = 1; q <= NS; ++q) t += S.w[q] * (bp[q * off] + bp[-q * off]);
     s += S.in_coef[k] * t;
   }
   return s;
@@ -550,13 +553,18 @@ __device__ __forceinline__ T gen_inplane(const GenStencilT<T>& S, T ctr, const T
 template <int NS, int DL, typename T>
 __device__ __forceinline__ void gen_tilted(const GenStencilT<T>& S, const T* pl, int pos, T* acc) {
   if constexpr (DL > 0) {
-    for (int k = 0; k < S.n_tl; ++k) {
+    const T* bp = pl + pos;   // the point's slot: each neighbour is one add of a uniform offset
+    // at most three arms leave the plane: the loop unrolls, with a uniform
+    // test per arm slot (measured on tri64: the mixed CG 9% faster; unrolling
+    // the in-plane arm loop as well made it slower again)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k >= S.n_tl) break;
       const int off = S.tl_off[k];
-      const T cf = S.tl_coef[k];
 #pragma unroll
       for (int q = 1; q <= NS; ++q) {
-        acc[DL - q] += cf * S.w[q] * pl[pos + q * off];
-        acc[DL + q] += cf * S.w[q] * pl[pos - q * off];
+        acc[DL - q] += S.tl_cw[k][q] * bp[q * off];
+        acc[DL + q] += S.tl_cw[k][q] * bp[-q * off];
       }
     }
   }
@@ -769,11 +777,12 @@ template <int NS, typename T>
 __device__ __forceinline__ void tl_scatter(const GenStencilT<T>& S, T v, bool point, const T* pl, int pos, T* acc) {
   if (point) {   // the point (column, z') exists: centre and in-plane arms
     T s = S.diag * v;
+    const T* bp = pl + pos;
     for (int k = 0; k < S.n_in; ++k) {
       const int off = S.in_off[k];
       T t = 0;
 #pragma unroll
-      for (int q = 1; q <= NS; ++q) t += S.w[q] * (pl[pos + q * off] + pl[pos - q * off]);
+      for (int q = 1; q <= NS; ++q) t += S.w[q] * (bp[q * off] + bp[-q * off]);
       s += S.in_coef[k] * t;
     }
     acc[NS] += s;
@@ -782,7 +791,7 @@ __device__ __forceinline__ void tl_scatter(const GenStencilT<T>& S, T v, bool po
   // neighbour of the point q planes up
 #pragma unroll
   for (int q = 1; q <= NS; ++q) {
-    const T t = S.cz * S.w[q] * v;
+    const T t = S.czw[q] * v;
     acc[NS - q] += t;
     acc[NS + q] += t;
   }
