@@ -536,13 +536,17 @@ double cell_strain(const double h[9], const double h0[9]) {
   return m;
 }
 
-// Moment tables of every class for the plan's current offset map, into the
-// class block (same sizes as at assembly).
+// Moment and boundary tables of every class for the plan's current offset
+// map, into the class block (same sizes as at assembly).
 exx_status upload_moment_tables(exx_plan_t P, const Geo& g) {
   const bool mixed = P->opt.precision == EXX_PREC_MIXED;
   int mom_rows = 0, mom_mfma_rows = 0;
   moment_layout(P->l_max, mixed, &mom_rows, &mom_mfma_rows);
   for (size_t k = 0; k < P->classes.size(); ++k) {
+    std::vector<double> btab;
+    build_boundary_table(P->classes[k], g.A, g.ylm_norm, P->l_max, &btab);
+    EXX_HIP(P, hipMemcpy((void*)P->class_dev_host[k].bnd_tab, btab.data(), btab.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
     std::vector<double> tab;
     build_moment_table(P->classes[k], g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);
     const ClassDev& D = P->class_dev_host[k];
@@ -747,7 +751,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
              align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) +
              align(C.halo_zidx.size() * sizeof(int)) + align(C.halo_zstart.size() * sizeof(int)) +
              align(C.fin_cols.size() * sizeof(int4)) + align(C.rhs_ptr.size() * sizeof(int)) +
-             align(C.rhs_ent.size() * sizeof(int2)) + align(C.me_scan.size() * sizeof(int)) + mom_bytes(C);
+             align(C.rhs_ent.size() * sizeof(int2)) + align(C.me_scan.size() * sizeof(int)) + mom_bytes(C) +
+             align((size_t)((C.n_halo + 15) / 16) * ((g.n_lm + 3) / 4) * 64 * sizeof(double));
   }
   void* block = nullptr;
   ClassDev* class_dev = nullptr;
@@ -802,6 +807,9 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.me_scan = (const int*)put(C.me_scan.data(), C.me_scan.size() * sizeof(int));
     D.n_scan = (long long)C.me_scan.size();
     D.mom_rows = mom_rows;
+    std::vector<double> btab;
+    build_boundary_table(C, g.A, g.ylm_norm, P->l_max, &btab);
+    D.bnd_tab = (const double*)put(btab.data(), btab.size() * sizeof(double));
     std::vector<double> tab;
     build_moment_table(C, g.A, P->l_max, mom_rows, mixed ? 8 : 4, &tab);
     bool tab_ok;
@@ -818,7 +826,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
       D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
       tab_ok = D.mom_f64 != nullptr;
     }
-    if (!D.cols || !D.plane_start || !D.me_off || !D.me_scan || !D.halo_map || (!general && (!D.col_map || !D.zr_map)) ||
+    if (!D.cols || !D.plane_start || !D.me_off || !D.me_scan || !D.bnd_tab || !D.halo_map ||
+        (!general && (!D.col_map || !D.zr_map)) ||
         (general != (D.pe_map != nullptr)) || !tab_ok)
       return give_up(EXX_EDEVICE, "upload of the subdomain tables failed");
     class_dev_host.push_back(D);
@@ -1349,7 +1358,8 @@ exx_status exx_eval(exx_plan_t P, int n_orb, const void* orbitals, exx_dtype dt,
     EXX_HIP(P, launch_moments(g, B, P->pair_count + 2 * n_orb + 1, ncls, mixed, P->rho_ws, P->rstride, P->rho_scale,
                               P->Qp_ws, moment_splits(B.nb, ncls, P->max_pe), P->Q_ws, s));
     if (launch_events) { exx_status es = record_moment_event(P, s); if (es != EXX_OK) return es; }
-    EXX_HIP(P, launch_boundary(g, B, P->max_halo, P->Q_ws, P->halo_ws, std::max<long long>(P->max_halo, 1), s));
+    EXX_HIP(P, launch_boundary(g, B, P->pair_count + 2 * n_orb + 1, ncls, P->max_halo, P->Q_ws, P->halo_ws,
+                               std::max<long long>(P->max_halo, 1), s));
     SolveArgs a;
     a.g = g;
     a.cls = P->class_dev;

@@ -105,6 +105,11 @@ struct ClassDev {
   // layout [k/4][row][4] for FP64 plans, split BF16 (hi, lo) in layout
   // [k/8][row][8] for mixed plans
   int mom_rows;
+  // boundary table: the far field's kernel at the Dirichlet points,
+  // 4 pi / (2l + 1) R_lm(rbar_h) / |rbar_h|^(2l + 1), FP64 in the operand order of
+  // the matrix cores: [h / 16][lm / 4][lm mod 4][h mod 16] over (l_max + 1)^2 rows
+  // rounded up to 4 and n_halo rounded up to 16 (zeros beyond)
+  const double* bnd_tab;
   const double* mom_f64;
   const unsigned short* mom_hi;
   const unsigned short* mom_lo;
@@ -168,6 +173,10 @@ std::string build_nk_arms(const double h[9], const int N[3], std::vector<NkArm>*
 // rounded up to 32, zeros in the padding and at dead slots.
 void build_moment_table(const ClassHost& C, const double A[9], int l_max, int rows, int group,
                         std::vector<double>* out);
+// The boundary table of a class (see ClassDev::bnd_tab) for the grid map A
+// (rbar = A o) and the harmonic normalisation norm.
+void build_boundary_table(const ClassHost& C, const double A[9], const double* norm, int l_max,
+                          std::vector<double>* out);
 
 // The device workspace of an evaluation that the plan holds pointers to: the
 // plan's own allocations, or, for exx_eval_noalloc, pieces of the library's

@@ -54,8 +54,10 @@ int moment_splits(long long nb, int ncls, long long max_pe);
 hipError_t launch_moments(const Geo& g, const Batch& B, const int* class_cnt, int ncls, bool mixed,
                           const double* rho_ws, long long rstride, const double* rho_scale, double* Qp, int splits,
                           double* Q_ws, hipStream_t s);
-hipError_t launch_boundary(const Geo& g, const Batch& B, long long max_halo, const double* Q_ws, double* halo_ws,
-                           long long hstride, hipStream_t s);
+// Far-field values at the Dirichlet points of every pair of the batch, from
+// its moments and the class's boundary table, on the matrix cores.
+hipError_t launch_boundary(const Geo& g, const Batch& B, const int* class_cnt, int ncls, long long max_halo,
+                           const double* Q_ws, double* halo_ws, long long hstride, hipStream_t s);
 
 struct SolveArgs {
   Geo g;

@@ -1,11 +1,9 @@
 // gfx950 kernels of the EXX pair path (the CG itself is in solve_impl.h, the
-// moment contraction in moments.hip).
+// moment and boundary contractions in moments.hip).
 //
 //   k_pair_count / k_pair_scan / k_pair_fill   unique pair list (Sec. III A Step II)
 //   k_pair_order                                processing order, largest spheres first
 //   k_gather                                    pair density on PE (Step III)
-//   k_boundary                                  far-field values at the Dirichlet points
-//                                               (Sec. I, eq. me)
 //   k_rhs                                       CG right-hand side 4 pi rho plus the
 //                                               Dirichlet terms of eq. d2_1
 //   k_finalize                                  the pair's E_xx and sigma_xx (eq. exxGen_mlwf,
@@ -220,28 +218,6 @@ __global__ __launch_bounds__(256) void k_gather(Geo g, const ClassDev* __restric
     if (amax > 0.0) (void)frexp(amax, &e);
     rho_scale[b] = ldexp(1.0, e);
   }
-}
-
-template <int L>
-__global__ __launch_bounds__(256) void k_boundary(Geo g, const ClassDev* __restrict__ cls,
-                                                  const PairDev* __restrict__ pairs, const int* __restrict__ order,
-                                                  long long p0, const int* __restrict__ n_eff,
-                                                  const double* __restrict__ Q_ws, double* __restrict__ halo_ws,
-                                                  long long hstride) {
-  constexpr int NLM = (L + 1) * (L + 1);
-  __shared__ double Q[NLM];
-  const int b = blockIdx.y;
-  if (p0 + b >= *n_eff) return;
-  const PairDev P = pairs[order[p0 + b]];
-  const ClassDev& C = cls[P.cls];
-  if (threadIdx.x < NLM) Q[threadIdx.x] = Q_ws[(long long)b * kMaxLM + threadIdx.x];
-  __syncthreads();
-  const long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= C.n_halo) return;
-  const short4 o = C.halo_off[h];
-  double x, y, z;
-  rbar_of(g, o, &x, &y, &z);
-  halo_ws[(long long)b * hstride + h] = far_field<L>(x, y, z, g.ylm_norm, Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -659,15 +635,6 @@ hipError_t launch_gather(const Geo& g, const Batch& B, const void* orb, int dt, 
   else
     k_gather<float><<<(unsigned)B.nb, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, (const float*)orb,
                                                    rho_ws, rstride, rho_scale);
-  return hipGetLastError();
-}
-
-hipError_t launch_boundary(const Geo& g, const Batch& B, long long max_halo, const double* Q_ws, double* halo_ws,
-                           long long hstride, hipStream_t s) {
-  if (B.nb <= 0 || max_halo <= 0) return hipSuccess;
-  dim3 grid((unsigned)((max_halo + 255) / 256), (unsigned)B.nb);
-  EXX_L_DISPATCH(g.l_max, (k_boundary<LL><<<grid, 256, 0, s>>>(g, B.cls, B.pairs, B.order, B.p0, B.n_eff, Q_ws,
-                                                               halo_ws, hstride)));
   return hipGetLastError();
 }
 

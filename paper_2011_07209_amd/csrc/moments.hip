@@ -284,6 +284,52 @@ __global__ __launch_bounds__(256) void k_moment_sum(Geo g, const double* __restr
   Q_ws[b * kMaxLM + lm] = g.dV * g.ylm_norm[lm] * sc * s;
 }
 
+// The far field at the Dirichlet points (Sec. I, eq. me) as a contraction on
+// the matrix cores: V[pair][h] = sum_lm Q[pair][lm] T[lm][h], with T the
+// class's boundary table.  A workgroup takes a 64-pair tile of one class (16
+// pairs per wavefront, the A operand: Q of pair (lane mod 16) at
+// lm = 4 s + lane / 16, kept in registers) and a chunk of the class's 16-point
+// tiles of Dirichlet points (the B operand: one coalesced 64-value row of
+// the table per k step).  v_mfma_f64_16x16x4_f64 leaves V[pair 4 u + lane / 16]
+// [point lane mod 16] in item u.
+template <int L>
+__global__ __launch_bounds__(256) void k_boundary_f64(const ClassDev* __restrict__ cls_tab,
+                                                      const int* __restrict__ class_cnt, int ncls, long long pbeg,
+                                                      long long pend, const int* __restrict__ n_eff,
+                                                      const double* __restrict__ Q_ws, double* __restrict__ halo_ws,
+                                                      long long hstride) {
+  constexpr int NLM = (L + 1) * (L + 1), S = (NLM + 3) / 4;
+  int cls;
+  long long tb, te;
+  if (!locate_tile(class_cnt, ncls, pbeg, pend, n_eff, &cls, &tb, &te)) return;
+  const ClassDev& C = cls_tab[cls];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const long long pa = tb + 16 * wave + col;   // this lane's pair of the A operand
+  double q[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int lm = 4 * s + kq;
+    q[s] = (pa < te && lm < NLM) ? Q_ws[(pa - pbeg) * kMaxLM + lm] : 0.0;
+  }
+  long long t0, t1;
+  chunk_range((C.n_halo + 15) / 16, &t0, &t1);
+  for (long long t = t0; t < t1; ++t) {
+    const double* tab = C.bnd_tab + t * (S * 64) + lane;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(q[s], tab[s * 64], acc, 0, 0, 0);
+    const long long h = 16 * t + col;
+    if (h < C.n_halo) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long p = tb + 16 * wave + 4 * u + kq;
+        if (p < te) halo_ws[(p - pbeg) * hstride + h] = acc[u];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void moment_layout(int l_max, bool mixed, int* rows, int* mfma_rows) {
@@ -306,6 +352,28 @@ int moment_splits(long long nb, int ncls, long long max_pe) {
   const long long max_chunks = std::max<long long>(1, max_pe / 2048);   // at least 2048 points per chunk
   s = std::min(s, std::min<long long>(max_chunks, 32));
   return (int)std::max<long long>(s, 1);
+}
+
+hipError_t launch_boundary(const Geo& g, const Batch& B, const int* class_cnt, int ncls, long long max_halo,
+                           const double* Q_ws, double* halo_ws, long long hstride, hipStream_t s) {
+  const long long nb = B.nb, pbeg = B.p0;
+  if (nb <= 0 || max_halo <= 0) return hipSuccess;
+  const long long tiles = (nb + kTilePairs - 1) / kTilePairs + ncls - 1;
+  // chunks of Dirichlet-point tiles: about 2048 workgroups in all
+  const long long htiles = (max_halo + 15) / 16;
+  const long long splits = std::max<long long>(1, std::min<long long>(htiles, (2048 + tiles - 1) / tiles));
+  const dim3 grid((unsigned)tiles, (unsigned)splits);
+  const long long pend = pbeg + nb;
+  switch (g.l_max) {
+#define EXX_BND(LL)                                                                                              \
+  case LL:                                                                                                       \
+    k_boundary_f64<LL><<<grid, 256, 0, s>>>(B.cls, class_cnt, ncls, pbeg, pend, B.n_eff, Q_ws, halo_ws, hstride); \
+    break;
+    EXX_BND(0) EXX_BND(1) EXX_BND(2) EXX_BND(3) EXX_BND(4) EXX_BND(5) EXX_BND(6) EXX_BND(7) EXX_BND(8)
+#undef EXX_BND
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_moments(const Geo& g, const Batch& B, const int* class_cnt, int ncls, bool mixed,

@@ -335,6 +335,31 @@ void build_moment_table(const ClassHost& C, const double A[9], int l_max, int ro
   }
 }
 
+void build_boundary_table(const ClassHost& C, const double A[9], const double* norm, int l_max,
+                          std::vector<double>* out) {
+  const int nlm = (l_max + 1) * (l_max + 1), steps = (nlm + 3) / 4;
+  const long long tiles = (C.n_halo + 15) / 16;
+  out->assign((size_t)(tiles * steps * 64), 0.0);
+  std::vector<double> v(kMaxLM, 0.0);
+  for (long long h = 0; h < C.n_halo; ++h) {
+    const short4 o = C.halo_off[(size_t)h];
+    const double x = A[0] * o.x + A[3] * o.y + A[6] * o.z;
+    const double y = A[1] * o.x + A[4] * o.y + A[7] * o.z;
+    const double z = A[2] * o.x + A[5] * o.y + A[8] * o.z;
+    solid_harmonics_host(l_max, x, y, z, norm, v.data());
+    const double rinv = 1.0 / std::sqrt(x * x + y * y + z * z);
+    double rp = rinv;   // |r|^-(2l + 1)
+    for (int l = 0; l <= l_max; ++l) {
+      for (int m = -l; m <= l; ++m) {
+        const int lm = l * l + l + m;
+        const double t = v[lm] * rp * (4.0 * 3.14159265358979323846 / (2.0 * l + 1.0));
+        (*out)[(size_t)(((h / 16) * steps + lm / 4) * 64 + (lm % 4) * 16 + (h % 16))] = t;
+      }
+      rp *= rinv * rinv;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // General (non-orthogonal) cells, Sec. III B 1: the PE sphere is the set of
 // grid offsets o with |r(o)| <= R_PE, r(o) = sum_al (o_al / N_al) L_al, an
