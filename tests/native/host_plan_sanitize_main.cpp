@@ -1,6 +1,6 @@
 // Drives the plan-time host code (sphere-class tables of orthorhombic and
-// general cells in both layouts, the NK arms, the moment tables) for a build
-// with AddressSanitizer and UndefinedBehaviorSanitizer, and checks the
+// general cells in both layouts, the NK arms, the moment and boundary tables)
+// for a build with AddressSanitizer and UndefinedBehaviorSanitizer, and checks the
 // invariants every table entry must satisfy on the way: indices in range,
 // planes stored as prefixes, each PE point once, the D scatter's raster
 // order.  Exits non-zero on a failed check (the sanitizers abort on their own
@@ -70,6 +70,16 @@ void check_class(const exx::ClassHost& C, int n, const char* name) {
   }
 }
 
+void boundary(const exx::ClassHost& C, const double A[9], const char* name) {
+  std::vector<double> norm(exx::kMaxLM, 1.0), tab;
+  for (int l_max : {0, 6, 8}) {
+    exx::build_boundary_table(C, A, norm.data(), l_max, &tab);
+    const long long steps = ((l_max + 1) * (l_max + 1) + 3) / 4;
+    check((long long)tab.size() == (C.n_halo + 15) / 16 * steps * 64, "boundary table size", name);
+    for (double v : tab) check(std::isfinite(v), "boundary table finite", name);
+  }
+}
+
 void moments(const exx::ClassHost& C, const double A[9], const char* name) {
   for (int group : {4, 8}) {
     std::vector<double> tab;
@@ -101,6 +111,7 @@ int main() {
         if (!e.empty()) continue;
         check_class(C, n, name);
         moments(C, A, name);
+        boundary(C, A, name);
       }
 
   // triclinic: NK arms, then the general tables along each sweep axis
@@ -126,6 +137,7 @@ int main() {
         if (!e.empty()) continue;
         check_class(C, 3, name);
         moments(C, Ag, name);
+        boundary(C, Ag, name);
       }
 
   // a monoclinic cell whose columns are symmetric about the sweep plane
