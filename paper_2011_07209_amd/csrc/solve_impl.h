@@ -536,12 +536,11 @@ __device__ __forceinline__ T gen_inplane(const GenStencilT<T>& S, T ctr, const T
 #pragma unroll
   for (int q = 1; q <= NS; ++q) sz += S.w[q] * (wz[NS + q] + wz[NS - q]);
   T s = S.diag * ctr + S.cz * sz;
-  const T* bp = pl + pos;   // the point's slot: each neighbour is one add of a uniform offset
   for (int k = 0; k < S.n_in; ++k) {
     const int off = S.in_off[k];
     T t = 0;
 #pragma unroll
-    for (int q = 1; q <= NS; ++q) t += S.w[q] * (bp[q * off] + bp[-q * off]);
+    for (int q = 1; q <= NS; ++q) t += S.w[q] * (pl[pos + q * off] + pl[pos - q * off]);
     s += S.in_coef[k] * t;
   }
   return s;
