@@ -751,7 +751,8 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
              align(C.zr_map.size() * sizeof(int)) + align(C.pe_map.size() * sizeof(int)) +
              align(C.halo_zidx.size() * sizeof(int)) + align(C.halo_zstart.size() * sizeof(int)) +
              align(C.fin_cols.size() * sizeof(int4)) + align(C.rhs_ptr.size() * sizeof(int)) +
-             align(C.rhs_ent.size() * sizeof(int2)) + align(C.me_scan.size() * sizeof(int)) + mom_bytes(C) +
+             align(C.rhs_ent.size() * sizeof(int2)) + align(C.me_scan.size() * sizeof(int)) +
+             align(C.scan_off.size() * sizeof(short4)) + mom_bytes(C) +
              align((size_t)((C.n_halo + 15) / 16) * ((g.n_lm + 3) / 4) * 64 * sizeof(double));
   }
   void* block = nullptr;
@@ -805,6 +806,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.rhs_ptr = (const int*)put(C.rhs_ptr.data(), C.rhs_ptr.size() * sizeof(int));
     D.rhs_ent = (const int2*)put(C.rhs_ent.data(), C.rhs_ent.size() * sizeof(int2));
     D.me_scan = (const int*)put(C.me_scan.data(), C.me_scan.size() * sizeof(int));
+    D.scan_off = (const short4*)put(C.scan_off.data(), C.scan_off.size() * sizeof(short4));
     D.n_scan = (long long)C.me_scan.size();
     D.mom_rows = mom_rows;
     std::vector<double> btab;
@@ -826,7 +828,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
       D.mom_f64 = (const double*)put(tab.data(), tab.size() * sizeof(double));
       tab_ok = D.mom_f64 != nullptr;
     }
-    if (!D.cols || !D.plane_start || !D.me_off || !D.me_scan || !D.bnd_tab || !D.halo_map ||
+    if (!D.cols || !D.plane_start || !D.me_off || !D.me_scan || !D.scan_off || !D.bnd_tab || !D.halo_map ||
         (!general && (!D.col_map || !D.zr_map)) ||
         (general != (D.pe_map != nullptr)) || !tab_ok)
       return give_up(EXX_EDEVICE, "upload of the subdomain tables failed");

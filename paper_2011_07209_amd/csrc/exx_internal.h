@@ -97,8 +97,11 @@ struct ClassDev {
   const int* rhs_ptr;
   const int2* rhs_ent;
   // the live entries of me_off (no dead slots) in grid raster order of their
-  // offsets (z, then y, then x), n_scan of them: the D scatter's order
+  // offsets (z, then y, then x), n_scan of them: the D scatter's order; and
+  // their offsets in that order (so that a point's offset and entry are two
+  // independent loads)
   const int* me_scan;
+  const short4* scan_off;
   long long n_scan;
   // moment table: unnormalised solid harmonics P_lm of the PE offsets over
   // mom_rows rows and n_pe rounded up to 32 points (zeros beyond); FP64 in
@@ -140,6 +143,7 @@ struct ClassHost {
   std::vector<int> rhs_ptr;                  // orthorhombic: CSR of the Dirichlet terms per PE slot
   std::vector<int2> rhs_ent;
   std::vector<int> me_scan;                  // the live ME entries in grid raster order (z, y, x)
+  std::vector<short4> scan_off;              // their offsets, in that order
   long long n_pe = 0, n_halo = 0, n_me = 0, n_real = 0;
 };
 

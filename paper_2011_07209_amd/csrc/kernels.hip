@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_dscatter(Geo g, const ClassDev* __restr
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= C.n_scan) return;
   const int e = C.me_scan[k];
-  const short4 o = C.me_off[e];
+  const short4 o = C.scan_off[k];
   double rx, ry, rz;
   rbar_of(g, o, &rx, &ry, &rz);
   const double v = (e < C.n_pe) ? v_ws[(long long)b * rstride + e] : far_field<L>(rx, ry, rz, g.ylm_norm, Q);

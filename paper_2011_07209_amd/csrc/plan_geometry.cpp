@@ -272,6 +272,8 @@ void build_scan_order(ClassHost* out) {
     if (p.y != q.y) return p.y < q.y;
     return p.x < q.x;
   });
+  C.scan_off.resize(C.me_scan.size());
+  for (size_t k = 0; k < C.me_scan.size(); ++k) C.scan_off[k] = C.me_off[(size_t)C.me_scan[k]];
 }
 
 void build_sweep_tables(int n, ClassHost* out) {

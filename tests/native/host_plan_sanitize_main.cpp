@@ -48,6 +48,11 @@ void check_class(const exx::ClassHost& C, int n, const char* name) {
   long long live = 0;
   for (const short4& o : C.me_off) live += o.w ? 0 : 1;
   check((long long)C.me_scan.size() == live, "scan order holds every live ME entry", name);
+  check(C.scan_off.size() == C.me_scan.size(), "scan offsets beside the scan order", name);
+  for (size_t k = 0; k < C.scan_off.size() && k < C.me_scan.size(); ++k) {
+    const short4 a = C.scan_off[k], b = C.me_off[(size_t)C.me_scan[k]];
+    check(a.x == b.x && a.y == b.y && a.z == b.z, "scan offset of its entry", name);
+  }
   std::set<int> scanned;
   for (size_t k = 0; k < C.me_scan.size(); ++k) {
     const int e = C.me_scan[k];
