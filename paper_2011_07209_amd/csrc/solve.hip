@@ -20,7 +20,7 @@ size_t solve_lds_bytes(const Geo& g, int max_zmax) {
 }
 
 long long solve_slot_bytes(bool mixed, long long sstride) {
-  const long long b = mixed ? 20 * sstride : 16 * sstride;
+  const long long b = mixed ? 24 * sstride : 16 * sstride;
   return (b + 255) & ~255LL;
 }
 

@@ -797,13 +797,18 @@ __device__ __forceinline__ void tl_scatter(const GenStencilT<T>& S, T v, bool po
   gen_tilted<NS, NS, T>(S, pl, pos, acc);
 }
 
-template <int NS, int CPT, typename T>
+// With QS (the fused sweeps below), pass A also stores Ap in q and forms
+// r.Ap and |Ap|^2 (r of the completed point kept in a window like p).
+template <int NS, int CPT, typename T, bool QS = false>
 __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax,
                              const T* __restrict__ r, T* __restrict__ p, T beta, bool first, T* pl0, T* pl1,
-                             double& pq, double& rr) {
+                             double& pq, double& rr, T* __restrict__ q = nullptr, double* ra = nullptr,
+                             double* aa = nullptr) {
   T pd[CPT][NS + 1];       // p of planes z - n .. z
+  T rd[CPT][QS ? NS + 1 : 1];   // (QS) r of planes z - n .. z
   T acc[CPT][2 * NS + 1];
   T cr[CPT], cp[CPT];      // r and the previous p of plane z
+  double sra = 0.0, saa = 0.0;
   pq = 0.0;
   rr = 0.0;
 #pragma unroll
@@ -812,6 +817,8 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
     for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0;
 #pragma unroll
     for (int k = 0; k < NS + 1; ++k) pd[c][k] = 0;
+#pragma unroll
+    for (int k = 0; k < (QS ? NS + 1 : 1); ++k) rd[c][k] = 0;
     cr[c] = 0;
     cp[c] = 0;
     if (EXX_GVALID(c, -Zmax)) {
@@ -842,6 +849,7 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
         rr += (double)cr[c] * (double)cr[c];
       }
       pd[c][NS] = v;
+      if constexpr (QS) rd[c][NS] = EXX_GVALID(c, z) ? cr[c] : (T)0;
       if (EXX_GHAS(c)) pl[cl.pos[c]] = v;
     }
     __syncthreads();
@@ -849,15 +857,31 @@ __device__ void cg_pass_a_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, cons
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (EXX_GHAS(c)) tl_scatter<NS, T>(S, pd[c][NS], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
-      if (EXX_GVALID(c, zo)) pq -= (double)pd[c][0] * (double)acc[c][0];
+      if (EXX_GVALID(c, zo)) {
+        pq -= (double)pd[c][0] * (double)acc[c][0];
+        if constexpr (QS) {
+          const T ap = -acc[c][0];
+          gstore(q, EXX_GIDX(c, zo), ap);
+          sra += (double)rd[c][0] * (double)ap;
+          saa += (double)ap * (double)ap;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < 2 * NS; ++k) acc[c][k] = acc[c][k + 1];
       acc[c][2 * NS] = 0;
 #pragma unroll
       for (int k = 0; k < NS; ++k) pd[c][k] = pd[c][k + 1];
+      if constexpr (QS) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) rd[c][k] = rd[c][k + 1];
+      }
       cr[c] = nr[c];
       cp[c] = np[c];
     }
+  }
+  if constexpr (QS) {
+    *ra = sra;
+    *aa = saa;
   }
 }
 
@@ -916,6 +940,110 @@ __device__ double cg_pass_b_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, co
     }
   }
   return sum;
+}
+
+// Pass B of iteration k and pass A of k+1 in one sweep, for the tilted-arm
+// form, with Ap kept in q between sweeps: the scatter form completes a point's
+// Ap only n planes after the point, so (unlike the quad sweep, which forms
+// Ap_k again from a window of p_k) the sweep cannot recompute Ap_k in time for
+// r_k+1 = r_k - alpha Ap_k at the plane it reaches.  Storing it instead keeps
+// one stencil per iteration and as many vector accesses as the two passes
+// (r, p, q in and out; x every other iteration, see XStep).  Along the sweep,
+// plane z: r_k+1 = r_k - alpha q_k, p_k+1 = r_k+1 + beta p_k (beta from
+// |r_k - alpha Ap_k|^2, known before the sweep), x += ap p_k + ar r_k; then
+// p_k+1 enters the plane's scatter, and the point n planes behind completes
+// Ap_k+1 for q, p_k+1.Ap_k+1, r_k+1.Ap_k+1 and |Ap_k+1|^2.  Returns |r_k+1|^2
+// and writes the three products of iteration k+1 to out3.
+template <int NS, int CPT, typename T>
+__device__ double cg_pass_fused_tl(const GenStencilT<T>& S, const ColsG<CPT>& cl, const int* pst, int Zmax, T* x,
+                                   T* r, T* p, T* q, T alpha, T beta, XStep<T> xs, T* pl0, T* pl1,
+                                   double (&out3)[3]) {
+  T pd[CPT][NS + 1];       // p_k+1 of planes z - n .. z
+  T rd[CPT][NS + 1];       // r_k+1 of planes z - n .. z
+  T acc[CPT][2 * NS + 1];
+  T cr[CPT], cp[CPT], cq[CPT];   // r_k, p_k, Ap_k of plane z
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+    for (int k = 0; k < 2 * NS + 1; ++k) acc[c][k] = 0;
+#pragma unroll
+    for (int k = 0; k < NS + 1; ++k) {
+      pd[c][k] = 0;
+      rd[c][k] = 0;
+    }
+    cr[c] = 0;
+    cp[c] = 0;
+    cq[c] = 0;
+    if (EXX_GVALID(c, -Zmax)) {
+      const unsigned idx = EXX_GIDX(c, -Zmax);
+      cr[c] = gload(r, idx);
+      cp[c] = gload(p, idx);
+      cq[c] = gload(q, idx);
+    }
+  }
+  double rn = 0.0, pq = 0.0, ra = 0.0, aa = 0.0;
+  for (int z = -Zmax; z <= Zmax + NS; ++z) {
+    T nr[CPT], np[CPT], nq[CPT], ox[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      nr[c] = 0;
+      np[c] = 0;
+      nq[c] = 0;
+      ox[c] = 0;
+      if (EXX_GVALID(c, z + 1)) {
+        const unsigned idx = EXX_GIDX(c, z + 1);
+        nr[c] = gload(r, idx);
+        np[c] = gload(p, idx);
+        nq[c] = gload(q, idx);
+      }
+      if (!xs.zero && !xs.skip && EXX_GVALID(c, z)) ox[c] = gload(x, EXX_GIDX(c, z));
+    }
+    T* pl = (z & 1) ? pl1 : pl0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      T rv = 0, pv = 0;
+      if (EXX_GVALID(c, z)) {
+        const unsigned idx = EXX_GIDX(c, z);
+        rv = cr[c] - alpha * cq[c];
+        pv = rv + beta * cp[c];
+        gstore(r, idx, rv);
+        gstore(p, idx, pv);
+        rn += (double)rv * (double)rv;
+      }
+      rd[c][NS] = rv;
+      pd[c][NS] = pv;
+      if (EXX_GHAS(c)) pl[cl.pos[c]] = pv;
+    }
+    __syncthreads();
+    const int zo = z - NS;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (!xs.skip && EXX_GVALID(c, z)) gstore(x, EXX_GIDX(c, z), ox[c] + xs.ap * cp[c] + xs.ar * cr[c]);
+      if (EXX_GHAS(c)) tl_scatter<NS, T>(S, pd[c][NS], EXX_GVALID(c, z), pl, cl.pos[c], acc[c]);
+      if (EXX_GVALID(c, zo)) {
+        const T ap = -acc[c][0];
+        gstore(q, EXX_GIDX(c, zo), ap);
+        pq += (double)pd[c][0] * (double)ap;
+        ra += (double)rd[c][0] * (double)ap;
+        aa += (double)ap * (double)ap;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * NS; ++k) acc[c][k] = acc[c][k + 1];
+      acc[c][2 * NS] = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        pd[c][k] = pd[c][k + 1];
+        rd[c][k] = rd[c][k + 1];
+      }
+      cr[c] = nr[c];
+      cp[c] = np[c];
+      cq[c] = nq[c];
+    }
+  }
+  out3[0] = pq;
+  out3[1] = ra;
+  out3[2] = aa;
+  return rn;
 }
 
 template <int NS, int CPT, typename TR>
@@ -1832,7 +1960,11 @@ template <int NS, int CPT, int NT, int PD, bool GEN, bool TL, bool QD>
 __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[NT / 64];
-  __shared__ double red4[QD ? 4 * (NT / 64) : 1];
+  // Tilted arms: the fused sweep with Ap kept in q (cg_pass_fused_tl),
+  // except with four columns per thread in 1024 threads, where its windows
+  // spill the plane loop's registers.
+  constexpr bool FUSE_TL = GEN && TL && !QD && (NT < 1024 || CPT <= 3);
+  __shared__ double red4[(QD || FUSE_TL) ? 4 * (NT / 64) : 1];
   __shared__ int s_item;
   const int tid = threadIdx.x;
   const int plane = kLdsWX * a.lds_wy;
@@ -1843,11 +1975,12 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
   float* fl2 = fl1 + plane;
   float* fl3 = fl2 + plane;
   int* pst = reinterpret_cast<int*>(lds + 2 * plane);
-  // slot: x (FP64), then r, p, y (FP32)
+  // slot: x (FP64), then r, p, y, q (FP32; q holds Ap between fused sweeps)
   double* x = (double*)((char*)a.slot_ws + (long long)blockIdx.x * a.slot_bytes);
   float* r = reinterpret_cast<float*>(x + a.sstride);
   float* p = r + a.sstride;
   float* y = p + a.sstride;
+  float* q = y + a.sstride;
   const StencilT<float> S32 = stencil_cast<float>(a.S);
   // Quad layout: pass B and the next pass A share a sweep (cg_pass_fused_quad)
   // in workgroups of up to 768 threads (one run per thread with 768, two with
@@ -1931,6 +2064,15 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
           pq = t[0];
           ra = t[1];
           aa = t[2];
+        } else if constexpr (FUSE_TL) {
+          double t[4], rr_t;
+          cg_pass_a_tl<NS, CPT, float, true>(a.G32, cl, pst, Zmax, r, p, uniform((float)beta), first, fl0, fl1, t[0],
+                                             rr_t, q, &t[1], &t[2]);
+          t[3] = 0.0;
+          block_sum4(t, red4);
+          pq = t[0];
+          ra = t[1];
+          aa = t[2];
         } else {
           double pq_t, rr_t;
           pass_a<NS, CPT, PD, GEN, TL, QD, float>(S32, a.G32, cl, pst, Zmax, r, p, (float)beta, first, fl0, fl1, pq_t,
@@ -1949,7 +2091,7 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
           xs.skip = true;
         }
         bool fused = false;
-        if constexpr (FUSE) {
+        if constexpr (FUSE || FUSE_TL) {
           // |r - alpha Ap|^2 before r is updated; the sweep is fused only where
           // this next norm stays clear of the reliable-update and stop thresholds
           // (2% margin), so that every update and stop test follows a pass B
@@ -1958,14 +2100,20 @@ __global__ __launch_bounds__(NT) void k_solve_mixed(SolveKArgs a) {
           if (rn_next > thr * thr && it + 1 < a.max_iter) {
             double o3[3], t[4];
             const float bnext = (float)(rn_next / rr);
-            t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, uniform((float)alpha),
-                                                          uniform(bnext), uniform(xs), fl0, fl1, fl2, fl3, o3);
+            if constexpr (FUSE)
+              t[0] = cg_pass_fused_quad<NS, PD, GEN, float>(S32, cl, pst, Zmax, y, r, p, uniform((float)alpha),
+                                                            uniform(bnext), uniform(xs), fl0, fl1, fl2, fl3, o3);
+            else
+              t[0] = cg_pass_fused_tl<NS, CPT, float>(a.G32, cl, pst, Zmax, y, r, p, q, uniform((float)alpha),
+                                                      uniform(bnext), uniform(xs), fl0, fl1, o3);
             t[1] = o3[0];
             t[2] = o3[1];
             t[3] = o3[2];
             block_sum4(t, red4);
             ++it;
-            nsav += xs.skip ? 2 : 1;
+            // (the tilted-arm sweep reads and writes q in place of a second
+            // pass over p: it saves no accesses beyond a deferred x step)
+            nsav += FUSE ? (xs.skip ? 2 : 1) : (xs.skip ? 1 : 0);
             first = false;
             if (!xs.skip) y_zero = false;
             pend = xs.skip;

@@ -440,6 +440,40 @@ def test_general_cell_full_size(key):
     assert np.abs(Da - Db).sum() <= 1e-6 * np.abs(Db).sum()
 
 
+def test_tri64_fused_tilted_sweeps_full_size():
+    """tri64 mixed in 512-thread (six columns per thread) and 1024-thread
+    (three) workgroups: the tilted-arm CG fuses each pass B with the next pass
+    A, keeping Ap between sweeps.  Sampled pairs against the oracle, E against
+    the FP64 path's value on the same pair list."""
+    cfg = synth.CONFIGS["tri64"]
+    orbs = synth.make_orbitals(cfg)
+    orb_t = synth.fill_orbitals_device(cfg, orbs, DEV)
+    cen_t = torch.from_numpy(orbs.centres).to(DEV)
+    res = {}
+    for prec, threads in (("mixed", 512), ("mixed1024", 1024), ("fp64", 1024)):
+        plan = _plan(cfg, solve_threads=threads,
+                     precision=exx.EXX_PREC_FP64 if prec == "fp64" else exx.EXX_PREC_MIXED)
+        E = torch.zeros(1, dtype=torch.float64, device=DEV)
+        plan.eval(orb_t, cen_t, E)
+        torch.cuda.synchronize()
+        st = plan.stats()
+        print(f"[tri64 {prec} {threads}] E={E.item():.12f} iters mean={st['cg_iter_sum'] / st['n_pairs']:.1f} "
+              f"solve {st['solve_ms']:.0f} ms threads={st['solve_threads']}", flush=True)
+        assert st["n_unconverged"] == 0
+        assert st["solve_threads"] == threads
+        res[prec] = (E.item(), plan.pair_results())
+        plan.close()
+    Ef, pf = res["fp64"]
+    for prec in ("mixed", "mixed1024"):
+        Em, pm = res[prec]
+        assert np.array_equal(pm["ij"], pf["ij"])
+        assert abs(Em - Ef) <= 1e-6 * cfg.n_orb / 4
+    _check_pairs("tri64 fused 512", cfg, orbs, orb_t, res["mixed"][1], _picks(res["mixed"][1], 8, 91), tol_E=1e-6,
+                 tol_S=1e-6)
+    _check_pairs("tri64 fused 1024", cfg, orbs, orb_t, res["mixed1024"][1], _picks(res["mixed1024"][1], 8, 92),
+                 tol_E=1e-6, tol_S=1e-6)
+
+
 # ---------------------------------------------------------------------------
 # fused CG sweeps on a sphere of more than 700 runs of four columns
 

@@ -89,6 +89,44 @@ def test_general_cell_cg_variants(threads):
     assert rel1(g["D"], o["D"]) <= TOL_D
 
 
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_general_cell_cg_variants_mixed(threads):
+    """Mixed precision on the same spheres (four columns per thread with 512
+    threads, two with 1024).  The tilted-arm CG runs fused sweeps (pass B with
+    the next pass A, Ap kept in a vector between them) wherever the next
+    residual norm is clear of the update and stop thresholds."""
+    cfg = _tri_big()
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    g = gpu_eval(cfg, orbs, phi, solve_threads=threads, precision=exx.EXX_PREC_MIXED)
+    o = _oracle_cached(cfg, orbs, phi)
+    print(f"[tri-big mixed {threads}] E gpu={g['E']:.15g} oracle={o['E']:.15g} iters max={g['stats']['cg_iter_max']}",
+          flush=True)
+    assert g["stats"]["solve_threads"] == threads
+    assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
+    _check_mixed(g, o, cfg.n_orb)
+    # every pair converged to the FP64 criterion: its E within the mixed bound
+    # of the oracle's
+    Eo = np.array([p.E for p in o["pairs"]])
+    assert np.abs(g["pairs"]["E"] - Eo).max() <= 1e-6 * np.abs(Eo).max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_general_cell_fused_tilted_sweeps_per_stencil_order(n):
+    """The fused tilted-arm sweeps (mixed, 512 and 1024 threads) for each
+    stencil order."""
+    h, N = CELLS["triclinic"]
+    cfg = _cfg(f"gen-tri-fused-n{n}", h, N, stencil_n=n, R_ME=4.9 if n < 3 else 6.3, seed_index=84 + n)
+    orbs = synth.make_orbitals(cfg)
+    phi = synth.fill_orbitals(cfg, orbs)
+    o = oracle_eval(cfg, orbs, phi)
+    for threads in (512, 1024):
+        g = gpu_eval(cfg, orbs, phi, solve_threads=threads, precision=exx.EXX_PREC_MIXED)
+        assert g["stats"]["solve_threads"] == threads
+        assert [tuple(x) for x in g["pairs"]["ij"]] == [(p.i, p.j) for p in o["pairs"]]
+        _check_mixed(g, o, cfg.n_orb)
+
+
 @pytest.mark.parametrize("name", ["triclinic", "monoclinic"])
 def test_general_cell_mixed_precision(name):
     h, N = CELLS[name]
