@@ -32,7 +32,7 @@ Every evaluation's statistics are checked: a pair whose CG did not converge
 pairs and the CG variant of each sphere class to stderr and exit with status 3.
 
 The roofline entry is for the dominant kernel, the persistent CG solve:
-algorithmic bytes (8 N_PE b per pair per iteration, 6 in a fused sweep) over
+algorithmic bytes (8 N_PE b per pair per iteration, 6 in a fused quad sweep) over
 the summed device time of its launches in the timed region, from HIP events
 that the library records on its stream (eager calls only).  moments_roofline
 gives the moment contraction's matrix-core rate.  The CPU baseline is the FP64

@@ -138,7 +138,11 @@ typedef struct {
      when no Laplacian arm leaves the sweep plane, at most one diagonal arm
      lies in it, and its columns are symmetric about the sweep plane.  With
      2, EXX_EINVAL when a class does not fit (more than 1024 runs, other arms
-     or columns) and with cell_fluctuation                                     */
+     or columns) and with cell_fluctuation.  Mixed plans of general cells
+     whose arms leave the sweep plane (single columns) also sweep each pass B
+     with the next pass A, keeping Ap in one more FP32 vector between sweeps
+     (as many accesses as two passes, one stencil per iteration), except with
+     four columns per thread in 1024 threads                                   */
   int cg_layout;
   /* mixed precision: a reliable update (the FP32 correction folded into the
      FP64 solution and the FP64 true residual recomputed) happens when the
@@ -253,8 +257,8 @@ typedef struct {
   double solve_ms;             /* device time of the solve kernels (last eval)     */
   double eval_ms;              /* device time of the whole evaluation              */
   double cg_alg_bytes;         /* algorithmic CG bytes: sum over pairs of (8 iters
-                                  - 2 fused sweeps - 2 passes that left x alone)
-                                  N_PE b                                            */
+                                  - 2 fused quad sweeps - 2 passes that left x
+                                  alone) N_PE b                                     */
   double moment_flops;         /* algorithmic moment flops: 2 N_lm N_PE per pair   */
   /* running totals since the plan was made (every completed exx_eval):       */
   long long n_evals;
@@ -262,8 +266,10 @@ typedef struct {
   double solve_ms_total;       /* their summed device time (HIP events)          */
   double cg_alg_bytes_total;   /* their summed algorithmic CG bytes (eight vector
                                   accesses per point and iteration, two fewer in
-                                  a fused sweep and in a pass B that leaves x
-                                  alone, which every other pass B does)            */
+                                  a fused quad sweep and in a pass B that leaves
+                                  x alone, which every other pass B does; a fused
+                                  tilted-arm sweep, which reads and writes Ap in
+                                  place of pass A's p, counts as the two passes) */
   double eval_ms_total;
   int solve_threads;           /* CG variant in use: workgroup size (quad layout:
                                   768 and 512 with fused sweeps, 512 with two
