@@ -752,7 +752,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
              align(C.halo_zidx.size() * sizeof(int)) + align(C.halo_zstart.size() * sizeof(int)) +
              align(C.fin_cols.size() * sizeof(int4)) + align(C.rhs_ptr.size() * sizeof(int)) +
              align(C.rhs_ent.size() * sizeof(int2)) + align(C.me_scan.size() * sizeof(int)) +
-             align(C.scan_off.size() * sizeof(short4)) + mom_bytes(C) +
+             align(C.scan_off.size() * sizeof(short4)) + align(C.rhs_edge.size() * sizeof(unsigned)) + mom_bytes(C) +
              align((size_t)((C.n_halo + 15) / 16) * ((g.n_lm + 3) / 4) * 64 * sizeof(double));
   }
   void* block = nullptr;
@@ -805,6 +805,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.n_fin = (int)C.fin_cols.size();
     D.rhs_ptr = (const int*)put(C.rhs_ptr.data(), C.rhs_ptr.size() * sizeof(int));
     D.rhs_ent = (const int2*)put(C.rhs_ent.data(), C.rhs_ent.size() * sizeof(int2));
+    D.rhs_edge = (const unsigned*)put(C.rhs_edge.data(), C.rhs_edge.size() * sizeof(unsigned));
     D.me_scan = (const int*)put(C.me_scan.data(), C.me_scan.size() * sizeof(int));
     D.scan_off = (const short4*)put(C.scan_off.data(), C.scan_off.size() * sizeof(short4));
     D.n_scan = (long long)C.me_scan.size();

@@ -96,6 +96,10 @@ struct ClassDev {
   // rhs_ent[rhs_ptr[k] .. rhs_ptr[k + 1]) = (halo index h, 4 al + q)
   const int* rhs_ptr;
   const int2* rhs_ent;
+  // general cells: bit k (word k / 32) set for the PE slots within n steps of a
+  // non-PE point along a direction the tables hold Dirichlet points for (the
+  // only slots whose right-hand side takes Dirichlet terms)
+  const unsigned* rhs_edge;
   // the live entries of me_off (no dead slots) in grid raster order of their
   // offsets (z, then y, then x), n_scan of them: the D scatter's order; and
   // their offsets in that order (so that a point's offset and entry are two
@@ -142,6 +146,7 @@ struct ClassHost {
   std::vector<int4> fin_cols;                // orthorhombic: the real columns (slot, zr, x, y)
   std::vector<int> rhs_ptr;                  // orthorhombic: CSR of the Dirichlet terms per PE slot
   std::vector<int2> rhs_ent;
+  std::vector<unsigned> rhs_edge;            // general: PE slots near the Dirichlet points (bits)
   std::vector<int> me_scan;                  // the live ME entries in grid raster order (z, y, x)
   std::vector<short4> scan_off;              // their offsets, in that order
   long long n_pe = 0, n_halo = 0, n_me = 0, n_real = 0;

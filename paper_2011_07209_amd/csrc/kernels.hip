@@ -269,8 +269,9 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const ClassDev* __restrict__
   }
   const short4 o = C.me_off[k];
   if (g.gen) {
-    // every arm of the NK Laplacian (eq. lapG_mod_nk3d), eq. d2_1 along it
-    if (!o.w) {
+    // every arm of the NK Laplacian (eq. lapG_mod_nk3d), eq. d2_1 along it, at
+    // the slots near the Dirichlet points (elsewhere every arm stays in PE)
+    if (!o.w && (!C.rhs_edge || ((C.rhs_edge[k >> 5] >> (k & 31)) & 1u))) {
       for (int m = 0; m < g.n_arms; ++m) {
         const int ux = g.arm_u[m][0], uy = g.arm_u[m][1], uz = g.arm_u[m][2];
         for (int q = 1; q <= g.n; ++q)

@@ -569,6 +569,19 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
         C.halo_off.push_back(make_short4((short)o0, (short)o1, (short)o2, 0));
       }
   C.n_halo = (long long)C.halo_off.size();
+  // the PE slots whose arm sums can reach a Dirichlet point: within n steps
+  // of a non-PE point along one of those directions
+  C.rhs_edge.assign((size_t)((C.n_pe + 31) / 32), 0u);
+  for (long long k = 0; k < C.n_pe; ++k) {
+    const short4 o = C.me_off[(size_t)k];
+    if (o.w) continue;
+    bool edge = false;
+    for (size_t d = 0; d < dirs.size() && !edge; ++d)
+      for (int q = 1; q <= n && !edge; ++q)
+        edge = !in_pe(o.x + q * dirs[d][0], o.y + q * dirs[d][1], o.z + q * dirs[d][2]) ||
+               !in_pe(o.x - q * dirs[d][0], o.y - q * dirs[d][1], o.z - q * dirs[d][2]);
+    if (edge) C.rhs_edge[(size_t)(k >> 5)] |= 1u << (k & 31);
+  }
 
   // ME shell after the PE slots
   int KM[3];

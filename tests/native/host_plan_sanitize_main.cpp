@@ -72,7 +72,35 @@ void check_class(const exx::ClassHost& C, int n, const char* name) {
     for (const int4& c : C.fin_cols) check(c.x >= 0 && c.y >= 0 && c.y <= C.Zmax, "finalize column", name);
   } else {
     check(C.halo_zidx.empty() && C.fin_cols.empty() && C.rhs_ptr.empty(), "no sweep tables for general cells", name);
+    check((long long)C.rhs_edge.size() == (C.n_pe + 31) / 32, "rhs_edge size", name);
   }
+}
+
+// General cells: every PE slot with a Dirichlet point among its arm
+// neighbours (q <= n steps along an NK arm) is marked in rhs_edge, so the
+// right-hand side kernel, which skips unmarked slots, misses no coupling.
+void check_edges(const exx::ClassHost& C, const std::vector<exx::NkArm>& arms, int n, const char* name) {
+  const int c0 = (C.Wm[0] - 1) / 2, c1 = (C.Wm[1] - 1) / 2, c2 = (C.Wm[2] - 1) / 2;
+  auto halo_at = [&](int o0, int o1, int o2) {
+    if (std::abs(o0) > c0 || std::abs(o1) > c1 || std::abs(o2) > c2) return false;
+    return C.halo_map[(size_t)(o0 + c0) + (size_t)C.Wm[0] * ((size_t)(o1 + c1) + (size_t)C.Wm[1] * (o2 + c2))] >= 0;
+  };
+  long long marked = 0, needed = 0;
+  for (long long k = 0; k < C.n_pe; ++k) {
+    const short4 o = C.me_off[(size_t)k];
+    if (o.w) continue;
+    bool need = false;
+    for (const exx::NkArm& A : arms)
+      for (int q = 1; q <= n; ++q)
+        for (int s = -1; s <= 1; s += 2)
+          need = need || halo_at(o.x + s * q * A.u[0], o.y + s * q * A.u[1], o.z + s * q * A.u[2]);
+    const bool bit = (C.rhs_edge[(size_t)(k >> 5)] >> (k & 31)) & 1u;
+    marked += bit;
+    needed += need;
+    if (need) check(bit, "slot with a Dirichlet arm neighbour is marked", name);
+  }
+  check(marked < C.n_real, "interior slots unmarked", name);
+  std::printf("  %s: %lld of %lld PE points marked (%lld need it)\n", name, marked, C.n_real, needed);
 }
 
 void boundary(const exx::ClassHost& C, const double A[9], const char* name) {
@@ -141,6 +169,7 @@ int main() {
         check(e.empty(), "build_class_general", name);
         if (!e.empty()) continue;
         check_class(C, 3, name);
+        check_edges(C, arms, 3, name);
         moments(C, Ag, name);
         boundary(C, Ag, name);
       }
@@ -155,7 +184,10 @@ int main() {
     e = exx::build_class_general(hm, Ng, 2, 2.4, 4.6, 3, arms, false, true, &C);
     std::printf("monoclinic quads: %s n_pe %lld quads %d\n", e.empty() ? "ok" : e.c_str(), C.n_pe, (int)C.quads);
     check(e.empty(), "build_class_general", "monoclinic");
-    if (e.empty()) check_class(C, 3, "monoclinic");
+    if (e.empty()) {
+      check_class(C, 3, "monoclinic");
+      check_edges(C, arms, 3, "monoclinic");
+    }
   }
   std::printf("failures %d\n", g_fail);
   return g_fail ? 1 : 0;
