@@ -800,7 +800,7 @@ exx_status assemble_cell(exx_plan_t P, const double h[9]) {
     D.pe_map = general ? (const int*)put(C.pe_map.data(), C.pe_map.size() * sizeof(int)) : nullptr;
     D.halo_zidx = (const int*)put(C.halo_zidx.data(), C.halo_zidx.size() * sizeof(int));
     D.halo_zstart = (const int*)put(C.halo_zstart.data(), C.halo_zstart.size() * sizeof(int));
-    D.Zh = general ? 0 : C.Zmax + n;
+    D.Zh = C.Zmax + n;
     D.fin_cols = (const int4*)put(C.fin_cols.data(), C.fin_cols.size() * sizeof(int4));
     D.n_fin = (int)C.fin_cols.size();
     D.rhs_ptr = (const int*)put(C.rhs_ptr.data(), C.rhs_ptr.size() * sizeof(int));

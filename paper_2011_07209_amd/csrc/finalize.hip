@@ -1,10 +1,13 @@
 // E_xx and sigma_xx of each pair as one plane sweep over its PE sphere
-// (orthorhombic cells, column or quad layout of the CG vectors):
+// (column or quad layout of the CG vectors):
 //   E = -w dV sum rho v                                   (eq. exxGen_mlwf)
 //   sigma^{a al} = -2 w dV sum_b (h^-1)_{al b} sum rbar_b rho dv/dr_a
 //                                                          (eq. sxx_working)
-// with dv/dr_a from the first-derivative stencil of eq. d1_1 along each axis
-// (the Jacobian of eq. jacb is the identity for an orthorhombic cell).
+// with dv/dr_a = sum_al J_{a al} dv/dxi_al (eq. jacb) and dv/dxi_al from the
+// first-derivative stencil of eq. d1_1 along lattice axis al (J is the
+// identity for an orthorhombic cell).  General cells sweep in their CG frame
+// (x', y', z') = (o[perm[0]], o[perm[1]], o[perm[2]]): lattice axes too, so
+// every derivative still reads the staged plane or the column's window.
 //
 // One workgroup per pair.  Thread t owns the sphere's columns t, t + 1024,
 // ... and marches z with the column's potential in a register window of
@@ -25,7 +28,7 @@ namespace {
 
 constexpr int kFinThreads = 1024;
 
-template <int NS, int CPT>
+template <int NS, int CPT, bool GEN>
 __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const ClassDev* __restrict__ cls,
                                                                 const PairDev* __restrict__ pairs,
                                                                 const int* __restrict__ order, long long p0,
@@ -51,34 +54,52 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
   const int W01 = C.Wm[0] * C.Wm[1];
 
   // this thread's columns (the sphere's columns without the quad layout's
-  // padding): slot in the layout, PE half-height zr (-1: none) and the x and
-  // y offsets packed in one register (16 bits each); the LDS position and the
-  // far-field map index follow from them where needed
-  int slot[CPT], zr[CPT], oxy[CPT];
+  // padding): slot in the layout, PE extent [lo, hi] along z (lo > hi: none)
+  // and the x and y offsets packed in one register (16 bits each); the LDS
+  // position and the far-field map index follow from them where needed.
+  // Orthorhombic columns are (slot, half-height, x, y), general ones (slot,
+  // lo, hi, x | y << 16), x, y, z in the CG frame.
+  int slot[CPT], lo[CPT], hi[CPT], oxy[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int col = threadIdx.x + c * kFinThreads;
     slot[c] = 0;
-    zr[c] = -1;
+    lo[c] = 1;
+    hi[c] = 0;
     oxy[c] = 0;
     if (col < C.n_fin) {
       const int4 cc = C.fin_cols[col];
       slot[c] = cc.x;
-      zr[c] = cc.y;
-      oxy[c] = (cc.z & 0xffff) | (cc.w << 16);
+      if constexpr (GEN) {
+        lo[c] = cc.y;
+        hi[c] = cc.z;
+        oxy[c] = cc.w;
+      } else {
+        lo[c] = -cc.y;
+        hi[c] = cc.y;
+        oxy[c] = (cc.z & 0xffff) | (cc.w << 16);
+      }
     }
   }
   auto ox_of = [&](int c) { return (int)(short)(oxy[c] & 0xffff); };
   auto oy_of = [&](int c) { return oxy[c] >> 16; };
   auto pos_of = [&](int c) { return (ox_of(c) + g.lds_cx) + kLdsWX * (oy_of(c) + g.lds_cy); };
+  auto inside = [&](int c, int zz) { return zz >= lo[c] && zz <= hi[c]; };
+  // the far-field map index of CG-frame point (x, y, z): the maps are over the
+  // lattice offsets, centred at (Wm - 1) / 2
+  auto map_index = [&](int px, int py, int pz) {
+    int o[3];
+    o[g.perm[0]] = px;
+    o[g.perm[1]] = py;
+    o[g.perm[2]] = pz;
+    return (o[0] + (C.Wm[0] - 1) / 2) + C.Wm[0] * (o[1] + (C.Wm[1] - 1) / 2) + W01 * (o[2] + (C.Wm[2] - 1) / 2);
+  };
   // the potential at (column c, plane zz): the solution inside PE, the
   // far-field value at the n points beyond each end of the column
   auto value = [&](int c, int zz) -> double {
-    const int az = abs(zz);
-    if (az <= zr[c]) return x[C.plane_start[zz + Zmax] + slot[c]];
-    if (zr[c] >= 0 && az <= zr[c] + NS) {
-      const int m = (ox_of(c) + C.Rg[0] + g.n) + C.Wm[0] * (oy_of(c) + C.Rg[1] + g.n) + W01 * (zz + C.Rg[2] + g.n);
-      const int h = C.halo_map[m];
+    if (inside(c, zz)) return x[C.plane_start[zz + Zmax] + slot[c]];
+    if (lo[c] <= hi[c] && zz >= lo[c] - NS && zz <= hi[c] + NS) {
+      const int h = C.halo_map[map_index(ox_of(c), oy_of(c), zz)];
       return h >= 0 ? halo[h] : 0.0;
     }
     return 0.0;
@@ -102,21 +123,22 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       nv[c] = value(c, z + NS + 1);
-      rh[c] = abs(z) <= zr[c] ? rho[C.plane_start[z + Zmax] + slot[c]] : 0.0;
+      rh[c] = inside(c, z) ? rho[C.plane_start[z + Zmax] + slot[c]] : 0.0;
     }
     double* pl = (z & 1) ? pl1 : pl0;
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
-      if (abs(z) <= zr[c]) pl[pos_of(c)] = win[c][NS];
+      if (inside(c, z)) pl[pos_of(c)] = win[c][NS];
     for (int k = C.halo_zstart[z + Zh] + (int)threadIdx.x; k < C.halo_zstart[z + Zh + 1]; k += kFinThreads) {
       const int h = C.halo_zidx[k];
       const short4 o = C.halo_off[h];
-      pl[(o.x + g.lds_cx) + kLdsWX * (o.y + g.lds_cy)] = halo[h];
+      const int oo[3] = {o.x, o.y, o.z};
+      pl[(oo[g.perm[0]] + g.lds_cx) + kLdsWX * (oo[g.perm[1]] + g.lds_cy)] = halo[h];
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      if (abs(z) <= zr[c]) {
+      if (inside(c, z)) {
         const int pos = pos_of(c);
         const double v = win[c][NS];
         double d0 = 0.0, d1 = 0.0, d2 = 0.0;
@@ -126,8 +148,31 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
           d1 += w1[q] * (pl[pos + q * kLdsWX] - pl[pos - q * kLdsWX]);
           d2 += w1[q] * (win[c][NS + q] - win[c][NS - q]);
         }
-        const double ga[3] = {d0 * g.inv_d[0], d1 * g.inv_d[1], d2 * g.inv_d[2]};
-        const double rb[3] = {ox_of(c) * g.d[0], oy_of(c) * g.d[1], z * g.d[2]};
+        double ga[3], rb[3];
+        if constexpr (GEN) {
+          // dv/dxi along the lattice axes, then dv/dr = J dv/dxi; rbar = A o
+          double dxi[3];
+          dxi[g.perm[0]] = d0;
+          dxi[g.perm[1]] = d1;
+          dxi[g.perm[2]] = d2;
+#pragma unroll
+          for (int al = 0; al < 3; ++al) dxi[al] *= g.inv_d[al];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) ga[a] = g.J[a] * dxi[0] + g.J[a + 3] * dxi[1] + g.J[a + 6] * dxi[2];
+          int o[3];
+          o[g.perm[0]] = ox_of(c);
+          o[g.perm[1]] = oy_of(c);
+          o[g.perm[2]] = z;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) rb[a] = g.A[a] * o[0] + g.A[a + 3] * o[1] + g.A[a + 6] * o[2];
+        } else {
+          ga[0] = d0 * g.inv_d[0];
+          ga[1] = d1 * g.inv_d[1];
+          ga[2] = d2 * g.inv_d[2];
+          rb[0] = ox_of(c) * g.d[0];
+          rb[1] = oy_of(c) * g.d[1];
+          rb[2] = z * g.d[2];
+        }
         e += rh[c] * v;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -154,16 +199,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
   }
 }
 
-template <int NS>
+template <int NS, bool GEN>
 hipError_t finalize_sweep_cpt(int cpt, const Geo& g, const Batch& B, const double* rho_ws, const double* v_ws,
                               long long rstride, const double* halo_ws, long long hstride, double* outE, double* outS,
                               size_t lds, hipStream_t s) {
   const void* fn = nullptr;
   switch (cpt) {
-    case 1: fn = (const void*)k_finalize_sweep<NS, 1>; break;
-    case 2: fn = (const void*)k_finalize_sweep<NS, 2>; break;
-    case 3: fn = (const void*)k_finalize_sweep<NS, 3>; break;
-    case 4: fn = (const void*)k_finalize_sweep<NS, 4>; break;
+    case 1: fn = (const void*)k_finalize_sweep<NS, 1, GEN>; break;
+    case 2: fn = (const void*)k_finalize_sweep<NS, 2, GEN>; break;
+    case 3: fn = (const void*)k_finalize_sweep<NS, 3, GEN>; break;
+    case 4: fn = (const void*)k_finalize_sweep<NS, 4, GEN>; break;
     default: return hipErrorInvalidValue;
   }
   if (lds > 64 * 1024) {
@@ -173,10 +218,10 @@ hipError_t finalize_sweep_cpt(int cpt, const Geo& g, const Batch& B, const doubl
   const dim3 grid((unsigned)B.nb);
 #define EXX_FIN_ARGS g, B.cls, B.pairs, B.order, B.p0, B.n_eff, rho_ws, v_ws, rstride, halo_ws, hstride, outE, outS
   switch (cpt) {
-    case 1: k_finalize_sweep<NS, 1><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
-    case 2: k_finalize_sweep<NS, 2><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
-    case 3: k_finalize_sweep<NS, 3><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
-    default: k_finalize_sweep<NS, 4><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
+    case 1: k_finalize_sweep<NS, 1, GEN><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
+    case 2: k_finalize_sweep<NS, 2, GEN><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
+    case 3: k_finalize_sweep<NS, 3, GEN><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
+    default: k_finalize_sweep<NS, 4, GEN><<<grid, kFinThreads, lds, s>>>(EXX_FIN_ARGS); break;
   }
 #undef EXX_FIN_ARGS
   return hipGetLastError();
@@ -185,7 +230,7 @@ hipError_t finalize_sweep_cpt(int cpt, const Geo& g, const Batch& B, const doubl
 }  // namespace
 
 bool finalize_sweep_supported(const Geo& g, long long max_cols) {
-  return !g.gen && max_cols > 0 && max_cols <= 4LL * kFinThreads && (size_t)2 * kLdsWX * g.lds_wy * sizeof(double) <= 160 * 1024;
+  return max_cols > 0 && max_cols <= 4LL * kFinThreads && (size_t)2 * kLdsWX * g.lds_wy * sizeof(double) <= 160 * 1024;
 }
 
 hipError_t launch_finalize_sweep(const Geo& g, const Batch& B, long long max_cols, const double* rho_ws,
@@ -195,12 +240,15 @@ hipError_t launch_finalize_sweep(const Geo& g, const Batch& B, long long max_col
   if (!finalize_sweep_supported(g, max_cols)) return hipErrorInvalidValue;
   const int cpt = (int)((max_cols + kFinThreads - 1) / kFinThreads);
   const size_t lds = (size_t)2 * kLdsWX * g.lds_wy * sizeof(double);
+#define EXX_FIN_CALL(NS, GEN) \
+  finalize_sweep_cpt<NS, GEN>(cpt, g, B, rho_ws, v_ws, rstride, halo_ws, hstride, outE, outS, lds, s)
   switch (g.n) {
-    case 1: return finalize_sweep_cpt<1>(cpt, g, B, rho_ws, v_ws, rstride, halo_ws, hstride, outE, outS, lds, s);
-    case 2: return finalize_sweep_cpt<2>(cpt, g, B, rho_ws, v_ws, rstride, halo_ws, hstride, outE, outS, lds, s);
-    case 3: return finalize_sweep_cpt<3>(cpt, g, B, rho_ws, v_ws, rstride, halo_ws, hstride, outE, outS, lds, s);
+    case 1: return g.gen ? EXX_FIN_CALL(1, true) : EXX_FIN_CALL(1, false);
+    case 2: return g.gen ? EXX_FIN_CALL(2, true) : EXX_FIN_CALL(2, false);
+    case 3: return g.gen ? EXX_FIN_CALL(3, true) : EXX_FIN_CALL(3, false);
     default: return hipErrorInvalidValue;
   }
+#undef EXX_FIN_CALL
 }
 
 }  // namespace exx

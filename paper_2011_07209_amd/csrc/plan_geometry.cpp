@@ -569,6 +569,27 @@ std::string build_class_general(const double h[9], const int N[3], int sweep, do
         C.halo_off.push_back(make_short4((short)o0, (short)o1, (short)o2, 0));
       }
   C.n_halo = (long long)C.halo_off.size();
+  // the plane-sweep E/sigma kernel's tables, in the CG frame: the Dirichlet
+  // points by plane z' and the real columns (slot, lo, hi, x' | y' << 16)
+  {
+    auto comp = [](const short4& o, int a) { return a == 0 ? (int)o.x : a == 1 ? (int)o.y : (int)o.z; };
+    const int Zh = C.Zmax + n;
+    C.halo_zstart.assign(2 * Zh + 2, 0);
+    for (const short4& o : C.halo_off) {
+      const int zp = comp(o, perm[2]);
+      if (std::abs(zp) > Zh) return "Dirichlet point beyond n planes of the PE sphere";
+      C.halo_zstart[zp + Zh + 1]++;
+    }
+    for (int z = 0; z < 2 * Zh + 1; ++z) C.halo_zstart[z + 1] += C.halo_zstart[z];
+    std::vector<int> fill(C.halo_zstart.begin(), C.halo_zstart.end() - 1);
+    C.halo_zidx.assign(C.halo_off.size(), 0);
+    for (size_t hh = 0; hh < C.halo_off.size(); ++hh) C.halo_zidx[fill[comp(C.halo_off[hh], perm[2]) + Zh]++] = (int)hh;
+    C.fin_cols.clear();
+    for (int c = 0; c < C.n_cols; ++c)
+      if (lay[c].lo <= lay[c].hi)
+        C.fin_cols.push_back(
+            make_int4(c, lay[c].lo, lay[c].hi, (int)(((unsigned)lay[c].x & 0xffffu) | ((unsigned)lay[c].y << 16))));
+  }
   // the PE slots whose arm sums can reach a Dirichlet point: within n steps
   // of a non-PE point along one of those directions
   C.rhs_edge.assign((size_t)((C.n_pe + 31) / 32), 0u);

@@ -71,8 +71,19 @@ void check_class(const exx::ClassHost& C, int n, const char* name) {
     for (const int2& e : C.rhs_ent) check(e.x >= 0 && e.x < C.n_halo && e.y >= 0 && e.y < 4 * 3, "rhs entry", name);
     for (const int4& c : C.fin_cols) check(c.x >= 0 && c.y >= 0 && c.y <= C.Zmax, "finalize column", name);
   } else {
-    check(C.halo_zidx.empty() && C.fin_cols.empty() && C.rhs_ptr.empty(), "no sweep tables for general cells", name);
+    check(C.rhs_ptr.empty(), "no right-hand side table for general cells", name);
     check((long long)C.rhs_edge.size() == (C.n_pe + 31) / 32, "rhs_edge size", name);
+    check((int)C.halo_zstart.size() == 2 * (C.Zmax + n) + 2, "halo_zstart size", name);
+    check((long long)C.halo_zidx.size() == C.n_halo, "halo_zidx holds every Dirichlet point", name);
+    for (int h : C.halo_zidx) check(h >= 0 && h < C.n_halo, "halo_zidx range", name);
+    // the real columns: every PE point once across [lo, hi] of its column
+    long long pts = 0;
+    for (const int4& c : C.fin_cols) {
+      check(c.x >= 0 && c.x < C.n_cols && c.y <= c.z && c.y >= -C.Zmax && c.z <= C.Zmax, "general finalize column",
+            name);
+      pts += c.z - c.y + 1;
+    }
+    check(pts == C.n_real, "finalize columns cover the PE points", name);
   }
 }
 
