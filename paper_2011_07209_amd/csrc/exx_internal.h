@@ -82,13 +82,14 @@ struct ClassDev {
   const int* halo_map;       // [Wm2][Wm1][Wm0] -> halo index or -1
   const int* col_map;        // [Wm1][Wm0] -> column index or -1
   const int* zr_map;         // [Wm1][Wm0] -> column half-height or -1
-  // orthorhombic cells: the Dirichlet points plane by plane, halo_zidx[halo_zstart[z + Zh] ..
-  // halo_zstart[z + Zh + 1]) the halo indices of plane z, Zh = Zmax + n (null for general cells)
+  // the Dirichlet points plane by plane (z in the CG frame), halo_zidx[halo_zstart[z + Zh] ..
+  // halo_zstart[z + Zh + 1]) the halo indices of plane z, Zh = Zmax + n
   const int* halo_zidx;
   const int* halo_zstart;
   int Zh;
-  // orthorhombic cells: the sphere's columns without the quad layout's padding columns,
-  // (slot in the layout, half-height, x, y) each; n_fin of them
+  // the sphere's columns without the quad layout's padding columns, n_fin of them: (slot in
+  // the layout, half-height, x, y) each for orthorhombic cells, (slot, lo, hi, x | y << 16) in
+  // the CG frame for general cells
   const int4* fin_cols;
   int n_fin;
   // orthorhombic cells: the Dirichlet terms of the right-hand side as a CSR
@@ -142,8 +143,8 @@ struct ClassHost {
   std::vector<short4> halo_off;
   std::vector<short4> me_off;
   std::vector<int> halo_map, col_map, zr_map, pe_map;
-  std::vector<int> halo_zidx, halo_zstart;   // orthorhombic: the Dirichlet points by plane
-  std::vector<int4> fin_cols;                // orthorhombic: the real columns (slot, zr, x, y)
+  std::vector<int> halo_zidx, halo_zstart;   // the Dirichlet points by plane (CG frame)
+  std::vector<int4> fin_cols;                // the real columns (slot, zr, x, y) or (slot, lo, hi, x | y << 16)
   std::vector<int> rhs_ptr;                  // orthorhombic: CSR of the Dirichlet terms per PE slot
   std::vector<int2> rhs_ent;
   std::vector<unsigned> rhs_edge;            // general: PE slots near the Dirichlet points (bits)
