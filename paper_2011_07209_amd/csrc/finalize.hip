@@ -64,8 +64,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
   for (int c = 0; c < CPT; ++c) {
     const int col = threadIdx.x + c * kFinThreads;
     slot[c] = 0;
-    lo[c] = 1;
-    hi[c] = 0;
+    lo[c] = 1;    // no column: empty for both forms (lo > hi, hi < 0)
+    hi[c] = -1;
     oxy[c] = 0;
     if (col < C.n_fin) {
       const int4 cc = C.fin_cols[col];
@@ -74,8 +74,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
         lo[c] = cc.y;
         hi[c] = cc.z;
         oxy[c] = cc.w;
-      } else {
-        lo[c] = -cc.y;
+      } else {   // (lo = -hi: only hi is read)
         hi[c] = cc.y;
         oxy[c] = (cc.z & 0xffff) | (cc.w << 16);
       }
@@ -84,21 +83,32 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
   auto ox_of = [&](int c) { return (int)(short)(oxy[c] & 0xffff); };
   auto oy_of = [&](int c) { return oxy[c] >> 16; };
   auto pos_of = [&](int c) { return (ox_of(c) + g.lds_cx) + kLdsWX * (oy_of(c) + g.lds_cy); };
-  auto inside = [&](int c, int zz) { return zz >= lo[c] && zz <= hi[c]; };
+  auto inside = [&](int c, int zz) {
+    if constexpr (GEN)
+      return zz >= lo[c] && zz <= hi[c];
+    else
+      return abs(zz) <= hi[c];
+  };
   // the far-field map index of CG-frame point (x, y, z): the maps are over the
-  // lattice offsets, centred at (Wm - 1) / 2
+  // lattice offsets, centred at (Wm - 1) / 2 = Rg + n
   auto map_index = [&](int px, int py, int pz) {
-    int o[3];
-    o[g.perm[0]] = px;
-    o[g.perm[1]] = py;
-    o[g.perm[2]] = pz;
-    return (o[0] + (C.Wm[0] - 1) / 2) + C.Wm[0] * (o[1] + (C.Wm[1] - 1) / 2) + W01 * (o[2] + (C.Wm[2] - 1) / 2);
+    if constexpr (GEN) {
+      int o[3];
+      o[g.perm[0]] = px;
+      o[g.perm[1]] = py;
+      o[g.perm[2]] = pz;
+      return (o[0] + (C.Wm[0] - 1) / 2) + C.Wm[0] * (o[1] + (C.Wm[1] - 1) / 2) + W01 * (o[2] + (C.Wm[2] - 1) / 2);
+    } else {
+      return (px + C.Rg[0] + g.n) + C.Wm[0] * (py + C.Rg[1] + g.n) + W01 * (pz + C.Rg[2] + g.n);
+    }
   };
   // the potential at (column c, plane zz): the solution inside PE, the
   // far-field value at the n points beyond each end of the column
   auto value = [&](int c, int zz) -> double {
     if (inside(c, zz)) return x[C.plane_start[zz + Zmax] + slot[c]];
-    if (lo[c] <= hi[c] && zz >= lo[c] - NS && zz <= hi[c] + NS) {
+    const bool reach = GEN ? lo[c] <= hi[c] && zz >= lo[c] - NS && zz <= hi[c] + NS
+                           : hi[c] >= 0 && abs(zz) <= hi[c] + NS;
+    if (reach) {
       const int h = C.halo_map[map_index(ox_of(c), oy_of(c), zz)];
       return h >= 0 ? halo[h] : 0.0;
     }
@@ -132,8 +142,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_sweep(Geo g, const Cla
     for (int k = C.halo_zstart[z + Zh] + (int)threadIdx.x; k < C.halo_zstart[z + Zh + 1]; k += kFinThreads) {
       const int h = C.halo_zidx[k];
       const short4 o = C.halo_off[h];
-      const int oo[3] = {o.x, o.y, o.z};
-      pl[(oo[g.perm[0]] + g.lds_cx) + kLdsWX * (oo[g.perm[1]] + g.lds_cy)] = halo[h];
+      int px = o.x, py = o.y;
+      if constexpr (GEN) {
+        const int oo[3] = {o.x, o.y, o.z};
+        px = oo[g.perm[0]];
+        py = oo[g.perm[1]];
+      }
+      pl[(px + g.lds_cx) + kLdsWX * (py + g.lds_cy)] = halo[h];
     }
     __syncthreads();
 #pragma unroll
