@@ -94,7 +94,8 @@ typedef struct {
                                  classes of at most 768 runs only, other classes
                                  keep their default                              */
   int solve_depth;            /* planes of loads in flight ahead of use, 1 or 2
-                                 (0: tuned/default)                                */
+                                 (0: tuned/default); cells with arms leaving the
+                                 sweep plane have depth 1 only (reported as 1)    */
   int autotune;               /* 1: the first exx_eval times the CG variants on a
                                  sample of each sphere class's pairs and keeps
                                  the fastest per class (threads x depth; for

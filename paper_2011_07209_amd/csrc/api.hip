@@ -340,6 +340,15 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
   return EXX_OK;
 }
 
+// Whether the plan's Laplacian has arms leaving the sweep plane: those classes
+// run the tilted-arm CG, which has one load depth (1).
+static bool tilted_arms(const Geo& g) {
+  if (!g.gen) return false;
+  for (int m = 0; m < g.n_arms; ++m)
+    if (g.arm_u[m][g.perm[2]] != 0) return true;
+  return false;
+}
+
 // Autotuner: for each sphere class with pairs in this batch, times every CG
 // variant (workgroup size x load depth) that can run it on a sample of the
 // class's pairs (one per workgroup of the grid), and keeps the fastest for
@@ -416,8 +425,9 @@ exx_status autotune_solve(exx_plan_t P, const SolveArgs& base, long long nb, hip
     int bt = P->class_threads[k], bd = P->class_depth[k];
     int order[7][2] = {{bt, bd}};
     int nc = 1;
+    const bool one_depth = !P->classes[k].quads && tilted_arms(P->geo);   // no deeper variant to try
     for (const auto& c : cand)
-      if (c[0] != bt || c[1] != bd) {
+      if ((c[0] != bt || c[1] != bd) && !(one_depth && c[1] != 1)) {
         order[nc][0] = c[0];
         order[nc][1] = c[1];
         ++nc;
@@ -897,6 +907,7 @@ void default_solve_variants(exx_plan_t P) {
     }
     P->class_threads[k] = (opt.solve_threads == 512 || opt.solve_threads == 1024) ? opt.solve_threads
                           : (nc <= cpt * 1024 ? 1024 : 512);
+    if (tilted_arms(P->geo)) P->class_depth[k] = 1;
   }
 }
 
