@@ -389,8 +389,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU pair sharding is "
-              f"a design, not part of this build)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library has no multi-GPU "
+              f"pair sharding)", file=sys.stderr)
         return 2
 
     import numpy as np
