@@ -275,6 +275,15 @@ exx_status harvest(exx_plan_t P) {
 // quad layout reads a run's four values as one vector).
 long long slot_stride(exx_plan_t P) { return (P->max_pe + 7) / 8 * 8; }
 
+// Whether the plan's Laplacian has arms leaving the sweep plane: those classes
+// run the tilted-arm CG, which has one load depth (1).
+static bool tilted_arms(const Geo& g) {
+  if (!g.gen) return false;
+  for (int m = 0; m < g.n_arms; ++m)
+    if (g.arm_u[m][g.perm[2]] != 0) return true;
+  return false;
+}
+
 exx_status apply_solve_variants(exx_plan_t P) {
   const bool mixed = P->opt.precision == EXX_PREC_MIXED;
   const size_t ncls = P->classes.size();
@@ -282,6 +291,7 @@ exx_status apply_solve_variants(exx_plan_t P) {
   int slots = 0;
   for (size_t k = 0; k < ncls; ++k) {
     const ClassHost& C = P->classes[k];
+    if (!C.quads && tilted_arms(P->geo)) P->class_depth[k] = 1;
     const int per_cu =
         solve_groups_per_cu(P->geo, C.n_cols, C.Zmax, mixed, C.quads, P->class_threads[k], P->class_depth[k]);
     if (per_cu < 1) return fail(P, EXX_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
@@ -338,15 +348,6 @@ exx_status launch_solves(exx_plan_t P, SolveArgs a, hipStream_t s) {
     EXX_HIP(P, launch_solve(a, C.n_cols, C.Zmax, (int)groups, s));
   }
   return EXX_OK;
-}
-
-// Whether the plan's Laplacian has arms leaving the sweep plane: those classes
-// run the tilted-arm CG, which has one load depth (1).
-static bool tilted_arms(const Geo& g) {
-  if (!g.gen) return false;
-  for (int m = 0; m < g.n_arms; ++m)
-    if (g.arm_u[m][g.perm[2]] != 0) return true;
-  return false;
 }
 
 // Autotuner: for each sphere class with pairs in this batch, times every CG
@@ -907,7 +908,6 @@ void default_solve_variants(exx_plan_t P) {
     }
     P->class_threads[k] = (opt.solve_threads == 512 || opt.solve_threads == 1024) ? opt.solve_threads
                           : (nc <= cpt * 1024 ? 1024 : 512);
-    if (tilted_arms(P->geo)) P->class_depth[k] = 1;
   }
 }
 
